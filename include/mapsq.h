@@ -1,0 +1,209 @@
+/*
+ * mapsq.h -- C ABI of libmapsq.so, an MI355X (gfx950) implementation of the
+ * MapReduce-based join of MapSQ (Feng, Zhang and Feng, "MapSQ: A
+ * MapReduce-based Framework for SPARQL Queries on GPU", arXiv 1702.03484).
+ *
+ * What the library computes
+ *   Section 1 of the paper: every triple pattern of a SPARQL basic graph
+ *   pattern yields a table of partial matches whose key is the variable it
+ *   shares with another pattern and whose value is its other variables; the
+ *   answer is the join of those tables (Table 1).  Section 2, Algorithm 1:
+ *   the join runs as Map (emit key/value records labelled LEFT or RIGHT),
+ *   Sort (group by key) and ReduceDuplicate (per key, pair every LEFT record
+ *   with every RIGHT record).  Section 2, text after Algorithm 1: results are
+ *   merged pattern by pattern on one shared variable; the CPU assigns the
+ *   subqueries and the GPU joins them (abstract).
+ *
+ * Conventions
+ *   - Every call returns a mapsq_status; 0 is success, negative values are
+ *     errors.  The message of the last error of a context is returned by
+ *     mapsq_last_error().  No C++ exception crosses this boundary.
+ *   - Arguments are checked before any GPU work is enqueued.  On error every
+ *     output struct is zeroed and nothing the library owns is left
+ *     half-written.
+ *   - Terms of a triple pattern: a value >= 0 is a constant (a dictionary
+ *     ID); a value < 0 is the variable number -t-1 (so -1 is variable 0).
+ *     IDs must lie in [0, 2^31 - 1).
+ *   - Tables are SoA: column c holds nrows int32 values in device memory and
+ *     carries the variable var[c].  A join's result has the columns
+ *     [key, left's other variables in left order, right's variables that the
+ *     left does not bind, in right order], as in Table 1(c).  Row order is
+ *     deterministic but not part of the result's meaning.
+ *   - Bag semantics: every matching triple, and every pair of matching rows,
+ *     gives one row; nothing is de-duplicated unless MAPSQ_LOAD_DEDUP asks
+ *     for set semantics at load time.
+ *
+ * Memory and streams
+ *   The caller owns all device memory.  mapsq_create() receives one device
+ *   arena (for instance a torch uint8 tensor) and a hipStream_t; the library
+ *   sub-allocates the store, its scratch buffers and result tables inside
+ *   that arena and never calls hipMalloc.  Host-side bookkeeping is the only
+ *   host allocation.  All GPU work of a context is enqueued on its stream.
+ *   A context is externally synchronised: one thread at a time per context.
+ *   Several contexts may share a device.
+ */
+#ifndef MAPSQ_H
+#define MAPSQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mapsq_status;
+
+#define MAPSQ_OK 0
+#define MAPSQ_ERR_INVALID_ARG (-1) /* a pointer, size or term is invalid */
+#define MAPSQ_ERR_UNSUPPORTED (-2) /* valid but not supported (e.g. a pattern with no variable) */
+#define MAPSQ_ERR_CAPACITY (-3)    /* the arena has no room for the request */
+#define MAPSQ_ERR_TOO_LARGE (-4)   /* the exact result exceeds the arena or 2^40 rows */
+#define MAPSQ_ERR_HIP (-5)         /* a HIP runtime call failed */
+#define MAPSQ_ERR_STATE (-6)       /* call out of order (e.g. no store loaded) */
+
+#define MAPSQ_MAX_COLS 16
+
+/* mapsq_load_triples flags */
+#define MAPSQ_LOAD_DEVICE_PTRS 1u /* s, p, o are device pointers (else host pointers) */
+#define MAPSQ_LOAD_DEDUP 2u       /* drop repeated triples (RDF set semantics) */
+
+typedef struct mapsq_ctx mapsq_ctx; /* opaque */
+
+/* A triple pattern (Section 1): each term a constant ID (>= 0) or a variable (< 0). */
+typedef struct {
+    int32_t s, p, o;
+} mapsq_pattern;
+
+/* A binding table in device memory (SoA int32 columns). */
+typedef struct {
+    int64_t nrows;
+    int32_t ncols;
+    int32_t owned;              /* 1: columns live in the context arena; release with mapsq_table_free.
+                                   0: a view (of the loaded store, or caller-owned columns). */
+    int32_t var[MAPSQ_MAX_COLS];/* variable number of each column */
+    int32_t* col[MAPSQ_MAX_COLS];/* device pointer of each column */
+    uint64_t block;             /* library bookkeeping (arena block id); 0 for views */
+    int32_t key_max;            /* upper bound of the IDs in the table, -1 if unknown */
+    int32_t reserved;
+} mapsq_table;
+
+/* Facts about the loaded store. */
+typedef struct {
+    int64_t n_triples;
+    int64_t n_predicates;  /* distinct predicate IDs */
+    int32_t max_id;        /* largest ID over s, p, o */
+    int32_t id_bits;       /* bit length of max_id */
+    uint64_t device_bytes; /* arena bytes held by the store and its indexes */
+} mapsq_store_facts;
+
+/* What the last join of a context did (filled by mapsq_join and mapsq_query). */
+typedef struct {
+    int64_t left_rows, right_rows;
+    int64_t segments;      /* distinct keys among the |L|+|R| sorted records */
+    int64_t out_rows;      /* exact |RS| = sum over keys of cL * cR (before equality filters) */
+    int32_t radix_bits;    /* digit width of the sort */
+    int32_t passes;        /* radix passes */
+    int32_t key_bits;      /* bits sorted */
+    int32_t reserved;
+} mapsq_join_stats;
+
+/* Create a context on `device`.  `arena` is device memory of `arena_bytes`
+ * bytes owned by the caller and kept alive until mapsq_destroy; it must be
+ * 256-byte aligned.  `hip_stream` is a hipStream_t (NULL = the null stream).
+ * Returns INVALID_ARG for a NULL out/arena, a misaligned arena or fewer than
+ * 64 MiB; HIP when the device cannot be selected. */
+mapsq_status mapsq_create(int device, void* arena, size_t arena_bytes, void* hip_stream, mapsq_ctx** out);
+
+/* Destroy a context (synchronises its stream first).  NULL is accepted. */
+mapsq_status mapsq_destroy(mapsq_ctx* ctx);
+
+/* Message of the last error of `ctx` ("" if none); valid until the next call. */
+const char* mapsq_last_error(const mapsq_ctx* ctx);
+
+/* Load a dictionary-encoded store of n triples (s[i], p[i], o[i]) and build
+ * its indexes: the raw SoA columns, a copy sorted by (p, s, o) and one
+ * sorted by (p, o, s), with the predicate ranges.  Replaces any store loaded
+ * before (tables that view the old store become invalid).  s, p, o are host
+ * pointers unless MAPSQ_LOAD_DEVICE_PTRS is set; the library copies them
+ * and the caller keeps ownership.  INVALID_ARG for n < 0, NULL columns with
+ * n > 0, n >= 2^31 or an ID outside [0, 2^31 - 1); CAPACITY when the arena
+ * cannot hold 28 bytes per triple plus scratch.  Synchronises once. */
+mapsq_status mapsq_load_triples(mapsq_ctx* ctx, const int32_t* s, const int32_t* p, const int32_t* o,
+                                int64_t n, uint32_t flags);
+
+mapsq_status mapsq_store_info(mapsq_ctx* ctx, mapsq_store_facts* out);
+
+/* Map (Section 1 partial matches; Algorithm 1's Map): the table of matches
+ * of one triple pattern, key variable `key_var` first (-1: no key, columns
+ * in first-appearance order over s, p, o), then the other variables in
+ * first-appearance order.  Constants are not materialised.  A pattern whose
+ * constants form a prefix of one index order and that has no repeated
+ * variable returns a view of the store (owned = 0); any other pattern is
+ * scanned and compacted into an owned table.  UNSUPPORTED for a pattern
+ * without variables; STATE without a store.  Synchronises once. */
+mapsq_status mapsq_map_pattern(mapsq_ctx* ctx, const mapsq_pattern* pattern, int32_t key_var, mapsq_table* out);
+
+/* Join (Algorithm 1): RS = left JOIN right on variable `key_var`, which both
+ * tables must bind.  Other variables bound by both sides are filtered for
+ * equality after the key join.  Tables may be views, owned results or
+ * caller-owned columns (owned = 0, key_max = bound or -1).  Each side may
+ * hold at most 2^31 - 1 rows.  TOO_LARGE when |RS| exceeds the arena's free
+ * space or 2^40 rows (nothing is allocated then).  Enqueues the sort and the
+ * counting, synchronises once to read the exact |RS|, then enqueues the
+ * materialisation and returns without waiting for it. */
+mapsq_status mapsq_join(mapsq_ctx* ctx, const mapsq_table* left, const mapsq_table* right, int32_t key_var,
+                        mapsq_table* out);
+
+/* Query (Section 2: pattern-by-pattern merging, CPU plans, GPU joins): the
+ * bag of solutions of the basic graph pattern pats[0..npats), projected on
+ * select_vars[0..nselect) in that order (nselect = 0: every variable, in
+ * first-appearance order).  The host maps every pattern, then joins greedily
+ * from the smallest partial-match table, always taking the smallest table
+ * connected to the bound variables; further shared variables are filtered
+ * by equality; an unconnected pattern joins by cross product.
+ * Intermediate tables are freed; the result is owned. */
+mapsq_status mapsq_query(mapsq_ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* select_vars,
+                         int32_t nselect, mapsq_table* out);
+
+/* Release an owned table (views are left alone); the struct is zeroed. */
+mapsq_status mapsq_table_free(mapsq_ctx* ctx, mapsq_table* t);
+
+/* Statistics of the most recent join of the context. */
+mapsq_status mapsq_last_join_stats(mapsq_ctx* ctx, mapsq_join_stats* out);
+
+/* Radix digit width (4..11 bits; 0 = automatic) and keys per thread of the
+ * sort tiles (8, 16 or 24; 0 = automatic) used by later joins.  Every choice
+ * gives the same rows in the same order. */
+mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_per_thread);
+
+/* Per-phase device time and algorithmic bytes, accumulated while profiling
+ * is on.  Phases: 0 map (range location and scan/compaction), 1 sort
+ * (histogram and radix passes), 2 count (segment heads, LEFT/RIGHT split,
+ * count and offset scan), 3 materialize, 4 equality filter, 5 index build.
+ * Times come from hipEvents recorded on the context's stream around each
+ * phase's launches.  Algorithmic bytes are what each phase must move given
+ * the exact sizes (formulas in the design notes of the repository). */
+#define MAPSQ_NPHASES 6
+typedef struct {
+    double ms[MAPSQ_NPHASES];
+    double bytes[MAPSQ_NPHASES];
+    int64_t launches[MAPSQ_NPHASES]; /* timed intervals per phase */
+    int64_t joins;
+    int64_t rows_out;                /* sum of exact |RS| over the joins */
+} mapsq_profile;
+
+/* Turn profiling on (1) or off (0); either way the accumulators are reset. */
+mapsq_status mapsq_profile_enable(mapsq_ctx* ctx, int32_t on);
+
+/* Synchronise the context's stream and return the accumulators. */
+mapsq_status mapsq_profile_read(mapsq_ctx* ctx, mapsq_profile* out);
+
+/* Bytes of the arena still free, and the largest free block. */
+mapsq_status mapsq_arena_free_bytes(mapsq_ctx* ctx, uint64_t* free_bytes, uint64_t* largest_block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAPSQ_H */

@@ -1,0 +1,234 @@
+"""ctypes binding of libmapsq.so (include/mapsq.h).
+
+Argument marshalling only: every step of the join runs in the library's HIP
+kernels.  The functions keep the C names; a status other than MAPSQ_OK
+raises :class:`MapSQError` carrying the code and the context's message.
+PyTorch is used for device memory (the arena tensor) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmapsq.so")
+MAX_COLS = 16
+
+MAPSQ_OK = 0
+MAPSQ_ERR_INVALID_ARG = -1
+MAPSQ_ERR_UNSUPPORTED = -2
+MAPSQ_ERR_CAPACITY = -3
+MAPSQ_ERR_TOO_LARGE = -4
+MAPSQ_ERR_HIP = -5
+MAPSQ_ERR_STATE = -6
+MAPSQ_LOAD_DEVICE_PTRS = 1
+MAPSQ_LOAD_DEDUP = 2
+
+ERROR_NAMES = {
+    -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "CAPACITY", -4: "TOO_LARGE", -5: "HIP", -6: "STATE",
+}
+
+
+class mapsq_pattern(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int32), ("p", ctypes.c_int32), ("o", ctypes.c_int32)]
+
+
+class mapsq_table(ctypes.Structure):
+    _fields_ = [
+        ("nrows", ctypes.c_int64),
+        ("ncols", ctypes.c_int32),
+        ("owned", ctypes.c_int32),
+        ("var", ctypes.c_int32 * MAX_COLS),
+        ("col", ctypes.c_void_p * MAX_COLS),
+        ("block", ctypes.c_uint64),
+        ("key_max", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    @property
+    def vars(self):
+        return [int(self.var[i]) for i in range(self.ncols)]
+
+
+class mapsq_store_facts(ctypes.Structure):
+    _fields_ = [
+        ("n_triples", ctypes.c_int64),
+        ("n_predicates", ctypes.c_int64),
+        ("max_id", ctypes.c_int32),
+        ("id_bits", ctypes.c_int32),
+        ("device_bytes", ctypes.c_uint64),
+    ]
+
+
+class mapsq_join_stats(ctypes.Structure):
+    _fields_ = [
+        ("left_rows", ctypes.c_int64),
+        ("right_rows", ctypes.c_int64),
+        ("segments", ctypes.c_int64),
+        ("out_rows", ctypes.c_int64),
+        ("radix_bits", ctypes.c_int32),
+        ("passes", ctypes.c_int32),
+        ("key_bits", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+NPHASES = 6
+PHASES = ["map", "sort", "count", "materialize", "filter", "index"]
+
+
+class mapsq_profile(ctypes.Structure):
+    _fields_ = [
+        ("ms", ctypes.c_double * NPHASES),
+        ("bytes", ctypes.c_double * NPHASES),
+        ("launches", ctypes.c_int64 * NPHASES),
+        ("joins", ctypes.c_int64),
+        ("rows_out", ctypes.c_int64),
+    ]
+
+
+class MapSQError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mapsq {ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported symbol
+_P = ctypes.c_void_p
+_SIGS = [
+    ("mapsq_create", ctypes.c_int32, [ctypes.c_int, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    ("mapsq_destroy", ctypes.c_int32, [_P]),
+    ("mapsq_last_error", ctypes.c_char_p, [_P]),
+    ("mapsq_load_triples", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_uint32]),
+    ("mapsq_store_info", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_store_facts)]),
+    ("mapsq_map_pattern", ctypes.c_int32,
+     [_P, ctypes.POINTER(mapsq_pattern), ctypes.c_int32, ctypes.POINTER(mapsq_table)]),
+    ("mapsq_join", ctypes.c_int32,
+     [_P, ctypes.POINTER(mapsq_table), ctypes.POINTER(mapsq_table), ctypes.c_int32, ctypes.POINTER(mapsq_table)]),
+    ("mapsq_query", ctypes.c_int32,
+     [_P, ctypes.POINTER(mapsq_pattern), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+      ctypes.POINTER(mapsq_table)]),
+    ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
+    ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
+    ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
+    ("mapsq_profile_enable", ctypes.c_int32, [_P, ctypes.c_int32]),
+    ("mapsq_profile_read", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_profile)]),
+    ("mapsq_arena_free_bytes", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+]
+EXPORTED = [s[0] for s in _SIGS]
+
+
+def lib():
+    """The loaded library; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(ctx, st):
+    if st != MAPSQ_OK:
+        msg = lib().mapsq_last_error(ctx).decode() if ctx else ""
+        raise MapSQError(int(st), msg)
+
+
+def mapsq_create(device: int, arena_ptr: int, arena_bytes: int, stream_ptr: int):
+    out = _P()
+    st = lib().mapsq_create(device, arena_ptr, arena_bytes, stream_ptr, ctypes.byref(out))
+    if st != MAPSQ_OK:
+        raise MapSQError(int(st), "mapsq_create failed")
+    return out
+
+
+def mapsq_destroy(ctx):
+    _check(ctx, lib().mapsq_destroy(ctx))
+
+
+def mapsq_last_error(ctx) -> str:
+    return lib().mapsq_last_error(ctx).decode()
+
+
+def mapsq_load_triples(ctx, s_ptr: int, p_ptr: int, o_ptr: int, n: int, flags: int = 0):
+    _check(ctx, lib().mapsq_load_triples(ctx, s_ptr, p_ptr, o_ptr, n, flags))
+
+
+def mapsq_store_info(ctx) -> mapsq_store_facts:
+    out = mapsq_store_facts()
+    _check(ctx, lib().mapsq_store_info(ctx, ctypes.byref(out)))
+    return out
+
+
+def mapsq_map_pattern(ctx, pattern, key_var: int = -1) -> mapsq_table:
+    pat = mapsq_pattern(*pattern)
+    out = mapsq_table()
+    _check(ctx, lib().mapsq_map_pattern(ctx, ctypes.byref(pat), key_var, ctypes.byref(out)))
+    return out
+
+
+def mapsq_join(ctx, left: mapsq_table, right: mapsq_table, key_var: int) -> mapsq_table:
+    out = mapsq_table()
+    _check(ctx, lib().mapsq_join(ctx, ctypes.byref(left), ctypes.byref(right), key_var, ctypes.byref(out)))
+    return out
+
+
+def mapsq_query(ctx, patterns, select=None) -> mapsq_table:
+    arr = (mapsq_pattern * len(patterns))(*[mapsq_pattern(*p) for p in patterns])
+    sel = list(select or [])
+    sarr = (ctypes.c_int32 * max(1, len(sel)))(*sel)
+    out = mapsq_table()
+    _check(ctx, lib().mapsq_query(ctx, arr, len(patterns), sarr, len(sel), ctypes.byref(out)))
+    return out
+
+
+def mapsq_table_free(ctx, t: mapsq_table):
+    _check(ctx, lib().mapsq_table_free(ctx, ctypes.byref(t)))
+
+
+def mapsq_last_join_stats(ctx) -> mapsq_join_stats:
+    out = mapsq_join_stats()
+    _check(ctx, lib().mapsq_last_join_stats(ctx, ctypes.byref(out)))
+    return out
+
+
+def mapsq_set_tuning(ctx, radix_bits: int = 0, keys_per_thread: int = 0):
+    _check(ctx, lib().mapsq_set_tuning(ctx, radix_bits, keys_per_thread))
+
+
+def mapsq_profile_enable(ctx, on: bool = True):
+    _check(ctx, lib().mapsq_profile_enable(ctx, 1 if on else 0))
+
+
+def mapsq_profile_read(ctx) -> mapsq_profile:
+    out = mapsq_profile()
+    _check(ctx, lib().mapsq_profile_read(ctx, ctypes.byref(out)))
+    return out
+
+
+def mapsq_arena_free_bytes(ctx):
+    a = ctypes.c_uint64()
+    b = ctypes.c_uint64()
+    _check(ctx, lib().mapsq_arena_free_bytes(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def make_table(vars, col_ptrs, nrows: int, key_max: int = -1) -> mapsq_table:
+    """A caller-owned table (owned = 0) over existing device columns."""
+    t = mapsq_table()
+    t.nrows = nrows
+    t.ncols = len(vars)
+    t.owned = 0
+    t.key_max = key_max
+    for i, (v, p) in enumerate(zip(vars, col_ptrs)):
+        t.var[i] = v
+        t.col[i] = p
+    return t

@@ -1,0 +1,193 @@
+// extern "C" boundary of libmapsq.so (declared in include/mapsq.h): checks
+// arguments, selects the context's device for the duration of the call and
+// keeps C++ exceptions from crossing the ABI.
+#include <cstring>
+#include <new>
+
+#include "runtime.h"
+
+using mq::Ctx;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename F>
+mapsq_status guarded(mapsq_ctx* c, F&& f) {
+    if (!c) return MAPSQ_ERR_INVALID_ARG;
+    Ctx* ctx = &c->impl;
+    ctx->err.clear();
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return ctx->fail(MAPSQ_ERR_HIP, "hipSetDevice failed");
+    try {
+        return f(ctx);
+    } catch (const std::bad_alloc&) {
+        return ctx->fail(MAPSQ_ERR_CAPACITY, "host allocation failed");
+    } catch (...) {
+        return ctx->fail(MAPSQ_ERR_HIP, "unexpected host exception");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+mapsq_status mapsq_create(int device, void* arena, size_t arena_bytes, void* hip_stream, mapsq_ctx** out) {
+    if (!out) return MAPSQ_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!arena || arena_bytes < (size_t(64) << 20) || reinterpret_cast<uintptr_t>(arena) % mq::ARENA_ALIGN)
+        return MAPSQ_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MAPSQ_ERR_HIP;
+    DeviceGuard g(device);
+    if (!g.ok) return MAPSQ_ERR_HIP;
+    mapsq_ctx* c = new (std::nothrow) mapsq_ctx();
+    if (!c) return MAPSQ_ERR_CAPACITY;
+    Ctx* ctx = &c->impl;
+    ctx->device = device;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    ctx->arena.init(reinterpret_cast<char*>(arena), arena_bytes);
+    ctx->small_off = ctx->arena.alloc(mq::SMALL_WORDS * 4);
+    ctx->small = reinterpret_cast<uint32_t*>(ctx->arena.ptr(ctx->small_off));
+    if (hipHostMalloc(&ctx->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return MAPSQ_ERR_HIP;
+    }
+    if (mq::launch_fill_u32(ctx->small, mq::SMALL_WORDS, 0u, ctx->stream) != hipSuccess ||
+        !ctx->ensure_status(1 << 16)) {
+        (void)hipHostFree(ctx->pinned);
+        delete c;
+        return MAPSQ_ERR_HIP;
+    }
+    *out = c;
+    return MAPSQ_OK;
+}
+
+mapsq_status mapsq_destroy(mapsq_ctx* c) {
+    if (!c) return MAPSQ_OK;
+    {
+        DeviceGuard g(c->impl.device);
+        (void)hipStreamSynchronize(c->impl.stream);
+        c->impl.prof_release();
+        if (c->impl.pinned) (void)hipHostFree(c->impl.pinned);
+    }
+    delete c;
+    return MAPSQ_OK;
+}
+
+const char* mapsq_last_error(const mapsq_ctx* c) {
+    if (!c) return "null context";
+    return c->impl.err.c_str();
+}
+
+mapsq_status mapsq_load_triples(mapsq_ctx* c, const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
+                                uint32_t flags) {
+    return guarded(c, [&](Ctx* ctx) { return mq::load_triples(ctx, s, p, o, n, flags); });
+}
+
+mapsq_status mapsq_store_info(mapsq_ctx* c, mapsq_store_facts* out) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        std::memset(out, 0, sizeof(*out));
+        if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
+        out->n_triples = ctx->store.n;
+        out->n_predicates = (int64_t)ctx->store.preds.size();
+        out->max_id = ctx->store.max_id;
+        out->id_bits = ctx->store.id_bits;
+        out->device_bytes = ctx->store.bytes;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
+mapsq_status mapsq_map_pattern(mapsq_ctx* c, const mapsq_pattern* pattern, int32_t key_var, mapsq_table* out) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!out || !pattern) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null argument");
+        return mq::map_pattern(ctx, pattern, key_var, out);
+    });
+}
+
+mapsq_status mapsq_join(mapsq_ctx* c, const mapsq_table* left, const mapsq_table* right, int32_t key_var,
+                        mapsq_table* out) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        return mq::join_tables(ctx, left, right, key_var, out);
+    });
+}
+
+mapsq_status mapsq_query(mapsq_ctx* c, const mapsq_pattern* pats, int32_t npats, const int32_t* select_vars,
+                         int32_t nselect, mapsq_table* out) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        return mq::query(ctx, pats, npats, select_vars, nselect, out);
+    });
+}
+
+mapsq_status mapsq_table_free(mapsq_ctx* c, mapsq_table* t) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!t) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null table");
+        return mq::free_table(ctx, t);
+    });
+}
+
+mapsq_status mapsq_last_join_stats(mapsq_ctx* c, mapsq_join_stats* out) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        *out = ctx->last;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
+mapsq_status mapsq_set_tuning(mapsq_ctx* c, int32_t radix_bits, int32_t keys_per_thread) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (radix_bits != 0 && (radix_bits < 4 || radix_bits > 11))
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "radix_bits must be 0 or in [4, 11]");
+        if (keys_per_thread != 0 && keys_per_thread != 8 && keys_per_thread != 16)
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "keys_per_thread must be 0, 8 or 16");
+        ctx->tune_rb = radix_bits;
+        ctx->tune_kpt = keys_per_thread;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
+mapsq_status mapsq_profile_enable(mapsq_ctx* c, int32_t on) {
+    return guarded(c, [&](Ctx* ctx) {
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->prof_harvest();
+        ctx->acc = mapsq_profile{};
+        ctx->prof = on != 0;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
+mapsq_status mapsq_profile_read(mapsq_ctx* c, mapsq_profile* out) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return ctx->fail(MAPSQ_ERR_HIP, hipGetErrorString(e));
+        ctx->prof_harvest();
+        *out = ctx->acc;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
+mapsq_status mapsq_arena_free_bytes(mapsq_ctx* c, uint64_t* free_bytes, uint64_t* largest_block) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!free_bytes || !largest_block) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        *free_bytes = ctx->arena.free_bytes();
+        *largest_block = ctx->arena.largest();
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Device helpers shared by the gfx950 kernels: wave64 scans, block scans and
+// the status words of single-pass decoupled look-back.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MQ_WAVE 64
+#define MQ_BLOCK 256
+#define MQ_WAVES (MQ_BLOCK / MQ_WAVE)
+
+namespace mq {
+
+__device__ __forceinline__ uint32_t lane() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+#pragma unroll
+    for (int o = 1; o < MQ_WAVE; o <<= 1) {
+        T t = __shfl_up(v, o, MQ_WAVE);
+        if ((int)lane() >= o) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, MQ_WAVE);
+    return v;
+}
+
+// Exclusive scan over the block (MQ_BLOCK threads).  `tmp` is MQ_WAVES
+// entries of LDS.  Returns the exclusive prefix; *total gets the block sum.
+// Contains __syncthreads(); every thread of the block must call it.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* tmp, T* total) {
+    T inc = wave_incl_scan(v);
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    if (lane() == MQ_WAVE - 1) tmp[w] = inc;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < MQ_WAVES; i++) {
+        T x = tmp[i];
+        if ((uint32_t)i < w) before += x;
+        all += x;
+    }
+    *total = all;
+    __syncthreads();
+    return before + inc - v;
+}
+
+// ---- decoupled look-back status words ------------------------------------
+// 64-bit word: [63:42] epoch (22 bits), [41:40] flag, [39:0] value.  A word
+// whose epoch differs from the running pass's epoch counts as "not yet
+// published", so the status array is never cleared between passes.
+constexpr uint32_t ST_AGG = 1;  // the tile's own aggregate
+constexpr uint32_t ST_INC = 2;  // inclusive prefix up to and including the tile
+constexpr uint64_t ST_VAL_MASK = (1ull << 40) - 1ull;
+constexpr uint64_t SAT40 = ST_VAL_MASK;  // saturation cap of 40-bit sums
+
+__device__ __forceinline__ uint64_t st_pack(uint32_t epoch, uint32_t flag, uint64_t v) {
+    return ((uint64_t)epoch << 42) | ((uint64_t)flag << 40) | (v & ST_VAL_MASK);
+}
+__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
+    uint64_t s = a + b;
+    return s > SAT40 ? SAT40 : s;
+}
+
+// Exclusive prefix of tile `tile` over tiles [first_tile, tile) for one
+// status column; `stride` is the distance between consecutive tiles' words.
+// Spins until predecessors publish.  Sums saturate at 2^40 - 1.
+__device__ __forceinline__ uint64_t lookback(const uint64_t* status, uint32_t tile, uint32_t first_tile,
+                                             uint32_t stride, uint32_t epoch) {
+    uint64_t excl = 0;
+    int64_t t = (int64_t)tile - 1;
+    while (t >= (int64_t)first_tile) {
+        uint64_t w = st_load(status + (uint64_t)t * stride);
+        uint32_t flag = (uint32_t)(w >> 40) & 3u;
+        if ((uint32_t)(w >> 42) != epoch || flag == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl = sat_add(excl, w & ST_VAL_MASK);
+        if (flag == ST_INC) break;
+        t--;
+    }
+    return excl;
+}
+
+// Next dynamic tile id from a counter (thread 0), broadcast through LDS.
+__device__ __forceinline__ uint32_t next_tile(uint32_t* counter, uint32_t* s_slot) {
+    if (threadIdx.x == 0) *s_slot = atomicAdd(counter, 1u);
+    __syncthreads();
+    uint32_t t = *s_slot;
+    __syncthreads();
+    return t;
+}
+
+}  // namespace mq

@@ -1,0 +1,117 @@
+// Small gfx950 utility kernels: fills, gathers, min/max, run boundaries,
+// duplicate flags and ID checks used when a store is loaded and indexed.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace mq {
+
+static uint32_t grid_for(uint64_t n, uint32_t per_block, uint32_t cap) {
+    uint64_t b = (n + per_block - 1) / per_block;
+    return (uint32_t)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ p, uint64_t n, T v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    fill_kernel<uint32_t><<<grid_for(n, 256 * 4, 4096), 256, 0, stream>>>(p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    fill_kernel<uint64_t><<<grid_for(n, 256 * 4, 4096), 256, 0, stream>>>(p, n, v);
+    return hipGetLastError();
+}
+
+__global__ void gather_kernel(const int32_t* __restrict__ src, const uint32_t* __restrict__ idx,
+                              int32_t* __restrict__ out, uint64_t n, int32_t base) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = src[idx[i]] - base;
+}
+hipError_t launch_gather(const int32_t* src, const uint32_t* idx, int32_t* out, uint64_t n, int32_t base,
+                         hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    gather_kernel<<<grid_for(n, 256 * 4, 8192), 256, 0, stream>>>(src, idx, out, n, base);
+    return hipGetLastError();
+}
+
+__global__ void minmax_kernel(const int32_t* __restrict__ a, uint64_t na, const int32_t* __restrict__ b,
+                              uint64_t nb, int32_t* __restrict__ mm) {
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    const uint64_t n = na + nb;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        int32_t v = i < na ? a[i] : b[i - na];
+        lo = min(lo, v);
+        hi = max(hi, v);
+    }
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, MQ_WAVE));
+        hi = max(hi, __shfl_xor(hi, o, MQ_WAVE));
+    }
+    if (mq::lane() == 0) {
+        atomicMin(&mm[0], lo);
+        atomicMax(&mm[1], hi);
+    }
+}
+hipError_t launch_minmax(const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int32_t* minmax,
+                         hipStream_t stream) {
+    if (na + nb == 0) return hipSuccess;
+    minmax_kernel<<<grid_for(na + nb, 256 * 16, 2048), 256, 0, stream>>>(a, na, b, nb, minmax);
+    return hipGetLastError();
+}
+
+__global__ void run_bounds_kernel(const int32_t* __restrict__ v, uint64_t n, int32_t* __restrict__ out_val,
+                                  int64_t* __restrict__ out_pos, uint32_t* __restrict__ count, uint32_t cap) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i == 0 || v[i] != v[i - 1]) {
+            uint32_t at = atomicAdd(count, 1u);
+            if (at < cap) {
+                out_val[at] = v[i];
+                out_pos[at] = (int64_t)i;
+            }
+        }
+    }
+}
+hipError_t launch_run_bounds(const int32_t* v, uint64_t n, int32_t* out_val, int64_t* out_pos, uint32_t* count,
+                             uint32_t cap, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    run_bounds_kernel<<<grid_for(n, 256 * 8, 4096), 256, 0, stream>>>(v, n, out_val, out_pos, count, cap);
+    return hipGetLastError();
+}
+
+__global__ void dup_flags_kernel(const int32_t* __restrict__ p, const int32_t* __restrict__ s,
+                                 const int32_t* __restrict__ o, const uint32_t* __restrict__ perm, uint64_t n,
+                                 int32_t* __restrict__ keep) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        bool first = i == 0 || p[i] != p[i - 1] || s[i] != s[i - 1] || o[i] != o[i - 1];
+        keep[perm[i]] = first ? 1 : 0;
+    }
+}
+hipError_t launch_dup_flags(const int32_t* p, const int32_t* s, const int32_t* o, const uint32_t* perm,
+                            uint64_t n, int32_t* keep, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    dup_flags_kernel<<<grid_for(n, 256 * 8, 8192), 256, 0, stream>>>(p, s, o, perm, n, keep);
+    return hipGetLastError();
+}
+
+__global__ void check_ids_kernel(const int32_t* __restrict__ a, uint64_t n, uint32_t* __restrict__ bad) {
+    uint32_t c = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        int32_t v = a[i];
+        c += (v < 0 || v == INT32_MAX) ? 1u : 0u;
+    }
+    c = wave_sum(c);
+    if (mq::lane() == 0 && c) atomicAdd(bad, c);
+}
+hipError_t launch_check_ids(const int32_t* a, uint64_t n, uint32_t* bad, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    check_ids_kernel<<<grid_for(n, 256 * 16, 2048), 256, 0, stream>>>(a, n, bad);
+    return hipGetLastError();
+}
+
+}  // namespace mq

@@ -1,0 +1,117 @@
+// Host-side launchers of the gfx950 kernels (one translation unit per
+// kernel family).  All launches are asynchronous on the given stream; a
+// launcher returns the launch error, if any.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mq {
+
+// ---- shuffle: LSD radix sort (k_sort.hip) --------------------------------
+// Keys of a first pass come from two int32 segments (k0[0..n0) then
+// k1[0..n1)), minus `base`; the payload is the position in that
+// concatenation.
+struct SortSrc {
+    const int32_t* k0;
+    uint32_t n0;
+    const int32_t* k1;
+    uint32_t n1;
+    int32_t base;
+};
+
+// Adds the digit histograms of `passes` passes to hist[passes][2^rb] (which
+// the caller zeroes).  keys == nullptr: read the keys from `src`.
+hipError_t launch_radix_hist(const SortSrc& src, const uint32_t* keys, uint32_t n, int rb, int passes,
+                             uint32_t* hist, hipStream_t stream);
+// One stable pass on digit `pass`.  kin == nullptr: first-pass mode from
+// `src` (vin ignored).  hist_pass = this pass's histogram; status holds
+// radix_tiles(n,kpt) * 2^rb words; tile_ctr is zero before the launch.
+hipError_t launch_radix_pass(int rb, int kpt, const SortSrc& src, const uint32_t* kin, const uint32_t* vin,
+                             uint32_t* kout, uint32_t* vout, uint32_t n, int pass, const uint32_t* hist_pass,
+                             uint64_t* status, uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
+uint32_t radix_tiles(uint32_t n, int kpt);
+
+// ---- reduce (k_reduce.hip) -------------------------------------------------
+// Segment heads of the sorted keys: seg_start[s] = first position of the
+// s-th distinct key; *nseg = number of segments.  Persistent grid.
+hipError_t launch_seg_heads(const uint32_t* keys, uint32_t n, uint32_t* seg_start, uint32_t* nseg,
+                            uint64_t* status, uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
+// Per segment: split = first position whose payload >= n_left (the first
+// RIGHT record), count = (split-start)*(end-split); off = exclusive scan of
+// the counts (saturating at 2^40-1); *total = the full sum.
+hipError_t launch_seg_count(const uint32_t* vals, uint32_t n, uint32_t n_left, const uint32_t* seg_start,
+                            const uint32_t* nseg, uint32_t max_seg, uint32_t* seg_split, uint64_t* seg_off,
+                            uint64_t* total, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch,
+                            hipStream_t stream);
+
+struct MatArgs {
+    const uint32_t* keys;      // sorted relative keys
+    const uint32_t* vals;      // sorted payloads (record positions)
+    const uint32_t* seg_start;
+    const uint32_t* seg_split;
+    const uint64_t* seg_off;
+    const uint32_t* nseg;      // device count of segments
+    uint32_t n;                // records
+    uint32_t n_left;
+    int32_t key_base;
+    int32_t nl, nr;            // value columns of each side
+    const int32_t* lcol[16];
+    const int32_t* rcol[16];
+    int32_t* out[16];          // 1 + nl + nr output columns
+    uint64_t row_begin, row_end;  // materialise output rows [row_begin, row_end)
+};
+hipError_t launch_materialize(const MatArgs& a, hipStream_t stream);
+
+// ---- map and filters (k_map.hip) -----------------------------------------
+// Stream compaction of the rows of up to 16 int32 columns that pass every
+// equality term; copies the selected columns.  A term compares column a
+// with column b (b >= 0) or with constant c (b < 0).
+struct CompactArgs {
+    const int32_t* in[16];
+    int32_t nin;
+    uint64_t n;
+    int32_t nterm;
+    int32_t term_a[6];
+    int32_t term_b[6];
+    int32_t term_c[6];
+    int32_t nout;
+    int32_t out_src[16];
+    int32_t* out[16];
+    uint64_t* count;           // device: rows kept
+};
+hipError_t launch_compact(const CompactArgs& a, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch,
+                          hipStream_t stream);
+
+// Range location in sorted columns: for query q, lo/hi start as the given
+// range; level 1 narrows it to rows whose col1 value equals v1, level 2
+// (if col2) narrows further to col2 == v2.  out[2q], out[2q+1] = result.
+struct LocateQuery {
+    const int32_t* col1;
+    const int32_t* col2;
+    int64_t lo, hi;
+    int32_t v1, v2;
+};
+hipError_t launch_locate(const LocateQuery* q_dev, int32_t nq, int64_t* out, hipStream_t stream);
+
+// ---- utilities (k_util.hip) -----------------------------------------------
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t stream);
+// out[i] = src[idx[i]] - base
+hipError_t launch_gather(const int32_t* src, const uint32_t* idx, int32_t* out, uint64_t n, int32_t base,
+                         hipStream_t stream);
+// minmax[0] = min, minmax[1] = max over the int32 values of two segments
+// (minmax pre-set to INT32_MAX / INT32_MIN by the caller).
+hipError_t launch_minmax(const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int32_t* minmax,
+                         hipStream_t stream);
+// Run boundaries of a sorted column: for every i with v[i] != v[i-1] (or
+// i == 0) appends (v[i], i) to out_val/out_pos at atomicAdd(count).
+hipError_t launch_run_bounds(const int32_t* v, uint64_t n, int32_t* out_val, int64_t* out_pos, uint32_t* count,
+                             uint32_t cap, hipStream_t stream);
+// Duplicate flags of the (p,s,o)-sorted store: keep[perm[i]] = 1 if triple
+// i differs from triple i-1 (or i == 0), else 0.
+hipError_t launch_dup_flags(const int32_t* p, const int32_t* s, const int32_t* o, const uint32_t* perm,
+                            uint64_t n, int32_t* keep, hipStream_t stream);
+// IDs outside [0, 2^31-1): count into *bad.
+hipError_t launch_check_ids(const int32_t* a, uint64_t n, uint32_t* bad, hipStream_t stream);
+
+}  // namespace mq

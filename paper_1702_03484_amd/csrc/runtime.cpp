@@ -1,0 +1,887 @@
+// Host runtime of libmapsq: arena, store loading and indexing, the map of a
+// triple pattern, and the plain join driver (Map -> Sort -> ReduceDuplicate
+// of Algorithm 1, with one read-back of the exact output size per join).
+#include "runtime.h"
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
+namespace mq {
+
+// ---------------------------------------------------------------- arena ---
+
+void Arena::init(char* base, size_t size) {
+    base_ = base;
+    size_ = size / ARENA_ALIGN * ARENA_ALIGN;
+    free_.clear();
+    used_.clear();
+    if (size_) free_[0] = size_;
+}
+
+size_t Arena::alloc(size_t bytes) {
+    bytes = align_up(std::max<size_t>(bytes, 1), ARENA_ALIGN);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= bytes) {
+            size_t off = it->first, sz = it->second;
+            free_.erase(it);
+            if (sz > bytes) free_[off + bytes] = sz - bytes;
+            used_[off] = bytes;
+            return off;
+        }
+    }
+    return SIZE_MAX;
+}
+
+void Arena::free(size_t off) {
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    size_t sz = u->second;
+    used_.erase(u);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + sz == nx->first) {
+        sz += nx->second;
+        nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == off) {
+            pv->second += sz;
+            return;
+        }
+    }
+    free_[off] = sz;
+}
+
+void Arena::shrink(size_t off, size_t bytes) {
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    bytes = align_up(std::max<size_t>(bytes, 1), ARENA_ALIGN);
+    if (bytes >= u->second) return;
+    size_t tail = off + bytes, tsz = u->second - bytes;
+    u->second = bytes;
+    used_[tail] = tsz;
+    free(tail);
+}
+
+size_t Arena::free_bytes() const {
+    size_t s = 0;
+    for (auto& kv : free_) s += kv.second;
+    return s;
+}
+
+size_t Arena::largest() const {
+    size_t s = 0;
+    for (auto& kv : free_) s = std::max(s, kv.second);
+    return s;
+}
+
+void Block::reset() {
+    if (ctx && off != SIZE_MAX) ctx->arena.free(off);
+    off = SIZE_MAX;
+}
+
+Block alloc_block(Ctx* ctx, size_t bytes) {
+    Block b;
+    b.ctx = ctx;
+    b.off = ctx->arena.alloc(bytes);
+    return b;
+}
+
+uint32_t Ctx::next_epoch() {
+    if (++epoch >= (1u << 22)) {
+        // every word of the status array is re-tagged as unpublished
+        (void)launch_fill_u64(status, status_words, 0ull, stream);
+        epoch = 1;
+    }
+    return epoch;
+}
+
+bool Ctx::ensure_status(size_t words) {
+    if (words <= status_words) return true;
+    size_t want = std::max(words, status_words * 3 / 2);
+    size_t off = arena.alloc(want * 8);
+    if (off == SIZE_MAX) {
+        want = words;
+        off = arena.alloc(want * 8);
+        if (off == SIZE_MAX) return false;
+    }
+    if (status_off != SIZE_MAX) arena.free(status_off);
+    status_off = off;
+    status = reinterpret_cast<uint64_t*>(arena.ptr(off));
+    status_words = want;
+    (void)launch_fill_u64(status, want, 0ull, stream);
+    return true;
+}
+
+int Ctx::prof_begin(int phase) {
+    if (!prof) return -1;
+    hipEvent_t ev[2];
+    for (auto& e : ev) {
+        if (!event_pool.empty()) {
+            e = event_pool.back();
+            event_pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            return -1;
+        }
+    }
+    (void)hipEventRecord(ev[0], stream);
+    pending.push_back(Interval{ev[0], ev[1], phase, 0.0});
+    return (int)pending.size() - 1;
+}
+
+void Ctx::prof_end(int h, double bytes) {
+    if (h < 0 || h >= (int)pending.size()) return;
+    (void)hipEventRecord(pending[h].b, stream);
+    pending[h].bytes = bytes;
+}
+
+void Ctx::prof_harvest() {
+    for (auto& iv : pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, iv.a, iv.b) == hipSuccess) {
+            acc.ms[iv.phase] += ms;
+            acc.bytes[iv.phase] += iv.bytes;
+            acc.launches[iv.phase] += 1;
+        }
+        event_pool.push_back(iv.a);
+        event_pool.push_back(iv.b);
+    }
+    pending.clear();
+}
+
+void Ctx::prof_release() {
+    for (auto& iv : pending) {
+        event_pool.push_back(iv.a);
+        event_pool.push_back(iv.b);
+    }
+    pending.clear();
+    for (auto e : event_pool) (void)hipEventDestroy(e);
+    event_pool.clear();
+}
+
+#define HIPCHK(x)                                                                                     \
+    do {                                                                                              \
+        hipError_t e_ = (x);                                                                          \
+        if (e_ != hipSuccess) return ctx->fail(MAPSQ_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static inline uint64_t* scalar64(Ctx* ctx, int word) {
+    return reinterpret_cast<uint64_t*>(ctx->small + SMALL_SCALARS + word);
+}
+static inline uint32_t* scalar32(Ctx* ctx, int word) { return ctx->small + SMALL_SCALARS + word; }
+static inline uint32_t* counter(Ctx* ctx, int i) { return ctx->small + SMALL_CTR + i; }
+
+// scalar slots (u32 word index inside the scalar area)
+enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10 };
+// counter slots
+enum { CT_PASS0 = 0, CT_HEADS = 8, CT_COUNT = 9, CT_COMPACT = 10 };
+
+static mapsq_status readback(Ctx* ctx, const void* dev, size_t bytes, void* host) {
+    HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::memcpy(host, ctx->pinned, bytes);
+    return MAPSQ_OK;
+}
+
+// ------------------------------------------------------------ radix sort ---
+
+struct SortBufs {
+    uint32_t* k[2];
+    uint32_t* v[2];
+};
+
+static void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt) {
+    rb = ctx->tune_rb;
+    kpt = ctx->tune_kpt ? ctx->tune_kpt : 16;
+    if (!rb) {
+        // fewest passes with digits of at most 8 bits, spread evenly
+        int passes = std::max(1, (key_bits + 7) / 8);
+        rb = std::max(4, (key_bits + passes - 1) / passes);
+    }
+}
+
+// Sort n records.  src != nullptr: first pass reads keys from src and
+// generates payloads; else the input sits in b.k[0], b.v[0].  Result buffer
+// index in *res.  Zeroes the histogram and tile counters itself.
+static mapsq_status radix_sort(Ctx* ctx, const SortSrc* src, uint32_t n, int key_bits, int rb, int kpt,
+                               SortBufs& b, int* res, int* passes_out) {
+    const int passes = std::max(1, (key_bits + rb - 1) / rb);
+    *passes_out = passes;
+    *res = 0;
+    if (n == 0) return MAPSQ_OK;
+    const size_t buckets = size_t(1) << rb;
+    if (passes * buckets > SMALL_HIST_WORDS) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "radix digit width too small");
+    if (!ctx->ensure_status(size_t(radix_tiles(n, kpt)) * buckets))
+        return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for sort status words");
+    HIPCHK(launch_fill_u32(ctx->small, SMALL_SCALARS, 0u, ctx->stream));
+    SortSrc none{};
+    HIPCHK(launch_radix_hist(src ? *src : none, src ? nullptr : b.k[0], n, rb, passes, ctx->small + SMALL_HIST,
+                             ctx->stream));
+    int cur = 0;
+    for (int p = 0; p < passes; p++) {
+        const bool gen = src && p == 0;
+        int dst = gen ? 0 : 1 - cur;
+        HIPCHK(launch_radix_pass(rb, kpt, gen ? *src : none, gen ? nullptr : b.k[cur], gen ? nullptr : b.v[cur],
+                                 b.k[dst], b.v[dst], n, p, ctx->small + SMALL_HIST + p * buckets, ctx->status,
+                                 counter(ctx, CT_PASS0 + p), ctx->next_epoch(), ctx->stream));
+        cur = dst;
+    }
+    *res = cur;
+    return MAPSQ_OK;
+}
+
+// --------------------------------------------------------- store loading ---
+
+static void free_store(Ctx* ctx) {
+    for (size_t off : ctx->store.blocks) ctx->arena.free(off);
+    ctx->store = Store{};
+}
+
+// Sort the store by (p, first, second) with three stable LSD sorts (second,
+// then first, then p - pmin) and gather the `first`/`second` columns in that
+// order.  On return b.v[*res] holds the permutation (sorted position ->
+// triple) and b.k[*res] the sorted p - pmin.
+static mapsq_status build_order(Ctx* ctx, int64_t n, const int32_t* first, const int32_t* second, int32_t so_max,
+                                int32_t pmin, int32_t pmax, SortBufs& b, int32_t* out_first, int32_t* out_second,
+                                bool want_preds, int* res_out) {
+    int rb, kpt, res, passes;
+    const int so_bits = bitlen((uint32_t)so_max);
+    const int p_bits = bitlen((uint32_t)(pmax - pmin));
+    SortSrc src{second, (uint32_t)n, nullptr, 0, 0};
+    pick_tuning(ctx, so_bits, rb, kpt);
+    mapsq_status st = radix_sort(ctx, &src, (uint32_t)n, so_bits, rb, kpt, b, &res, &passes);
+    if (st) return st;
+    auto to_front = [&]() {
+        if (res != 0) {
+            std::swap(b.k[0], b.k[1]);
+            std::swap(b.v[0], b.v[1]);
+        }
+    };
+    to_front();
+    // then by `first` (stable)
+    HIPCHK(launch_gather(first, b.v[0], reinterpret_cast<int32_t*>(b.k[0]), n, 0, ctx->stream));
+    st = radix_sort(ctx, nullptr, (uint32_t)n, so_bits, rb, kpt, b, &res, &passes);
+    if (st) return st;
+    to_front();
+    // then by p - pmin (stable)
+    HIPCHK(launch_gather(ctx->store.p, b.v[0], reinterpret_cast<int32_t*>(b.k[0]), n, pmin, ctx->stream));
+    pick_tuning(ctx, p_bits, rb, kpt);
+    st = radix_sort(ctx, nullptr, (uint32_t)n, p_bits, rb, kpt, b, &res, &passes);
+    if (st) return st;
+    *res_out = res;
+    HIPCHK(launch_gather(first, b.v[res], out_first, n, 0, ctx->stream));
+    HIPCHK(launch_gather(second, b.v[res], out_second, n, 0, ctx->stream));
+    if (want_preds) {
+        const uint32_t cap = (uint32_t)std::min<int64_t>(n, 1 << 22);
+        Block vals = alloc_block(ctx, size_t(cap) * 4);
+        Block pos = alloc_block(ctx, size_t(cap) * 8);
+        if (!vals.ok() || !pos.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for predicate table");
+        HIPCHK(launch_fill_u32(scalar32(ctx, SC_NPRED), 1, 0u, ctx->stream));
+        HIPCHK(launch_run_bounds(reinterpret_cast<const int32_t*>(b.k[res]), n, vals.as<int32_t>(),
+                                 pos.as<int64_t>(), scalar32(ctx, SC_NPRED), cap, ctx->stream));
+        uint32_t np = 0;
+        if ((st = readback(ctx, scalar32(ctx, SC_NPRED), 4, &np))) return st;
+        if (np > cap) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 2^22 distinct predicates");
+        std::vector<int32_t> pv(np);
+        std::vector<int64_t> pp(np);
+        HIPCHK(hipMemcpyAsync(pv.data(), vals.as<int32_t>(), size_t(np) * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(pp.data(), pos.as<int64_t>(), size_t(np) * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        std::vector<uint32_t> ord(np);
+        for (uint32_t i = 0; i < np; i++) ord[i] = i;
+        std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t c) { return pp[a] < pp[c]; });
+        ctx->store.preds.resize(np);
+        ctx->store.pred_off.resize(np + 1);
+        for (uint32_t i = 0; i < np; i++) {
+            ctx->store.preds[i] = pv[ord[i]] + pmin;
+            ctx->store.pred_off[i] = pp[ord[i]];
+        }
+        ctx->store.pred_off[np] = n;
+    }
+    return MAPSQ_OK;
+}
+
+mapsq_status load_triples(Ctx* ctx, const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
+                          uint32_t flags) {
+    if (n < 0 || n >= (int64_t(1) << 31)) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+    if (n > 0 && (!s || !p || !o)) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null triple column");
+    if (flags & ~(MAPSQ_LOAD_DEVICE_PTRS | MAPSQ_LOAD_DEDUP)) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "unknown flag");
+    free_store(ctx);
+    Store& S = ctx->store;
+    const size_t cb = align_up(size_t(std::max<int64_t>(n, 1)) * 4, ARENA_ALIGN);
+    auto take = [&](int32_t*& dst) -> bool {
+        size_t off = ctx->arena.alloc(cb);
+        if (off == SIZE_MAX) return false;
+        S.blocks.push_back(off);
+        dst = reinterpret_cast<int32_t*>(ctx->arena.ptr(off));
+        S.bytes += cb;
+        return true;
+    };
+    if (!take(S.s) || !take(S.p) || !take(S.o)) {
+        free_store(ctx);
+        return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the raw triples");
+    }
+    const hipMemcpyKind kind = (flags & MAPSQ_LOAD_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    mapsq_status st;
+#define LCHK(x)                   \
+    do {                          \
+        st = (x);                 \
+        if (st) {                 \
+            free_store(ctx);      \
+            return st;            \
+        }                         \
+    } while (0)
+#define LHIP(x)                                                                                       \
+    do {                                                                                              \
+        hipError_t e_ = (x);                                                                          \
+        if (e_ != hipSuccess) {                                                                       \
+            free_store(ctx);                                                                          \
+            return ctx->fail(MAPSQ_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));          \
+        }                                                                                             \
+    } while (0)
+    if (n > 0) {
+        LHIP(hipMemcpyAsync(S.s, s, size_t(n) * 4, kind, ctx->stream));
+        LHIP(hipMemcpyAsync(S.p, p, size_t(n) * 4, kind, ctx->stream));
+        LHIP(hipMemcpyAsync(S.o, o, size_t(n) * 4, kind, ctx->stream));
+    }
+    // ID range check and bounds
+    {
+        // words SC_MINMAX .. SC_MINMAX+5: min/max of s and o, bad-ID count, (unused), min/max of p
+        int32_t init[6] = {INT32_MAX, INT32_MIN, 0, 0, INT32_MAX, INT32_MIN};
+        static_assert(SC_BAD == SC_MINMAX + 2 && SC_MINMAX2 == SC_MINMAX + 4, "scalar layout");
+        std::memcpy(ctx->pinned, init, sizeof(init));
+        LHIP(hipMemcpyAsync(scalar32(ctx, SC_MINMAX), ctx->pinned, sizeof(init), hipMemcpyHostToDevice,
+                            ctx->stream));
+        LHIP(hipStreamSynchronize(ctx->stream));
+    }
+    LHIP(launch_check_ids(S.s, n, scalar32(ctx, SC_BAD), ctx->stream));
+    LHIP(launch_check_ids(S.p, n, scalar32(ctx, SC_BAD), ctx->stream));
+    LHIP(launch_check_ids(S.o, n, scalar32(ctx, SC_BAD), ctx->stream));
+    LHIP(launch_minmax(S.s, n, S.o, n, reinterpret_cast<int32_t*>(scalar32(ctx, SC_MINMAX)), ctx->stream));
+    LHIP(launch_minmax(S.p, n, nullptr, 0, reinterpret_cast<int32_t*>(scalar32(ctx, SC_MINMAX2)), ctx->stream));
+    uint32_t sc[6];
+    LCHK(readback(ctx, scalar32(ctx, SC_MINMAX), 24, sc));  // minmax(2), bad, npred, minmax2(2)
+    if (sc[2] != 0) {
+        free_store(ctx);
+        return ctx->fail(MAPSQ_ERR_INVALID_ARG, "an ID lies outside [0, 2^31 - 1)");
+    }
+    int32_t so_max = n ? (int32_t)sc[1] : 0, pmin = n ? (int32_t)sc[4] : 0, pmax = n ? (int32_t)sc[5] : 0;
+    S.n = n;
+    S.max_id = std::max(so_max, pmax);
+    S.id_bits = bitlen((uint32_t)S.max_id);
+
+    // sort scratch: two key and two payload buffers
+    Block sk0 = alloc_block(ctx, cb), sk1 = alloc_block(ctx, cb), sv0 = alloc_block(ctx, cb),
+          sv1 = alloc_block(ctx, cb);
+    if (!sk0.ok() || !sk1.ok() || !sv0.ok() || !sv1.ok()) {
+        free_store(ctx);
+        return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for index-build scratch");
+    }
+    SortBufs b{{sk0.as<uint32_t>(), sk1.as<uint32_t>()}, {sv0.as<uint32_t>(), sv1.as<uint32_t>()}};
+
+    if ((flags & MAPSQ_LOAD_DEDUP) && n > 0) {
+        // order by (p, s, o), flag the first triple of every run of equal
+        // triples, and keep the flagged triples in input order
+        Block t1 = alloc_block(ctx, cb), t2 = alloc_block(ctx, cb), keep = alloc_block(ctx, cb);
+        Block ns = alloc_block(ctx, cb), np_ = alloc_block(ctx, cb), no = alloc_block(ctx, cb);
+        if (!t1.ok() || !t2.ok() || !keep.ok() || !ns.ok() || !np_.ok() || !no.ok()) {
+            free_store(ctx);
+            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for de-duplication");
+        }
+        int res = 0;
+        LCHK(build_order(ctx, n, S.s, S.o, so_max, pmin, pmax, b, t1.as<int32_t>(), t2.as<int32_t>(), false, &res));
+        LHIP(launch_dup_flags(reinterpret_cast<const int32_t*>(b.k[res]), t1.as<int32_t>(), t2.as<int32_t>(),
+                              b.v[res], n, keep.as<int32_t>(), ctx->stream));
+        CompactArgs c{};
+        c.nin = 4;
+        c.in[0] = S.s;
+        c.in[1] = S.p;
+        c.in[2] = S.o;
+        c.in[3] = keep.as<int32_t>();
+        c.n = (uint64_t)n;
+        c.nterm = 1;
+        c.term_a[0] = 3;
+        c.term_b[0] = -1;
+        c.term_c[0] = 1;
+        c.nout = 3;
+        for (int i = 0; i < 3; i++) c.out_src[i] = i;
+        c.out[0] = ns.as<int32_t>();
+        c.out[1] = np_.as<int32_t>();
+        c.out[2] = no.as<int32_t>();
+        c.count = scalar64(ctx, SC_COUNT);
+        if (!ctx->ensure_status(size_t(n / 4096 + 2))) {
+            free_store(ctx);
+            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
+        }
+        LHIP(launch_fill_u32(counter(ctx, CT_COMPACT), 1, 0u, ctx->stream));
+        LHIP(launch_fill_u32(scalar32(ctx, SC_COUNT), 2, 0u, ctx->stream));
+        LHIP(launch_compact(c, ctx->status, counter(ctx, CT_COMPACT), ctx->next_epoch(), ctx->stream));
+        uint64_t kept = 0;
+        LCHK(readback(ctx, scalar64(ctx, SC_COUNT), 8, &kept));
+        LHIP(hipMemcpyAsync(S.s, ns.as<int32_t>(), kept * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        LHIP(hipMemcpyAsync(S.p, np_.as<int32_t>(), kept * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        LHIP(hipMemcpyAsync(S.o, no.as<int32_t>(), kept * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        n = (int64_t)kept;
+        S.n = n;
+    }
+
+    if (!take(S.pso_s) || !take(S.pso_o) || !take(S.pos_o) || !take(S.pos_s)) {
+        free_store(ctx);
+        return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the PSO/POS indexes");
+    }
+    if (n > 0) {
+        int res = 0;
+        int ph = ctx->prof_begin(5);
+        LCHK(build_order(ctx, n, S.s, S.o, so_max, pmin, pmax, b, S.pso_s, S.pso_o, true, &res));
+        LCHK(build_order(ctx, n, S.o, S.s, so_max, pmin, pmax, b, S.pos_o, S.pos_s, false, &res));
+        ctx->prof_end(ph, 0.0);
+    }
+    LHIP(hipStreamSynchronize(ctx->stream));
+    S.loaded = true;
+#undef LCHK
+#undef LHIP
+    return MAPSQ_OK;
+}
+
+// -------------------------------------------------------------------- map ---
+
+static void zero_table(mapsq_table* t) { std::memset(t, 0, sizeof(*t)); }
+
+static int find_pred(const Store& S, int32_t p) {
+    auto it = std::lower_bound(S.preds.begin(), S.preds.end(), p);
+    if (it == S.preds.end() || *it != p) return -1;
+    return int(it - S.preds.begin());
+}
+
+// Allocate an owned table of `rows` rows x `ncols` columns (one block).
+static mapsq_status alloc_table(Ctx* ctx, int64_t rows, int ncols, mapsq_table* t) {
+    const size_t colb = align_up(size_t(std::max<int64_t>(rows, 1)) * 4, ARENA_ALIGN);
+    size_t off = ctx->arena.alloc(colb * std::max(ncols, 1));
+    if (off == SIZE_MAX) return MAPSQ_ERR_CAPACITY;
+    t->owned = 1;
+    t->block = off + 1;
+    t->ncols = ncols;
+    t->nrows = rows;
+    for (int c = 0; c < ncols; c++) t->col[c] = reinterpret_cast<int32_t*>(ctx->arena.ptr(off + c * colb));
+    return MAPSQ_OK;
+}
+
+mapsq_status free_table(Ctx* ctx, mapsq_table* t) {
+    if (t->owned && t->block) ctx->arena.free(size_t(t->block - 1));
+    zero_table(t);
+    return MAPSQ_OK;
+}
+
+mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out) {
+    zero_table(out);
+    if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
+    const Store& S = ctx->store;
+    const int32_t term[3] = {pat->s, pat->p, pat->o};
+    // variables in first-appearance order and their first position
+    std::vector<int32_t> vars;
+    std::vector<int> first_pos;
+    int rep_a[3], rep_b[3], nrep = 0;
+    for (int pos = 0; pos < 3; pos++) {
+        if (term[pos] < 0) {
+            int32_t v = -term[pos] - 1;
+            auto it = std::find(vars.begin(), vars.end(), v);
+            if (it == vars.end()) {
+                vars.push_back(v);
+                first_pos.push_back(pos);
+            } else {
+                rep_a[nrep] = first_pos[it - vars.begin()];
+                rep_b[nrep] = pos;
+                nrep++;
+            }
+        } else if (term[pos] == INT32_MAX) {
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "constant outside [0, 2^31 - 1)");
+        }
+    }
+    if (vars.empty()) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "a triple pattern without variables");
+    // output column order: key first, then the others
+    std::vector<int> order;  // index into vars
+    if (key_var >= 0) {
+        auto it = std::find(vars.begin(), vars.end(), key_var);
+        if (it == vars.end()) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "key variable not in the pattern");
+        order.push_back(int(it - vars.begin()));
+    }
+    for (int i = 0; i < (int)vars.size(); i++)
+        if (std::find(order.begin(), order.end(), i) == order.end()) order.push_back(i);
+    const int ncols = (int)vars.size();
+    out->ncols = ncols;
+    out->key_max = S.max_id;
+    for (int c = 0; c < ncols; c++) out->var[c] = vars[order[c]];
+
+    // the three source columns and the row range to scan
+    const int32_t* col[3] = {S.s, S.p, S.o};
+    int64_t lo = 0, hi = S.n;
+    bool s_const = term[0] >= 0, p_const = term[1] >= 0, o_const = term[2] >= 0;
+    int nterm = 0;
+    int32_t ta[6], tb[6], tc[6];
+    if (p_const) {
+        int pi = find_pred(S, term[1]);
+        if (pi < 0) {
+            out->nrows = 0;
+            return MAPSQ_OK;
+        }
+        lo = S.pred_off[pi];
+        hi = S.pred_off[pi + 1];
+        LocateQuery q{};
+        q.lo = lo;
+        q.hi = hi;
+        if (s_const) {  // PSO: (p, s[, o])
+            col[0] = S.pso_s;
+            col[2] = S.pso_o;
+            q.col1 = S.pso_s;
+            q.v1 = term[0];
+            if (o_const) {
+                q.col2 = S.pso_o;
+                q.v2 = term[2];
+            }
+        } else if (o_const) {  // POS: (p, o)
+            col[0] = S.pos_s;
+            col[2] = S.pos_o;
+            q.col1 = S.pos_o;
+            q.v1 = term[2];
+        } else {
+            col[0] = S.pso_s;
+            col[2] = S.pso_o;
+        }
+        col[1] = nullptr;
+        if (q.col1) {
+            LocateQuery* qd = reinterpret_cast<LocateQuery*>(ctx->small + SMALL_SCALARS + 16);
+            int64_t* od = reinterpret_cast<int64_t*>(ctx->small + SMALL_SCALARS + 48);
+            std::memcpy(ctx->pinned, &q, sizeof(q));
+            HIPCHK(hipMemcpyAsync(qd, ctx->pinned, sizeof(q), hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(launch_locate(qd, 1, od, ctx->stream));
+            int64_t r[2];
+            mapsq_status st = readback(ctx, od, 16, r);
+            if (st) return st;
+            lo = r[0];
+            hi = r[1];
+        }
+    } else {
+        // variable predicate: full scan of the raw columns, constants tested
+        for (int pos = 0; pos < 3; pos++)
+            if (term[pos] >= 0) {
+                ta[nterm] = pos;
+                tb[nterm] = -1;
+                tc[nterm] = term[pos];
+                nterm++;
+            }
+    }
+    for (int r = 0; r < nrep; r++) {
+        ta[nterm] = rep_a[r];
+        tb[nterm] = rep_b[r];
+        tc[nterm] = 0;
+        nterm++;
+    }
+    const int64_t rows = hi - lo;
+    if (nterm == 0) {
+        // a view of the store
+        out->owned = 0;
+        out->nrows = rows;
+        for (int c = 0; c < ncols; c++) out->col[c] = const_cast<int32_t*>(col[first_pos[order[c]]]) + lo;
+        return MAPSQ_OK;
+    }
+    // scan + compaction into an owned table (sized for the whole range, then shrunk)
+    mapsq_table t{};
+    if (alloc_table(ctx, rows, ncols, &t)) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the map output");
+    CompactArgs a{};
+    a.nin = 3;
+    for (int pos = 0; pos < 3; pos++) a.in[pos] = col[pos] ? col[pos] + lo : nullptr;
+    a.n = (uint64_t)rows;
+    a.nterm = nterm;
+    for (int i = 0; i < nterm; i++) {
+        a.term_a[i] = ta[i];
+        a.term_b[i] = tb[i];
+        a.term_c[i] = tc[i];
+    }
+    a.nout = ncols;
+    for (int c = 0; c < ncols; c++) {
+        a.out_src[c] = first_pos[order[c]];
+        a.out[c] = t.col[c];
+    }
+    a.count = scalar64(ctx, SC_COUNT);
+    if (!ctx->ensure_status(size_t(rows / 4096 + 2))) {
+        free_table(ctx, &t);
+        return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for status words");
+    }
+    int ph = ctx->prof_begin(0);
+    hipError_t e = launch_fill_u32(ctx->small + SMALL_CTR, 32, 0u, ctx->stream);
+    if (e == hipSuccess) e = launch_fill_u32(scalar32(ctx, SC_COUNT), 2, 0u, ctx->stream);
+    if (e == hipSuccess) e = launch_compact(a, ctx->status, counter(ctx, CT_COMPACT), ctx->next_epoch(), ctx->stream);
+    {
+        int ncol_read = 0;
+        for (int pos = 0; pos < 3; pos++) ncol_read += a.in[pos] ? 1 : 0;
+        ctx->prof_end(ph, 4.0 * ncol_read * (double)rows);
+    }
+    if (e != hipSuccess) {
+        free_table(ctx, &t);
+        return ctx->fail(MAPSQ_ERR_HIP, std::string("map scan: ") + hipGetErrorString(e));
+    }
+    uint64_t kept = 0;
+    mapsq_status st = readback(ctx, scalar64(ctx, SC_COUNT), 8, &kept);
+    if (st) {
+        free_table(ctx, &t);
+        return st;
+    }
+    if (ph >= 0) ctx->pending[ph].bytes += 4.0 * ncols * (double)kept;
+    // columns were laid out for `rows`; keep the layout, only the row count changes
+    out->owned = 1;
+    out->block = t.block;
+    out->nrows = (int64_t)kept;
+    for (int c = 0; c < ncols; c++) out->col[c] = t.col[c];
+    return MAPSQ_OK;
+}
+
+// ------------------------------------------------------------------- join ---
+
+static int col_of(const mapsq_table* t, int32_t v) {
+    for (int c = 0; c < t->ncols; c++)
+        if (t->var[c] == v) return c;
+    return -1;
+}
+
+static mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name) {
+    if (!t) return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + " is null");
+    if (t->ncols < 1 || t->ncols > MAPSQ_MAX_COLS)
+        return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": ncols must be in [1, 16]");
+    if (t->nrows < 0 || t->nrows >= (int64_t(1) << 31))
+        return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": nrows must be in [0, 2^31)");
+    for (int c = 0; c < t->ncols; c++) {
+        if (t->nrows > 0 && !t->col[c]) return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": null column");
+        for (int d = 0; d < c; d++)
+            if (t->var[d] == t->var[c])
+                return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": a variable appears twice");
+    }
+    return MAPSQ_OK;
+}
+
+mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, int32_t key_var, mapsq_table* out) {
+    zero_table(out);
+    mapsq_status st;
+    if ((st = check_table(ctx, L, "left")) || (st = check_table(ctx, R, "right"))) return st;
+    const int lk = col_of(L, key_var), rk = col_of(R, key_var);
+    if (lk < 0 || rk < 0) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "both tables must bind the key variable");
+    // output columns: key, L's others, R's vars not in L; R's vars in L are filtered
+    std::vector<int> lv, rv, extra_l, extra_r;
+    for (int c = 0; c < L->ncols; c++)
+        if (c != lk) lv.push_back(c);
+    for (int c = 0; c < R->ncols; c++) {
+        if (c == rk) continue;
+        int cl = col_of(L, R->var[c]);
+        if (cl >= 0) {
+            extra_l.push_back(cl);
+            extra_r.push_back(c);
+        }
+        rv.push_back(c);  // materialised (filtered copies dropped afterwards)
+    }
+    const int nc_mat = 1 + (int)lv.size() + (int)rv.size();
+    const int nc_out = nc_mat - (int)extra_r.size();
+    if (nc_mat > MAPSQ_MAX_COLS) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 16 columns in the join");
+    const uint32_t nL = (uint32_t)L->nrows, nR = (uint32_t)R->nrows;
+    const uint32_t N = nL + nR;
+
+    std::vector<int32_t> mat_vars;
+    mat_vars.push_back(key_var);
+    for (int c : lv) mat_vars.push_back(L->var[c]);
+    for (int c : rv) mat_vars.push_back(R->var[c]);
+    auto set_meta = [&](mapsq_table* t) {
+        int k = 0;
+        for (int c = 0; c < nc_mat; c++) {
+            bool drop = c >= 1 + (int)lv.size() &&
+                        std::find(extra_r.begin(), extra_r.end(), rv[c - 1 - lv.size()]) != extra_r.end();
+            if (!drop) t->var[k++] = mat_vars[c];
+        }
+        t->ncols = nc_out;
+        t->key_max = (L->key_max >= 0 && R->key_max >= 0) ? std::max(L->key_max, R->key_max) : -1;
+    };
+    mapsq_join_stats js{};
+    js.left_rows = nL;
+    js.right_rows = nR;
+    ctx->last = js;
+    if (nL == 0 || nR == 0) {
+        set_meta(out);
+        out->owned = 1;
+        out->nrows = 0;
+        return MAPSQ_OK;
+    }
+
+    // key range: known bound, else a min/max pass
+    const int32_t* lkey = L->col[lk];
+    const int32_t* rkey = R->col[rk];
+    int32_t kmin = 0, kmax;
+    if (L->key_max >= 0 && R->key_max >= 0) {
+        kmax = std::max(L->key_max, R->key_max);
+    } else {
+        int32_t init[2] = {INT32_MAX, INT32_MIN};
+        int32_t* mm = reinterpret_cast<int32_t*>(scalar32(ctx, SC_MINMAX));
+        std::memcpy(ctx->pinned, init, 8);
+        HIPCHK(hipMemcpyAsync(mm, ctx->pinned, 8, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(launch_minmax(lkey, nL, rkey, nR, mm, ctx->stream));
+        int32_t r[2];
+        if ((st = readback(ctx, mm, 8, r))) return st;
+        kmin = r[0];
+        kmax = r[1];
+    }
+    const int key_bits = bitlen((uint64_t)((int64_t)kmax - (int64_t)kmin));
+    int rb, kpt;
+    pick_tuning(ctx, key_bits, rb, kpt);
+
+    // scratch: sort buffers (16 N) and segment offsets (8 N); the spare sort
+    // buffers later hold the segment starts and splits
+    const size_t nb4 = align_up(size_t(N) * 4, ARENA_ALIGN);
+    Block scratch = alloc_block(ctx, nb4 * 4 + nb4 * 2);
+    if (!scratch.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for join scratch");
+    char* sb = ctx->arena.ptr(scratch.off);
+    SortBufs b{{reinterpret_cast<uint32_t*>(sb), reinterpret_cast<uint32_t*>(sb + nb4)},
+               {reinterpret_cast<uint32_t*>(sb + 2 * nb4), reinterpret_cast<uint32_t*>(sb + 3 * nb4)}};
+    uint64_t* seg_off = reinterpret_cast<uint64_t*>(sb + 4 * nb4);
+
+    // Map + Sort: first pass reads the LEFT then the RIGHT key column
+    SortSrc src{lkey, nL, rkey, nR, kmin};
+    int res, passes;
+    int ph = ctx->prof_begin(1);
+    if ((st = radix_sort(ctx, &src, N, key_bits, rb, kpt, b, &res, &passes))) return st;
+    // histogram reads 4N; the first pass reads 4N keys, later passes 8N; every pass writes 8N
+    ctx->prof_end(ph, 16.0 * N * passes);
+    const uint32_t* skeys = b.k[res];
+    const uint32_t* svals = b.v[res];
+    uint32_t* seg_start = b.k[1 - res];
+    uint32_t* seg_split = b.v[1 - res];
+    // ReduceDuplicate: segments, counts, offsets
+    if (!ctx->ensure_status(size_t(N) / 2048 + 2)) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
+    ph = ctx->prof_begin(2);
+    HIPCHK(launch_seg_heads(skeys, N, seg_start, scalar32(ctx, SC_NSEG), ctx->status, counter(ctx, CT_HEADS),
+                            ctx->next_epoch(), ctx->stream));
+    HIPCHK(launch_seg_count(svals, N, nL, seg_start, scalar32(ctx, SC_NSEG), N, seg_split, seg_off,
+                            scalar64(ctx, SC_TOTAL), ctx->status, counter(ctx, CT_COUNT), ctx->next_epoch(),
+                            ctx->stream));
+    uint32_t sc[4];
+    {
+        // bytes are filled in once the segment count is known (below)
+        ctx->prof_end(ph, 0.0);
+    }
+    if ((st = readback(ctx, scalar32(ctx, SC_NSEG), 16, sc))) return st;
+    const uint32_t nseg = sc[0];
+    // heads: read 4N keys, write 4S starts; count: read 8S starts, 4S splits-worth of
+    // payload probes, write 4S splits and 8S offsets
+    if (ph >= 0) ctx->pending[ph].bytes = 4.0 * N + 24.0 * nseg;
+    uint64_t total;
+    std::memcpy(&total, &sc[2], 8);
+    js.segments = nseg;
+    js.out_rows = (int64_t)total;
+    js.radix_bits = rb;
+    js.passes = passes;
+    js.key_bits = key_bits;
+    ctx->last = js;
+    if (total >= SAT40_HOST) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds 2^40 rows");
+    set_meta(out);
+    if (total == 0) {
+        out->owned = 1;
+        out->nrows = 0;
+        return MAPSQ_OK;
+    }
+    mapsq_table m{};
+    {
+        const size_t colb = align_up(size_t(total) * 4, ARENA_ALIGN);
+        if (ctx->arena.largest() < colb * nc_mat)
+            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result (" + std::to_string(total) +
+                                                      " rows) exceeds the arena's free space");
+        if (alloc_table(ctx, (int64_t)total, nc_mat, &m))
+            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds the arena's free space");
+    }
+    MatArgs a{};
+    a.keys = skeys;
+    a.vals = svals;
+    a.seg_start = seg_start;
+    a.seg_split = seg_split;
+    a.seg_off = seg_off;
+    a.nseg = scalar32(ctx, SC_NSEG);
+    a.n = N;
+    a.n_left = nL;
+    a.key_base = kmin;
+    a.nl = (int)lv.size();
+    a.nr = (int)rv.size();
+    for (int i = 0; i < a.nl; i++) a.lcol[i] = L->col[lv[i]];
+    for (int i = 0; i < a.nr; i++) a.rcol[i] = R->col[rv[i]];
+    for (int c = 0; c < nc_mat; c++) a.out[c] = m.col[c];
+    a.row_begin = 0;
+    a.row_end = total;
+    ph = ctx->prof_begin(3);
+    hipError_t e = launch_materialize(a, ctx->stream);
+    // writes 4 B per output cell; reads every record's payload once, each
+    // segment's key and table entries, and each value cell of both sides
+    ctx->prof_end(ph, 4.0 * nc_mat * (double)total + 4.0 * N + 20.0 * nseg +
+                          4.0 * (a.nl * (double)nL + a.nr * (double)nR));
+    ctx->acc.joins += 1;
+    ctx->acc.rows_out += (int64_t)total;
+    if (e != hipSuccess) {
+        free_table(ctx, &m);
+        return ctx->fail(MAPSQ_ERR_HIP, std::string("materialize: ") + hipGetErrorString(e));
+    }
+    if (extra_r.empty()) {
+        out->owned = 1;
+        out->block = m.block;
+        out->nrows = (int64_t)total;
+        for (int c = 0; c < nc_mat; c++) out->col[c] = m.col[c];
+        return MAPSQ_OK;
+    }
+    // further shared variables: keep rows where both copies agree, drop R's copy
+    mapsq_table f{};
+    if (alloc_table(ctx, (int64_t)total, nc_out, &f)) {
+        free_table(ctx, &m);
+        return ctx->fail(MAPSQ_ERR_TOO_LARGE, "filtered join result exceeds the arena's free space");
+    }
+    CompactArgs c{};
+    c.nin = nc_mat;
+    for (int i = 0; i < nc_mat; i++) c.in[i] = m.col[i];
+    c.n = total;
+    c.nterm = 0;
+    for (size_t i = 0; i < extra_r.size(); i++) {
+        if (c.nterm >= 6) {
+            free_table(ctx, &m);
+            free_table(ctx, &f);
+            return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 6 further shared variables");
+        }
+        int li = 1 + int(std::find(lv.begin(), lv.end(), extra_l[i]) - lv.begin());
+        int ri = 1 + (int)lv.size() + int(std::find(rv.begin(), rv.end(), extra_r[i]) - rv.begin());
+        c.term_a[c.nterm] = li;
+        c.term_b[c.nterm] = ri;
+        c.nterm++;
+    }
+    c.nout = 0;
+    for (int i = 0; i < nc_mat; i++) {
+        bool drop = i >= 1 + (int)lv.size() &&
+                    std::find(extra_r.begin(), extra_r.end(), rv[i - 1 - lv.size()]) != extra_r.end();
+        if (!drop) {
+            c.out_src[c.nout] = i;
+            c.out[c.nout] = f.col[c.nout];
+            c.nout++;
+        }
+    }
+    c.count = scalar64(ctx, SC_COUNT);
+    uint64_t kept = 0;
+    e = hipSuccess;
+    if (!ctx->ensure_status(size_t(total / 4096 + 2))) e = hipErrorOutOfMemory;
+    ph = ctx->prof_begin(4);
+    if (e == hipSuccess) e = launch_fill_u32(counter(ctx, CT_COMPACT), 1, 0u, ctx->stream);
+    if (e == hipSuccess) e = launch_compact(c, ctx->status, counter(ctx, CT_COMPACT), ctx->next_epoch(), ctx->stream);
+    ctx->prof_end(ph, 4.0 * (double)c.nterm * 2 * total);
+    if (e == hipSuccess) st = readback(ctx, scalar64(ctx, SC_COUNT), 8, &kept);
+    if (ph >= 0) ctx->pending[ph].bytes += 4.0 * (double)c.nout * (double)kept;
+    free_table(ctx, &m);
+    if (e != hipSuccess || st) {
+        free_table(ctx, &f);
+        return e != hipSuccess ? ctx->fail(MAPSQ_ERR_HIP, "equality filter launch failed") : st;
+    }
+    out->owned = 1;
+    out->block = f.block;
+    out->nrows = (int64_t)kept;
+    for (int i = 0; i < nc_out; i++) out->col[i] = f.col[i];
+    return MAPSQ_OK;
+}
+
+}  // namespace mq

@@ -1,0 +1,168 @@
+// Host runtime of libmapsq: the context, the arena sub-allocator and the
+// internal entry points shared by the plain, batched and serving paths.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/mapsq.h"
+#include "kernels.h"
+
+namespace mq {
+
+constexpr size_t ARENA_ALIGN = 256;
+constexpr uint64_t SAT40_HOST = (1ull << 40) - 1ull;  // saturation cap of device row counts
+
+// First-fit sub-allocator over the caller's arena.  All users of a context
+// enqueue on one stream, so a block freed on the host can be handed out
+// again at once: later work on the stream runs after earlier work.
+class Arena {
+   public:
+    void init(char* base, size_t size);
+    // returns offset or SIZE_MAX
+    size_t alloc(size_t bytes);
+    void free(size_t off);
+    // shrink an allocated block to `bytes` (returns the tail to the free list)
+    void shrink(size_t off, size_t bytes);
+    char* ptr(size_t off) const { return base_ + off; }
+    size_t free_bytes() const;
+    size_t largest() const;
+    char* base() const { return base_; }
+    size_t size() const { return size_; }
+
+   private:
+    char* base_ = nullptr;
+    size_t size_ = 0;
+    std::map<size_t, size_t> free_;           // offset -> size
+    std::unordered_map<size_t, size_t> used_;  // offset -> size
+};
+
+struct Ctx;
+
+// A block of the arena freed when the guard goes out of scope (unless released).
+struct Block {
+    Ctx* ctx = nullptr;
+    size_t off = SIZE_MAX;
+    Block() = default;
+    Block(const Block&) = delete;
+    Block& operator=(const Block&) = delete;
+    Block(Block&& o) noexcept : ctx(o.ctx), off(o.off) { o.off = SIZE_MAX; }
+    Block& operator=(Block&& o) noexcept {
+        if (this != &o) {
+            reset();
+            ctx = o.ctx;
+            off = o.off;
+            o.off = SIZE_MAX;
+        }
+        return *this;
+    }
+    ~Block() { reset(); }
+    void reset();
+    bool ok() const { return off != SIZE_MAX; }
+    template <typename T>
+    T* as() const;
+    size_t release() {
+        size_t o = off;
+        off = SIZE_MAX;
+        return o;
+    }
+};
+
+struct Store {
+    bool loaded = false;
+    int64_t n = 0;
+    int32_t max_id = 0;
+    int32_t id_bits = 0;
+    int32_t *s = nullptr, *p = nullptr, *o = nullptr;            // raw SoA
+    int32_t *pso_s = nullptr, *pso_o = nullptr;                  // sorted by (p, s, o)
+    int32_t *pos_o = nullptr, *pos_s = nullptr;                  // sorted by (p, o, s)
+    std::vector<int32_t> preds;                                  // distinct predicates, ascending
+    std::vector<int64_t> pred_off;                               // preds.size() + 1 offsets
+    std::vector<size_t> blocks;
+    uint64_t bytes = 0;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Arena arena;
+    std::string err;
+    Store store;
+    // persistent look-back status words (epoch-tagged, never cleared between uses)
+    size_t status_off = SIZE_MAX;
+    uint64_t* status = nullptr;
+    size_t status_words = 0;
+    uint32_t epoch = 0;
+    // small per-call device area: counters, histograms and scalars
+    size_t small_off = SIZE_MAX;
+    uint32_t* small = nullptr;
+    // pinned host staging for read-backs
+    void* pinned = nullptr;
+    int32_t tune_rb = 0, tune_kpt = 0;
+    mapsq_join_stats last{};
+    // profiling: pairs of events around phases, harvested after a sync
+    bool prof = false;
+    struct Interval {
+        hipEvent_t a, b;
+        int phase;
+        double bytes;
+    };
+    std::vector<Interval> pending;
+    std::vector<hipEvent_t> event_pool;
+    mapsq_profile acc{};
+    // returns an interval handle (-1 when profiling is off)
+    int prof_begin(int phase);
+    void prof_end(int h, double bytes);
+    void prof_harvest();  // caller has synchronised the stream
+    void prof_release();
+
+    mapsq_status fail(mapsq_status code, const std::string& msg) {
+        err = msg;
+        return code;
+    }
+    // make sure the status array holds `words` words; returns false on CAPACITY
+    bool ensure_status(size_t words);
+    uint32_t next_epoch();
+};
+
+// layout of the small device area (u32 words)
+constexpr size_t SMALL_HIST = 0;                  // up to 8 passes x 2048 buckets
+constexpr size_t SMALL_HIST_WORDS = 8 * 2048;
+constexpr size_t SMALL_CTR = SMALL_HIST + SMALL_HIST_WORDS;  // 32 tile counters
+constexpr size_t SMALL_SCALARS = SMALL_CTR + 32;             // 64 words of device scalars
+constexpr size_t SMALL_WORDS = SMALL_SCALARS + 64;
+
+template <typename T>
+T* Block::as() const {
+    return reinterpret_cast<T*>(ctx->arena.ptr(off));
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int bitlen(uint64_t v) {
+    int b = 0;
+    while (v) {
+        b++;
+        v >>= 1;
+    }
+    return b;
+}
+
+// internal entry points (return mapsq_status, set ctx->err)
+mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, int32_t key_var, mapsq_table* out);
+mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out);
+mapsq_status free_table(Ctx* ctx, mapsq_table* t);
+mapsq_status load_triples(Ctx* ctx, const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
+                          uint32_t flags);
+mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
+                   mapsq_table* out);
+Block alloc_block(Ctx* ctx, size_t bytes);
+
+}  // namespace mq
+
+struct mapsq_ctx {
+    mq::Ctx impl;
+};

@@ -1,0 +1,95 @@
+"""A small session object over the C ABI: it owns the torch arena tensor and
+uses torch's current HIP stream, and turns result columns into tensors.
+
+Every computation is a libmapsq.so call; this module only marshals.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class MapSQ:
+    def __init__(self, arena_bytes: int = 8 << 30, device: int = 0, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("MapSQ needs a GPU (gfx950); there is no CPU path")
+        self.device = device
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.ctx = B.mapsq_create(device, self.arena.data_ptr(), self.arena.numel(), self.stream.cuda_stream)
+        self._keep = []
+
+    def close(self):
+        if self.ctx is not None:
+            B.mapsq_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- store ------------------------------------------------------------
+    def load(self, s, p, o, dedup: bool = False):
+        flags = B.MAPSQ_LOAD_DEDUP if dedup else 0
+        if isinstance(s, torch.Tensor) and s.is_cuda:
+            cols = [x.contiguous().to(torch.int32) for x in (s, p, o)]
+            flags |= B.MAPSQ_LOAD_DEVICE_PTRS
+            ptrs = [c.data_ptr() for c in cols]
+            n = cols[0].numel()
+        else:
+            cols = [np.ascontiguousarray(x, dtype=np.int32) for x in (s, p, o)]
+            ptrs = [c.ctypes.data for c in cols]
+            n = cols[0].size
+        B.mapsq_load_triples(self.ctx, *ptrs, n, flags)
+        return B.mapsq_store_info(self.ctx)
+
+    # ---- the path ---------------------------------------------------------
+    def map(self, pattern, key_var: int = -1) -> B.mapsq_table:
+        return B.mapsq_map_pattern(self.ctx, pattern, key_var)
+
+    def join(self, left: B.mapsq_table, right: B.mapsq_table, key_var: int) -> B.mapsq_table:
+        return B.mapsq_join(self.ctx, left, right, key_var)
+
+    def query(self, patterns, select=None) -> B.mapsq_table:
+        return B.mapsq_query(self.ctx, patterns, select)
+
+    def free(self, t: B.mapsq_table):
+        B.mapsq_table_free(self.ctx, t)
+
+    def stats(self) -> B.mapsq_join_stats:
+        return B.mapsq_last_join_stats(self.ctx)
+
+    def set_tuning(self, radix_bits: int = 0, keys_per_thread: int = 0):
+        B.mapsq_set_tuning(self.ctx, radix_bits, keys_per_thread)
+
+    # ---- tables <-> tensors -------------------------------------------------
+    def table(self, vars, tensors, key_max: int = -1) -> B.mapsq_table:
+        """Wrap caller-owned int32 device tensors (kept alive by this session)."""
+        ts = [t.contiguous() for t in tensors]
+        assert all(t.dtype == torch.int32 and t.is_cuda for t in ts)
+        n = ts[0].numel() if ts else 0
+        self._keep.extend(ts)
+        return B.make_table(vars, [t.data_ptr() for t in ts], n, key_max)
+
+    def column(self, t: B.mapsq_table, c: int) -> torch.Tensor:
+        """Column c of a table as an int32 tensor view (no copy)."""
+        n = int(t.nrows)
+        if n == 0:
+            return torch.empty(0, dtype=torch.int32, device=self.arena.device)
+        ptr = int(t.col[c])
+        off = ptr - self.arena.data_ptr()
+        if 0 <= off and off + 4 * n <= self.arena.numel():
+            return self.arena[off:off + 4 * n].view(torch.int32)
+        for k in self._keep:
+            if k.data_ptr() <= ptr and ptr + 4 * n <= k.data_ptr() + 4 * k.numel():
+                i = (ptr - k.data_ptr()) // 4
+                return k[i:i + n]
+        raise ValueError("column is outside the arena and the wrapped tensors")
+
+    def to_numpy(self, t: B.mapsq_table):
+        torch.cuda.current_stream(self.device).synchronize()
+        return [self.column(t, c).cpu().numpy() for c in range(t.ncols)]

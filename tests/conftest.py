@@ -28,3 +28,18 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def sess():
+    """One library context per test session (GPU tests only)."""
+    from paper_1702_03484_amd.engine import MapSQ
+
+    s = MapSQ(arena_bytes=48 << 30)
+    yield s
+    s.close()
+
+
+def announce(msg: str):
+    """Name the GPU case before it runs (flushed, so a crash still shows it)."""
+    print(f"\n[gpu-case] {msg}", flush=True)

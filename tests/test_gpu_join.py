@@ -1,0 +1,312 @@
+"""GPU parity of the whole join path (map, sort, count/scan, materialise)
+against the oracle, through the C ABI.  Integer work: results must be the
+same bag of int32 rows exactly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.core import Table
+from paper_1702_03484_amd import binding as B
+from synth import random_store, random_table, store_cfg1, var
+from tests.conftest import announce
+from tests.fixtures import load_table1
+from tests.gpu_util import assert_same_bag, host_table
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
+def keyset(seed, card, lo=0, hi=(1 << 31) - 1):
+    r = np.random.default_rng(seed)
+    return np.unique(r.integers(lo, hi, size=card * 3))[:card]
+
+
+# ------------------------------------------------------------ worked example
+
+def test_table1_on_gpu(sess):
+    announce("table1 map/join/query")
+    f = load_table1()
+    sess.load(f["s"], f["p"], f["o"])
+    t1 = sess.map(f["P1"], key_var=1)
+    t2 = sess.map(f["P2"], key_var=1)
+    assert t1.vars == [1, 0] and t2.vars == [1]
+    assert sorted(map(tuple, np.stack(sess.to_numpy(t1), 1).tolist())) == sorted(f["Tp1"][0])
+    assert sorted(map(tuple, np.stack(sess.to_numpy(t2), 1).tolist())) == sorted(f["Tp2"][0])
+    rs = sess.join(t1, t2, 1)
+    assert rs.vars == [1, 0]
+    assert sorted(map(tuple, np.stack(sess.to_numpy(rs), 1).tolist())) == sorted(f["RS"][0])
+    st = sess.stats()
+    assert st.out_rows == 2 and st.left_rows == 3 and st.right_rows == 2
+    sess.free(rs)
+    q = sess.query([f["P1"], f["P2"]], select=[0])
+    assert sorted(map(tuple, np.stack(sess.to_numpy(q), 1).tolist())) == sorted(f["SELECT"][0])
+    sess.free(q)
+
+
+# ---------------------------------------------------------------- plain joins
+
+JOIN_CASES = [
+    # (nL, nR, key cardinality, left value cols, right value cols, key_max known)
+    (1, 1, 1, 1, 0, True),
+    (3, 5, 2, 0, 0, True),
+    (4096, 4096, 300, 1, 1, True),            # exactly one sort tile per side
+    (65536, 65536 - 1, 4000, 2, 1, False),    # tile multiples and a ragged tail
+    (100_003, 77_777, 5000, 2, 1, False),
+    (300_001, 17, 50, 1, 0, True),            # skewed: few keys, big left side
+    (3001, 2999, 1, 1, 1, True),              # a single key: |L| x |R| rows
+    (250_000, 250_000, 200_000, 1, 2, False), # mostly unique keys
+    (1_000_003, 1000, 900, 3, 3, False),      # many columns
+]
+
+
+@pytest.mark.parametrize("nl,nr,card,vl,vr,known", JOIN_CASES)
+def test_join_matches_oracle(sess, nl, nr, card, vl, vr, known):
+    announce(f"join nl={nl} nr={nr} card={card} vl={vl} vr={vr} known={known}")
+    keys = keyset(nl * 7 + nr, card)
+    lc = random_table(nl, nl, card, vl, key_ids=keys)
+    rc = random_table(nr + 1, nr, card, vr, key_ids=keys)
+    lvars = [0] + list(range(10, 10 + vl))
+    rvars = [0] + list(range(20, 20 + vr))
+    kmax = int(keys.max()) if known else -1
+    L = sess.table(lvars, [dev(c) for c in lc], key_max=kmax)
+    R = sess.table(rvars, [dev(c) for c in rc], key_max=kmax)
+    out = sess.join(L, R, 0)
+    exp = oracle.join(Table(lvars, lc), Table(rvars, rc), 0)
+    assert out.vars == exp.vars
+    assert_same_bag(host_table(sess, out), exp)
+    st = sess.stats()
+    assert st.out_rows == exp.n
+    sess.free(out)
+
+
+def test_join_high_ids_and_negative_base(sess):
+    announce("join ids near 2^31-2")
+    keys = (1 << 31) - 2 - np.arange(0, 700 * 13, 13)
+    lc = random_table(5, 20000, 700, 1, key_ids=keys)
+    rc = random_table(6, 9000, 700, 1, key_ids=keys)
+    L = sess.table([0, 1], [dev(c) for c in lc])
+    R = sess.table([0, 2], [dev(c) for c in rc])
+    out = sess.join(L, R, 0)
+    assert_same_bag(host_table(sess, out), oracle.join(Table([0, 1], lc), Table([0, 2], rc), 0))
+    sess.free(out)
+
+
+def test_join_further_shared_variable(sess):
+    announce("join with a second shared variable (equality filter)")
+    keys = keyset(3, 500)
+    lc = random_table(7, 30000, 500, 2, key_ids=keys, val_hi=5)
+    rc = random_table(8, 20000, 500, 2, key_ids=keys, val_hi=5)
+    L = sess.table([0, 1, 2], [dev(c) for c in lc])
+    R = sess.table([0, 3, 1], [dev(c) for c in rc])  # variable 1 on both sides
+    out = sess.join(L, R, 0)
+    exp = oracle.join(Table([0, 1, 2], lc), Table([0, 3, 1], rc), 0)
+    assert out.vars == exp.vars == [0, 1, 2, 3]
+    assert_same_bag(host_table(sess, out), exp)
+    sess.free(out)
+
+
+def test_join_empty_and_disjoint(sess):
+    announce("empty and disjoint joins")
+    a = sess.table([0, 1], [dev(np.arange(10)), dev(np.arange(10))])
+    e = sess.table([0, 2], [dev(np.zeros(0)), dev(np.zeros(0))])
+    d = sess.table([0, 2], [dev(np.arange(100, 110)), dev(np.arange(10))])
+    for r in (e, d):
+        out = sess.join(a, r, 0)
+        assert out.nrows == 0 and out.vars == [0, 1, 2]
+        sess.free(out)
+
+
+def test_join_order_is_deterministic_and_tuning_invariant(sess):
+    announce("determinism and radix digit width / tile invariance")
+    keys = keyset(11, 3000)
+    lc = random_table(12, 150_000, 3000, 1, key_ids=keys)
+    rc = random_table(13, 60_000, 3000, 1, key_ids=keys)
+    L = sess.table([0, 1], [dev(c) for c in lc])
+    R = sess.table([0, 2], [dev(c) for c in rc])
+    ref = sess.join(L, R, 0)
+    ref_cols = sess.to_numpy(ref)
+    # key, then LEFT rows in input order, then RIGHT rows in input order
+    k = ref_cols[0]
+    assert np.all(k[1:] >= k[:-1])
+    for rb in range(4, 12):
+        for kpt in (8, 16):
+            sess.set_tuning(rb, kpt)
+            out = sess.join(L, R, 0)
+            cols = sess.to_numpy(out)
+            assert all(np.array_equal(a, b) for a, b in zip(cols, ref_cols)), (rb, kpt)
+            assert sess.stats().radix_bits == rb
+            sess.free(out)
+    sess.set_tuning(0, 0)
+    sess.free(ref)
+
+
+def test_join_too_large_is_refused_without_leak(sess):
+    announce("TOO_LARGE: over 2^40 rows and over the arena")
+    free0 = None
+    for n in (1_100_000, 1_100_000, 400_000):  # 1.2e12 rows > 2^40 ; 1.6e11 rows > arena
+        L = sess.table([0, 1], [dev(np.zeros(n)), dev(np.arange(n))], key_max=0)
+        R = sess.table([0, 2], [dev(np.zeros(n)), dev(np.arange(n))], key_max=0)
+        with pytest.raises(B.MapSQError) as ei:
+            sess.join(L, R, 0)
+        assert ei.value.code == B.MAPSQ_ERR_TOO_LARGE
+        assert sess.stats().out_rows in (n * n, (1 << 40) - 1)
+        if free0 is None:  # after the first call (the status words may grow once)
+            free0 = B.mapsq_arena_free_bytes(sess.ctx)[0]
+    assert B.mapsq_arena_free_bytes(sess.ctx)[0] == free0
+
+
+def test_invalid_arguments(sess):
+    announce("argument errors")
+    a = sess.table([0, 1], [dev(np.arange(10)), dev(np.arange(10))])
+    b = sess.table([2, 3], [dev(np.arange(10)), dev(np.arange(10))])
+    with pytest.raises(B.MapSQError) as ei:
+        sess.join(a, b, 0)
+    assert ei.value.code == B.MAPSQ_ERR_INVALID_ARG
+    with pytest.raises(B.MapSQError) as ei:
+        sess.map((5, 6, 7))
+    assert ei.value.code in (B.MAPSQ_ERR_UNSUPPORTED, B.MAPSQ_ERR_STATE)
+    with pytest.raises(B.MapSQError) as ei:
+        B.mapsq_set_tuning(sess.ctx, 3, 0)
+    assert ei.value.code == B.MAPSQ_ERR_INVALID_ARG
+
+
+# ----------------------------------------------------------------------- map
+
+def _store_with_repeats(seed, n, ne, npred):
+    w = random_store(seed, n, ne, npred)
+    w.o[: n // 10] = w.s[: n // 10]
+    w.s[n // 10: n // 8] = w.p[n // 10: n // 8]
+    w.o[n // 10: n // 8] = w.p[n // 10: n // 8]
+    return w
+
+
+MAP_SHAPES = [
+    (var(0), "P", var(1)), (var(0), "P", "O"), ("S", "P", var(1)), (var(0), var(1), var(2)),
+    (var(0), var(1), "O"), ("S", var(0), var(1)), (var(0), "P", var(0)), (var(0), var(0), var(0)),
+    (var(0), var(1), var(0)), ("S", var(0), "O"), (var(0), "Q", var(1)),
+]
+
+
+def test_map_matches_oracle(sess):
+    w = _store_with_repeats(21, 300_007, 3000, 6)
+    sess.load(w.s, w.p, w.o)
+    info = B.mapsq_store_info(sess.ctx)
+    assert info.n_triples == w.n and info.n_predicates == 6 and info.max_id == int(max(w.s.max(), w.p.max(), w.o.max()))
+    r = np.random.default_rng(0)
+    for shape in MAP_SHAPES:
+        for _ in range(3):
+            t = int(r.integers(0, w.n))
+            const = {"S": int(w.s[t]), "P": int(w.p[t]), "O": int(w.o[t]), "Q": 10**9}
+            pat = tuple(const[x] if isinstance(x, str) else x for x in shape)
+            announce(f"map {pat}")
+            exp = oracle.match_pattern(w.s, w.p, w.o, pat)
+            for key in [-1] + exp.vars:
+                got = sess.map(pat, key_var=key)
+                if key >= 0:
+                    assert got.vars[0] == key
+                assert_same_bag(host_table(sess, got), exp)
+                sess.free(got)
+
+
+def test_map_dedup_load(sess):
+    announce("load with MAPSQ_LOAD_DEDUP")
+    w = random_store(31, 50_000, 50, 3)
+    sess.load(w.s, w.p, w.o, dedup=True)
+    ds, dp, do = oracle.core.dedup_triples(w.s, w.p, w.o)
+    assert B.mapsq_store_info(sess.ctx).n_triples == ds.size
+    pat = (var(0), var(1), var(2))
+    got = sess.map(pat)
+    assert_same_bag(host_table(sess, got), oracle.match_pattern(ds, dp, do, pat))
+    pat2 = (var(0), int(w.p[0]), var(1))
+    got = sess.map(pat2)
+    assert_same_bag(host_table(sess, got), oracle.match_pattern(ds, dp, do, pat2))
+
+
+# --------------------------------------------------------------------- query
+
+def test_cfg1_query(sess):
+    w = store_cfg1()
+    announce(f"cfg1 query {w.patterns}")
+    sess.load(w.s, w.p, w.o)
+    got = sess.query(w.patterns)
+    exp = oracle.query(w.s, w.p, w.o, w.patterns)
+    assert exp.n >= 1
+    assert_same_bag(host_table(sess, got), exp)
+    sess.free(got)
+
+
+def _random_queries(w, seed, count):
+    """Connected BGPs of 1-4 patterns: every pattern after the first reuses a
+    bound variable; constants, variable predicates and repeated variables
+    appear at random."""
+    r = np.random.default_rng(seed)
+    preds = np.unique(w.p)
+    out = []
+    for _ in range(count):
+        m = int(r.integers(1, 5))
+        pats, used, nxt = [], [], 0
+        for i in range(m):
+            t = int(r.integers(0, w.n))
+            if i == 0:
+                a = nxt
+                nxt += 1
+            else:
+                a = int(r.choice(used))
+            used.append(a) if a not in used else None
+            u = r.random()
+            if u < 0.3:
+                b = int(w.o[t])                # constant
+            elif u < 0.4:
+                b = var(a)                     # repeated variable
+            elif u < 0.6 and len(used) > 1:
+                b = var(int(r.choice(used)))
+            else:
+                b = var(nxt)
+                used.append(nxt)
+                nxt += 1
+            p = int(r.choice(preds)) if r.random() < 0.85 else var(10 + i)
+            s_, o_ = (var(a), b) if r.random() < 0.5 else (b, var(a))
+            if s_ >= 0 and o_ >= 0 and p >= 0:
+                o_ = var(a)
+            pats.append((s_, p, o_))
+        out.append(pats)
+    return out
+
+
+def test_random_queries_match_oracle(sess):
+    w = random_store(41, 20_000, 400, 5)
+    sess.load(w.s, w.p, w.o)
+    done = 0
+    for pats in _random_queries(w, 5, 60):
+        exp_n = None
+        try:
+            exp = oracle.query(w.s, w.p, w.o, pats)
+            exp_n = exp.n
+        except MemoryError:
+            continue
+        if exp_n > 5_000_000:
+            continue
+        announce(f"query {pats}")
+        got = sess.query(pats)
+        assert_same_bag(host_table(sess, got), exp)
+        sess.free(got)
+        done += 1
+    assert done >= 40
+
+
+def test_query_select_projection(sess):
+    w = random_store(42, 5000, 80, 3)
+    sess.load(w.s, w.p, w.o)
+    e = w.n_entities
+    pats = [(var(0), e, var(1)), (var(1), e + 1, var(2)), (var(2), e + 2, var(3))]
+    announce(f"projection {pats}")
+    for sel in ([3, 0], [1], [2, 1, 0, 3]):
+        got = sess.query(pats, select=sel)
+        exp = oracle.query(w.s, w.p, w.o, pats, select=sel)
+        assert got.vars == sel
+        assert_same_bag(host_table(sess, got), exp, var_order=sel)
+        sess.free(got)
