@@ -166,6 +166,27 @@ mapsq_status mapsq_join(mapsq_ctx* ctx, const mapsq_table* left, const mapsq_tab
 mapsq_status mapsq_query(mapsq_ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* select_vars,
                          int32_t nselect, mapsq_table* out);
 
+/* One join of a batch: left JOIN right on key_var (see mapsq_join). */
+typedef struct {
+    const mapsq_table* left;
+    const mapsq_table* right;
+    int32_t key_var;
+    int32_t reserved;
+} mapsq_join_desc;
+
+/* Batched joins (the batched form of Algorithm 1): the n independent joins
+ * run together as one captured hipGraph launch (radix passes, counting,
+ * device-side placement of every result in one output region and the
+ * materialisation), then the stream is synchronised once and outs[i] is
+ * filled.  Each join's result equals what mapsq_join returns for it, row for
+ * row.  Joins the batched kernels do not cover (more than 8 output columns
+ * or a further shared variable) and results that do not fit the output
+ * region run through the plain path afterwards.  The result tables of one
+ * batch share an arena block that is released when the last of them is
+ * freed.  On error every outs[i] is zeroed and nothing stays allocated.
+ * The caller's tables must stay valid until the call returns. */
+mapsq_status mapsq_join_batch(mapsq_ctx* ctx, const mapsq_join_desc* joins, int32_t n, mapsq_table* outs);
+
 /* Release an owned table (views are left alone); the struct is zeroed. */
 mapsq_status mapsq_table_free(mapsq_ctx* ctx, mapsq_table* t);
 
@@ -182,9 +203,10 @@ mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_p
  * (histogram and radix passes), 2 count (segment heads, LEFT/RIGHT split,
  * count and offset scan), 3 materialize, 4 equality filter, 5 index build.
  * Times come from hipEvents recorded on the context's stream around each
- * phase's launches.  Algorithmic bytes are what each phase must move given
+ * phase's launches; 6 is a whole batched launch (mapsq_join_batch).
+ * Algorithmic bytes are what each phase must move given
  * the exact sizes (formulas in the design notes of the repository). */
-#define MAPSQ_NPHASES 6
+#define MAPSQ_NPHASES 7
 typedef struct {
     double ms[MAPSQ_NPHASES];
     double bytes[MAPSQ_NPHASES];

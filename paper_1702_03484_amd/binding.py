@@ -73,8 +73,8 @@ class mapsq_join_stats(ctypes.Structure):
     ]
 
 
-NPHASES = 6
-PHASES = ["map", "sort", "count", "materialize", "filter", "index"]
+NPHASES = 7
+PHASES = ["map", "sort", "count", "materialize", "filter", "index", "batch"]
 
 
 class mapsq_profile(ctypes.Structure):
@@ -84,6 +84,15 @@ class mapsq_profile(ctypes.Structure):
         ("launches", ctypes.c_int64 * NPHASES),
         ("joins", ctypes.c_int64),
         ("rows_out", ctypes.c_int64),
+    ]
+
+
+class mapsq_join_desc(ctypes.Structure):
+    _fields_ = [
+        ("left", ctypes.POINTER(mapsq_table)),
+        ("right", ctypes.POINTER(mapsq_table)),
+        ("key_var", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -110,6 +119,8 @@ _SIGS = [
     ("mapsq_query", ctypes.c_int32,
      [_P, ctypes.POINTER(mapsq_pattern), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
       ctypes.POINTER(mapsq_table)]),
+    ("mapsq_join_batch", ctypes.c_int32,
+     [_P, ctypes.POINTER(mapsq_join_desc), ctypes.c_int32, ctypes.POINTER(mapsq_table)]),
     ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
     ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
     ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
@@ -188,6 +199,19 @@ def mapsq_query(ctx, patterns, select=None) -> mapsq_table:
     out = mapsq_table()
     _check(ctx, lib().mapsq_query(ctx, arr, len(patterns), sarr, len(sel), ctypes.byref(out)))
     return out
+
+
+def mapsq_join_batch(ctx, joins) -> list:
+    """joins: list of (left table, right table, key variable)."""
+    n = len(joins)
+    descs = (mapsq_join_desc * max(1, n))()
+    for i, (L, R, k) in enumerate(joins):
+        descs[i].left = ctypes.pointer(L)
+        descs[i].right = ctypes.pointer(R)
+        descs[i].key_var = k
+    outs = (mapsq_table * max(1, n))()
+    _check(ctx, lib().mapsq_join_batch(ctx, descs, n, outs))
+    return [outs[i] for i in range(n)]
 
 
 def mapsq_table_free(ctx, t: mapsq_table):

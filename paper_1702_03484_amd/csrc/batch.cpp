@@ -1,0 +1,300 @@
+// Host side of mapsq_join_batch: lays the joins' records out in whole record
+// tiles, uploads one device header and the per-join descriptors, replays a
+// cached hipGraph of the batched kernels (captured on first use per digit
+// width, tile size and pass count), synchronises once, and turns the
+// device-placed results into tables.  Joins outside the batched kernels'
+// scope, and results that did not fit the output region, go through the
+// plain path afterwards.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace mq {
+
+#define HIPCHK_B(x)                                                                                   \
+    do {                                                                                              \
+        hipError_t e_ = (x);                                                                          \
+        if (e_ != hipSuccess) return ctx->fail(MAPSQ_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void Ctx::release_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+}
+
+static bool ensure_stage(Ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->stage_bytes) return true;
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    ctx->stage = nullptr;
+    ctx->stage_bytes = 0;
+    size_t want = std::max(bytes, size_t(1) << 20);
+    if (hipHostMalloc(&ctx->stage, want, hipHostMallocDefault) != hipSuccess) return false;
+    ctx->stage_bytes = want;
+    return true;
+}
+
+namespace {
+struct Plan {
+    int idx;             // position in the caller's array
+    bool batched;        // runs in the batched kernels
+    bool empty;          // one side has no rows
+    int lk, rk;          // key columns
+    std::vector<int> lv, rv;  // value columns
+};
+}  // namespace
+
+mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_table* outs) {
+    if (n < 0 || (n > 0 && (!d || !outs))) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "bad batch arguments");
+    for (int i = 0; i < n; i++) std::memset(&outs[i], 0, sizeof(mapsq_table));
+    if (n == 0) return MAPSQ_OK;
+    std::vector<Plan> plan(n);
+    int32_t kmax = 0;
+    bool known = true;
+    for (int i = 0; i < n; i++) {
+        mapsq_status st;
+        if ((st = check_table(ctx, d[i].left, "left")) || (st = check_table(ctx, d[i].right, "right"))) return st;
+        const mapsq_table* L = d[i].left;
+        const mapsq_table* R = d[i].right;
+        Plan& p = plan[i];
+        p.idx = i;
+        p.lk = col_of(L, d[i].key_var);
+        p.rk = col_of(R, d[i].key_var);
+        if (p.lk < 0 || p.rk < 0)
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "join " + std::to_string(i) + ": key variable not bound on both sides");
+        bool extra = false;
+        for (int c = 0; c < L->ncols; c++)
+            if (c != p.lk) p.lv.push_back(c);
+        for (int c = 0; c < R->ncols; c++) {
+            if (c == p.rk) continue;
+            if (col_of(L, R->var[c]) >= 0) extra = true;
+            p.rv.push_back(c);
+        }
+        p.empty = L->nrows == 0 || R->nrows == 0;
+        p.batched = !extra && 1 + p.lv.size() + p.rv.size() <= (size_t)BATCH_MAXNC;
+        if (p.batched && !p.empty) {
+            if (L->key_max < 0 || R->key_max < 0) known = false;
+            kmax = std::max(kmax, std::max(L->key_max, R->key_max));
+        }
+    }
+    const int key_bits = known ? bitlen((uint32_t)kmax) : 31;
+    int rb, kpt;
+    pick_tuning(ctx, key_bits, rb, kpt);
+    const int passes = std::max(1, (key_bits + rb - 1) / rb);
+    const uint32_t TILE = BLOCK_THREADS * (uint32_t)kpt;  // records per tile
+    const size_t buckets = size_t(1) << rb;
+
+    // record tiles of the batched, non-empty joins
+    std::vector<BatchJoin> J(n);
+    std::vector<uint32_t> tile_join;
+    uint64_t tiles = 0;
+    for (int i = 0; i < n; i++) {
+        std::memset(&J[i], 0, sizeof(BatchJoin));
+        const Plan& p = plan[i];
+        if (!p.batched) continue;
+        const mapsq_table* L = d[i].left;
+        const mapsq_table* R = d[i].right;
+        BatchJoin& b = J[i];
+        b.lkey = L->col[p.lk];
+        b.rkey = R->col[p.rk];
+        b.nvl = (int)p.lv.size();
+        b.nvr = (int)p.rv.size();
+        for (int c = 0; c < b.nvl; c++) b.lcol[c] = L->col[p.lv[c]];
+        for (int c = 0; c < b.nvr; c++) b.rcol[c] = R->col[p.rv[c]];
+        if (p.empty) continue;
+        b.nl = (uint32_t)L->nrows;
+        b.nr = (uint32_t)R->nrows;
+        if ((uint64_t)b.nl + b.nr >= (1ull << 32)) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "a join with 2^32 records");
+        b.ntiles = (uint32_t)((uint64_t(b.nl) + b.nr + TILE - 1) / TILE);
+        b.tile_off = (uint32_t)tiles;
+        b.rec_off = (uint32_t)(tiles * TILE);
+        tiles += b.ntiles;
+        if (tiles * TILE >= (1ull << 32)) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "a batch of 2^32 records or more");
+        tile_join.insert(tile_join.end(), b.ntiles, (uint32_t)i);
+    }
+    const uint64_t nrec = tiles * TILE;
+
+    std::vector<mapsq_table> res(n);
+    std::vector<bool> done(n, false);
+    auto fail_all = [&](mapsq_status code, const std::string& msg) {
+        for (int i = 0; i < n; i++) {
+            free_table(ctx, &res[i]);
+            std::memset(&outs[i], 0, sizeof(mapsq_table));
+        }
+        return ctx->fail(code, msg);
+    };
+    auto meta = [&](int i, mapsq_table* t) {
+        const mapsq_table* L = d[i].left;
+        const mapsq_table* R = d[i].right;
+        const Plan& p = plan[i];
+        t->ncols = 1 + (int)p.lv.size() + (int)p.rv.size();
+        t->var[0] = d[i].key_var;
+        int k = 1;
+        for (int c : p.lv) t->var[k++] = L->var[c];
+        for (int c : p.rv) t->var[k++] = R->var[c];
+        t->key_max = (L->key_max >= 0 && R->key_max >= 0) ? std::max(L->key_max, R->key_max) : -1;
+    };
+
+    if (tiles > 0) {
+        // scratch: sort ping-pong (16 B/record; the spare pair later holds
+        // segment starts and splits) and segment offsets (8 B/record)
+        const size_t nb4 = align_up(nrec * 4, ARENA_ALIGN);
+        const size_t hist_bytes = align_up(size_t(n) * passes * buckets * 4, ARENA_ALIGN);
+        const size_t tj_bytes = align_up(tiles * 4, ARENA_ALIGN);
+        const size_t jd_bytes = align_up(sizeof(BatchJoin) * n, ARENA_ALIGN);
+        Block scratch = alloc_block(ctx, nb4 * 6 + hist_bytes + tj_bytes + jd_bytes);
+        if (!scratch.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for batch scratch");
+        if (!ctx->ensure_status(size_t(tiles) * buckets))
+            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for batch status words");
+        if (ctx->bhdr_off == SIZE_MAX) {
+            ctx->bhdr_off = ctx->arena.alloc(sizeof(BatchHdr));
+            if (ctx->bhdr_off == SIZE_MAX) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the batch header");
+            ctx->bhdr = reinterpret_cast<BatchHdr*>(ctx->arena.ptr(ctx->bhdr_off));
+        }
+        char* sb = ctx->arena.ptr(scratch.off);
+        // the output region: the largest free block that is left
+        const size_t cap_bytes = ctx->arena.largest() / ARENA_ALIGN * ARENA_ALIGN;
+        Block region;
+        if (cap_bytes >= ARENA_ALIGN) region = alloc_block(ctx, cap_bytes);
+        BatchHdr H{};
+        H.joins = reinterpret_cast<BatchJoin*>(sb + nb4 * 6 + hist_bytes + tj_bytes);
+        H.tile_join = reinterpret_cast<const uint32_t*>(sb + nb4 * 6 + hist_bytes);
+        H.njoins = (uint32_t)n;
+        H.total_tiles = (uint32_t)tiles;
+        H.passes = (uint32_t)passes;
+        if (ctx->epoch + passes + 2 >= (1u << 22)) {
+            (void)launch_fill_u64(ctx->status, ctx->status_words, 0ull, ctx->stream);
+            ctx->epoch = 0;
+        }
+        H.epoch0 = ctx->epoch + 1;
+        ctx->epoch += passes + 2;
+        for (int k = 0; k < 2; k++) {
+            H.keys[k] = reinterpret_cast<uint32_t*>(sb + nb4 * k);
+            H.vals[k] = reinterpret_cast<uint32_t*>(sb + nb4 * (2 + k));
+        }
+        H.seg_off = reinterpret_cast<uint64_t*>(sb + nb4 * 4);
+        H.hist = reinterpret_cast<uint32_t*>(sb + nb4 * 6);
+        H.ctr = ctx->small + SMALL_CTR;
+        H.status = ctx->status;
+        H.out_base = region.ok() ? region.as<int32_t>() : nullptr;
+        H.out_cap_words = region.ok() ? cap_bytes / 4 : 0;
+        // upload header, descriptors and the tile map through pinned staging
+        const size_t up = sizeof(BatchHdr) + sizeof(BatchJoin) * n + tiles * 4;
+        if (!ensure_stage(ctx, up)) return ctx->fail(MAPSQ_ERR_HIP, "pinned staging allocation failed");
+        char* stg = reinterpret_cast<char*>(ctx->stage);
+        std::memcpy(stg, &H, sizeof(BatchHdr));
+        std::memcpy(stg + sizeof(BatchHdr), J.data(), sizeof(BatchJoin) * n);
+        std::memcpy(stg + sizeof(BatchHdr) + sizeof(BatchJoin) * n, tile_join.data(), tiles * 4);
+        HIPCHK_B(hipMemcpyAsync(ctx->bhdr, stg, sizeof(BatchHdr), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK_B(hipMemcpyAsync(H.joins, stg + sizeof(BatchHdr), sizeof(BatchJoin) * n, hipMemcpyHostToDevice,
+                                ctx->stream));
+        HIPCHK_B(hipMemcpyAsync(const_cast<uint32_t*>(H.tile_join), stg + sizeof(BatchHdr) + sizeof(BatchJoin) * n,
+                                tiles * 4, hipMemcpyHostToDevice, ctx->stream));
+        // launch: a cached graph when the stream can be captured
+        const int ph = ctx->prof_begin(6);
+        const uint64_t gkey = (uint64_t)rb | ((uint64_t)kpt << 8) | ((uint64_t)passes << 16);
+        const char* env = std::getenv("MAPSQ_BATCH_GRAPH");
+        const bool graph = ctx->use_graph && ctx->stream != nullptr && !(env && env[0] == '0');
+        if (graph) {
+            auto it = ctx->graphs.find(gkey);
+            if (it == ctx->graphs.end()) {
+                hipGraph_t g = nullptr;
+                hipGraphExec_t ge = nullptr;
+                HIPCHK_B(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t le = launch_batch(ctx->bhdr, rb, kpt, passes, ctx->stream);
+                hipError_t ce = hipStreamEndCapture(ctx->stream, &g);
+                if (le != hipSuccess || ce != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return ctx->fail(MAPSQ_ERR_HIP, std::string("batch capture: ") +
+                                                        hipGetErrorString(le != hipSuccess ? le : ce));
+                }
+                hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess) return ctx->fail(MAPSQ_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+                it = ctx->graphs.emplace(gkey, ge).first;
+            }
+            HIPCHK_B(hipGraphLaunch(it->second, ctx->stream));
+        } else {
+            HIPCHK_B(launch_batch(ctx->bhdr, rb, kpt, passes, ctx->stream));
+        }
+        // read back the placed results (the one synchronisation of the batch)
+        const size_t down = sizeof(BatchHdr) + sizeof(BatchJoin) * n;
+        HIPCHK_B(hipMemcpyAsync(stg, ctx->bhdr, sizeof(BatchHdr), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK_B(hipMemcpyAsync(stg + sizeof(BatchHdr), H.joins, sizeof(BatchJoin) * n, hipMemcpyDeviceToHost,
+                                ctx->stream));
+        HIPCHK_B(hipStreamSynchronize(ctx->stream));
+        (void)down;
+        BatchHdr Hr;
+        std::memcpy(&Hr, stg, sizeof(BatchHdr));
+        std::memcpy(J.data(), stg + sizeof(BatchHdr), sizeof(BatchJoin) * n);
+        {
+            double bytes = 0;
+            for (int i = 0; i < n; i++) {
+                const BatchJoin& b = J[i];
+                if (!plan[i].batched || plan[i].empty) continue;
+                const double N = double(b.nl) + b.nr;
+                bytes += 16.0 * N * passes + 8.0 * N + 28.0 * b.nseg;
+                if (b.status == 0)
+                    bytes += 4.0 * (1 + b.nvl + b.nvr) * double(b.total) + 4.0 * N + 20.0 * b.nseg +
+                             4.0 * (b.nvl * double(b.nl) + b.nvr * double(b.nr));
+                ctx->acc.rows_out += (int64_t)b.total;
+                ctx->acc.joins += 1;
+            }
+            ctx->prof_end(ph, bytes);
+        }
+        for (int i = 0; i < n; i++)
+            if (plan[i].batched && !plan[i].empty && J[i].status == 2)
+                return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join " + std::to_string(i) + ": over 2^40 rows");
+        // results in the output region share its block
+        const size_t used = size_t(Hr.out_used_words) * 4;
+        uint32_t refs = 0;
+        for (int i = 0; i < n; i++) {
+            const BatchJoin& b = J[i];
+            if (!plan[i].batched || plan[i].empty) continue;
+            if (b.status != 0) continue;
+            mapsq_table& t = res[i];
+            meta(i, &t);
+            t.owned = 1;
+            t.nrows = (int64_t)b.total;
+            if (b.total > 0) {
+                t.block = region.off + 1;
+                for (int c = 0; c < t.ncols; c++)
+                    t.col[c] = region.as<int32_t>() + b.out_word + (uint64_t)c * b.col_words;
+                refs++;
+            }
+            done[i] = true;
+        }
+        if (region.ok()) {
+            if (refs == 0 || used == 0) {
+                region.reset();
+                for (int i = 0; i < n; i++) res[i].block = 0;
+            } else {
+                ctx->arena.shrink(region.off, used);
+                ctx->shared_refs[region.off] = refs;
+                region.release();
+            }
+        }
+    }
+    // empty joins, and the joins the batched kernels did not take
+    for (int i = 0; i < n; i++) {
+        if (done[i]) continue;
+        if (plan[i].batched && plan[i].empty) {
+            meta(i, &res[i]);
+            res[i].owned = 1;
+            res[i].nrows = 0;
+            done[i] = true;
+            continue;
+        }
+        mapsq_status st = join_tables(ctx, d[i].left, d[i].right, d[i].key_var, &res[i]);
+        if (st) {
+            std::string msg = ctx->err;
+            return fail_all(st, "join " + std::to_string(i) + ": " + msg);
+        }
+        done[i] = true;
+    }
+    for (int i = 0; i < n; i++) outs[i] = res[i];
+    return MAPSQ_OK;
+}
+
+}  // namespace mq

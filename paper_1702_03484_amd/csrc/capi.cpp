@@ -80,6 +80,8 @@ mapsq_status mapsq_destroy(mapsq_ctx* c) {
         DeviceGuard g(c->impl.device);
         (void)hipStreamSynchronize(c->impl.stream);
         c->impl.prof_release();
+        c->impl.release_graphs();
+        if (c->impl.stage) (void)hipHostFree(c->impl.stage);
         if (c->impl.pinned) (void)hipHostFree(c->impl.pinned);
     }
     delete c;
@@ -131,6 +133,10 @@ mapsq_status mapsq_query(mapsq_ctx* c, const mapsq_pattern* pats, int32_t npats,
         if (!out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
         return mq::query(ctx, pats, npats, select_vars, nselect, out);
     });
+}
+
+mapsq_status mapsq_join_batch(mapsq_ctx* c, const mapsq_join_desc* joins, int32_t n, mapsq_table* outs) {
+    return guarded(c, [&](Ctx* ctx) { return mq::join_batch(ctx, joins, n, outs); });
 }
 
 mapsq_status mapsq_table_free(mapsq_ctx* c, mapsq_table* t) {

@@ -76,23 +76,86 @@ __device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
 
 // Exclusive prefix of tile `tile` over tiles [first_tile, tile) for one
 // status column; `stride` is the distance between consecutive tiles' words.
-// Spins until predecessors publish.  Sums saturate at 2^40 - 1.
+// Reads up to 8 predecessors per round so their load latencies overlap;
+// spins until predecessors publish.  Sums saturate at 2^40 - 1.
 __device__ __forceinline__ uint64_t lookback(const uint64_t* status, uint32_t tile, uint32_t first_tile,
                                              uint32_t stride, uint32_t epoch) {
+    constexpr int WIN = 8;
     uint64_t excl = 0;
     int64_t t = (int64_t)tile - 1;
     while (t >= (int64_t)first_tile) {
-        uint64_t w = st_load(status + (uint64_t)t * stride);
-        uint32_t flag = (uint32_t)(w >> 40) & 3u;
-        if ((uint32_t)(w >> 42) != epoch || flag == 0) {
+        uint64_t w[WIN];
+#pragma unroll
+        for (int k = 0; k < WIN; k++)
+            w[k] = (t - k >= (int64_t)first_tile) ? st_load(status + (uint64_t)(t - k) * stride) : 0ull;
+        int k = 0;
+        bool done = false;
+        for (; k < WIN && t - k >= (int64_t)first_tile; k++) {
+            const uint32_t flag = (uint32_t)(w[k] >> 40) & 3u;
+            if ((uint32_t)(w[k] >> 42) != epoch || flag == 0) break;  // not yet published: retry from here
+            excl = sat_add(excl, w[k] & ST_VAL_MASK);
+            if (flag == ST_INC) {
+                done = true;
+                break;
+            }
+        }
+        if (done) break;
+        if (k == 0) __builtin_amdgcn_s_sleep(1);
+        t -= k;
+    }
+    return excl;
+}
+
+// Wave-parallel look-back over one status column (stride 1): each probe
+// reads the 64 predecessors below `top` at once and stops at the nearest
+// inclusive prefix.  Every lane of the calling wave must call it; all lanes
+// return the exclusive prefix of `tile` (saturating at 2^40 - 1).
+__device__ __forceinline__ uint64_t wave_lookback(const uint64_t* status, uint32_t tile, uint32_t first_tile,
+                                                  uint32_t epoch) {
+    uint64_t excl = 0;
+    int64_t top = (int64_t)tile - 1;
+    while (top >= (int64_t)first_tile) {
+        const int64_t t = top - (int64_t)lane();
+        const bool inr = t >= (int64_t)first_tile;
+        const uint64_t w = inr ? st_load(status + t) : 0ull;
+        const uint32_t flag = (uint32_t)(w >> 40) & 3u;
+        const bool valid = !inr || ((uint32_t)(w >> 42) == epoch && flag != 0);
+        const bool inc = !inr || (valid && flag == ST_INC);
+        const uint64_t incm = __ballot(inc);
+        const uint64_t invm = __ballot(!valid);
+        const uint32_t stop = incm ? (uint32_t)__builtin_ctzll(incm) : 64u;  // lanes 0..stop count
+        const uint64_t need = stop >= 63 ? ~0ull : ((2ull << stop) - 1ull);
+        if (invm & need) {
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl = sat_add(excl, w & ST_VAL_MASK);
-        if (flag == ST_INC) break;
-        t--;
+        uint64_t v = (lane() <= stop && inr) ? (w & ST_VAL_MASK) : 0ull;
+        v = wave_sum(v);  // at most 64 * 2^40: no overflow
+        excl = sat_add(excl, v > SAT40 ? SAT40 : v);
+        if (stop < 64) break;
+        top -= MQ_WAVE;
     }
     return excl;
+}
+
+// Publish a tile aggregate and resolve its exclusive prefix over tiles
+// [first_tile, tile) with one wave (all 64 lanes of that wave call it).
+// Returns the exclusive prefix in every lane of the wave.
+__device__ __forceinline__ uint64_t tile_prefix_wave(uint64_t* status, uint32_t tile, uint32_t first_tile,
+                                                     uint32_t epoch, uint64_t agg) {
+    agg = agg > SAT40 ? SAT40 : agg;
+    if (tile == first_tile) {
+        if (lane() == 0) st_store(status + tile, st_pack(epoch, ST_INC, agg));
+        return 0;
+    }
+    if (lane() == 0) st_store(status + tile, st_pack(epoch, ST_AGG, agg));
+    const uint64_t ex = wave_lookback(status, tile, first_tile, epoch);
+    if (lane() == 0) st_store(status + tile, st_pack(epoch, ST_INC, sat_add(ex, agg)));
+    return ex;
+}
+
+__device__ __forceinline__ uint64_t tile_prefix_wave0(uint64_t* status, uint32_t tile, uint32_t epoch, uint64_t agg) {
+    return tile_prefix_wave(status, tile, 0, epoch, agg);
 }
 
 // Next dynamic tile id from a counter (thread 0), broadcast through LDS.

@@ -1,0 +1,286 @@
+// Batched joins on gfx950: many independent joins of uneven sizes in one
+// sequence of persistent launches (captured once as a hipGraph by the host).
+// Each join's records occupy whole record tiles; a tile -> join table sends
+// every tile to its join, each join's look-back stops at its own first tile,
+// and a placement kernel lays the results out in one output region on the
+// device, so no size travels to the host between launches.
+#include <algorithm>
+
+#include "device_common.h"
+#include "kernels.h"
+#include "tile_ops.h"
+
+namespace mq {
+
+constexpr uint32_t BATCH_BLOCKS = 1024;
+constexpr uint32_t BMAT_BLOCKS = 2048;
+constexpr int BMAT_RPT = 8;
+constexpr uint32_t BMAT_WROWS = MQ_WAVE * BMAT_RPT;
+
+uint32_t batch_chunk_rows() { return BMAT_WROWS; }
+
+__device__ __forceinline__ uint32_t bsrc_key(const BatchJoin& J, uint32_t idx) {
+    const int32_t k = idx < J.nl ? J.lkey[idx] : J.rkey[idx - J.nl];
+    return (uint32_t)k - (uint32_t)J.key_base;
+}
+
+template <int RB>
+__global__ void bclear_kernel(const BatchHdr* __restrict__ h) {
+    const uint64_t words = (uint64_t)h->njoins * h->passes * Radix<RB>::BUCKETS;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+        h->hist[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < h->passes + 4) h->ctr[threadIdx.x] = 0;
+}
+
+// Per-join digit histograms of all passes.  Block b takes a contiguous range
+// of record tiles and flushes its LDS counts whenever the join changes.
+template <int RB, int KPT>
+__global__ __launch_bounds__(MQ_BLOCK) void bhist_kernel(const BatchHdr* __restrict__ h) {
+    using R = Radix<RB>;
+    constexpr uint32_t TILE = MQ_BLOCK * KPT;
+    __shared__ uint32_t sh[R::MAXP * R::BUCKETS];
+    const uint32_t T = h->total_tiles, passes = h->passes;
+    const uint32_t t0 = (uint32_t)((uint64_t)blockIdx.x * T / gridDim.x);
+    const uint32_t t1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * T / gridDim.x);
+    for (int i = threadIdx.x; i < R::MAXP * R::BUCKETS; i += MQ_BLOCK) sh[i] = 0;
+    __syncthreads();
+    int64_t cur = -1;
+    for (uint32_t t = t0; t < t1; t++) {
+        const uint32_t j = h->tile_join[t];
+        if ((int64_t)j != cur) {
+            if (cur >= 0) {
+                __syncthreads();
+                for (uint32_t i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
+                    const uint32_t c = sh[i];
+                    if (c) atomicAdd(&h->hist[(uint64_t)cur * passes * R::BUCKETS + i], c);
+                    sh[i] = 0;
+                }
+                __syncthreads();
+            }
+            cur = j;
+        }
+        const BatchJoin& J = h->joins[j];
+        const uint32_t n = J.nl + J.nr;
+        const uint32_t base = (t - J.tile_off) * TILE;
+        uint32_t k[KPT];
+#pragma unroll
+        for (int i = 0; i < KPT; i++) {
+            const uint32_t idx = base + i * MQ_BLOCK + threadIdx.x;
+            k[i] = idx < n ? bsrc_key(J, idx) : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < KPT; i++) {
+            const uint32_t idx = base + i * MQ_BLOCK + threadIdx.x;
+            if (idx < n)
+                for (uint32_t p = 0; p < passes; p++) atomicAdd(&sh[p * R::BUCKETS + ((k[i] >> (p * RB)) & R::MASK)], 1u);
+        }
+    }
+    __syncthreads();
+    if (cur >= 0)
+        for (uint32_t i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
+            const uint32_t c = sh[i];
+            if (c) atomicAdd(&h->hist[(uint64_t)cur * passes * R::BUCKETS + i], c);
+        }
+}
+
+template <int RB, int KPT, bool GEN>
+__global__ __launch_bounds__(MQ_BLOCK) void bpass_kernel(const BatchHdr* __restrict__ h, int pass) {
+    using R = Radix<RB>;
+    constexpr uint32_t TILE = MQ_BLOCK * KPT;
+    __shared__ SortSmem<RB, KPT> sm;
+    __shared__ uint32_t s_tile;
+    const uint32_t T = h->total_tiles, passes = h->passes;
+    const uint32_t epoch = h->epoch0 + pass;
+    const int src = (pass - 1) & 1, dst = pass & 1;  // the first pass writes buffer 0
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    for (;;) {
+        const uint32_t t = next_tile(&h->ctr[pass], &s_tile);
+        if (t >= T) break;
+        const uint32_t j = h->tile_join[t];
+        const BatchJoin& J = h->joins[j];
+        const uint32_t n = J.nl + J.nr;
+        const uint32_t base = (t - J.tile_off) * TILE;
+        const uint32_t valid_n = min(TILE, n - base);
+        uint32_t key[KPT], val[KPT];
+        const uint32_t* kin = GEN ? nullptr : h->keys[src] + J.rec_off;
+        const uint32_t* vin = GEN ? nullptr : h->vals[src] + J.rec_off;
+#pragma unroll
+        for (int i = 0; i < KPT; i++) {
+            const uint32_t off = (w * KPT + i) * MQ_WAVE + lane();
+            const uint32_t idx = base + off;
+            const bool ok = off < valid_n;
+            if (GEN) {
+                key[i] = ok ? bsrc_key(J, idx) : 0u;
+                val[i] = idx;
+            } else {
+                key[i] = ok ? kin[idx] : 0u;
+                val[i] = ok ? vin[idx] : 0u;
+            }
+        }
+        sort_tile<RB, KPT>(sm, key, val, valid_n, pass * RB,
+                           h->hist + ((uint64_t)j * passes + pass) * R::BUCKETS, h->status, t, J.tile_off, epoch,
+                           h->keys[dst] + J.rec_off, h->vals[dst] + J.rec_off);
+    }
+}
+
+template <int KPT>
+__global__ __launch_bounds__(MQ_BLOCK) void bheads_kernel(BatchHdr* __restrict__ h) {
+    constexpr uint32_t TILE = MQ_BLOCK * KPT;
+    __shared__ HeadsSmem sm;
+    __shared__ uint32_t s_tile;
+    const uint32_t T = h->total_tiles, passes = h->passes;
+    const int fin = (passes - 1) & 1;
+    const uint32_t epoch = h->epoch0 + passes;
+    for (;;) {
+        const uint32_t t = next_tile(&h->ctr[passes], &s_tile);
+        if (t >= T) break;
+        const uint32_t j = h->tile_join[t];
+        BatchJoin& J = h->joins[j];
+        const uint32_t lt = t - J.tile_off;
+        heads_tile<KPT>(sm, h->keys[fin] + J.rec_off, h->vals[fin] + J.rec_off, J.nl + J.nr, J.nl, lt * TILE, t,
+                        J.tile_off, lt + 1 == J.ntiles, h->keys[1 - fin] + J.rec_off, h->vals[1 - fin] + J.rec_off,
+                        &J.nseg, h->status, epoch);
+    }
+}
+
+template <int KPT>
+__global__ __launch_bounds__(MQ_BLOCK) void bcount_kernel(BatchHdr* __restrict__ h) {
+    constexpr uint32_t TILE = MQ_BLOCK * KPT;
+    __shared__ CountSmem sm;
+    __shared__ uint32_t s_tile;
+    const uint32_t T = h->total_tiles, passes = h->passes;
+    const int fin = (passes - 1) & 1;
+    const uint32_t epoch = h->epoch0 + passes + 1;
+    for (;;) {
+        const uint32_t t = next_tile(&h->ctr[passes + 1], &s_tile);
+        if (t >= T) break;
+        const uint32_t j = h->tile_join[t];
+        BatchJoin& J = h->joins[j];
+        const uint32_t lt = t - J.tile_off;
+        const uint32_t ns = J.nseg;
+        if (lt * TILE >= ns) continue;  // beyond the join's segments (block-uniform)
+        const uint32_t last = (ns + TILE - 1) / TILE - 1;
+        count_tile<KPT>(sm, J.nl + J.nr, ns, lt * TILE, t, J.tile_off, lt == last, h->keys[1 - fin] + J.rec_off,
+                        h->vals[1 - fin] + J.rec_off, h->seg_off + J.rec_off, &J.total, h->status, epoch);
+    }
+}
+
+// One block: lay every join's result out in the output region (columns of a
+// multiple of 64 rows, 256-byte aligned), flag joins that do not fit, and
+// number the materialisation chunks.
+__global__ __launch_bounds__(MQ_BLOCK) void bplace_kernel(BatchHdr* __restrict__ h) {
+    __shared__ uint64_t s_tmp[MQ_WAVES];
+    uint64_t run_words = 0, run_chunks = 0;
+    const uint32_t nj = h->njoins;
+    for (uint32_t b = 0; b < nj; b += MQ_BLOCK) {
+        const uint32_t j = b + threadIdx.x;
+        uint64_t words = 0, cw = 0, tot = 0;
+        uint32_t st = 0;
+        int nc = 0;
+        if (j < nj) {
+            const BatchJoin& J = h->joins[j];
+            tot = J.total;
+            nc = 1 + J.nvl + J.nvr;
+            if (tot >= SAT40) {
+                st = 2;
+            } else {
+                cw = (tot + 63) / 64 * 64;
+                words = cw * (uint64_t)nc;
+            }
+        }
+        uint64_t wsum;
+        const uint64_t wex = block_excl_scan<uint64_t>(words, s_tmp, &wsum);
+        const uint64_t at = run_words + wex;
+        if (st == 0 && at + words > h->out_cap_words) st = 1;
+        const uint64_t chunks = (st == 0) ? (tot + BMAT_WROWS - 1) / BMAT_WROWS : 0;
+        uint64_t csum;
+        const uint64_t cex = block_excl_scan<uint64_t>(chunks, s_tmp, &csum);
+        if (j < nj) {
+            BatchJoin& J = h->joins[j];
+            J.status = st;
+            J.out_word = at;
+            J.col_words = cw;
+            J.chunk_off = run_chunks + cex;
+            for (int c = 0; c < BATCH_MAXNC; c++) J.out[c] = (st == 0 && c < nc) ? h->out_base + at + c * cw : nullptr;
+        }
+        run_words += wsum;
+        run_chunks += csum;
+    }
+    if (threadIdx.x == 0) {
+        h->out_used_words = run_words < h->out_cap_words ? run_words : h->out_cap_words;
+        h->total_chunks = run_chunks;
+    }
+}
+
+// last join j with chunk_off <= c (wave-uniform; every lane calls it)
+__device__ __forceinline__ uint32_t wave_join_of(const BatchJoin* __restrict__ js, uint32_t nj, uint64_t c) {
+    uint32_t lo = 0, hi = nj - 1;
+    while (hi > lo) {
+        const uint32_t step = (hi - lo + MQ_WAVE) / MQ_WAVE;
+        const uint32_t pos = lo + lane() * step;
+        const bool ok = pos <= hi && js[pos].chunk_off <= c;
+        const uint64_t m = __ballot(ok);
+        const uint32_t top = 63u - (uint32_t)__clzll(m);
+        lo = lo + top * step;
+        hi = min(hi, lo + step - 1);
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restrict__ h) {
+    const uint64_t nchunks = h->total_chunks;
+    const uint32_t passes = h->passes;
+    const int fin = (passes - 1) & 1;
+    const uint64_t gw = (uint64_t)blockIdx.x * MQ_WAVES + threadIdx.x / MQ_WAVE;
+    const uint64_t nw = (uint64_t)gridDim.x * MQ_WAVES;
+    for (uint64_t c = gw; c < nchunks; c += nw) {
+        const uint32_t j = wave_join_of(h->joins, h->njoins, c);
+        const BatchJoin& J = h->joins[j];
+        MatJoin mj;
+        mj.keys = h->keys[fin] + J.rec_off;
+        mj.vals = h->vals[fin] + J.rec_off;
+        mj.seg_start = h->keys[1 - fin] + J.rec_off;
+        mj.seg_split = h->vals[1 - fin] + J.rec_off;
+        mj.seg_off = h->seg_off + J.rec_off;
+        mj.ns = J.nseg;
+        mj.n = J.nl + J.nr;
+        mj.n_left = J.nl;
+        mj.key_base = J.key_base;
+        mj.nl = J.nvl;
+        mj.nr = J.nvr;
+        mj.lcol = J.lcol;
+        mj.rcol = J.rcol;
+        mj.out = J.out;
+        const uint64_t j0 = (c - J.chunk_off) * BMAT_WROWS;
+        mat_wave_chunk<BATCH_MAXNC, BMAT_RPT>(mj, j0, min(j0 + BMAT_WROWS, J.total));
+    }
+}
+
+template <int RB, int KPT>
+static hipError_t launch_batch_t(const BatchHdr* hdr, int passes, hipStream_t stream) {
+    BatchHdr* h = const_cast<BatchHdr*>(hdr);
+    bclear_kernel<RB><<<64, MQ_BLOCK, 0, stream>>>(hdr);
+    bhist_kernel<RB, KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
+    for (int p = 0; p < passes; p++) {
+        if (p == 0) bpass_kernel<RB, KPT, true><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr, p);
+        else bpass_kernel<RB, KPT, false><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr, p);
+    }
+    bheads_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(h);
+    bcount_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(h);
+    bplace_kernel<<<1, MQ_BLOCK, 0, stream>>>(h);
+    bmat_kernel<<<BMAT_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchHdr* hdr, int rb, int kpt, int passes, hipStream_t stream) {
+#define MQ_B(B)                                                                                 \
+    case B:                                                                                     \
+        return kpt == 8 ? launch_batch_t<B, 8>(hdr, passes, stream) : launch_batch_t<B, 16>(hdr, passes, stream);
+    switch (rb) {
+        MQ_B(4) MQ_B(5) MQ_B(6) MQ_B(7) MQ_B(8) MQ_B(9) MQ_B(10) MQ_B(11)
+        default: return hipErrorInvalidValue;
+    }
+#undef MQ_B
+}
+
+}  // namespace mq

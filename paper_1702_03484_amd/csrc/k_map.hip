@@ -50,17 +50,12 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_kernel(CompactArgs a, uint64
             if ((uint32_t)i < w) wex += s_wtot[i];
             ttot += s_wtot[i];
         }
-        if (threadIdx.x == 0) {
-            uint64_t ex = 0;
-            if (tile == 0) {
-                st_store(status, st_pack(epoch, ST_INC, ttot));
-            } else {
-                st_store(status + tile, st_pack(epoch, ST_AGG, ttot));
-                ex = lookback(status, tile, 0, 1, epoch);
-                st_store(status + tile, st_pack(epoch, ST_INC, ex + ttot));
+        if (w == 0) {
+            const uint64_t ex = tile_prefix_wave0(status, tile, epoch, ttot);
+            if (lane() == 0) {
+                s_excl = ex;
+                if (tile == ntiles - 1) *a.count = ex + ttot;
             }
-            s_excl = ex;
-            if (tile == ntiles - 1) *a.count = ex + ttot;
         }
         __syncthreads();
         uint64_t pos = s_excl + wex;
@@ -85,45 +80,55 @@ hipError_t launch_compact(const CompactArgs& a, uint64_t* status, uint32_t* tile
     return hipGetLastError();
 }
 
-__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* c, int64_t lo, int64_t hi, int32_t v) {
+// First index in [lo, hi) whose value is >= v (upper = false) or > v
+// (upper = true), by a 64-ary search: one coalesced probe of 64 positions and
+// one __ballot per level.  Every lane of the wave calls it with the same
+// arguments.
+__device__ __forceinline__ int64_t wave_bound(const int32_t* __restrict__ c, int64_t lo, int64_t hi, int32_t v,
+                                              bool upper) {
     while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        if (c[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-__device__ __forceinline__ int64_t upper_bound_i32(const int32_t* c, int64_t lo, int64_t hi, int32_t v) {
-    while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        if (c[mid] <= v) lo = mid + 1;
-        else hi = mid;
+        const int64_t step = (hi - lo + MQ_WAVE - 1) / MQ_WAVE;
+        const int64_t pos = lo + (int64_t)lane() * step;
+        bool below = false;
+        if (pos < hi) {
+            const int32_t x = c[pos];
+            below = upper ? x <= v : x < v;
+        }
+        const uint32_t cnt = (uint32_t)__popcll(__ballot(below));  // probes before the bound (a prefix)
+        if (cnt == 0) return lo;
+        const int64_t nlo = lo + (int64_t)(cnt - 1) * step + 1;
+        hi = std::min(hi, lo + (int64_t)cnt * step);
+        lo = nlo;
     }
     return lo;
 }
 
-__global__ void locate_kernel(const LocateQuery* __restrict__ q, int32_t nq, int64_t* __restrict__ out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per query
+__global__ __launch_bounds__(MQ_WAVE) void locate_kernel(const LocateQuery* __restrict__ q, int32_t nq,
+                                                         int64_t* __restrict__ out) {
+    const int i = blockIdx.x;
     if (i >= nq) return;
-    LocateQuery x = q[i];
+    const LocateQuery x = q[i];
     int64_t lo = x.lo, hi = x.hi;
     if (x.col1) {
-        int64_t l = lower_bound_i32(x.col1, lo, hi, x.v1);
-        hi = upper_bound_i32(x.col1, l, hi, x.v1);
+        const int64_t l = wave_bound(x.col1, lo, hi, x.v1, false);
+        hi = wave_bound(x.col1, l, hi, x.v1, true);
         lo = l;
     }
     if (x.col2) {
-        int64_t l = lower_bound_i32(x.col2, lo, hi, x.v2);
-        hi = upper_bound_i32(x.col2, l, hi, x.v2);
+        const int64_t l = wave_bound(x.col2, lo, hi, x.v2, false);
+        hi = wave_bound(x.col2, l, hi, x.v2, true);
         lo = l;
     }
-    out[2 * i] = lo;
-    out[2 * i + 1] = hi;
+    if (lane() == 0) {
+        out[2 * i] = lo;
+        out[2 * i + 1] = hi;
+    }
 }
 
 hipError_t launch_locate(const LocateQuery* q_dev, int32_t nq, int64_t* out, hipStream_t stream) {
     if (nq <= 0) return hipSuccess;
-    locate_kernel<<<(nq + 63) / 64, 64, 0, stream>>>(q_dev, nq, out);
+    locate_kernel<<<nq, MQ_WAVE, 0, stream>>>(q_dev, nq, out);
     return hipGetLastError();
 }
 

@@ -14,23 +14,21 @@
 // the intermediate records are never written out before the first scatter.
 #include "device_common.h"
 #include "kernels.h"
+#include "tile_ops.h"
 
 #include <algorithm>
 
 namespace mq {
 
-template <int RB>
-struct Radix {
-    static constexpr int BUCKETS = 1 << RB;
-    static constexpr uint32_t MASK = BUCKETS - 1;
-    static constexpr int MAXP = (32 + RB - 1) / RB;
-    static constexpr int BPT = (BUCKETS + MQ_BLOCK - 1) / MQ_BLOCK;  // buckets per thread
-};
-
 __device__ __forceinline__ uint32_t src_key(const SortSrc& s, uint32_t idx) {
     int32_t k = idx < s.n0 ? s.k0[idx] : s.k1[idx - s.n0];
     return (uint32_t)k - (uint32_t)s.base;
 }
+
+// Digit histograms of every pass.  Each block takes tiles of 256*HIST_IPT
+// keys with all loads of a tile in flight at once, counts into LDS, and adds
+// its LDS counts to the global histogram once at the end.
+constexpr int HIST_IPT = 16;
 
 template <int RB, bool GEN>
 __global__ __launch_bounds__(MQ_BLOCK) void radix_hist_kernel(SortSrc src, const uint32_t* __restrict__ keys,
@@ -39,40 +37,27 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_hist_kernel(SortSrc src, const
     __shared__ uint32_t sh[R::MAXP * R::BUCKETS];
     for (int i = threadIdx.x; i < R::MAXP * R::BUCKETS; i += MQ_BLOCK) sh[i] = 0;
     __syncthreads();
-    const uint32_t stride = gridDim.x * MQ_BLOCK;
-    for (uint32_t i = blockIdx.x * MQ_BLOCK + threadIdx.x; i < n; i += stride) {
-        uint32_t k = GEN ? src_key(src, i) : keys[i];
-        for (int p = 0; p < passes; p++) atomicAdd(&sh[p * R::BUCKETS + ((k >> (p * RB)) & R::MASK)], 1u);
+    constexpr uint32_t TILE = MQ_BLOCK * HIST_IPT;
+    const uint32_t ntiles = (n + TILE - 1) / TILE;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t k[HIST_IPT];
+#pragma unroll
+        for (int i = 0; i < HIST_IPT; i++) {
+            const uint32_t idx = t * TILE + i * MQ_BLOCK + threadIdx.x;
+            k[i] = idx < n ? (GEN ? src_key(src, idx) : keys[idx]) : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < HIST_IPT; i++) {
+            const uint32_t idx = t * TILE + i * MQ_BLOCK + threadIdx.x;
+            if (idx < n)
+                for (int p = 0; p < passes; p++) atomicAdd(&sh[p * R::BUCKETS + ((k[i] >> (p * RB)) & R::MASK)], 1u);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
         uint32_t c = sh[i];
         if (c) atomicAdd(&hist[i], c);
     }
-}
-
-// Exclusive scan of BUCKETS values held in LDS `in`, written to LDS `out`
-// (may alias).  Thread t owns the BPT consecutive buckets t*BPT...
-template <int RB>
-__device__ __forceinline__ void scan_buckets(const uint32_t* in, uint32_t* out, uint32_t* tmp) {
-    using R = Radix<RB>;
-    uint32_t loc[R::BPT];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < R::BPT; k++) {
-        uint32_t d = threadIdx.x * R::BPT + k;
-        loc[k] = d < (uint32_t)R::BUCKETS ? in[d] : 0u;
-        sum += loc[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(sum, tmp, &tot);
-#pragma unroll
-    for (int k = 0; k < R::BPT; k++) {
-        uint32_t d = threadIdx.x * R::BPT + k;
-        if (d < (uint32_t)R::BUCKETS) out[d] = ex;
-        ex += loc[k];
-    }
-    __syncthreads();
 }
 
 template <int RB, int KPT, bool GEN>
@@ -83,39 +68,20 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
                                                               const uint32_t* __restrict__ ghist,
                                                               uint64_t* __restrict__ status,
                                                               uint32_t* __restrict__ tile_ctr, uint32_t epoch) {
-    using R = Radix<RB>;
     constexpr int TILE = MQ_BLOCK * KPT;
-    __shared__ uint32_t s_keys[TILE];
-    __shared__ uint32_t s_vals[TILE];
-    __shared__ uint32_t s_wcnt[MQ_WAVES][R::BUCKETS];
-    __shared__ uint32_t s_local[R::BUCKETS];
-    __shared__ uint32_t s_goff[R::BUCKETS];
-    __shared__ uint32_t s_tmp[MQ_WAVES];
+    __shared__ SortSmem<RB, KPT> sm;
     __shared__ uint32_t s_tile;
-
     const uint32_t tile = next_tile(tile_ctr, &s_tile);
     const uint32_t base = tile * (uint32_t)TILE;
     const uint32_t valid_n = min((uint32_t)TILE, n - base);
     const uint32_t w = threadIdx.x / MQ_WAVE;
-    const uint32_t ln = lane();
-
-    // global start of every digit for this pass, and cleared wave counters
-    for (int d = threadIdx.x; d < R::BUCKETS; d += MQ_BLOCK) {
-        s_goff[d] = ghist[d];
-#pragma unroll
-        for (int i = 0; i < MQ_WAVES; i++) s_wcnt[i][d] = 0;
-    }
-    __syncthreads();
-    scan_buckets<RB>(s_goff, s_goff, s_tmp);
-
-    // load a wave-striped slice: element i of this lane is base + (w*KPT + i)*64 + lane
-    uint32_t key[KPT], val[KPT], rank[KPT];
-    const uint64_t lt = lanemask_lt();
+    // wave-striped slice: element i of this lane is base + (w*KPT + i)*64 + lane
+    uint32_t key[KPT], val[KPT];
 #pragma unroll
     for (int i = 0; i < KPT; i++) {
-        uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
-        uint32_t idx = base + off;
-        bool ok = off < valid_n;
+        const uint32_t off = (w * KPT + i) * MQ_WAVE + lane();
+        const uint32_t idx = base + off;
+        const bool ok = off < valid_n;
         if (GEN) {
             key[i] = ok ? src_key(src, idx) : 0u;
             val[i] = idx;
@@ -124,83 +90,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
             val[i] = ok ? vin[idx] : 0u;
         }
     }
-    // stable rank within the wave, digit by digit through the wave counters
-#pragma unroll
-    for (int i = 0; i < KPT; i++) {
-        uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
-        bool ok = off < valid_n;
-        uint32_t dg = (key[i] >> shift) & R::MASK;
-        uint64_t peers = __ballot(ok);
-#pragma unroll
-        for (int b = 0; b < RB; b++) {
-            uint32_t bit = (dg >> b) & 1u;
-            uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        uint32_t below = __popcll(peers & lt);
-        uint32_t old = ok ? s_wcnt[w][dg] : 0u;
-        if (ok && below == 0) s_wcnt[w][dg] = old + (uint32_t)__popcll(peers);
-        rank[i] = old + below;
-    }
-    __syncthreads();
-
-    // per digit: exclusive prefix over waves, tile total, local digit starts
-    uint32_t tot[R::BPT];
-#pragma unroll
-    for (int k = 0; k < R::BPT; k++) {
-        uint32_t d = threadIdx.x * R::BPT + k;
-        uint32_t run = 0;
-        if (d < (uint32_t)R::BUCKETS) {
-#pragma unroll
-            for (int i = 0; i < MQ_WAVES; i++) {
-                uint32_t c = s_wcnt[i][d];
-                s_wcnt[i][d] = run;
-                run += c;
-            }
-            s_local[d] = run;
-        }
-        tot[k] = run;
-    }
-    __syncthreads();
-    scan_buckets<RB>(s_local, s_local, s_tmp);
-
-    // publish this tile's digit totals, then look back for the prefix
-    uint64_t* st = status + (uint64_t)tile * R::BUCKETS;
-#pragma unroll
-    for (int k = 0; k < R::BPT; k++) {
-        uint32_t d = threadIdx.x * R::BPT + k;
-        if (d < (uint32_t)R::BUCKETS) st_store(st + d, st_pack(epoch, tile == 0 ? ST_INC : ST_AGG, tot[k]));
-    }
-    if (tile > 0) {
-#pragma unroll
-        for (int k = 0; k < R::BPT; k++) {
-            uint32_t d = threadIdx.x * R::BPT + k;
-            if (d < (uint32_t)R::BUCKETS) {
-                uint64_t ex = lookback(status + d, tile, 0, R::BUCKETS, epoch);
-                st_store(st + d, st_pack(epoch, ST_INC, ex + tot[k]));
-                s_goff[d] += (uint32_t)ex;
-            }
-        }
-    }
-    // local scatter into LDS in digit order
-#pragma unroll
-    for (int i = 0; i < KPT; i++) {
-        uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
-        if (off < valid_n) {
-            uint32_t dg = (key[i] >> shift) & R::MASK;
-            uint32_t pos = s_local[dg] + s_wcnt[w][dg] + rank[i];
-            s_keys[pos] = key[i];
-            s_vals[pos] = val[i];
-        }
-    }
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < valid_n; j += MQ_BLOCK) {
-        uint32_t k = s_keys[j];
-        uint32_t dg = (k >> shift) & R::MASK;
-        uint32_t g = s_goff[dg] + (j - s_local[dg]);
-        kout[g] = k;
-        vout[g] = s_vals[j];
-    }
+    sort_tile<RB, KPT>(sm, key, val, valid_n, shift, ghist, status, tile, 0, epoch, kout, vout);
 }
 
 #define MQ_RB_LIST(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
@@ -208,7 +98,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
 hipError_t launch_radix_hist(const SortSrc& src, const uint32_t* keys, uint32_t n, int rb, int passes,
                              uint32_t* hist, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    uint32_t blocks = std::min((n + MQ_BLOCK * 16 - 1) / (MQ_BLOCK * 16), 2048u);
+    uint32_t blocks = std::min((n + MQ_BLOCK * HIST_IPT - 1) / (MQ_BLOCK * HIST_IPT), 1024u);
     bool gen = keys == nullptr;
 #define MQ_H(B)                                                                                         \
     case B:                                                                                             \

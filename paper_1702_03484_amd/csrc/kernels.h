@@ -7,6 +7,8 @@
 
 namespace mq {
 
+constexpr uint32_t BLOCK_THREADS = 256;  // threads per block of every tiled kernel
+
 // ---- shuffle: LSD radix sort (k_sort.hip) --------------------------------
 // Keys of a first pass come from two int32 segments (k0[0..n0) then
 // k1[0..n1)), minus `base`; the payload is the position in that
@@ -32,17 +34,18 @@ hipError_t launch_radix_pass(int rb, int kpt, const SortSrc& src, const uint32_t
 uint32_t radix_tiles(uint32_t n, int kpt);
 
 // ---- reduce (k_reduce.hip) -------------------------------------------------
-// Segment heads of the sorted keys: seg_start[s] = first position of the
-// s-th distinct key; *nseg = number of segments.  Persistent grid.
-hipError_t launch_seg_heads(const uint32_t* keys, uint32_t n, uint32_t* seg_start, uint32_t* nseg,
-                            uint64_t* status, uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
-// Per segment: split = first position whose payload >= n_left (the first
-// RIGHT record), count = (split-start)*(end-split); off = exclusive scan of
-// the counts (saturating at 2^40-1); *total = the full sum.
-hipError_t launch_seg_count(const uint32_t* vals, uint32_t n, uint32_t n_left, const uint32_t* seg_start,
-                            const uint32_t* nseg, uint32_t max_seg, uint32_t* seg_split, uint64_t* seg_off,
-                            uint64_t* total, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch,
-                            hipStream_t stream);
+// Segment heads of the sorted records: seg_start[s] = first position of the
+// s-th distinct key, seg_split[s] = position of its first RIGHT record
+// (payload >= n_left), or its end when it has none; *nseg = segments.
+hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
+                            uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, uint64_t* status,
+                            uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
+// count[s] = (split - start) * (end - split); seg_off = exclusive scan of the
+// counts (saturating at 2^40-1); *total = the full sum.  max_seg bounds the
+// device count *nseg (sizes the persistent grid).
+hipError_t launch_seg_count(uint32_t n, const uint32_t* seg_start, const uint32_t* nseg, uint32_t max_seg,
+                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, uint64_t* status,
+                            uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
 
 struct MatArgs {
     const uint32_t* keys;      // sorted relative keys
@@ -92,6 +95,56 @@ struct LocateQuery {
     int32_t v1, v2;
 };
 hipError_t launch_locate(const LocateQuery* q_dev, int32_t nq, int64_t* out, hipStream_t stream);
+
+// ---- batched joins (k_batch.hip) -----------------------------------------
+// Every size and pointer of a batch lives in device memory (BatchHdr and
+// its BatchJoin array), so one captured graph serves every batch that uses
+// the same digit width, tile size and pass count.
+constexpr int BATCH_MAXNC = 8;  // output columns per batched join
+
+struct BatchJoin {
+    const int32_t* lkey;
+    const int32_t* rkey;
+    const int32_t* lcol[BATCH_MAXNC];
+    const int32_t* rcol[BATCH_MAXNC];
+    int32_t* out[BATCH_MAXNC];  // set on the device by the placement kernel
+    uint32_t nl, nr;            // rows of each side
+    uint32_t rec_off;           // first record slot (a multiple of the record tile)
+    uint32_t tile_off, ntiles;  // record tiles [tile_off, tile_off + ntiles)
+    int32_t key_base;
+    int32_t nvl, nvr;           // value columns of each side
+    // results (written on the device)
+    uint32_t nseg;
+    uint32_t status;            // 0 ok, 1 did not fit the output region, 2 over 2^40 rows
+    uint64_t total;             // exact |RS| (saturating at 2^40 - 1)
+    uint64_t out_word;          // word offset of column 0 in the output region
+    uint64_t col_words;         // words per column (a multiple of 64)
+    uint64_t chunk_off;         // first materialisation chunk
+};
+
+struct BatchHdr {
+    BatchJoin* joins;
+    const uint32_t* tile_join;  // record tile -> join
+    uint32_t njoins;
+    uint32_t total_tiles;
+    uint32_t passes;
+    uint32_t epoch0;            // kernels use epoch0 .. epoch0 + passes + 1
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    uint64_t* seg_off;
+    uint32_t* hist;             // [njoins][passes][2^rb]
+    uint32_t* ctr;              // tile counters: passes + 4 words, zero before the launch
+    uint64_t* status;
+    int32_t* out_base;          // output region
+    uint64_t out_cap_words;
+    uint64_t out_used_words;    // result
+    uint64_t total_chunks;      // result
+};
+
+// The whole batch in kernel launches (a graph capture records them).
+hipError_t launch_batch(const BatchHdr* hdr_dev, int rb, int kpt, int passes, hipStream_t stream);
+// Rows per materialisation chunk of the batched kernels.
+uint32_t batch_chunk_rows();
 
 // ---- utilities (k_util.hip) -----------------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream);

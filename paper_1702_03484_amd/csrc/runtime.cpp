@@ -191,7 +191,7 @@ struct SortBufs {
     uint32_t* v[2];
 };
 
-static void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt) {
+void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt) {
     rb = ctx->tune_rb;
     kpt = ctx->tune_kpt ? ctx->tune_kpt : 16;
     if (!rb) {
@@ -468,7 +468,16 @@ static mapsq_status alloc_table(Ctx* ctx, int64_t rows, int ncols, mapsq_table* 
 }
 
 mapsq_status free_table(Ctx* ctx, mapsq_table* t) {
-    if (t->owned && t->block) ctx->arena.free(size_t(t->block - 1));
+    if (t->owned && t->block) {
+        const size_t off = size_t(t->block - 1);
+        auto it = ctx->shared_refs.find(off);
+        if (it != ctx->shared_refs.end() && --it->second > 0) {
+            zero_table(t);
+            return MAPSQ_OK;
+        }
+        if (it != ctx->shared_refs.end()) ctx->shared_refs.erase(it);
+        ctx->arena.free(off);
+    }
     zero_table(t);
     return MAPSQ_OK;
 }
@@ -638,13 +647,13 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
 
 // ------------------------------------------------------------------- join ---
 
-static int col_of(const mapsq_table* t, int32_t v) {
+int col_of(const mapsq_table* t, int32_t v) {
     for (int c = 0; c < t->ncols; c++)
         if (t->var[c] == v) return c;
     return -1;
 }
 
-static mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name) {
+mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name) {
     if (!t) return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + " is null");
     if (t->ncols < 1 || t->ncols > MAPSQ_MAX_COLS)
         return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": ncols must be in [1, 16]");
@@ -754,11 +763,10 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // ReduceDuplicate: segments, counts, offsets
     if (!ctx->ensure_status(size_t(N) / 2048 + 2)) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
     ph = ctx->prof_begin(2);
-    HIPCHK(launch_seg_heads(skeys, N, seg_start, scalar32(ctx, SC_NSEG), ctx->status, counter(ctx, CT_HEADS),
-                            ctx->next_epoch(), ctx->stream));
-    HIPCHK(launch_seg_count(svals, N, nL, seg_start, scalar32(ctx, SC_NSEG), N, seg_split, seg_off,
-                            scalar64(ctx, SC_TOTAL), ctx->status, counter(ctx, CT_COUNT), ctx->next_epoch(),
-                            ctx->stream));
+    HIPCHK(launch_seg_heads(skeys, svals, N, nL, seg_start, seg_split, scalar32(ctx, SC_NSEG), ctx->status,
+                            counter(ctx, CT_HEADS), ctx->next_epoch(), ctx->stream));
+    HIPCHK(launch_seg_count(N, seg_start, scalar32(ctx, SC_NSEG), N, seg_split, seg_off, scalar64(ctx, SC_TOTAL),
+                            ctx->status, counter(ctx, CT_COUNT), ctx->next_epoch(), ctx->stream));
     uint32_t sc[4];
     {
         // bytes are filled in once the segment count is known (below)
@@ -766,9 +774,9 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     }
     if ((st = readback(ctx, scalar32(ctx, SC_NSEG), 16, sc))) return st;
     const uint32_t nseg = sc[0];
-    // heads: read 4N keys, write 4S starts; count: read 8S starts, 4S splits-worth of
-    // payload probes, write 4S splits and 8S offsets
-    if (ph >= 0) ctx->pending[ph].bytes = 4.0 * N + 24.0 * nseg;
+    // heads: read 4N keys and 4N payloads, write 4S starts and 4S splits;
+    // count: read 8S starts and 4S splits, write 8S offsets
+    if (ph >= 0) ctx->pending[ph].bytes = 8.0 * N + 28.0 * nseg;
     uint64_t total;
     std::memcpy(&total, &sc[2], 8);
     js.segments = nseg;

@@ -114,6 +114,17 @@ struct Ctx {
     std::vector<Interval> pending;
     std::vector<hipEvent_t> event_pool;
     mapsq_profile acc{};
+    // tables of one batch share an arena block: offset -> tables still alive
+    std::unordered_map<size_t, uint32_t> shared_refs;
+    // batched joins: a fixed device header (so captured graphs can be
+    // replayed), pinned staging for descriptor uploads, cached graphs
+    size_t bhdr_off = SIZE_MAX;
+    BatchHdr* bhdr = nullptr;
+    void* stage = nullptr;
+    size_t stage_bytes = 0;
+    std::map<uint64_t, hipGraphExec_t> graphs;
+    bool use_graph = true;
+    void release_graphs();
     // returns an interval handle (-1 when profiling is off)
     int prof_begin(int phase);
     void prof_end(int h, double bytes);
@@ -159,6 +170,10 @@ mapsq_status load_triples(Ctx* ctx, const int32_t* s, const int32_t* p, const in
                           uint32_t flags);
 mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
                    mapsq_table* out);
+mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_table* outs);
+mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name);
+void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt);
+int col_of(const mapsq_table* t, int32_t v);
 Block alloc_block(Ctx* ctx, size_t bytes);
 
 }  // namespace mq

@@ -1,0 +1,424 @@
+// Per-tile bodies of the join kernels, shared by the one-join kernels
+// (k_sort.hip, k_reduce.hip) and the batched ones (k_batch.hip).  A "tile"
+// is a contiguous slice of one join's records; every function works on
+// join-relative indexes and takes the first tile of its join, so that the
+// decoupled look-back of a batched launch never crosses into another join.
+#pragma once
+#include "device_common.h"
+
+namespace mq {
+
+// ----------------------------------------------------------------- sort ---
+
+template <int RB>
+struct Radix {
+    static constexpr int BUCKETS = 1 << RB;
+    static constexpr uint32_t MASK = BUCKETS - 1;
+    static constexpr int MAXP = (32 + RB - 1) / RB;
+    static constexpr int BPT = (BUCKETS + MQ_BLOCK - 1) / MQ_BLOCK;  // buckets per thread
+};
+
+template <int RB, int KPT>
+struct SortSmem {
+    static constexpr int TILE = MQ_BLOCK * KPT;
+    uint32_t keys[TILE];
+    uint32_t vals[TILE];
+    uint32_t wcnt[MQ_WAVES][Radix<RB>::BUCKETS];
+    uint32_t local[Radix<RB>::BUCKETS];
+    uint32_t goff[Radix<RB>::BUCKETS];
+    uint32_t tmp[MQ_WAVES];
+};
+
+// Exclusive scan of the BUCKETS values in LDS `in` into LDS `out` (may
+// alias).  Thread t owns the BPT consecutive buckets t*BPT...
+template <int RB>
+__device__ __forceinline__ void scan_buckets(const uint32_t* in, uint32_t* out, uint32_t* tmp) {
+    using R = Radix<RB>;
+    uint32_t loc[R::BPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < R::BPT; k++) {
+        uint32_t d = threadIdx.x * R::BPT + k;
+        loc[k] = d < (uint32_t)R::BUCKETS ? in[d] : 0u;
+        sum += loc[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(sum, tmp, &tot);
+#pragma unroll
+    for (int k = 0; k < R::BPT; k++) {
+        uint32_t d = threadIdx.x * R::BPT + k;
+        if (d < (uint32_t)R::BUCKETS) out[d] = ex;
+        ex += loc[k];
+    }
+    __syncthreads();
+}
+
+// One stable radix pass over one tile whose records are already in
+// registers (wave-striped: element i of a lane is tile position
+// (wave*KPT + i)*64 + lane; positions >= valid_n are padding).  Ranks the
+// digits, publishes the tile's digit counts, looks back over the join's
+// earlier tiles, and scatters the tile to kout/vout (join-relative).
+// `ghist` is the join's digit histogram of this pass.  Every thread of the
+// block calls it.
+template <int RB, int KPT>
+__device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t (&key)[KPT],
+                                          const uint32_t (&val)[KPT], uint32_t valid_n, int shift,
+                                          const uint32_t* __restrict__ ghist, uint64_t* __restrict__ status,
+                                          uint32_t tile, uint32_t first_tile, uint32_t epoch,
+                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+    using R = Radix<RB>;
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint32_t ln = lane();
+    for (int d = threadIdx.x; d < R::BUCKETS; d += MQ_BLOCK) {
+        sm.goff[d] = ghist[d];
+#pragma unroll
+        for (int i = 0; i < MQ_WAVES; i++) sm.wcnt[i][d] = 0;
+    }
+    __syncthreads();
+    scan_buckets<RB>(sm.goff, sm.goff, sm.tmp);
+
+    // stable rank within the wave, digit by digit through the wave counters
+    uint32_t rank[KPT];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < KPT; i++) {
+        const uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
+        const bool ok = off < valid_n;
+        const uint32_t dg = (key[i] >> shift) & R::MASK;
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < RB; b++) {
+            const uint32_t bit = (dg >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = __popcll(peers & lt);
+        const uint32_t old = ok ? sm.wcnt[w][dg] : 0u;
+        if (ok && below == 0) sm.wcnt[w][dg] = old + (uint32_t)__popcll(peers);
+        rank[i] = old + below;
+    }
+    __syncthreads();
+
+    // per digit: exclusive prefix over waves, tile total, local digit starts
+    uint32_t tot[R::BPT];
+#pragma unroll
+    for (int k = 0; k < R::BPT; k++) {
+        const uint32_t d = threadIdx.x * R::BPT + k;
+        uint32_t run = 0;
+        if (d < (uint32_t)R::BUCKETS) {
+#pragma unroll
+            for (int i = 0; i < MQ_WAVES; i++) {
+                const uint32_t c = sm.wcnt[i][d];
+                sm.wcnt[i][d] = run;
+                run += c;
+            }
+            sm.local[d] = run;
+        }
+        tot[k] = run;
+    }
+    __syncthreads();
+    scan_buckets<RB>(sm.local, sm.local, sm.tmp);
+
+    // publish this tile's digit totals, then look back for the prefix
+    uint64_t* st = status + (uint64_t)tile * R::BUCKETS;
+#pragma unroll
+    for (int k = 0; k < R::BPT; k++) {
+        const uint32_t d = threadIdx.x * R::BPT + k;
+        if (d < (uint32_t)R::BUCKETS) st_store(st + d, st_pack(epoch, tile == first_tile ? ST_INC : ST_AGG, tot[k]));
+    }
+    if (tile > first_tile) {
+#pragma unroll
+        for (int k = 0; k < R::BPT; k++) {
+            const uint32_t d = threadIdx.x * R::BPT + k;
+            if (d < (uint32_t)R::BUCKETS) {
+                const uint64_t ex = lookback(status + d, tile, first_tile, R::BUCKETS, epoch);
+                st_store(st + d, st_pack(epoch, ST_INC, ex + tot[k]));
+                sm.goff[d] += (uint32_t)ex;
+            }
+        }
+    }
+    // local scatter into LDS in digit order
+#pragma unroll
+    for (int i = 0; i < KPT; i++) {
+        const uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
+        if (off < valid_n) {
+            const uint32_t dg = (key[i] >> shift) & R::MASK;
+            const uint32_t pos = sm.local[dg] + sm.wcnt[w][dg] + rank[i];
+            sm.keys[pos] = key[i];
+            sm.vals[pos] = val[i];
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < valid_n; j += MQ_BLOCK) {
+        const uint32_t k = sm.keys[j];
+        const uint32_t dg = (k >> shift) & R::MASK;
+        const uint32_t g = sm.goff[dg] + (j - sm.local[dg]);
+        kout[g] = k;
+        vout[g] = sm.vals[j];
+    }
+}
+
+// ------------------------------------------------- segment heads/splits ---
+// Within a key every LEFT record (payload < n_left) precedes every RIGHT
+// one, so exactly one record of each segment writes its split: the first
+// RIGHT record (split = its position), or, in a segment without RIGHT
+// records, the last record (split = its position + 1).
+
+struct HeadsSmem {
+    uint32_t wtot[MQ_WAVES];
+    uint64_t excl;
+};
+
+// One tile of IPT*256 records at join-relative positions base..; returns
+// (in every thread) nothing; the tile's last-segment count goes to *nseg
+// when `last_tile`.
+template <int IPT>
+__device__ __forceinline__ void heads_tile(HeadsSmem& sm, const uint32_t* __restrict__ keys,
+                                           const uint32_t* __restrict__ vals, uint32_t n, uint32_t n_left,
+                                           uint32_t base, uint32_t tile, uint32_t first_tile, bool last_tile,
+                                           uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_split,
+                                           uint32_t* __restrict__ nseg, uint64_t* __restrict__ status,
+                                           uint32_t epoch) {
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint64_t lt = lanemask_lt();
+    uint64_t hm[IPT];
+    uint32_t wbits = 0, sbits = 0;  // per item: writes a split; is a first RIGHT record
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; i++) {
+        const uint32_t idx = base + (w * IPT + i) * MQ_WAVE + lane();
+        bool h = false;
+        if (idx < n) {
+            const uint32_t k = keys[idx];
+            const bool is_r = vals[idx] >= n_left;
+            h = idx == 0 || keys[idx - 1] != k;
+            const bool last = idx + 1 == n || keys[idx + 1] != k;
+            const bool first_r = is_r && (h || vals[idx - 1] < n_left);
+            if (first_r || (last && !is_r)) wbits |= 1u << i;
+            if (first_r) sbits |= 1u << i;
+        }
+        hm[i] = __ballot(h);
+        run += (uint32_t)__popcll(hm[i]);
+    }
+    if (lane() == 0) sm.wtot[w] = run;
+    __syncthreads();
+    uint32_t wex = 0, ttot = 0;
+#pragma unroll
+    for (int i = 0; i < MQ_WAVES; i++) {
+        if ((uint32_t)i < w) wex += sm.wtot[i];
+        ttot += sm.wtot[i];
+    }
+    if (w == 0) {
+        const uint64_t ex = tile_prefix_wave(status, tile, first_tile, epoch, ttot);
+        if (lane() == 0) {
+            sm.excl = ex;
+            if (last_tile) *nseg = (uint32_t)(ex + ttot);
+        }
+    }
+    __syncthreads();
+    uint32_t pos = (uint32_t)sm.excl + wex;  // heads before item i's lane 0
+#pragma unroll
+    for (int i = 0; i < IPT; i++) {
+        const uint32_t idx = base + (w * IPT + i) * MQ_WAVE + lane();
+        const bool h = (hm[i] >> lane()) & 1ull;
+        const uint32_t before = pos + (uint32_t)__popcll(hm[i] & lt);  // heads before this record
+        if (h) seg_start[before] = idx;
+        if ((wbits >> i) & 1u) {
+            const uint32_t sid = h ? before : before - 1u;  // record 0 is always a head
+            seg_split[sid] = ((sbits >> i) & 1u) ? idx : idx + 1;
+        }
+        pos += (uint32_t)__popcll(hm[i]);
+    }
+}
+
+// ------------------------------------------------------ count and scan ---
+
+struct CountSmem {
+    uint64_t tmp[MQ_WAVES];
+    uint64_t excl;
+};
+
+// Segments base + t*IPT ... (blocked) of one join: count cL*cR, scan into
+// exact offsets (saturating at 2^40-1); the join's last tile writes *total.
+template <int IPT>
+__device__ __forceinline__ void count_tile(CountSmem& sm, uint32_t n, uint32_t ns, uint32_t base, uint32_t tile,
+                                           uint32_t first_tile, bool last_tile,
+                                           const uint32_t* __restrict__ seg_start,
+                                           const uint32_t* __restrict__ seg_split, uint64_t* __restrict__ seg_off,
+                                           uint64_t* __restrict__ total, uint64_t* __restrict__ status,
+                                           uint32_t epoch) {
+    const uint32_t first = base + threadIdx.x * IPT;
+    uint64_t cnt[IPT];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; i++) {
+        const uint32_t s = first + i;
+        cnt[i] = 0;
+        if (s < ns) {
+            const uint32_t st = seg_start[s];
+            const uint32_t en = s + 1 < ns ? seg_start[s + 1] : n;
+            const uint32_t sp = seg_split[s];
+            const uint64_t c = (uint64_t)(sp - st) * (uint64_t)(en - sp);
+            cnt[i] = c > SAT40 ? SAT40 : c;
+        }
+        sum += cnt[i];
+    }
+    uint64_t ttot;
+    const uint64_t ex_in = block_excl_scan<uint64_t>(sum, sm.tmp, &ttot);
+    if (threadIdx.x < MQ_WAVE) {
+        const uint64_t ex = tile_prefix_wave(status, tile, first_tile, epoch, ttot);
+        if (lane() == 0) {
+            sm.excl = ex;
+            if (last_tile) *total = sat_add(ex, ttot > SAT40 ? SAT40 : ttot);
+        }
+    }
+    __syncthreads();
+    uint64_t off = sm.excl + ex_in;
+#pragma unroll
+    for (int i = 0; i < IPT; i++) {
+        const uint32_t s = first + i;
+        if (s < ns) seg_off[s] = off > SAT40 ? SAT40 : off;
+        off += cnt[i];
+    }
+}
+
+// --------------------------------------------------------- materialise ---
+// Output row j of segment s (offset off[s]) is the pair (LEFT record li,
+// RIGHT record ri) with r = j - off[s], li = r / cR, ri = r % cR.  A wave
+// owns a chunk of 64*RPT consecutive rows and finds the chunk's segments with
+// a 64-ary search (one coalesced probe and one __ballot per level); each
+// lane owns RPT consecutive rows: one division, then increments, and
+// 16-byte stores.
+
+// last s in [lo, hi] with off[s] <= j; off is non-decreasing and off[lo] <= j.
+// Wave-uniform arguments; every lane of the wave must call it.
+__device__ __forceinline__ uint32_t wave_seg_of(const uint64_t* __restrict__ off, uint32_t lo, uint32_t hi,
+                                                uint64_t j) {
+    while (hi > lo) {
+        const uint32_t step = (hi - lo + MQ_WAVE) / MQ_WAVE;  // ceil(span / 64)
+        const uint32_t pos = lo + lane() * step;
+        const bool ok = pos <= hi && off[pos] <= j;
+        const uint64_t m = __ballot(ok);  // a prefix of lanes, lane 0 always set
+        const uint32_t top = 63u - (uint32_t)__clzll(m);
+        lo = lo + top * step;
+        hi = min(hi, lo + step - 1);
+    }
+    return lo;
+}
+
+// last s in [lo, hi] with off[s] <= j (per lane)
+__device__ __forceinline__ uint32_t seg_of(const uint64_t* __restrict__ off, uint32_t lo, uint32_t hi, uint64_t j) {
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (off[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct MatJoin {
+    const uint32_t* keys;  // sorted relative keys
+    const uint32_t* vals;  // sorted payloads
+    const uint32_t* seg_start;
+    const uint32_t* seg_split;
+    const uint64_t* seg_off;
+    uint32_t ns, n, n_left;
+    int32_t key_base;
+    int32_t nl, nr;
+    const int32_t* const* lcol;
+    const int32_t* const* rcol;
+    int32_t* const* out;
+};
+
+// Materialise output rows [j0, jend) (at most 64*RPT rows, j0 a multiple of
+// 4) of one join with one wave.  The chunk is cut into RPT/4 sub-chunks of
+// 256 rows; in each, lane L writes rows 4L..4L+3, so every 16-byte store
+// instruction of the wave covers 1 KB of one column contiguously.  NC is an
+// upper bound of the column count 1 + nl + nr.
+template <int NC, int RPT>
+__device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend) {
+    const bool has_l = a.nl > 0, has_r = a.nr > 0;
+    const int nc = 1 + a.nl + a.nr;
+    const uint32_t s_first = wave_seg_of(a.seg_off, 0, a.ns - 1, j0);
+    const uint32_t s_last = wave_seg_of(a.seg_off, s_first, a.ns - 1, jend - 1);
+    uint32_t s = s_first;
+    uint32_t st = a.seg_start[s], sp = a.seg_split[s];
+    uint32_t en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
+    uint64_t so = a.seg_off[s];
+    int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
+#pragma unroll
+    for (int q = 0; q < RPT / 4; q++) {
+        const uint64_t j = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
+        if (j < jend) {
+            const uint32_t s2 = seg_of(a.seg_off, s, s_last, j);
+            if (s2 != s) {
+                s = s2;
+                st = a.seg_start[s];
+                sp = a.seg_split[s];
+                en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
+                so = a.seg_off[s];
+                key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
+            }
+            uint32_t cl = sp - st, cr = en - sp;
+            const uint64_t r = j - so;
+            uint32_t li, ri;
+            if (r < 0xffffffffull) {
+                li = (uint32_t)r / cr;
+                ri = (uint32_t)r - li * cr;
+            } else {
+                li = (uint32_t)(r / cr);
+                ri = (uint32_t)(r - (uint64_t)li * cr);
+            }
+            // a sub-chunk row may run into later segments; walk them locally
+            uint32_t ls = s, lst = st, lsp = sp;
+            int32_t lkey = key;
+            uint32_t lrow = has_l ? a.vals[st + li] : 0u;
+            int32_t v[NC][4];
+            const int nk = (int)min((uint64_t)4, jend - j);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                if (k < nk) {
+                    if (li == cl) {  // next non-empty segment
+                        do {
+                            ls++;
+                        } while (ls + 1 < a.ns && a.seg_off[ls + 1] <= j + k);
+                        lst = a.seg_start[ls];
+                        lsp = a.seg_split[ls];
+                        const uint32_t len = ls + 1 < a.ns ? a.seg_start[ls + 1] : a.n;
+                        cl = lsp - lst;
+                        cr = len - lsp;
+                        li = 0;
+                        ri = 0;
+                        lkey = (int32_t)(a.keys[lst] + (uint32_t)a.key_base);
+                        lrow = has_l ? a.vals[lst] : 0u;
+                    }
+                    const uint32_t rrow = has_r ? a.vals[lsp + ri] - a.n_left : 0u;
+                    v[0][k] = lkey;
+#pragma unroll
+                    for (int col = 1; col < NC; col++)
+                        if (col < nc)
+                            v[col][k] = col <= a.nl ? a.lcol[col - 1][lrow] : a.rcol[col - 1 - a.nl][rrow];
+                    if (++ri == cr) {
+                        ri = 0;
+                        if (++li < cl && has_l) lrow = a.vals[lst + li];
+                    }
+                }
+            }
+            if (nk == 4) {
+#pragma unroll
+                for (int col = 0; col < NC; col++)
+                    if (col < nc)
+                        *reinterpret_cast<int4*>(a.out[col] + j) = make_int4(v[col][0], v[col][1], v[col][2], v[col][3]);
+            } else {
+#pragma unroll
+                for (int col = 0; col < NC; col++)
+                    if (col < nc)
+#pragma unroll
+                        for (int k = 0; k < 4; k++)
+                            if (k < nk) a.out[col][j + k] = v[col][k];
+            }
+        }
+    }
+}
+
+}  // namespace mq

@@ -57,6 +57,10 @@ class MapSQ:
     def query(self, patterns, select=None) -> B.mapsq_table:
         return B.mapsq_query(self.ctx, patterns, select)
 
+    def join_batch(self, joins) -> list:
+        """joins: list of (left, right, key_var); one batched launch."""
+        return B.mapsq_join_batch(self.ctx, joins)
+
     def free(self, t: B.mapsq_table):
         B.mapsq_table_free(self.ctx, t)
 

@@ -14,9 +14,11 @@ from .gen import (  # noqa: F401
     store_cfg1,
     store_cfg2,
     store_cfg3,
+    query_cfg3,
     random_store,
     random_table,
     batch_cfg4,
+    cfg4_vars,
     serving_cfg5,
     var,
 )

@@ -230,28 +230,30 @@ def store_cfg2(seed: int = 1, n: int = 50_000_000, n_entities: int = 10_000_000,
 # o Zipf(1.2) over 50M; query ?x p1 ?y . ?x p2 ?z . ?x p3 c . ?w p4 ?y.
 # ---------------------------------------------------------------------------
 
-def store_cfg3(seed: int = 1, n: int = 200_000_000, n_entities: int = 50_000_000,
-               draw: int = 0) -> Workload:
-    """Store and one seeded draw of (p1, p2, p3, p4, c).
-
-    p1..p4 are distinct predicates among the 8 most frequent; c is one of the
-    50 most frequent objects of p3.  ``draw`` selects the draw; callers that
-    need an output size inside a band try successive draws.
-    """
+def store_cfg3(seed: int = 1, n: int = 200_000_000, n_entities: int = 50_000_000) -> Workload:
+    """Store of config 3 (no query yet; see ``query_cfg3``)."""
     npred = 64
     cfg = 3000 + seed
     s, p, o = _store_zipf(cfg, n, n_entities, npred, 1.0, None, 1.2, s_uniform=True)
-    r = _rng(cfg, 1, draw)
-    preds = n_entities + r.permutation(8)[:4]
+    return Workload("cfg3", s, p, o, n_entities, npred, meta={"seed": seed})
+
+
+def query_cfg3(w: Workload, draw: int = 0) -> list:
+    """One seeded draw of ``?x p1 ?y . ?x p2 ?z . ?x p3 c . ?w p4 ?y``.
+
+    p1..p4 are distinct predicates among the 8 most frequent; c is an object
+    of p3 whose frequency rank under p3 is drawn uniformly from [50, 1000)
+    (the hottest objects make the output billions of rows).  Callers that
+    need the output inside a size band try successive draws.
+    """
+    r = _rng(3000 + w.meta["seed"], 1, draw)
+    preds = w.n_entities + r.permutation(8)[:4]
     p1, p2, p3, p4 = (int(v) for v in preds)
-    objs = o[p == p3]
-    vals, cnts = np.unique(objs, return_counts=True)
-    top = vals[np.argsort(-cnts, kind="stable")[:50]]
-    c = int(top[int(r.integers(0, top.size))])
-    x, y, z, w = var(0), var(1), var(2), var(3)
-    return Workload("cfg3", s, p, o, n_entities, npred,
-                    patterns=[(x, p1, y), (x, p2, z), (x, p3, c), (w, p4, y)],
-                    meta={"p": [p1, p2, p3, p4], "c": c, "seed": seed, "draw": draw})
+    vals, cnts = np.unique(w.o[w.p == p3], return_counts=True)
+    ranked = vals[np.argsort(-cnts, kind="stable")[:1000]]
+    c = int(ranked[int(r.integers(50, ranked.size))])
+    x, y, z, u = var(0), var(1), var(2), var(3)
+    return [(x, p1, y), (x, p2, z), (x, p3, c), (u, p4, y)]
 
 
 # ---------------------------------------------------------------------------
@@ -281,8 +283,87 @@ def random_table(seed: int, nrows: int, key_card: int, nvals: int, key_ids: np.n
     return cols
 
 
-def batch_cfg4(*a, **k):  # filled in with the batched executor
-    raise NotImplementedError
+def _loguniform(r, lo, hi):
+    return int(np.exp(r.uniform(np.log(lo), np.log(hi))))
+
+
+def _distinct_ids(r, k):
+    ids = np.unique(r.integers(0, ID_LIMIT, size=int(k * 1.1) + 16, dtype=np.int64))
+    while ids.size < k:
+        ids = np.unique(np.concatenate([ids, r.integers(0, ID_LIMIT, size=k, dtype=np.int64)]))
+    return r.permutation(ids[:k]).astype(np.int32)
+
+
+def batch_cfg4(seed: int = 1, n_sub: int = 512, size_lo: float = 1e3, size_hi: float = 1e7,
+               card_lo: float = 1e2, card_hi: float = 1e6, cap: float = 2.0 ** 24) -> list:
+    """Config 4: ``n_sub`` independent subqueries, half of them one join
+    (T1 JOIN T2 on variable 0), half a chain of two (then JOIN T3 on T2's
+    first value column, variable 20).  Every table has log-uniform
+    [size_lo, size_hi] rows, 1-3 value columns uniform in [0, 2^31-1), and
+    keys drawn uniformly from a seeded set of K distinct IDs, K log-uniform
+    in [card_lo, card_hi].  A join is redrawn while |L|*|R|/K exceeds ``cap``
+    (the expected output); for a chain the cap also holds for the second join.
+    Variables: T1 = [0, 10..], T2 = [0, 20, 21..], T3 = [20, 30..].
+
+    Returns a list of dicts with 'kind' (2 or 3 patterns) and 'T1', 'T2'
+    (and 'T3') as lists of int32 columns (key first).  Sizes are drawn first
+    and the columns afterwards, one seeded stream per table, in parallel.
+    """
+    r = _rng(4000 + seed, 1)
+    specs = []
+    for q in range(n_sub):
+        kind = 2 if q % 2 == 0 else 3
+        while True:
+            n1, n2 = _loguniform(r, size_lo, size_hi), _loguniform(r, size_lo, size_hi)
+            k1 = _loguniform(r, card_lo, card_hi)
+            v1, v2 = int(r.integers(1, 4)), int(r.integers(1, 4))
+            est = n1 * n2 / k1
+            if est > cap:
+                continue
+            if kind == 3:
+                n3 = _loguniform(r, size_lo, size_hi)
+                k2 = _loguniform(r, card_lo, card_hi)
+                v3 = int(r.integers(1, 4))
+                if est * n3 / k2 > cap:
+                    continue
+            break
+        spec = {"kind": kind, "n1": n1, "n2": n2, "k1": k1, "v1": v1, "v2": v2}
+        if kind == 3:
+            spec.update({"n3": n3, "k2": k2, "v3": v3})
+        specs.append(spec)
+
+    def build(q):
+        sp = specs[q]
+        rq = _rng(4000 + seed, 2, q)
+        keys1 = _distinct_ids(rq, sp["k1"])
+        keys2 = _distinct_ids(rq, sp["k2"]) if sp["kind"] == 3 else None
+
+        def table(n, keyset, nv, first_from=None):
+            cols = [keyset[rq.integers(0, keyset.size, size=n)]]
+            for c in range(nv):
+                if c == 0 and first_from is not None:
+                    cols.append(first_from[rq.integers(0, first_from.size, size=n)])
+                else:
+                    cols.append(rq.integers(0, ID_LIMIT, size=n, dtype=np.int64).astype(np.int32))
+            return cols
+
+        out = {"kind": sp["kind"], "T1": table(sp["n1"], keys1, sp["v1"]),
+               "T2": table(sp["n2"], keys1, sp["v2"], first_from=keys2)}
+        if sp["kind"] == 3:
+            out["T3"] = table(sp["n3"], keys2, sp["v3"])
+        return out
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        return list(ex.map(build, range(n_sub)))
+
+
+def cfg4_vars(sub: dict):
+    """Variables of the tables of one config-4 subquery."""
+    v = {"T1": [0] + [10 + c for c in range(len(sub["T1"]) - 1)],
+         "T2": [0] + [20 + c for c in range(len(sub["T2"]) - 1)]}
+    if "T3" in sub:
+        v["T3"] = [20] + [30 + c for c in range(len(sub["T3"]) - 1)]
+    return v
 
 
 def serving_cfg5(*a, **k):  # filled in with the serving loop

@@ -1,0 +1,142 @@
+"""GPU parity of mapsq_join_batch: every join of a batch equals the oracle
+(as a bag) and the plain mapsq_join (row for row), with and without graph
+capture, on replays, and for joins that fall back to the plain path."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.core import Table
+from paper_1702_03484_amd import binding as B
+from synth import random_table
+from tests.conftest import announce
+from tests.gpu_util import assert_same_bag, host_table
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
+def make_batch(sess, seed, count, max_rows=300_000):
+    """Joins of uneven sizes (log-uniform), 0-3 value columns a side, key
+    cardinality log-uniform; some empty sides and disjoint key sets."""
+    r = np.random.default_rng(seed)
+    joins, host = [], []
+    for i in range(count):
+        nl = int(np.exp(r.uniform(0, np.log(max_rows))))
+        nr = int(np.exp(r.uniform(0, np.log(max_rows))))
+        if i % 13 == 5:
+            nl = 0
+        card = int(np.exp(r.uniform(0, np.log(50_000))))
+        card = max(card, nl * nr // 2_000_000 + 1)  # expected output at most ~2M rows
+        vl, vr = int(r.integers(0, 4)), int(r.integers(0, 4))
+        keys = np.unique(r.integers(0, (1 << 31) - 1, size=card * 2))[:card]
+        rkeys = keys if i % 11 != 7 else keys + 1  # disjoint now and then
+        lc = random_table(seed * 1000 + 2 * i, nl, card, vl, key_ids=keys)
+        rc = random_table(seed * 1000 + 2 * i + 1, nr, card, vr, key_ids=rkeys)
+        lv = [0] + [10 + k for k in range(vl)]
+        rv = [0] + [20 + k for k in range(vr)]
+        km = int(max(keys.max(), rkeys.max())) if i % 2 else -1
+        L = sess.table(lv, [dev(c) for c in lc], key_max=km)
+        R = sess.table(rv, [dev(c) for c in rc], key_max=km)
+        joins.append((L, R, 0))
+        host.append((Table(lv, lc), Table(rv, rc)))
+    return joins, host
+
+
+def check_against_plain_and_oracle(sess, joins, host, outs):
+    for i, ((L, R, k), (hl, hr), t) in enumerate(zip(joins, host, outs)):
+        exp = oracle.join(hl, hr, 0)
+        assert t.vars == exp.vars, i
+        got = host_table(sess, t)
+        assert_same_bag(got, exp)
+        p = sess.join(L, R, k)
+        pc = sess.to_numpy(p)
+        assert all(np.array_equal(a, b) for a, b in zip(got.cols, pc)), f"join {i}: row order differs from mapsq_join"
+        sess.free(p)
+
+
+def test_batch_matches_oracle_and_plain(sess):
+    announce("batch of 40 uneven joins (graph)")
+    joins, host = make_batch(sess, 1, 40)
+    outs = sess.join_batch(joins)
+    check_against_plain_and_oracle(sess, joins, host, outs)
+    for t in outs:
+        sess.free(t)
+
+
+def test_batch_graph_replay_and_direct_launch_agree(sess, monkeypatch):
+    announce("batch: graph replays and direct launches agree")
+    joins, host = make_batch(sess, 2, 25, max_rows=100_000)
+    runs = []
+    for mode in ["1", "1", "0", "1"]:
+        monkeypatch.setenv("MAPSQ_BATCH_GRAPH", mode)
+        outs = sess.join_batch(joins)
+        runs.append([sess.to_numpy(t) for t in outs])
+        for t in outs:
+            sess.free(t)
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    outs = sess.join_batch(joins)
+    check_against_plain_and_oracle(sess, joins, host, outs)
+    for t in outs:
+        sess.free(t)
+
+
+def test_batch_fallbacks_and_freeing(sess):
+    announce("batch: plain-path fallbacks, shared block release")
+    free0 = B.mapsq_arena_free_bytes(sess.ctx)[0]
+    keys = np.arange(1000, 1300)
+    lc = random_table(70, 5000, 300, 2, key_ids=keys, val_hi=7)
+    rc = random_table(71, 3000, 300, 2, key_ids=keys, val_hi=7)
+    L = sess.table([0, 1, 2], [dev(c) for c in lc], key_max=1299)
+    R = sess.table([0, 3, 1], [dev(c) for c in rc], key_max=1299)   # shares variable 1: plain path
+    wide_l = random_table(72, 4000, 300, 5, key_ids=keys)
+    wide_r = random_table(73, 4000, 300, 4, key_ids=keys)
+    WL = sess.table([0] + list(range(30, 35)), [dev(c) for c in wide_l])
+    WR = sess.table([0] + list(range(40, 44)), [dev(c) for c in wide_r])  # 10 columns: plain path
+    R2 = sess.table([0, 9], [dev(rc[0]), dev(rc[1])], key_max=1299)
+    joins = [(L, R, 0), (WL, WR, 0), (L, R2, 0)]
+    outs = sess.join_batch(joins)
+    exps = [oracle.join(Table([0, 1, 2], lc), Table([0, 3, 1], rc), 0),
+            oracle.join(Table([0] + list(range(30, 35)), wide_l), Table([0] + list(range(40, 44)), wide_r), 0),
+            oracle.join(Table([0, 1, 2], lc), Table([0, 9], rc[:2]), 0)]
+    for t, e in zip(outs, exps):
+        assert t.vars == e.vars
+        assert_same_bag(host_table(sess, t), e)
+    for t in outs:
+        sess.free(t)
+    torch.cuda.synchronize()
+    # status words may have grown once; everything else is returned
+    assert B.mapsq_arena_free_bytes(sess.ctx)[0] >= free0 - (64 << 20)
+
+
+def test_batch_chain(sess):
+    announce("batch: chained second stage keyed on a value column of the first")
+    r = np.random.default_rng(5)
+    k1 = np.unique(r.integers(0, 1 << 30, 4000))[:3000]
+    k2 = np.unique(r.integers(0, 1 << 30, 3000))[:2000]
+    stage1, hosts = [], []
+    for i in range(12):
+        t1 = random_table(100 + i, int(r.integers(100, 50_000)), 3000, 1, key_ids=k1)
+        n2 = int(r.integers(100, 50_000))
+        t2 = [k1[r.integers(0, k1.size, n2)].astype(np.int32), k2[r.integers(0, k2.size, n2)].astype(np.int32)]
+        t3 = random_table(300 + i, int(r.integers(100, 4_000)), 2000, 2, key_ids=k2)
+        A = sess.table([0, 1], [dev(c) for c in t1], key_max=int(k1.max()))
+        Bt = sess.table([0, 2], [dev(c) for c in t2], key_max=int(max(k1.max(), k2.max())))
+        C = sess.table([2, 3, 4], [dev(c) for c in t3], key_max=int(k2.max()))
+        stage1.append((A, Bt, 0))
+        hosts.append((Table([0, 1], t1), Table([0, 2], t2), Table([2, 3, 4], t3), C))
+    outs1 = sess.join_batch(stage1)
+    stage2 = [(o, h[3], 2) for o, h in zip(outs1, hosts)]
+    outs2 = sess.join_batch(stage2)
+    for o2, (a, b, c, _) in zip(outs2, hosts):
+        exp = oracle.join(oracle.join(a, b, 0), c, 2)
+        assert_same_bag(host_table(sess, o2), exp)
+    for t in outs1 + outs2:
+        sess.free(t)
