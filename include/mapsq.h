@@ -134,6 +134,13 @@ mapsq_status mapsq_load_triples(mapsq_ctx* ctx, const int32_t* s, const int32_t*
 
 mapsq_status mapsq_store_info(mapsq_ctx* ctx, mapsq_store_facts* out);
 
+/* Statistics of one predicate of the loaded store (computed at load time
+ * when the store has at most 4096 distinct predicates): its triples and its
+ * distinct subjects and objects.  A predicate absent from the store gives
+ * zeros.  UNSUPPORTED when the statistics were not computed. */
+mapsq_status mapsq_predicate_stats(mapsq_ctx* ctx, int32_t predicate, int64_t* triples, int64_t* distinct_s,
+                                   int64_t* distinct_o);
+
 /* Map (Section 1 partial matches; Algorithm 1's Map): the table of matches
  * of one triple pattern, key variable `key_var` first (-1: no key, columns
  * in first-appearance order over s, p, o), then the other variables in
@@ -186,6 +193,36 @@ typedef struct {
  * freed.  On error every outs[i] is zeroed and nothing stays allocated.
  * The caller's tables must stay valid until the call returns. */
 mapsq_status mapsq_join_batch(mapsq_ctx* ctx, const mapsq_join_desc* joins, int32_t n, mapsq_table* outs);
+
+/* ---- serving: continuous batching over the resident store -------------
+ * Queries are queued by mapsq_submit.  Each mapsq_serve_step is one
+ * scheduling round: waiting queries get exact pattern sizes from the index
+ * ranges and a predicted intermediate-byte cost (greedy plan, join sizes
+ * estimated from per-predicate distinct counts); queries are admitted in
+ * arrival order while the predicted bytes of all admitted queries stay
+ * within the budget (a query predicted above the whole budget fails with
+ * TOO_LARGE); newly admitted queries map their patterns; then the next join
+ * step of every admitted query runs in one batched launch.  A query that
+ * arrives while others are in flight joins the next round.  Each result is
+ * exactly what mapsq_query returns for the query alone.  Serving calls use
+ * the context like every other call: one thread at a time. */
+
+/* Budget of predicted intermediate bytes (0: 60% of the arena's free space
+ * at the first round) and the most queries in flight (0: 256). */
+mapsq_status mapsq_serve_config(mapsq_ctx* ctx, uint64_t budget_bytes, int32_t max_active);
+
+/* Queue a query (arguments as mapsq_query); *ticket identifies it. */
+mapsq_status mapsq_submit(mapsq_ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* select_vars,
+                          int32_t nselect, uint64_t* ticket);
+
+/* One scheduling round (synchronises the stream once per batched launch);
+ * reports the queries in flight and still waiting. */
+mapsq_status mapsq_serve_step(mapsq_ctx* ctx, int32_t* active, int32_t* waiting);
+
+/* *done = 0: still pending.  *done = 1 and OK: the result moves to *out (an
+ * owned table or a view) and the ticket is retired.  *done = 1 and an error
+ * status: the query failed with that status and the ticket is retired. */
+mapsq_status mapsq_poll(mapsq_ctx* ctx, uint64_t ticket, int32_t* done, mapsq_table* out);
 
 /* Release an owned table (views are left alone); the struct is zeroed. */
 mapsq_status mapsq_table_free(mapsq_ctx* ctx, mapsq_table* t);

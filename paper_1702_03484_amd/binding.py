@@ -112,6 +112,9 @@ _SIGS = [
     ("mapsq_last_error", ctypes.c_char_p, [_P]),
     ("mapsq_load_triples", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_uint32]),
     ("mapsq_store_info", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_store_facts)]),
+    ("mapsq_predicate_stats", ctypes.c_int32,
+     [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+      ctypes.POINTER(ctypes.c_int64)]),
     ("mapsq_map_pattern", ctypes.c_int32,
      [_P, ctypes.POINTER(mapsq_pattern), ctypes.c_int32, ctypes.POINTER(mapsq_table)]),
     ("mapsq_join", ctypes.c_int32,
@@ -121,6 +124,12 @@ _SIGS = [
       ctypes.POINTER(mapsq_table)]),
     ("mapsq_join_batch", ctypes.c_int32,
      [_P, ctypes.POINTER(mapsq_join_desc), ctypes.c_int32, ctypes.POINTER(mapsq_table)]),
+    ("mapsq_serve_config", ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_int32]),
+    ("mapsq_submit", ctypes.c_int32,
+     [_P, ctypes.POINTER(mapsq_pattern), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+      ctypes.POINTER(ctypes.c_uint64)]),
+    ("mapsq_serve_step", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    ("mapsq_poll", ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(mapsq_table)]),
     ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
     ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
     ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
@@ -179,6 +188,13 @@ def mapsq_store_info(ctx) -> mapsq_store_facts:
     return out
 
 
+def mapsq_predicate_stats(ctx, predicate: int):
+    """(triples, distinct subjects, distinct objects) of one predicate."""
+    a, s, o = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(ctx, lib().mapsq_predicate_stats(ctx, predicate, ctypes.byref(a), ctypes.byref(s), ctypes.byref(o)))
+    return int(a.value), int(s.value), int(o.value)
+
+
 def mapsq_map_pattern(ctx, pattern, key_var: int = -1) -> mapsq_table:
     pat = mapsq_pattern(*pattern)
     out = mapsq_table()
@@ -212,6 +228,33 @@ def mapsq_join_batch(ctx, joins) -> list:
     outs = (mapsq_table * max(1, n))()
     _check(ctx, lib().mapsq_join_batch(ctx, descs, n, outs))
     return [outs[i] for i in range(n)]
+
+
+def mapsq_serve_config(ctx, budget_bytes: int = 0, max_active: int = 0):
+    _check(ctx, lib().mapsq_serve_config(ctx, budget_bytes, max_active))
+
+
+def mapsq_submit(ctx, patterns, select=None) -> int:
+    arr = (mapsq_pattern * len(patterns))(*[mapsq_pattern(*p) for p in patterns])
+    sel = list(select or [])
+    sarr = (ctypes.c_int32 * max(1, len(sel)))(*sel)
+    t = ctypes.c_uint64()
+    _check(ctx, lib().mapsq_submit(ctx, arr, len(patterns), sarr, len(sel), ctypes.byref(t)))
+    return int(t.value)
+
+
+def mapsq_serve_step(ctx):
+    a, w = ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, lib().mapsq_serve_step(ctx, ctypes.byref(a), ctypes.byref(w)))
+    return int(a.value), int(w.value)
+
+
+def mapsq_poll(ctx, ticket: int):
+    """(done, table or None); raises MapSQError if the query failed."""
+    d = ctypes.c_int32()
+    out = mapsq_table()
+    _check(ctx, lib().mapsq_poll(ctx, ticket, ctypes.byref(d), ctypes.byref(out)))
+    return bool(d.value), (out if d.value else None)
 
 
 def mapsq_table_free(ctx, t: mapsq_table):

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmapsq.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["k_sort.hip", "k_reduce.hip", "k_map.hip", "k_util.hip", "k_batch.hip", "runtime.cpp", "planner.cpp",
-           "batch.cpp", "capi.cpp"]
+           "batch.cpp", "serve.cpp", "capi.cpp"]
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
     # packed fp32 instructions are kept out of every kernel

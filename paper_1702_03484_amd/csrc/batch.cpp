@@ -24,7 +24,7 @@ void Ctx::release_graphs() {
     graphs.clear();
 }
 
-static bool ensure_stage(Ctx* ctx, size_t bytes) {
+bool ensure_stage(Ctx* ctx, size_t bytes) {
     if (bytes <= ctx->stage_bytes) return true;
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     ctx->stage = nullptr;
@@ -45,9 +45,12 @@ struct Plan {
 };
 }  // namespace
 
-mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_table* outs) {
+mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_table* outs,
+                        mapsq_status* per_join) {
     if (n < 0 || (n > 0 && (!d || !outs))) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "bad batch arguments");
     for (int i = 0; i < n; i++) std::memset(&outs[i], 0, sizeof(mapsq_table));
+    if (per_join)
+        for (int i = 0; i < n; i++) per_join[i] = MAPSQ_OK;
     if (n == 0) return MAPSQ_OK;
     std::vector<Plan> plan(n);
     int32_t kmax = 0;
@@ -244,14 +247,17 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
             ctx->prof_end(ph, bytes);
         }
         for (int i = 0; i < n; i++)
-            if (plan[i].batched && !plan[i].empty && J[i].status == 2)
-                return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join " + std::to_string(i) + ": over 2^40 rows");
+            if (plan[i].batched && !plan[i].empty && J[i].status == 2) {
+                if (!per_join) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join " + std::to_string(i) + ": over 2^40 rows");
+                per_join[i] = MAPSQ_ERR_TOO_LARGE;
+                done[i] = true;
+            }
         // results in the output region share its block
         const size_t used = size_t(Hr.out_used_words) * 4;
         uint32_t refs = 0;
         for (int i = 0; i < n; i++) {
             const BatchJoin& b = J[i];
-            if (!plan[i].batched || plan[i].empty) continue;
+            if (!plan[i].batched || plan[i].empty || done[i]) continue;
             if (b.status != 0) continue;
             mapsq_table& t = res[i];
             meta(i, &t);
@@ -289,7 +295,9 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         mapsq_status st = join_tables(ctx, d[i].left, d[i].right, d[i].key_var, &res[i]);
         if (st) {
             std::string msg = ctx->err;
-            return fail_all(st, "join " + std::to_string(i) + ": " + msg);
+            if (!per_join) return fail_all(st, "join " + std::to_string(i) + ": " + msg);
+            per_join[i] = st;
+            std::memset(&res[i], 0, sizeof(mapsq_table));
         }
         done[i] = true;
     }

@@ -1,6 +1,7 @@
 // extern "C" boundary of libmapsq.so (declared in include/mapsq.h): checks
 // arguments, selects the context's device for the duration of the call and
 // keeps C++ exceptions from crossing the ABI.
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -79,6 +80,7 @@ mapsq_status mapsq_destroy(mapsq_ctx* c) {
     {
         DeviceGuard g(c->impl.device);
         (void)hipStreamSynchronize(c->impl.stream);
+        mq::destroy_server(&c->impl);
         c->impl.prof_release();
         c->impl.release_graphs();
         if (c->impl.stage) (void)hipHostFree(c->impl.stage);
@@ -112,6 +114,24 @@ mapsq_status mapsq_store_info(mapsq_ctx* c, mapsq_store_facts* out) {
     });
 }
 
+mapsq_status mapsq_predicate_stats(mapsq_ctx* c, int32_t predicate, int64_t* triples, int64_t* distinct_s,
+                                   int64_t* distinct_o) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!triples || !distinct_s || !distinct_o) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        *triples = *distinct_s = *distinct_o = 0;
+        const mq::Store& S = ctx->store;
+        if (!S.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
+        if (S.pred_ds.size() != S.preds.size()) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "no predicate statistics");
+        auto it = std::lower_bound(S.preds.begin(), S.preds.end(), predicate);
+        if (it == S.preds.end() || *it != predicate) return (mapsq_status)MAPSQ_OK;
+        const size_t i = size_t(it - S.preds.begin());
+        *triples = S.pred_off[i + 1] - S.pred_off[i];
+        *distinct_s = S.pred_ds[i];
+        *distinct_o = S.pred_do[i];
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
 mapsq_status mapsq_map_pattern(mapsq_ctx* c, const mapsq_pattern* pattern, int32_t key_var, mapsq_table* out) {
     return guarded(c, [&](Ctx* ctx) {
         if (!out || !pattern) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null argument");
@@ -137,6 +157,23 @@ mapsq_status mapsq_query(mapsq_ctx* c, const mapsq_pattern* pats, int32_t npats,
 
 mapsq_status mapsq_join_batch(mapsq_ctx* c, const mapsq_join_desc* joins, int32_t n, mapsq_table* outs) {
     return guarded(c, [&](Ctx* ctx) { return mq::join_batch(ctx, joins, n, outs); });
+}
+
+mapsq_status mapsq_serve_config(mapsq_ctx* c, uint64_t budget_bytes, int32_t max_active) {
+    return guarded(c, [&](Ctx* ctx) { return mq::serve_config(ctx, budget_bytes, max_active); });
+}
+
+mapsq_status mapsq_submit(mapsq_ctx* c, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
+                          uint64_t* ticket) {
+    return guarded(c, [&](Ctx* ctx) { return mq::submit(ctx, pats, npats, sel, nsel, ticket); });
+}
+
+mapsq_status mapsq_serve_step(mapsq_ctx* c, int32_t* active, int32_t* waiting) {
+    return guarded(c, [&](Ctx* ctx) { return mq::serve_step(ctx, active, waiting); });
+}
+
+mapsq_status mapsq_poll(mapsq_ctx* c, uint64_t ticket, int32_t* done, mapsq_table* out) {
+    return guarded(c, [&](Ctx* ctx) { return mq::poll(ctx, ticket, done, out); });
 }
 
 mapsq_status mapsq_table_free(mapsq_ctx* c, mapsq_table* t) {

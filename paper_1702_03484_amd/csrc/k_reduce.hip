@@ -129,7 +129,7 @@ hipError_t launch_materialize(const MatArgs& a, hipStream_t stream) {
 #define MQ_M(C)                                                                                  \
     case C: {                                                                                    \
         uint64_t chunks = (rows + MatShape<C>::WROWS - 1) / MatShape<C>::WROWS;                  \
-        uint32_t blocks = (uint32_t)std::min<uint64_t>((chunks + MQ_WAVES - 1) / MQ_WAVES, 256ull * 8); \
+        uint32_t blocks = (uint32_t)std::min<uint64_t>((chunks + MQ_WAVES - 1) / MQ_WAVES, 256ull * 32); \
         materialize_kernel<C><<<blocks, MQ_BLOCK, 0, stream>>>(a);                               \
     } break;
     switch (nc) {

@@ -98,7 +98,9 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
 hipError_t launch_radix_hist(const SortSrc& src, const uint32_t* keys, uint32_t n, int rb, int passes,
                              uint32_t* hist, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    uint32_t blocks = std::min((n + MQ_BLOCK * HIST_IPT - 1) / (MQ_BLOCK * HIST_IPT), 1024u);
+    // every block adds passes * 2^rb counters to the global histogram with
+    // device-wide atomics; a small grid keeps that traffic low
+    uint32_t blocks = std::min((n + MQ_BLOCK * HIST_IPT - 1) / (MQ_BLOCK * HIST_IPT), 128u);
     bool gen = keys == nullptr;
 #define MQ_H(B)                                                                                         \
     case B:                                                                                             \

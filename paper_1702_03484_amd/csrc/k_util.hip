@@ -114,4 +114,22 @@ hipError_t launch_check_ids(const int32_t* a, uint64_t n, uint32_t* bad, hipStre
     return hipGetLastError();
 }
 
+// Number of runs of equal values in x[lo, hi) (a sorted range): one per
+// position i with i == lo or x[i] != x[i-1].  Adds the count to *out with one
+// atomic per wave.
+__global__ void count_runs_kernel(const int32_t* __restrict__ x, uint64_t lo, uint64_t hi,
+                                  unsigned long long* __restrict__ out) {
+    uint32_t c = 0;
+    for (uint64_t i = lo + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < hi; i += (uint64_t)gridDim.x * blockDim.x)
+        c += (i == lo || x[i] != x[i - 1]) ? 1u : 0u;
+    c = wave_sum(c);
+    if (mq::lane() == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+hipError_t launch_count_runs(const int32_t* x, uint64_t lo, uint64_t hi, unsigned long long* out,
+                             hipStream_t stream) {
+    if (hi <= lo) return hipSuccess;
+    count_runs_kernel<<<grid_for(hi - lo, 256 * 16, 512), 256, 0, stream>>>(x, lo, hi, out);
+    return hipGetLastError();
+}
+
 }  // namespace mq

@@ -164,6 +164,9 @@ hipError_t launch_run_bounds(const int32_t* v, uint64_t n, int32_t* out_val, int
 // i differs from triple i-1 (or i == 0), else 0.
 hipError_t launch_dup_flags(const int32_t* p, const int32_t* s, const int32_t* o, const uint32_t* perm,
                             uint64_t n, int32_t* keep, hipStream_t stream);
+// Runs of equal values in the sorted range x[lo, hi), added to *out.
+hipError_t launch_count_runs(const int32_t* x, uint64_t lo, uint64_t hi, unsigned long long* out,
+                             hipStream_t stream);
 // IDs outside [0, 2^31-1): count into *bad.
 hipError_t launch_check_ids(const int32_t* a, uint64_t n, uint32_t* bad, hipStream_t stream);
 

@@ -20,6 +20,50 @@ static bool binds(const mapsq_table& t, int32_t v) {
     return false;
 }
 
+// Greedy join order (the host's share of the CPU/GPU split): start from the
+// smallest table, then repeatedly take the smallest table that shares a
+// variable with the bound ones (ties: lowest index), joining on the first
+// shared variable in the query's first-appearance order; a table sharing
+// nothing joins by cross product.
+void greedy_plan(const std::vector<std::vector<int32_t>>& vars, const std::vector<int64_t>& rows,
+                 const std::vector<int32_t>& qvars, int* start, std::vector<PlanStep>* steps) {
+    const int m = (int)vars.size();
+    *start = 0;
+    for (int i = 1; i < m; i++)
+        if (rows[i] < rows[*start]) *start = i;
+    std::vector<int32_t> bound = vars[*start];
+    std::vector<bool> used(m, false);
+    used[*start] = true;
+    steps->clear();
+    auto has = [](const std::vector<int32_t>& vs, int32_t v) { return std::find(vs.begin(), vs.end(), v) != vs.end(); };
+    for (int step = 1; step < m; step++) {
+        int pick = -1;
+        bool connected = false;
+        for (int i = 0; i < m; i++) {
+            if (used[i]) continue;
+            bool con = false;
+            for (int32_t v : vars[i]) con = con || has(bound, v);
+            if (pick < 0 || (con && !connected) || (con == connected && rows[i] < rows[pick])) {
+                pick = i;
+                connected = con;
+            }
+        }
+        PlanStep ps{pick, -1, !connected};
+        if (connected)
+            for (int32_t v : qvars)
+                if (has(bound, v) && has(vars[pick], v)) {
+                    ps.key = v;
+                    break;
+                }
+        for (int32_t v : vars[pick])
+            if (!has(bound, v)) bound.push_back(v);
+        used[pick] = true;
+        steps->push_back(ps);
+    }
+}
+
+mapsq_status cross_join(Ctx* ctx, const mapsq_table& a, const mapsq_table& b, mapsq_table* out);
+
 // Table with one extra all-zero column bound to CROSS_VAR (owned scratch).
 static mapsq_status with_zero_key(Ctx* ctx, const mapsq_table& t, mapsq_table* out, Block* zeros) {
     if (t.ncols >= MAPSQ_MAX_COLS) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 16 columns");
@@ -38,14 +82,52 @@ static mapsq_status with_zero_key(Ctx* ctx, const mapsq_table& t, mapsq_table* o
     return MAPSQ_OK;
 }
 
-mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
-                   mapsq_table* out) {
-    std::memset(out, 0, sizeof(*out));
+// Cartesian product as a join on a constant key (one segment); the key
+// column is dropped from the result.
+mapsq_status cross_join(Ctx* ctx, const mapsq_table& cur, const mapsq_table& other, mapsq_table* nxt) {
+    mapsq_table a{}, b{};
+    Block za, zb;
+    mapsq_status st = with_zero_key(ctx, cur, &a, &za);
+    if (!st) st = with_zero_key(ctx, other, &b, &zb);
+    if (!st) st = join_tables(ctx, &a, &b, CROSS_VAR, nxt);
+    if (st) return st;
+    for (int c = 1; c < nxt->ncols; c++) {
+        nxt->var[c - 1] = nxt->var[c];
+        nxt->col[c - 1] = nxt->col[c];
+    }
+    nxt->ncols -= 1;
+    nxt->col[nxt->ncols] = nullptr;
+    nxt->key_max = (cur.key_max >= 0 && other.key_max >= 0) ? std::max(cur.key_max, other.key_max) : -1;
+    return MAPSQ_OK;
+}
+
+// The columns of `cur` picked in the order of `want` (a bag projection; the
+// table keeps its block).
+mapsq_table project_table(const mapsq_table& cur, const std::vector<int32_t>& want) {
+    mapsq_table res = cur;
+    for (size_t i = 0; i < want.size(); i++) {
+        int c = -1;
+        for (int k = 0; k < cur.ncols; k++)
+            if (cur.var[k] == want[i]) c = k;
+        res.var[i] = want[i];
+        res.col[i] = cur.col[c];
+    }
+    for (size_t i = want.size(); i < MAPSQ_MAX_COLS; i++) {
+        res.var[i] = 0;
+        res.col[i] = nullptr;
+    }
+    res.ncols = (int32_t)want.size();
+    return res;
+}
+
+// Query variables (first-appearance order) and the projection list; checks
+// the patterns and the SELECT list.
+mapsq_status query_vars(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
+                        std::vector<int32_t>* qvars, std::vector<int32_t>* want) {
     if (!pats || npats < 1 || npats > 64) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "npats must be in [1, 64]");
     if (nsel < 0 || (nsel > 0 && !sel)) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "bad select list");
-    if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
-    // query variables in first-appearance order
-    std::vector<int32_t> qvars;
+    qvars->clear();
+    want->clear();
     for (int i = 0; i < npats; i++) {
         const int32_t t[3] = {pats[i].s, pats[i].p, pats[i].o};
         bool any = false;
@@ -53,23 +135,32 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
             if (t[k] < 0) {
                 any = true;
                 int32_t v = -t[k] - 1;
-                if (std::find(qvars.begin(), qvars.end(), v) == qvars.end()) qvars.push_back(v);
+                if (std::find(qvars->begin(), qvars->end(), v) == qvars->end()) qvars->push_back(v);
             }
         if (!any) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "a triple pattern without variables");
     }
-    std::vector<int32_t> want;
     if (nsel == 0) {
-        want = qvars;
+        *want = *qvars;
     } else {
         for (int i = 0; i < nsel; i++) {
-            if (std::find(qvars.begin(), qvars.end(), sel[i]) == qvars.end())
+            if (std::find(qvars->begin(), qvars->end(), sel[i]) == qvars->end())
                 return ctx->fail(MAPSQ_ERR_INVALID_ARG, "a selected variable is not in the query");
-            if (std::find(want.begin(), want.end(), sel[i]) != want.end())
+            if (std::find(want->begin(), want->end(), sel[i]) != want->end())
                 return ctx->fail(MAPSQ_ERR_INVALID_ARG, "a variable is selected twice");
-            want.push_back(sel[i]);
+            want->push_back(sel[i]);
         }
     }
-    if ((int)want.size() > MAPSQ_MAX_COLS) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 16 variables");
+    if ((int)want->size() > MAPSQ_MAX_COLS) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 16 variables");
+    return MAPSQ_OK;
+}
+
+mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
+                   mapsq_table* out) {
+    std::memset(out, 0, sizeof(*out));
+    if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
+    std::vector<int32_t> qvars, want;
+    mapsq_status vst = query_vars(ctx, pats, npats, sel, nsel, &qvars, &want);
+    if (vst) return vst;
 
     // partial matching of every pattern
     std::vector<mapsq_table> tabs(npats);
@@ -85,78 +176,33 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
             return st;
         }
     }
-    // greedy order: start from the smallest table; next, the smallest table
-    // connected to the bound variables (ties: lowest pattern index)
-    int start = 0;
-    for (int i = 1; i < npats; i++)
-        if (tabs[i].nrows < tabs[start].nrows) start = i;
+    std::vector<std::vector<int32_t>> tv(npats);
+    std::vector<int64_t> tr(npats);
+    for (int i = 0; i < npats; i++) {
+        tv[i].assign(tabs[i].var, tabs[i].var + tabs[i].ncols);
+        tr[i] = tabs[i].nrows;
+    }
+    int start;
+    std::vector<PlanStep> steps;
+    greedy_plan(tv, tr, qvars, &start, &steps);
     mapsq_table cur = tabs[start];
     used[start] = true;
-    for (int step = 1; step < npats; step++) {
-        int pick = -1;
-        bool connected = false;
-        for (int i = 0; i < npats; i++) {
-            if (used[i]) continue;
-            bool con = false;
-            for (int c = 0; c < tabs[i].ncols; c++) con = con || binds(cur, tabs[i].var[c]);
-            if (pick < 0 || (con && !connected) || (con == connected && tabs[i].nrows < tabs[pick].nrows)) {
-                pick = i;
-                connected = con;
-            }
-        }
+    for (const PlanStep& ps : steps) {
         mapsq_table nxt{};
-        mapsq_status st;
-        if (connected) {
-            int32_t key = -1;
-            for (int32_t v : qvars)
-                if (binds(cur, v) && binds(tabs[pick], v)) {
-                    key = v;
-                    break;
-                }
-            st = join_tables(ctx, &cur, &tabs[pick], key, &nxt);
-        } else {
-            mapsq_table a{}, b{};
-            Block za, zb;
-            st = with_zero_key(ctx, cur, &a, &za);
-            if (!st) st = with_zero_key(ctx, tabs[pick], &b, &zb);
-            if (!st) st = join_tables(ctx, &a, &b, CROSS_VAR, &nxt);
-            if (!st) {
-                // drop the constant key column (column 0)
-                for (int c = 1; c < nxt.ncols; c++) {
-                    nxt.var[c - 1] = nxt.var[c];
-                    nxt.col[c - 1] = nxt.col[c];
-                }
-                nxt.ncols -= 1;
-                nxt.col[nxt.ncols] = nullptr;
-                nxt.key_max = (cur.key_max >= 0 && tabs[pick].key_max >= 0)
-                                  ? std::max(cur.key_max, tabs[pick].key_max)
-                                  : -1;
-            }
-        }
+        mapsq_status st = ps.cross ? cross_join(ctx, cur, tabs[ps.pick], &nxt)
+                                   : join_tables(ctx, &cur, &tabs[ps.pick], ps.key, &nxt);
         if (st) {
             free_table(ctx, &cur);
             cleanup();
             return st;
         }
         free_table(ctx, &cur);
-        free_table(ctx, &tabs[pick]);
-        used[pick] = true;
+        free_table(ctx, &tabs[ps.pick]);
+        used[ps.pick] = true;
         cur = nxt;
     }
     // projection (bag): pick the selected columns in the requested order
-    mapsq_table res = cur;
-    for (size_t i = 0; i < want.size(); i++) {
-        int c = -1;
-        for (int k = 0; k < cur.ncols; k++)
-            if (cur.var[k] == want[i]) c = k;
-        res.var[i] = want[i];
-        res.col[i] = cur.col[c];
-    }
-    for (size_t i = want.size(); i < MAPSQ_MAX_COLS; i++) {
-        res.var[i] = 0;
-        res.col[i] = nullptr;
-    }
-    res.ncols = (int32_t)want.size();
+    mapsq_table res = project_table(cur, want);
     *out = res;
     return MAPSQ_OK;
 }

@@ -437,6 +437,27 @@ mapsq_status load_triples(Ctx* ctx, const int32_t* s, const int32_t* p, const in
         LCHK(build_order(ctx, n, S.o, S.s, so_max, pmin, pmax, b, S.pos_o, S.pos_s, false, &res));
         ctx->prof_end(ph, 0.0);
     }
+    // per-predicate statistics for the planner's size estimates: distinct
+    // subjects (runs in the PSO subject column) and objects (POS object column)
+    if (n > 0 && S.preds.size() <= 4096) {
+        const size_t np = S.preds.size();
+        Block cnt = alloc_block(ctx, np * 16);
+        if (!cnt.ok()) {
+            free_store(ctx);
+            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for predicate statistics");
+        }
+        unsigned long long* c = cnt.as<unsigned long long>();
+        LHIP(launch_fill_u64(reinterpret_cast<uint64_t*>(c), np * 2, 0ull, ctx->stream));
+        for (size_t i = 0; i < np; i++) {
+            LHIP(launch_count_runs(S.pso_s, S.pred_off[i], S.pred_off[i + 1], c + i, ctx->stream));
+            LHIP(launch_count_runs(S.pos_o, S.pred_off[i], S.pred_off[i + 1], c + np + i, ctx->stream));
+        }
+        std::vector<int64_t> h(np * 2);
+        LHIP(hipMemcpyAsync(h.data(), c, np * 16, hipMemcpyDeviceToHost, ctx->stream));
+        LHIP(hipStreamSynchronize(ctx->stream));
+        S.pred_ds.assign(h.begin(), h.begin() + np);
+        S.pred_do.assign(h.begin() + np, h.end());
+    }
     LHIP(hipStreamSynchronize(ctx->stream));
     S.loaded = true;
 #undef LCHK

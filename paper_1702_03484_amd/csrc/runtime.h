@@ -42,6 +42,7 @@ class Arena {
 };
 
 struct Ctx;
+struct Server;
 
 // A block of the arena freed when the guard goes out of scope (unless released).
 struct Block {
@@ -82,6 +83,7 @@ struct Store {
     int32_t *pos_o = nullptr, *pos_s = nullptr;                  // sorted by (p, o, s)
     std::vector<int32_t> preds;                                  // distinct predicates, ascending
     std::vector<int64_t> pred_off;                               // preds.size() + 1 offsets
+    std::vector<int64_t> pred_ds, pred_do;                       // distinct subjects / objects per predicate
     std::vector<size_t> blocks;
     uint64_t bytes = 0;
 };
@@ -125,6 +127,8 @@ struct Ctx {
     std::map<uint64_t, hipGraphExec_t> graphs;
     bool use_graph = true;
     void release_graphs();
+    // serving scheduler (created on first use)
+    Server* server = nullptr;
     // returns an interval handle (-1 when profiling is off)
     int prof_begin(int phase);
     void prof_end(int h, double bytes);
@@ -170,7 +174,30 @@ mapsq_status load_triples(Ctx* ctx, const int32_t* s, const int32_t* p, const in
                           uint32_t flags);
 mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
                    mapsq_table* out);
-mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_table* outs);
+// per_join == nullptr: any failing join fails the whole batch.  Otherwise a
+// join that fails leaves its status there (and a zeroed table) while the
+// others complete.
+mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_table* outs,
+                        mapsq_status* per_join = nullptr);
+struct PlanStep {
+    int pick;     // table joined at this step
+    int32_t key;  // join variable (-1 for a cross product)
+    bool cross;
+};
+void greedy_plan(const std::vector<std::vector<int32_t>>& vars, const std::vector<int64_t>& rows,
+                 const std::vector<int32_t>& qvars, int* start, std::vector<PlanStep>* steps);
+mapsq_status cross_join(Ctx* ctx, const mapsq_table& a, const mapsq_table& b, mapsq_table* out);
+mapsq_table project_table(const mapsq_table& cur, const std::vector<int32_t>& want);
+bool ensure_stage(Ctx* ctx, size_t bytes);
+// serving (serve.cpp)
+mapsq_status serve_config(Ctx* ctx, uint64_t budget_bytes, int32_t max_active);
+mapsq_status submit(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
+                    uint64_t* ticket);
+mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting);
+mapsq_status poll(Ctx* ctx, uint64_t ticket, int32_t* done, mapsq_table* out);
+void destroy_server(Ctx* ctx);
+mapsq_status query_vars(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
+                        std::vector<int32_t>* qvars, std::vector<int32_t>* want);
 mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name);
 void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt);
 int col_of(const mapsq_table* t, int32_t v);

@@ -1,0 +1,384 @@
+// Serving: continuous batching of queries over the resident store.
+//
+// mapsq_submit queues a query.  Each mapsq_serve_step is one scheduling
+// round: the waiting queries get exact partial-match sizes from the index
+// ranges (one batched range-location launch), a greedy join plan and a
+// predicted intermediate-byte cost; the head of the queue is admitted while
+// the predicted bytes of the admitted queries stay within the budget;
+// newly admitted queries map their patterns; then the next join step of
+// every active query runs in one batched launch (mapsq_join_batch's graph).
+// Queries that arrive while others are in flight join at the next round, so
+// their steps share launches with the others'.  The CPU assigns the steps
+// and the GPU joins them (the paper's coprocessing split).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <unordered_map>
+
+#include "runtime.h"
+
+namespace mq {
+
+namespace {
+
+enum QState { Q_WAITING = 0, Q_ACTIVE = 1, Q_DONE = 2, Q_FAILED = 3 };
+
+struct SQuery {
+    uint64_t ticket = 0;
+    std::vector<mapsq_pattern> pats;
+    std::vector<int32_t> qvars, want;
+    int state = Q_WAITING;
+    mapsq_status err = MAPSQ_OK;
+    bool sized = false;
+    std::vector<int64_t> rows;             // pattern sizes (exact, or an upper bound for scans)
+    double predicted = 0;                  // predicted intermediate bytes
+    std::vector<mapsq_table> tabs;         // partial-match tables
+    std::vector<bool> consumed;
+    int start = 0;
+    std::vector<PlanStep> steps;
+    size_t next = 0;
+    mapsq_table cur{};
+    mapsq_table result{};
+    int retries = 0;  // rounds a step waited for memory
+};
+
+constexpr int MAX_RETRIES = 64;
+
+}  // namespace
+
+struct Server {
+    uint64_t next_ticket = 1;
+    std::deque<SQuery*> waiting;
+    std::vector<SQuery*> active;
+    std::unordered_map<uint64_t, std::unique_ptr<SQuery>> all;
+    double budget = 0;  // 0: set from the arena at the first round
+    double reserved = 0;
+    int max_active = 256;
+};
+
+void destroy_server(Ctx* ctx) {
+    if (!ctx->server) return;
+    for (auto& kv : ctx->server->all) {
+        SQuery* q = kv.second.get();
+        for (size_t i = 0; i < q->tabs.size(); i++)
+            if (!q->consumed[i]) free_table(ctx, &q->tabs[i]);
+        if (q->state == Q_ACTIVE && q->cur.owned) free_table(ctx, &q->cur);
+        if (q->state == Q_DONE) free_table(ctx, &q->result);
+    }
+    delete ctx->server;
+    ctx->server = nullptr;
+}
+
+static Server* server(Ctx* ctx) {
+    if (!ctx->server) ctx->server = new Server();
+    return ctx->server;
+}
+
+mapsq_status serve_config(Ctx* ctx, uint64_t budget_bytes, int32_t max_active) {
+    if (max_active < 0) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "max_active must be >= 0");
+    Server* S = server(ctx);
+    S->budget = (double)budget_bytes;
+    S->max_active = max_active ? max_active : 256;
+    return MAPSQ_OK;
+}
+
+mapsq_status submit(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
+                    uint64_t* ticket) {
+    if (!ticket) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null ticket");
+    *ticket = 0;
+    if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
+    std::unique_ptr<SQuery> q(new SQuery());
+    mapsq_status st = query_vars(ctx, pats, npats, sel, nsel, &q->qvars, &q->want);
+    if (st) return st;
+    for (int i = 0; i < npats; i++) {
+        const int32_t t[3] = {pats[i].s, pats[i].p, pats[i].o};
+        for (int k = 0; k < 3; k++)
+            if (t[k] == INT32_MAX) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "constant outside [0, 2^31 - 1)");
+    }
+    Server* S = server(ctx);
+    q->pats.assign(pats, pats + npats);
+    q->ticket = S->next_ticket++;
+    *ticket = q->ticket;
+    S->waiting.push_back(q.get());
+    S->all.emplace(q->ticket, std::move(q));
+    return MAPSQ_OK;
+}
+
+// Exact sizes of the waiting queries' patterns: predicate ranges from the
+// host table, narrowed on the device by one batched range-location launch;
+// patterns that need a scan (variable predicate or a repeated variable)
+// get the scanned range as an upper bound.
+static mapsq_status size_waiting(Ctx* ctx, Server* S) {
+    const Store& St = ctx->store;
+    std::vector<LocateQuery> lq;
+    std::vector<std::pair<SQuery*, int>> who;
+    for (SQuery* q : S->waiting) {
+        if (q->sized) continue;
+        q->rows.assign(q->pats.size(), 0);
+        for (size_t i = 0; i < q->pats.size(); i++) {
+            const mapsq_pattern& p = q->pats[i];
+            const bool rep = (p.s < 0 && (p.s == p.p || p.s == p.o)) || (p.p < 0 && p.p == p.o);
+            if (p.p < 0) {
+                q->rows[i] = St.n;
+                continue;
+            }
+            auto it = std::lower_bound(St.preds.begin(), St.preds.end(), p.p);
+            if (it == St.preds.end() || *it != p.p) {
+                q->rows[i] = 0;
+                continue;
+            }
+            const size_t pi = size_t(it - St.preds.begin());
+            LocateQuery x{};
+            x.lo = St.pred_off[pi];
+            x.hi = St.pred_off[pi + 1];
+            if (p.s >= 0) {
+                x.col1 = St.pso_s;
+                x.v1 = p.s;
+                if (p.o >= 0) {
+                    x.col2 = St.pso_o;
+                    x.v2 = p.o;
+                }
+            } else if (p.o >= 0) {
+                x.col1 = St.pos_o;
+                x.v1 = p.o;
+            }
+            if (!x.col1 || rep) {
+                q->rows[i] = x.hi - x.lo;
+                continue;
+            }
+            lq.push_back(x);
+            who.emplace_back(q, (int)i);
+        }
+        q->sized = true;
+    }
+    if (lq.empty()) return MAPSQ_OK;
+    Block buf = alloc_block(ctx, lq.size() * (sizeof(LocateQuery) + 16));
+    if (!buf.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for range queries");
+    LocateQuery* qd = buf.as<LocateQuery>();
+    int64_t* od = reinterpret_cast<int64_t*>(qd + lq.size());
+    const size_t up = lq.size() * sizeof(LocateQuery), down = lq.size() * 16;
+    if (!ensure_stage(ctx, std::max(up, down))) return ctx->fail(MAPSQ_ERR_HIP, "pinned staging allocation failed");
+    std::memcpy(ctx->stage, lq.data(), up);
+    hipError_t e = hipMemcpyAsync(qd, ctx->stage, up, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = launch_locate(qd, (int32_t)lq.size(), od, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->stage, od, down, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return ctx->fail(MAPSQ_ERR_HIP, std::string("range location: ") + hipGetErrorString(e));
+    const int64_t* r = reinterpret_cast<const int64_t*>(ctx->stage);
+    for (size_t k = 0; k < who.size(); k++) who[k].first->rows[who[k].second] = r[2 * k + 1] - r[2 * k];
+    return MAPSQ_OK;
+}
+
+// Predicted intermediate bytes of a query: the greedy plan on the exact
+// pattern sizes, each join's output estimated as |L| |R| / max(distinct
+// keys) from the per-predicate statistics (System-R style), plus the scan
+// outputs and the join scratch (24 B per record).
+static void predict(Ctx* ctx, SQuery* q) {
+    const Store& St = ctx->store;
+    const size_t m = q->pats.size();
+    std::vector<std::vector<int32_t>> vars(m);
+    std::vector<std::vector<double>> dist(m);
+    double bytes = 0;
+    for (size_t i = 0; i < m; i++) {
+        const mapsq_pattern& p = q->pats[i];
+        const int32_t t[3] = {p.s, p.p, p.o};
+        double ds = (double)q->rows[i], dob = (double)q->rows[i];
+        if (p.p >= 0 && St.pred_ds.size() == St.preds.size()) {
+            auto it = std::lower_bound(St.preds.begin(), St.preds.end(), p.p);
+            if (it != St.preds.end() && *it == p.p) {
+                const size_t pi = size_t(it - St.preds.begin());
+                ds = std::min(ds, (double)St.pred_ds[pi]);
+                dob = std::min(dob, (double)St.pred_do[pi]);
+            }
+        }
+        for (int k = 0; k < 3; k++)
+            if (t[k] < 0) {
+                const int32_t v = -t[k] - 1;
+                if (std::find(vars[i].begin(), vars[i].end(), v) != vars[i].end()) continue;
+                vars[i].push_back(v);
+                dist[i].push_back(k == 0 ? ds : (k == 2 ? dob : (double)q->rows[i]));
+            }
+        const bool scan = p.p < 0 || (p.s < 0 && (p.s == p.p || p.s == p.o)) || (p.p < 0 && p.p == p.o);
+        if (scan) bytes += 4.0 * vars[i].size() * (double)q->rows[i];
+    }
+    int start;
+    std::vector<PlanStep> steps;
+    greedy_plan(vars, q->rows, q->qvars, &start, &steps);
+    double rows = (double)q->rows[start];
+    std::vector<int32_t> cv = vars[start];
+    std::vector<double> cd = dist[start];
+    for (const PlanStep& ps : steps) {
+        const double r2 = (double)q->rows[ps.pick];
+        double est;
+        if (ps.cross) {
+            est = rows * r2;
+        } else {
+            double d1 = 1, d2 = 1;
+            for (size_t k = 0; k < cv.size(); k++)
+                if (cv[k] == ps.key) d1 = cd[k];
+            for (size_t k = 0; k < vars[ps.pick].size(); k++)
+                if (vars[ps.pick][k] == ps.key) d2 = dist[ps.pick][k];
+            est = rows * r2 / std::max(1.0, std::max(d1, d2));
+        }
+        bytes += 24.0 * (rows + r2);
+        for (size_t k = 0; k < vars[ps.pick].size(); k++)
+            if (std::find(cv.begin(), cv.end(), vars[ps.pick][k]) == cv.end()) {
+                cv.push_back(vars[ps.pick][k]);
+                cd.push_back(dist[ps.pick][k]);
+            }
+        for (double& d : cd) d = std::min(d, est);
+        bytes += 4.0 * cv.size() * est;
+        rows = est;
+    }
+    q->predicted = bytes;
+}
+
+static void fail_query(Ctx* ctx, Server* S, SQuery* q, mapsq_status err) {
+    for (size_t i = 0; i < q->tabs.size(); i++)
+        if (!q->consumed[i]) free_table(ctx, &q->tabs[i]);
+    if (q->cur.owned) free_table(ctx, &q->cur);
+    std::memset(&q->cur, 0, sizeof(mapsq_table));
+    if (q->state == Q_ACTIVE) S->reserved -= q->predicted;
+    q->state = Q_FAILED;
+    q->err = err;
+}
+
+static void finish_query(Server* S, SQuery* q) {
+    q->result = project_table(q->cur, q->want);
+    std::memset(&q->cur, 0, sizeof(mapsq_table));
+    q->state = Q_DONE;
+    S->reserved -= q->predicted;
+}
+
+// Map the patterns of a newly admitted query and fix its plan on the exact
+// table sizes.
+static mapsq_status activate(Ctx* ctx, Server* S, SQuery* q) {
+    const size_t m = q->pats.size();
+    q->tabs.assign(m, mapsq_table{});
+    q->consumed.assign(m, true);
+    for (size_t i = 0; i < m; i++) {
+        mapsq_status st = map_pattern(ctx, &q->pats[i], -1, &q->tabs[i]);
+        if (st) return st;
+        q->consumed[i] = false;
+    }
+    std::vector<std::vector<int32_t>> vars(m);
+    std::vector<int64_t> rows(m);
+    for (size_t i = 0; i < m; i++) {
+        vars[i].assign(q->tabs[i].var, q->tabs[i].var + q->tabs[i].ncols);
+        rows[i] = q->tabs[i].nrows;
+    }
+    greedy_plan(vars, rows, q->qvars, &q->start, &q->steps);
+    q->cur = q->tabs[q->start];
+    q->consumed[q->start] = true;
+    q->next = 0;
+    q->state = Q_ACTIVE;
+    if (q->steps.empty()) finish_query(S, q);
+    return MAPSQ_OK;
+}
+
+mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
+    Server* S = server(ctx);
+    if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
+    if (S->budget <= 0) S->budget = 0.6 * (double)ctx->arena.free_bytes();
+    // 1. sizes, plans and predictions of the waiting queries; FIFO admission
+    mapsq_status st = size_waiting(ctx, S);
+    if (st) return st;
+    while (!S->waiting.empty()) {
+        SQuery* q = S->waiting.front();
+        if (q->predicted == 0) predict(ctx, q);
+        if (q->predicted > S->budget) {
+            S->waiting.pop_front();
+            q->state = Q_FAILED;
+            q->err = MAPSQ_ERR_TOO_LARGE;
+            continue;
+        }
+        if ((int)S->active.size() >= S->max_active || S->reserved + q->predicted > S->budget) break;
+        S->waiting.pop_front();
+        S->reserved += q->predicted;
+        S->active.push_back(q);
+        q->state = Q_ACTIVE;
+        st = activate(ctx, S, q);
+        if (st) fail_query(ctx, S, q, st);
+    }
+    // 2. the next join step of every active query, in one batched launch
+    std::vector<SQuery*> in_batch;
+    std::vector<mapsq_join_desc> descs;
+    for (SQuery* q : S->active) {
+        if (q->state != Q_ACTIVE || q->next >= q->steps.size()) continue;
+        const PlanStep& ps = q->steps[q->next];
+        if (ps.cross) {  // rare: run it now through the plain path
+            mapsq_table nxt{};
+            st = cross_join(ctx, q->cur, q->tabs[ps.pick], &nxt);
+            if (st) {
+                fail_query(ctx, S, q, st);
+                continue;
+            }
+            free_table(ctx, &q->cur);
+            free_table(ctx, &q->tabs[ps.pick]);
+            q->consumed[ps.pick] = true;
+            q->cur = nxt;
+            if (++q->next == q->steps.size()) finish_query(S, q);
+            continue;
+        }
+        in_batch.push_back(q);
+        descs.push_back(mapsq_join_desc{&q->cur, &q->tabs[ps.pick], ps.key, 0});
+    }
+    if (!descs.empty()) {
+        std::vector<mapsq_table> outs(descs.size());
+        std::vector<mapsq_status> per(descs.size());
+        st = join_batch(ctx, descs.data(), (int32_t)descs.size(), outs.data(), per.data());
+        if (st) return st;
+        const bool others = S->active.size() > 1;
+        for (size_t k = 0; k < in_batch.size(); k++) {
+            SQuery* q = in_batch[k];
+            const PlanStep& ps = q->steps[q->next];
+            if (per[k] != MAPSQ_OK) {
+                // memory may free up when other queries finish: retry next round
+                if ((per[k] == MAPSQ_ERR_CAPACITY || per[k] == MAPSQ_ERR_TOO_LARGE) && others &&
+                    ++q->retries < MAX_RETRIES)
+                    continue;
+                fail_query(ctx, S, q, per[k]);
+                continue;
+            }
+            free_table(ctx, &q->cur);
+            free_table(ctx, &q->tabs[ps.pick]);
+            q->consumed[ps.pick] = true;
+            q->cur = outs[k];
+            if (++q->next == q->steps.size()) finish_query(S, q);
+        }
+    }
+    // 3. retire finished queries from the active set
+    S->active.erase(std::remove_if(S->active.begin(), S->active.end(),
+                                   [](SQuery* q) { return q->state != Q_ACTIVE; }),
+                    S->active.end());
+    if (n_active) *n_active = (int32_t)S->active.size();
+    if (n_waiting) *n_waiting = (int32_t)S->waiting.size();
+    return MAPSQ_OK;
+}
+
+mapsq_status poll(Ctx* ctx, uint64_t ticket, int32_t* done, mapsq_table* out) {
+    if (!done || !out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+    *done = 0;
+    std::memset(out, 0, sizeof(mapsq_table));
+    Server* S = server(ctx);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "unknown ticket");
+    SQuery* q = it->second.get();
+    if (q->state == Q_DONE) {
+        *out = q->result;
+        *done = 1;
+        S->all.erase(it);
+        return MAPSQ_OK;
+    }
+    if (q->state == Q_FAILED) {
+        const mapsq_status err = q->err;
+        *done = 1;
+        S->all.erase(it);
+        return ctx->fail(err, "query " + std::to_string(ticket) + " failed");
+    }
+    return MAPSQ_OK;
+}
+
+}  // namespace mq

@@ -330,37 +330,80 @@ struct MatJoin {
     int32_t* const* out;
 };
 
+// Rows [j, j + nk) of one lane, in order, when they may run into later
+// segments.  s is the segment of row j; later segments are found by binary
+// search in (s, s_last] (empty segments are skipped, never walked).
+template <int NC>
+__device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint32_t s_last, uint64_t j, int nk,
+                                              int32_t (&v)[NC][4]) {
+    const bool has_l = a.nl > 0, has_r = a.nr > 0;
+    const int nc = 1 + a.nl + a.nr;
+    uint32_t st = a.seg_start[s], sp = a.seg_split[s];
+    uint32_t en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
+    uint64_t so = a.seg_off[s];
+    uint32_t cl = sp - st, cr = en - sp;
+    const uint64_t r = j - so;
+    uint32_t li = (uint32_t)(r / cr), ri = (uint32_t)(r - (uint64_t)li * cr);
+    int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
+    uint32_t lrow = has_l ? a.vals[st + li] : 0u;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if (k < nk) {
+            if (li == cl) {  // the next non-empty segment holds row j + k
+                s = seg_of(a.seg_off, s + 1, s_last, j + k);
+                st = a.seg_start[s];
+                sp = a.seg_split[s];
+                en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
+                cl = sp - st;
+                cr = en - sp;
+                li = 0;
+                ri = 0;
+                key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
+                lrow = has_l ? a.vals[st] : 0u;
+            }
+            const uint32_t rrow = has_r ? a.vals[sp + ri] - a.n_left : 0u;
+            v[0][k] = key;
+#pragma unroll
+            for (int col = 1; col < NC; col++)
+                if (col < nc) v[col][k] = col <= a.nl ? a.lcol[col - 1][lrow] : a.rcol[col - 1 - a.nl][rrow];
+            if (++ri == cr) {
+                ri = 0;
+                if (++li < cl && has_l) lrow = a.vals[st + li];
+            }
+        }
+    }
+}
+
 // Materialise output rows [j0, jend) (at most 64*RPT rows, j0 a multiple of
 // 4) of one join with one wave.  The chunk is cut into RPT/4 sub-chunks of
 // 256 rows; in each, lane L writes rows 4L..4L+3, so every 16-byte store
-// instruction of the wave covers 1 KB of one column contiguously.  NC is an
-// upper bound of the column count 1 + nl + nr.
+// instruction of the wave covers 1 KB of one column contiguously.  A lane's
+// four rows that lie in one segment take the fast path, whose payload and
+// value loads are all independent; rows that cross into later segments take
+// mat_rows_slow.  NC is an upper bound of the column count 1 + nl + nr.
 template <int NC, int RPT>
 __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend) {
+    constexpr int Q = RPT / 4;
     const bool has_l = a.nl > 0, has_r = a.nr > 0;
     const int nc = 1 + a.nl + a.nr;
     const uint32_t s_first = wave_seg_of(a.seg_off, 0, a.ns - 1, j0);
     const uint32_t s_last = wave_seg_of(a.seg_off, s_first, a.ns - 1, jend - 1);
+    // phase 1: each sub-chunk's segment and first (li, ri)
+    uint32_t qs[Q], qst[Q], qsp[Q], qcr[Q], qli[Q], qri[Q];
+    int32_t qkey[Q];
+    bool qon[Q], qfast[Q];
     uint32_t s = s_first;
-    uint32_t st = a.seg_start[s], sp = a.seg_split[s];
-    uint32_t en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
-    uint64_t so = a.seg_off[s];
-    int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
 #pragma unroll
-    for (int q = 0; q < RPT / 4; q++) {
+    for (int q = 0; q < Q; q++) {
         const uint64_t j = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
-        if (j < jend) {
-            const uint32_t s2 = seg_of(a.seg_off, s, s_last, j);
-            if (s2 != s) {
-                s = s2;
-                st = a.seg_start[s];
-                sp = a.seg_split[s];
-                en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
-                so = a.seg_off[s];
-                key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
-            }
-            uint32_t cl = sp - st, cr = en - sp;
-            const uint64_t r = j - so;
+        qon[q] = j < jend;
+        qfast[q] = false;
+        if (qon[q]) {
+            s = seg_of(a.seg_off, s, s_last, j);
+            const uint32_t st = a.seg_start[s], sp = a.seg_split[s];
+            const uint32_t en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
+            const uint32_t cl = sp - st, cr = en - sp;
+            const uint64_t r = j - a.seg_off[s];
             uint32_t li, ri;
             if (r < 0xffffffffull) {
                 li = (uint32_t)r / cr;
@@ -369,54 +412,66 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
                 li = (uint32_t)(r / cr);
                 ri = (uint32_t)(r - (uint64_t)li * cr);
             }
-            // a sub-chunk row may run into later segments; walk them locally
-            uint32_t ls = s, lst = st, lsp = sp;
-            int32_t lkey = key;
-            uint32_t lrow = has_l ? a.vals[st + li] : 0u;
-            int32_t v[NC][4];
-            const int nk = (int)min((uint64_t)4, jend - j);
+            qs[q] = s;
+            qst[q] = st;
+            qsp[q] = sp;
+            qcr[q] = cr;
+            qli[q] = li;
+            qri[q] = ri;
+            qkey[q] = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
+            qfast[q] = j + 4 <= jend && r + 4 <= (uint64_t)cl * cr;
+        }
+    }
+    // phase 2: payloads of the fast sub-chunks (independent loads)
+    uint32_t lrow[Q][4], rrow[Q][4];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            lrow[q][k] = 0;
+            rrow[q][k] = 0;
+            if (qfast[q]) {
+                uint32_t li = qli[q], ri = qri[q] + k;
+                while (ri >= qcr[q]) {  // at most 3 steps
+                    ri -= qcr[q];
+                    li++;
+                }
+                if (has_l) lrow[q][k] = a.vals[qst[q] + li];
+                if (has_r) rrow[q][k] = a.vals[qsp[q] + ri] - a.n_left;
+            }
+        }
+    }
+    // phase 3: values and 16-byte stores
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        if (!qon[q]) continue;
+        const uint64_t j = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
+        int32_t v[NC][4];
+        int nk = 4;
+        if (qfast[q]) {
 #pragma unroll
             for (int k = 0; k < 4; k++) {
-                if (k < nk) {
-                    if (li == cl) {  // next non-empty segment
-                        do {
-                            ls++;
-                        } while (ls + 1 < a.ns && a.seg_off[ls + 1] <= j + k);
-                        lst = a.seg_start[ls];
-                        lsp = a.seg_split[ls];
-                        const uint32_t len = ls + 1 < a.ns ? a.seg_start[ls + 1] : a.n;
-                        cl = lsp - lst;
-                        cr = len - lsp;
-                        li = 0;
-                        ri = 0;
-                        lkey = (int32_t)(a.keys[lst] + (uint32_t)a.key_base);
-                        lrow = has_l ? a.vals[lst] : 0u;
-                    }
-                    const uint32_t rrow = has_r ? a.vals[lsp + ri] - a.n_left : 0u;
-                    v[0][k] = lkey;
+                v[0][k] = qkey[q];
 #pragma unroll
-                    for (int col = 1; col < NC; col++)
-                        if (col < nc)
-                            v[col][k] = col <= a.nl ? a.lcol[col - 1][lrow] : a.rcol[col - 1 - a.nl][rrow];
-                    if (++ri == cr) {
-                        ri = 0;
-                        if (++li < cl && has_l) lrow = a.vals[lst + li];
-                    }
-                }
-            }
-            if (nk == 4) {
-#pragma unroll
-                for (int col = 0; col < NC; col++)
+                for (int col = 1; col < NC; col++)
                     if (col < nc)
-                        *reinterpret_cast<int4*>(a.out[col] + j) = make_int4(v[col][0], v[col][1], v[col][2], v[col][3]);
-            } else {
-#pragma unroll
-                for (int col = 0; col < NC; col++)
-                    if (col < nc)
-#pragma unroll
-                        for (int k = 0; k < 4; k++)
-                            if (k < nk) a.out[col][j + k] = v[col][k];
+                        v[col][k] = col <= a.nl ? a.lcol[col - 1][lrow[q][k]] : a.rcol[col - 1 - a.nl][rrow[q][k]];
             }
+        } else {
+            nk = (int)min((uint64_t)4, jend - j);
+            mat_rows_slow<NC>(a, qs[q], s_last, j, nk, v);
+        }
+        if (nk == 4) {
+#pragma unroll
+            for (int col = 0; col < NC; col++)
+                if (col < nc) *reinterpret_cast<int4*>(a.out[col] + j) = make_int4(v[col][0], v[col][1], v[col][2], v[col][3]);
+        } else {
+#pragma unroll
+            for (int col = 0; col < NC; col++)
+                if (col < nc)
+#pragma unroll
+                    for (int k = 0; k < 4; k++)
+                        if (k < nk) a.out[col][j + k] = v[col][k];
         }
     }
 }

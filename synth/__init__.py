@@ -20,5 +20,6 @@ from .gen import (  # noqa: F401
     batch_cfg4,
     cfg4_vars,
     serving_cfg5,
+    store_cfg5,
     var,
 )

@@ -366,5 +366,67 @@ def cfg4_vars(sub: dict):
     return v
 
 
-def serving_cfg5(*a, **k):  # filled in with the serving loop
-    raise NotImplementedError
+def store_cfg5(seed: int = 1, n: int = 500_000_000, n_entities: int = 100_000_000, n_pred: int = 128) -> Workload:
+    """Config 5 store: predicates Zipf(1.0) over 128, subjects and objects
+    Zipf(1.1) over 100M entities with one rank->ID map for both roles."""
+    cfg = 5000 + seed
+    s, p, o = _store_zipf(cfg, n, n_entities, n_pred, 1.0, 1.1, 1.1)
+    return Workload("cfg5", s, p, o, n_entities, n_pred, meta={"seed": seed})
+
+
+def serving_cfg5(w: Workload, n_queries: int, seed: int = 1, sample: int = 20_000_000) -> list:
+    """Queries of 1-5 triple patterns, each a seeded random walk over the
+    store's first ``sample`` triples (so every query has at least one
+    answer): start at a random triple, then repeatedly step from a visited
+    entity to a random triple that has it as subject or object.  Each
+    pattern keeps 0, 1 or 2 of its positions constant (probabilities 0.05,
+    0.45, 0.5; a kept position is the predicate with probability 0.8 when
+    it is free) and turns the rest into variables, one variable per distinct
+    value of the walk, so consecutive patterns share variables.
+    """
+    m = min(sample, w.n)
+    S, P, O = w.s[:m], w.p[:m], w.o[:m]
+    by_s = np.argsort(S, kind="stable")
+    by_o = np.argsort(O, kind="stable")
+    s_sorted, o_sorted = S[by_s], O[by_o]
+    r = _rng(5000 + seed, 2)
+    out = []
+    for _ in range(n_queries):
+        npat = int(r.integers(1, 6))
+        walk = [int(r.integers(0, m))]
+        nodes = [int(S[walk[0]]), int(O[walk[0]])]
+        tries = 0
+        while len(walk) < npat and tries < 50:
+            tries += 1
+            e = nodes[int(r.integers(0, len(nodes)))]
+            use_s = bool(r.integers(0, 2))
+            arr, order = (s_sorted, by_s) if use_s else (o_sorted, by_o)
+            lo, hi = np.searchsorted(arr, e, "left"), np.searchsorted(arr, e, "right")
+            if hi <= lo:
+                continue
+            t = int(order[lo + int(r.integers(0, hi - lo))])
+            if t in walk:
+                continue
+            walk.append(t)
+            nodes += [int(S[t]), int(O[t])]
+        varof = {}
+        pats = []
+        for t in walk:
+            trip = [int(S[t]), int(P[t]), int(O[t])]
+            k = int(r.choice(3, p=[0.05, 0.45, 0.5]))
+            keep = set()
+            while len(keep) < k:
+                if 1 not in keep and r.random() < 0.8:
+                    keep.add(1)
+                else:
+                    keep.add(int(r.integers(0, 3)))
+            pat = []
+            for pos in range(3):
+                if pos in keep:
+                    pat.append(trip[pos])
+                else:
+                    v = varof.setdefault(trip[pos], len(varof))
+                    pat.append(var(v))
+            pats.append(tuple(pat))
+        out.append(pats)
+    return out
