@@ -17,7 +17,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -28,15 +27,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "materialize_cfg2_traffic.json")
-MATERIALIZE_SRC = os.path.join(ROOT, "paper_1702_03484_amd", "csrc", "k_reduce.hip")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-def file_sha(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
 def traffic_from_profile():
@@ -46,7 +40,9 @@ def traffic_from_profile():
         d = json.load(open(PROFILE_TRAFFIC))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha256") != file_sha(MATERIALIZE_SRC):
+    from paper_1702_03484_amd.profile_summary import kernel_sha
+
+    if d.get("kernel_source_sha256") != kernel_sha():
         return None
     return d.get("hbm_bytes_per_launch")
 

@@ -258,6 +258,13 @@ mapsq_status mapsq_profile_enable(mapsq_ctx* ctx, int32_t on);
 /* Synchronise the context's stream and return the accumulators. */
 mapsq_status mapsq_profile_read(mapsq_ctx* ctx, mapsq_profile* out);
 
+/* Autotuner table: for sorts of keys of `key_bits` bits over about
+ * 2^(log2_records-1) .. 2^log2_records records, use digit width `radix_bits`
+ * (4..11) and `keys_per_thread` (8 or 16).  Consulted when no explicit
+ * mapsq_set_tuning is in force.  radix_bits = 0 removes the entry. */
+mapsq_status mapsq_tune_record(mapsq_ctx* ctx, int32_t key_bits, int32_t log2_records, int32_t radix_bits,
+                               int32_t keys_per_thread);
+
 /* Bytes of the arena still free, and the largest free block. */
 mapsq_status mapsq_arena_free_bytes(mapsq_ctx* ctx, uint64_t* free_bytes, uint64_t* largest_block);
 

@@ -135,6 +135,7 @@ _SIGS = [
     ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_profile_enable", ctypes.c_int32, [_P, ctypes.c_int32]),
     ("mapsq_profile_read", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_profile)]),
+    ("mapsq_tune_record", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_arena_free_bytes", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
@@ -279,6 +280,10 @@ def mapsq_profile_read(ctx) -> mapsq_profile:
     out = mapsq_profile()
     _check(ctx, lib().mapsq_profile_read(ctx, ctypes.byref(out)))
     return out
+
+
+def mapsq_tune_record(ctx, key_bits: int, log2_records: int, radix_bits: int, keys_per_thread: int):
+    _check(ctx, lib().mapsq_tune_record(ctx, key_bits, log2_records, radix_bits, keys_per_thread))
 
 
 def mapsq_arena_free_bytes(ctx):

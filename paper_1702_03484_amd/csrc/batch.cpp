@@ -82,8 +82,11 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         }
     }
     const int key_bits = known ? bitlen((uint32_t)kmax) : 31;
+    uint64_t all_rec = 0;
+    for (int i = 0; i < n; i++)
+        if (plan[i].batched && !plan[i].empty) all_rec += (uint64_t)d[i].left->nrows + (uint64_t)d[i].right->nrows;
     int rb, kpt;
-    pick_tuning(ctx, key_bits, rb, kpt);
+    pick_tuning(ctx, key_bits, rb, kpt, all_rec);
     const int passes = std::max(1, (key_bits + rb - 1) / rb);
     const uint32_t TILE = BLOCK_THREADS * (uint32_t)kpt;  // records per tile
     const size_t buckets = size_t(1) << rb;
@@ -147,13 +150,16 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         const size_t tj_bytes = align_up(tiles * 4, ARENA_ALIGN);
         const size_t jd_bytes = align_up(sizeof(BatchJoin) * n, ARENA_ALIGN);
         Block scratch = alloc_block(ctx, nb4 * 6 + hist_bytes + tj_bytes + jd_bytes);
-        if (!scratch.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for batch scratch");
-        if (!ctx->ensure_status(size_t(tiles) * buckets))
-            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for batch status words");
-        if (ctx->bhdr_off == SIZE_MAX) {
+        bool room = scratch.ok() && ctx->ensure_status(size_t(tiles) * buckets);
+        if (room && ctx->bhdr_off == SIZE_MAX) {
             ctx->bhdr_off = ctx->arena.alloc(sizeof(BatchHdr));
-            if (ctx->bhdr_off == SIZE_MAX) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the batch header");
-            ctx->bhdr = reinterpret_cast<BatchHdr*>(ctx->arena.ptr(ctx->bhdr_off));
+            room = ctx->bhdr_off != SIZE_MAX;
+            if (room) ctx->bhdr = reinterpret_cast<BatchHdr*>(ctx->arena.ptr(ctx->bhdr_off));
+        }
+        if (!room) {
+            if (!per_join) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the batch scratch");
+            // tolerant mode: every join goes through the plain path below
+            goto plain_rest;
         }
         char* sb = ctx->arena.ptr(scratch.off);
         // the output region: the largest free block that is left
@@ -282,6 +288,7 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
             }
         }
     }
+plain_rest:
     // empty joins, and the joins the batched kernels did not take
     for (int i = 0; i < n; i++) {
         if (done[i]) continue;

@@ -224,6 +224,23 @@ mapsq_status mapsq_profile_read(mapsq_ctx* c, mapsq_profile* out) {
     });
 }
 
+mapsq_status mapsq_tune_record(mapsq_ctx* c, int32_t key_bits, int32_t log2_records, int32_t radix_bits,
+                               int32_t keys_per_thread) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (key_bits < 0 || key_bits > 32 || log2_records < 0 || log2_records > 40)
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "key_bits in [0, 32], log2_records in [0, 40]");
+        const uint32_t k = ((uint32_t)key_bits << 8) | (uint32_t)log2_records;
+        if (radix_bits == 0) {
+            ctx->tuned.erase(k);
+            return (mapsq_status)MAPSQ_OK;
+        }
+        if (radix_bits < 4 || radix_bits > 11 || (keys_per_thread != 8 && keys_per_thread != 16))
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "radix_bits in [4, 11], keys_per_thread 8 or 16");
+        ctx->tuned[k] = ((uint32_t)radix_bits << 8) | (uint32_t)keys_per_thread;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
 mapsq_status mapsq_arena_free_bytes(mapsq_ctx* c, uint64_t* free_bytes, uint64_t* largest_block) {
     return guarded(c, [&](Ctx* ctx) {
         if (!free_bytes || !largest_block) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");

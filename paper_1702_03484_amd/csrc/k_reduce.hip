@@ -94,7 +94,7 @@ struct MatShape {
     static constexpr uint32_t WROWS = MQ_WAVE * RPT;               // rows per wave chunk
 };
 
-template <int NC>
+template <int NC, int NLC>
 __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     constexpr uint32_t WROWS = MatShape<NC>::WROWS;
     MatJoin mj;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     const uint64_t nw = (uint64_t)gridDim.x * MQ_WAVES;
     for (uint64_t c = gw; c < nchunks; c += nw) {
         const uint64_t j0 = a.row_begin + c * WROWS;
-        mat_wave_chunk<NC, MatShape<NC>::RPT>(mj, j0, min(j0 + WROWS, a.row_end));
+        mat_wave_chunk<NC, MatShape<NC>::RPT, NLC>(mj, j0, min(j0 + WROWS, a.row_end));
     }
 }
 
@@ -126,18 +126,46 @@ hipError_t launch_materialize(const MatArgs& a, hipStream_t stream) {
     if (a.row_begin % 16) return hipErrorInvalidValue;
     const int nc = 1 + a.nl + a.nr;
     const uint64_t rows = a.row_end - a.row_begin;
-#define MQ_M(C)                                                                                  \
-    case C: {                                                                                    \
-        uint64_t chunks = (rows + MatShape<C>::WROWS - 1) / MatShape<C>::WROWS;                  \
+    // narrow joins get the value-column split fixed at compile time
+#define MQ_LAUNCH(C, L)                                                                             \
+    {                                                                                               \
+        uint64_t chunks = (rows + MatShape<C>::WROWS - 1) / MatShape<C>::WROWS;                     \
         uint32_t blocks = (uint32_t)std::min<uint64_t>((chunks + MQ_WAVES - 1) / MQ_WAVES, 256ull * 32); \
-        materialize_kernel<C><<<blocks, MQ_BLOCK, 0, stream>>>(a);                               \
-    } break;
+        materialize_kernel<C, L><<<blocks, MQ_BLOCK, 0, stream>>>(a);                               \
+    }
+    if (nc <= 4) {
+        const int key = nc * 4 + a.nl;
+        switch (key) {
+            case 1 * 4 + 0: MQ_LAUNCH(1, 0) break;
+            case 2 * 4 + 0: MQ_LAUNCH(2, 0) break;
+            case 2 * 4 + 1: MQ_LAUNCH(2, 1) break;
+            case 3 * 4 + 0: MQ_LAUNCH(3, 0) break;
+            case 3 * 4 + 1: MQ_LAUNCH(3, 1) break;
+            case 3 * 4 + 2: MQ_LAUNCH(3, 2) break;
+            case 4 * 4 + 0: MQ_LAUNCH(4, 0) break;
+            case 4 * 4 + 1: MQ_LAUNCH(4, 1) break;
+            case 4 * 4 + 2: MQ_LAUNCH(4, 2) break;
+            case 4 * 4 + 3: MQ_LAUNCH(4, 3) break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (nc) {
-        MQ_M(1) MQ_M(2) MQ_M(3) MQ_M(4) MQ_M(5) MQ_M(6) MQ_M(7) MQ_M(8)
-        MQ_M(9) MQ_M(10) MQ_M(11) MQ_M(12) MQ_M(13) MQ_M(14) MQ_M(15) MQ_M(16)
+        case 5: MQ_LAUNCH(5, -1) break;
+        case 6: MQ_LAUNCH(6, -1) break;
+        case 7: MQ_LAUNCH(7, -1) break;
+        case 8: MQ_LAUNCH(8, -1) break;
+        case 9: MQ_LAUNCH(9, -1) break;
+        case 10: MQ_LAUNCH(10, -1) break;
+        case 11: MQ_LAUNCH(11, -1) break;
+        case 12: MQ_LAUNCH(12, -1) break;
+        case 13: MQ_LAUNCH(13, -1) break;
+        case 14: MQ_LAUNCH(14, -1) break;
+        case 15: MQ_LAUNCH(15, -1) break;
+        case 16: MQ_LAUNCH(16, -1) break;
         default: return hipErrorInvalidValue;
     }
-#undef MQ_M
+#undef MQ_LAUNCH
     return hipGetLastError();
 }
 

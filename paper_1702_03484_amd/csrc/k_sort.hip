@@ -25,14 +25,16 @@ __device__ __forceinline__ uint32_t src_key(const SortSrc& s, uint32_t idx) {
     return (uint32_t)k - (uint32_t)s.base;
 }
 
-// Digit histograms of every pass.  Each block takes tiles of 256*HIST_IPT
-// keys with all loads of a tile in flight at once, counts into LDS, and adds
-// its LDS counts to the global histogram once at the end.
+// Digit histograms of every pass in two launches: each block counts its
+// keys into LDS (all loads of a tile in flight at once) and stores its
+// counts to its own row of a partial table; a second kernel sums the rows.
+// No device-wide atomics: they serialise on the few hundred counters.
 constexpr int HIST_IPT = 16;
+constexpr uint32_t HIST_BLOCKS = 512;
 
 template <int RB, bool GEN>
 __global__ __launch_bounds__(MQ_BLOCK) void radix_hist_kernel(SortSrc src, const uint32_t* __restrict__ keys,
-                                                              uint32_t n, int passes, uint32_t* __restrict__ hist) {
+                                                              uint32_t n, int passes, uint32_t* __restrict__ part) {
     using R = Radix<RB>;
     __shared__ uint32_t sh[R::MAXP * R::BUCKETS];
     for (int i = threadIdx.x; i < R::MAXP * R::BUCKETS; i += MQ_BLOCK) sh[i] = 0;
@@ -54,11 +56,21 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_hist_kernel(SortSrc src, const
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
-        uint32_t c = sh[i];
-        if (c) atomicAdd(&hist[i], c);
-    }
+    uint32_t* row = part + (uint64_t)blockIdx.x * passes * R::BUCKETS;
+    for (int i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) row[i] = sh[i];
 }
+
+// hist[i] = sum over the partial rows (one thread per counter)
+__global__ void hist_reduce_kernel(const uint32_t* __restrict__ part, uint32_t rows, uint32_t width,
+                                   uint32_t* __restrict__ hist) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= width) return;
+    uint32_t s = 0;
+    for (uint32_t r = 0; r < rows; r++) s += part[(uint64_t)r * width + i];
+    hist[i] = s;
+}
+
+uint32_t radix_hist_part_words(int rb, int passes) { return HIST_BLOCKS * (uint32_t)passes << rb; }
 
 template <int RB, int KPT, bool GEN>
 __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const uint32_t* __restrict__ kin,
@@ -96,24 +108,24 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
 #define MQ_RB_LIST(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
 
 hipError_t launch_radix_hist(const SortSrc& src, const uint32_t* keys, uint32_t n, int rb, int passes,
-                             uint32_t* hist, hipStream_t stream) {
+                             uint32_t* part, uint32_t* hist, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    // every block adds passes * 2^rb counters to the global histogram with
-    // device-wide atomics; a small grid keeps that traffic low
-    uint32_t blocks = std::min((n + MQ_BLOCK * HIST_IPT - 1) / (MQ_BLOCK * HIST_IPT), 128u);
+    const uint32_t blocks = std::min((n + MQ_BLOCK * HIST_IPT - 1) / (MQ_BLOCK * HIST_IPT), HIST_BLOCKS);
     bool gen = keys == nullptr;
 #define MQ_H(B)                                                                                         \
     case B:                                                                                             \
         if (gen)                                                                                        \
-            radix_hist_kernel<B, true><<<blocks, MQ_BLOCK, 0, stream>>>(src, keys, n, passes, hist);    \
+            radix_hist_kernel<B, true><<<blocks, MQ_BLOCK, 0, stream>>>(src, keys, n, passes, part);    \
         else                                                                                            \
-            radix_hist_kernel<B, false><<<blocks, MQ_BLOCK, 0, stream>>>(src, keys, n, passes, hist);   \
+            radix_hist_kernel<B, false><<<blocks, MQ_BLOCK, 0, stream>>>(src, keys, n, passes, part);   \
         break;
     switch (rb) {
         MQ_RB_LIST(MQ_H)
         default: return hipErrorInvalidValue;
     }
 #undef MQ_H
+    const uint32_t width = (uint32_t)passes << rb;
+    hist_reduce_kernel<<<(width + 255) / 256, 256, 0, stream>>>(part, blocks, width, hist);
     return hipGetLastError();
 }
 

@@ -21,10 +21,12 @@ struct SortSrc {
     int32_t base;
 };
 
-// Adds the digit histograms of `passes` passes to hist[passes][2^rb] (which
-// the caller zeroes).  keys == nullptr: read the keys from `src`.
+// Digit histograms of `passes` passes into hist[passes][2^rb] (overwritten).
+// keys == nullptr: read the keys from `src`.  `part` is scratch of
+// radix_hist_part_words(rb, passes) words.
 hipError_t launch_radix_hist(const SortSrc& src, const uint32_t* keys, uint32_t n, int rb, int passes,
-                             uint32_t* hist, hipStream_t stream);
+                             uint32_t* part, uint32_t* hist, hipStream_t stream);
+uint32_t radix_hist_part_words(int rb, int passes);
 // One stable pass on digit `pass`.  kin == nullptr: first-pass mode from
 // `src` (vin ignored).  hist_pass = this pass's histogram; status holds
 // radix_tiles(n,kpt) * 2^rb words; tile_ctr is zero before the launch.

@@ -191,9 +191,18 @@ struct SortBufs {
     uint32_t* v[2];
 };
 
-void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt) {
+void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt, uint64_t nrec) {
     rb = ctx->tune_rb;
-    kpt = ctx->tune_kpt ? ctx->tune_kpt : 16;
+    kpt = ctx->tune_kpt;
+    if (!rb && !kpt && nrec) {
+        // an autotuned entry for this key width and size class
+        auto it = ctx->tuned.find(((uint32_t)key_bits << 8) | (uint32_t)bitlen(nrec));
+        if (it != ctx->tuned.end()) {
+            rb = (int)(it->second >> 8);
+            kpt = (int)(it->second & 0xff);
+        }
+    }
+    if (!kpt) kpt = 16;
     if (!rb) {
         // fewest passes with digits of at most 8 bits, spread evenly
         int passes = std::max(1, (key_bits + 7) / 8);
@@ -214,10 +223,12 @@ static mapsq_status radix_sort(Ctx* ctx, const SortSrc* src, uint32_t n, int key
     if (passes * buckets > SMALL_HIST_WORDS) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "radix digit width too small");
     if (!ctx->ensure_status(size_t(radix_tiles(n, kpt)) * buckets))
         return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for sort status words");
-    HIPCHK(launch_fill_u32(ctx->small, SMALL_SCALARS, 0u, ctx->stream));
+    HIPCHK(launch_fill_u32(ctx->small + SMALL_CTR, SMALL_SCALARS - SMALL_CTR, 0u, ctx->stream));
     SortSrc none{};
-    HIPCHK(launch_radix_hist(src ? *src : none, src ? nullptr : b.k[0], n, rb, passes, ctx->small + SMALL_HIST,
-                             ctx->stream));
+    Block part = alloc_block(ctx, size_t(radix_hist_part_words(rb, passes)) * 4);
+    if (!part.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for histogram partials");
+    HIPCHK(launch_radix_hist(src ? *src : none, src ? nullptr : b.k[0], n, rb, passes, part.as<uint32_t>(),
+                             ctx->small + SMALL_HIST, ctx->stream));
     int cur = 0;
     for (int p = 0; p < passes; p++) {
         const bool gen = src && p == 0;
@@ -758,7 +769,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     }
     const int key_bits = bitlen((uint64_t)((int64_t)kmax - (int64_t)kmin));
     int rb, kpt;
-    pick_tuning(ctx, key_bits, rb, kpt);
+    pick_tuning(ctx, key_bits, rb, kpt, (uint64_t)nL + nR);
 
     // scratch: sort buffers (16 N) and segment offsets (8 N); the spare sort
     // buffers later hold the segment starts and splits

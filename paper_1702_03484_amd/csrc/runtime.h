@@ -105,6 +105,8 @@ struct Ctx {
     // pinned host staging for read-backs
     void* pinned = nullptr;
     int32_t tune_rb = 0, tune_kpt = 0;
+    // autotuned choices: (key bits << 8 | log2 records) -> (rb << 8 | kpt)
+    std::map<uint32_t, uint32_t> tuned;
     mapsq_join_stats last{};
     // profiling: pairs of events around phases, harvested after a sync
     bool prof = false;
@@ -199,7 +201,7 @@ void destroy_server(Ctx* ctx);
 mapsq_status query_vars(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
                         std::vector<int32_t>* qvars, std::vector<int32_t>* want);
 mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name);
-void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt);
+void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt, uint64_t nrec = 0);
 int col_of(const mapsq_table* t, int32_t v);
 Block alloc_block(Ctx* ctx, size_t bytes);
 

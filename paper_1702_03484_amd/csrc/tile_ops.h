@@ -333,11 +333,12 @@ struct MatJoin {
 // Rows [j, j + nk) of one lane, in order, when they may run into later
 // segments.  s is the segment of row j; later segments are found by binary
 // search in (s, s_last] (empty segments are skipped, never walked).
-template <int NC>
+template <int NC, int NLC>
 __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint32_t s_last, uint64_t j, int nk,
                                               int32_t (&v)[NC][4]) {
-    const bool has_l = a.nl > 0, has_r = a.nr > 0;
-    const int nc = 1 + a.nl + a.nr;
+    const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
+    const bool has_l = nl > 0, has_r = nr > 0;
+    const int nc = 1 + nl + nr;
     uint32_t st = a.seg_start[s], sp = a.seg_split[s];
     uint32_t en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
     uint64_t so = a.seg_off[s];
@@ -365,7 +366,7 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint
             v[0][k] = key;
 #pragma unroll
             for (int col = 1; col < NC; col++)
-                if (col < nc) v[col][k] = col <= a.nl ? a.lcol[col - 1][lrow] : a.rcol[col - 1 - a.nl][rrow];
+                if (col < nc) v[col][k] = col <= nl ? a.lcol[col - 1][lrow] : a.rcol[col - 1 - nl][rrow];
             if (++ri == cr) {
                 ri = 0;
                 if (++li < cl && has_l) lrow = a.vals[st + li];
@@ -380,12 +381,14 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint
 // instruction of the wave covers 1 KB of one column contiguously.  A lane's
 // four rows that lie in one segment take the fast path, whose payload and
 // value loads are all independent; rows that cross into later segments take
-// mat_rows_slow.  NC is an upper bound of the column count 1 + nl + nr.
-template <int NC, int RPT>
+// mat_rows_slow.  NC is an upper bound of the column count 1 + nl + nr;
+// NLC >= 0 fixes nl = NLC and nr = NC - 1 - NLC at compile time.
+template <int NC, int RPT, int NLC = -1>
 __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend) {
     constexpr int Q = RPT / 4;
-    const bool has_l = a.nl > 0, has_r = a.nr > 0;
-    const int nc = 1 + a.nl + a.nr;
+    const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
+    const bool has_l = nl > 0, has_r = nr > 0;
+    const int nc = 1 + nl + nr;
     const uint32_t s_first = wave_seg_of(a.seg_off, 0, a.ns - 1, j0);
     const uint32_t s_last = wave_seg_of(a.seg_off, s_first, a.ns - 1, jend - 1);
     // phase 1: each sub-chunk's segment and first (li, ri)
@@ -455,11 +458,11 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
 #pragma unroll
                 for (int col = 1; col < NC; col++)
                     if (col < nc)
-                        v[col][k] = col <= a.nl ? a.lcol[col - 1][lrow[q][k]] : a.rcol[col - 1 - a.nl][rrow[q][k]];
+                        v[col][k] = col <= nl ? a.lcol[col - 1][lrow[q][k]] : a.rcol[col - 1 - nl][rrow[q][k]];
             }
         } else {
             nk = (int)min((uint64_t)4, jend - j);
-            mat_rows_slow<NC>(a, qs[q], s_last, j, nk, v);
+            mat_rows_slow<NC, NLC>(a, qs[q], s_last, j, nk, v);
         }
         if (nk == 4) {
 #pragma unroll

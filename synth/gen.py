@@ -401,7 +401,8 @@ def serving_cfg5(w: Workload, n_queries: int, seed: int = 1, sample: int = 20_00
             e = nodes[int(r.integers(0, len(nodes)))]
             use_s = bool(r.integers(0, 2))
             arr, order = (s_sorted, by_s) if use_s else (o_sorted, by_o)
-            lo, hi = np.searchsorted(arr, e, "left"), np.searchsorted(arr, e, "right")
+            ev = np.int32(e)  # a typed scalar: no conversion of the whole array
+            lo, hi = int(np.searchsorted(arr, ev, "left")), int(np.searchsorted(arr, ev, "right"))
             if hi <= lo:
                 continue
             t = int(order[lo + int(r.integers(0, hi - lo))])

@@ -1,0 +1,89 @@
+"""Serving: each result is the same alone and in the mix (exact, row for
+row), admission by predicted bytes, and agreement with the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_03484_amd import binding as B
+from paper_1702_03484_amd import serving
+from synth import serving_cfg5, store_cfg5
+from tests.conftest import announce
+from tests.gpu_util import assert_same_bag
+from oracle.core import Table
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def served(sess):
+    w = store_cfg5(n=4_000_000, n_entities=800_000)
+    sess.load(w.s, w.p, w.o)
+    qs = serving_cfg5(w, 120, sample=2_000_000)
+    return w, qs
+
+
+def _alone(sess, qs):
+    out = {}
+    for j, q in enumerate(qs):
+        try:
+            t = B.mapsq_query(sess.ctx, q)
+        except B.MapSQError as e:
+            out[j] = e.code
+            continue
+        out[j] = (list(t.vars), sess.to_numpy(t))
+        B.mapsq_table_free(sess.ctx, t)
+    return out
+
+
+def test_results_alone_equal_results_in_the_mix(sess, served):
+    w, qs = served
+    announce(f"serving: {len(qs)} queries alone vs all at once vs Poisson arrivals")
+    alone = _alone(sess, qs)
+    ok = [j for j in alone if not isinstance(alone[j], int)]
+    assert len(ok) >= len(qs) // 2
+    for arrivals in (np.zeros(len(qs)), serving.poisson_arrivals(1, len(qs), 2000.0)):
+        got = {}
+        summ, lat, status = serving.run_continuous(sess, qs, arrivals, collect=got)
+        assert summ["rounds"] >= 1
+        for j in ok:
+            assert status[j] == 0, (j, status[j])
+            gv, gc = got[j]
+            av, ac = alone[j]
+            assert gv == av
+            assert all(np.array_equal(a, b) for a, b in zip(gc, ac)), f"query {j} differs in the mix"
+
+
+def test_served_results_match_the_oracle(sess, served):
+    w, qs = served
+    announce("serving: small results against the oracle")
+    got = {}
+    serving.run_continuous(sess, qs[:60], np.zeros(60), collect=got)
+    checked = 0
+    for j, (vs, cols) in got.items():
+        if cols and len(cols[0]) > 200_000:
+            continue
+        exp = oracle.query(w.s, w.p, w.o, qs[j])
+        assert_same_bag(Table(vs, cols, n=len(cols[0]) if cols else 0), exp)
+        checked += 1
+    assert checked >= 20
+
+
+def test_admission_budget_rejects_only_what_cannot_fit(sess, served):
+    w, qs = served
+    announce("serving: tiny admission budget")
+    summ, lat, status = serving.run_continuous(sess, qs[:40], np.zeros(40), budget_bytes=1 << 20, max_active=4)
+    assert summ["completed"] + summ["rejected"] == 40
+    assert summ["completed"] > 0
+    B.mapsq_serve_config(sess.ctx, 0, 0)
+
+
+def test_plain_and_continuous_agree(sess, served):
+    w, qs = served
+    announce("serving: plain form vs continuous batching")
+    a, b = {}, {}
+    serving.run_plain(sess, qs[:50], np.zeros(50), collect=a)
+    serving.run_continuous(sess, qs[:50], np.zeros(50), collect=b)
+    assert a.keys() == b.keys()
+    for j in a:
+        assert a[j][0] == b[j][0]
+        assert all(np.array_equal(x, y) for x, y in zip(a[j][1], b[j][1]))
