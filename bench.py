@@ -189,6 +189,49 @@ def run_cfg4(seed=1, n_sub=512, reps=2):
             "exact_vs_plain": exact}
 
 
+def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1.0, 2.0), seed=1):
+    """Serving over the resident store: plain one-query-at-a-time vs
+    continuous batching, Poisson arrivals at fractions of the plain form's
+    saturated rate; p50/p99 latency and completed queries/s."""
+    import numpy as np
+    import torch
+
+    from paper_1702_03484_amd import binding as B
+    from paper_1702_03484_amd import serving
+    from paper_1702_03484_amd.engine import MapSQ
+    from synth import serving_cfg5, store_cfg5
+
+    log(f"[cfg5] generating the {n_triples}-triple store")
+    t0 = time.perf_counter()
+    w = store_cfg5(n=n_triples, n_entities=max(1000, n_triples // 5))
+    log(f"[cfg5] generated in {time.perf_counter() - t0:.1f} s; drawing queries")
+    qs = serving_cfg5(w, warm + n_queries, seed=seed)
+    sess = MapSQ(arena_bytes=160 << 30)
+    info = sess.load(w.s, w.p, w.o)
+    del w
+    torch.cuda.synchronize()
+    log(f"[cfg5] store resident: {info.n_triples} triples, {info.n_predicates} predicates")
+    warm_q, qs = qs[:warm], qs[warm:]
+    serving.run_plain(sess, warm_q, np.zeros(len(warm_q)))
+    serving.run_continuous(sess, warm_q, np.zeros(len(warm_q)))
+    sat_plain, _, _ = serving.run_plain(sess, qs, np.zeros(len(qs)))
+    sat_cont, _, _ = serving.run_continuous(sess, qs, np.zeros(len(qs)))
+    log(f"[cfg5] saturated: plain {sat_plain['qps']:.0f} q/s, continuous {sat_cont['qps']:.0f} q/s")
+    rows = []
+    for f in loads:
+        qps = f * sat_plain["qps"]
+        arr = serving.poisson_arrivals(seed, len(qs), qps)
+        p, _, _ = serving.run_plain(sess, qs, arr)
+        c, _, _ = serving.run_continuous(sess, qs, arr)
+        rows.append({"load": f, "offered_qps": qps, "plain": p, "continuous": c})
+        log(f"[cfg5] load {f}: plain p50 {p['p50_ms']:.2f} ms p99 {p['p99_ms']:.2f} ms {p['qps']:.0f} q/s; "
+            f"continuous p50 {c['p50_ms']:.2f} ms p99 {c['p99_ms']:.2f} ms {c['qps']:.0f} q/s")
+    sess.close()
+    return {"workload": f"{info.n_triples}-triple resident store (128 predicates Zipf 1.0, entities Zipf 1.1 over "
+                        f"{n_triples // 5}), {len(qs)} random-walk queries of 1-5 patterns with 0-2 constants each",
+            "saturated_plain": sat_plain, "saturated_continuous": sat_cont, "poisson": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +242,8 @@ def main():
     ap.add_argument("--n", type=int, default=50_000_000, help="triples (default: the full workload)")
     ap.add_argument("--batched", action="store_true", help="add the 512-subquery batched-vs-plain measurement")
     ap.add_argument("--cfg4-only", action="store_true")
+    ap.add_argument("--serving", action="store_true", help="add the serving measurement (500M-triple store)")
+    ap.add_argument("--cfg5-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build runs the join on "
@@ -209,6 +254,9 @@ def main():
         return
     if args.cfg4_only:
         print(json.dumps(run_cfg4()), flush=True)
+        return
+    if args.cfg5_only:
+        print(json.dumps(run_cfg5()), flush=True)
         return
 
     import torch
@@ -256,7 +304,9 @@ def main():
     log(f"[bench] timed {args.steps} steps in {el:.4f} s")
 
     phases = {}
-    for k, name in enumerate(B.PHASES[:5]):
+    for k, name in enumerate(B.PHASES):
+        if name in ("index", "batch"):
+            continue
         n = prof.launches[k]
         if n == 0:
             continue
@@ -282,6 +332,7 @@ def main():
 
     sess.close()
     batched = run_cfg4() if args.batched else None
+    served = run_cfg5() if args.serving else None
     out = {
         "metric": "joined output rows/s",
         "value": rows * args.steps / el,
@@ -304,6 +355,7 @@ def main():
         "cpu_baseline": cpu,
         "phases": phases,
         "batched": batched,
+        "serving": served,
     }
     print(json.dumps(out), flush=True)
 

@@ -200,11 +200,17 @@ mapsq_status mapsq_join_batch(mapsq_ctx* ctx, const mapsq_join_desc* joins, int3
  * ranges and a predicted intermediate-byte cost (greedy plan, join sizes
  * estimated from per-predicate distinct counts); queries are admitted in
  * arrival order while the predicted bytes of all admitted queries stay
- * within the budget (a query predicted above the whole budget fails with
- * TOO_LARGE); newly admitted queries map their patterns; then the next join
- * step of every admitted query runs in one batched launch.  A query that
- * arrives while others are in flight joins the next round.  Each result is
- * exactly what mapsq_query returns for the query alone.  Serving calls use
+ * within the budget; a query predicted above the whole budget waits until
+ * nothing else is in flight and then runs alone.  Newly admitted queries
+ * map their patterns; then the next join step of every admitted query runs
+ * in one batched launch.  A step that finds no memory waits while other
+ * queries in flight hold memory; when a round makes no progress at all, the
+ * most recently admitted waiting query frees what it holds and is queued
+ * again at the head, and nothing is admitted until some query ends.  A
+ * query fails with TOO_LARGE only when it does not fit with nothing else in
+ * flight, or when an intermediate reaches 2^31 rows.  A query that arrives
+ * while others are in flight joins the next round.  Each result is exactly
+ * what mapsq_query returns for the query alone.  Serving calls use
  * the context like every other call: one thread at a time. */
 
 /* Budget of predicted intermediate bytes (0: 60% of the arena's free space
@@ -240,10 +246,12 @@ mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_p
  * (histogram and radix passes), 2 count (segment heads, LEFT/RIGHT split,
  * count and offset scan), 3 materialize, 4 equality filter, 5 index build.
  * Times come from hipEvents recorded on the context's stream around each
- * phase's launches; 6 is a whole batched launch (mapsq_join_batch).
+ * phase's launches; 6 is a whole batched launch (mapsq_join_batch); 7 is
+ * the gather of value cells into sorted record order that precedes
+ * materialisation when the result has at least as many rows as records.
  * Algorithmic bytes are what each phase must move given
  * the exact sizes (formulas in the design notes of the repository). */
-#define MAPSQ_NPHASES 7
+#define MAPSQ_NPHASES 8
 typedef struct {
     double ms[MAPSQ_NPHASES];
     double bytes[MAPSQ_NPHASES];

@@ -245,7 +245,7 @@ def project(T: Table, select) -> Table:
     return Table(list(select), [T.col(v) for v in select], n=T.n)
 
 
-def query(s, p, o, patterns, select=None) -> Table:
+def query(s, p, o, patterns, select=None, max_rows=None) -> Table:
     """Basic graph pattern evaluation by pattern-by-pattern merging (Section 2).
 
     Fixed oracle order: start from pattern 0, then repeatedly take the
@@ -253,7 +253,9 @@ def query(s, p, o, patterns, select=None) -> Table:
     ones and join on the first shared variable in the query's
     first-appearance order (the rest are filtered by equality); with none
     connected, take the lowest-index one by cross product.  Columns end in
-    first-appearance order, then ``select`` projects.
+    first-appearance order, then ``select`` projects.  With ``max_rows``,
+    an intermediate that would exceed it raises OverflowError before it is
+    built (a guard on the oracle's memory; results are unchanged).
     """
     order = query_vars(patterns)
     tabs = [match_pattern(s, p, o, pat) for pat in patterns]
@@ -268,6 +270,8 @@ def query(s, p, o, patterns, select=None) -> Table:
         if pick is None:
             pick = left[0]
             nxt = tabs[pick]
+            if max_rows is not None and cur.n * nxt.n > max_rows:
+                raise OverflowError("intermediate over max_rows")
             if not nxt.vars:
                 cur = Table(cur.vars, [np.tile(c, nxt.n) for c in cur.cols], n=cur.n * nxt.n)
             else:
@@ -275,6 +279,8 @@ def query(s, p, o, patterns, select=None) -> Table:
         else:
             nxt = tabs[pick]
             shared = [v for v in order if v in cur.vars and v in nxt.vars]
+            if max_rows is not None and join_cardinality(cur, nxt, shared[0]) > max_rows:
+                raise OverflowError("intermediate over max_rows")
             cur = join(cur, nxt, shared[0])
         left.remove(pick)
     vs = [v for v in order if v in cur.vars]

@@ -73,8 +73,8 @@ class mapsq_join_stats(ctypes.Structure):
     ]
 
 
-NPHASES = 7
-PHASES = ["map", "sort", "count", "materialize", "filter", "index", "batch"]
+NPHASES = 8
+PHASES = ["map", "sort", "count", "materialize", "filter", "index", "batch", "gather"]
 
 
 class mapsq_profile(ctypes.Structure):

@@ -55,17 +55,30 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
     std::vector<Plan> plan(n);
     int32_t kmax = 0;
     bool known = true;
+    std::vector<bool> invalid(n, false);
     for (int i = 0; i < n; i++) {
         mapsq_status st;
-        if ((st = check_table(ctx, d[i].left, "left")) || (st = check_table(ctx, d[i].right, "right"))) return st;
-        const mapsq_table* L = d[i].left;
-        const mapsq_table* R = d[i].right;
         Plan& p = plan[i];
         p.idx = i;
+        p.batched = false;
+        p.empty = false;
+        if ((st = check_table(ctx, d[i].left, "left")) || (st = check_table(ctx, d[i].right, "right"))) {
+            if (!per_join) return st;
+            per_join[i] = st;  // tolerant mode: this join fails alone
+            invalid[i] = true;
+            continue;
+        }
+        const mapsq_table* L = d[i].left;
+        const mapsq_table* R = d[i].right;
         p.lk = col_of(L, d[i].key_var);
         p.rk = col_of(R, d[i].key_var);
-        if (p.lk < 0 || p.rk < 0)
-            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "join " + std::to_string(i) + ": key variable not bound on both sides");
+        if (p.lk < 0 || p.rk < 0) {
+            if (!per_join)
+                return ctx->fail(MAPSQ_ERR_INVALID_ARG, "join " + std::to_string(i) + ": key variable not bound on both sides");
+            per_join[i] = MAPSQ_ERR_INVALID_ARG;
+            invalid[i] = true;
+            continue;
+        }
         bool extra = false;
         for (int c = 0; c < L->ncols; c++)
             if (c != p.lk) p.lv.push_back(c);
@@ -98,7 +111,7 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
     for (int i = 0; i < n; i++) {
         std::memset(&J[i], 0, sizeof(BatchJoin));
         const Plan& p = plan[i];
-        if (!p.batched) continue;
+        if (!p.batched || invalid[i]) continue;
         const mapsq_table* L = d[i].left;
         const mapsq_table* R = d[i].right;
         BatchJoin& b = J[i];
@@ -122,7 +135,7 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
     const uint64_t nrec = tiles * TILE;
 
     std::vector<mapsq_table> res(n);
-    std::vector<bool> done(n, false);
+    std::vector<bool> done(invalid);
     auto fail_all = [&](mapsq_status code, const std::string& msg) {
         for (int i = 0; i < n; i++) {
             free_table(ctx, &res[i]);

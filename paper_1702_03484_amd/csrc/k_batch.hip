@@ -248,9 +248,12 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
         mj.key_base = J.key_base;
         mj.nl = J.nvl;
         mj.nr = J.nvr;
-        mj.lcol = J.lcol;
-        mj.rcol = J.rcol;
-        mj.out = J.out;
+        mj.sorted_vals = false;
+#pragma unroll
+        for (int col = 0; col < BATCH_MAXNC; col++) {
+            mj.out[col] = J.out[col];
+            if (col >= 1) mj.src[col] = col <= J.nvl ? J.lcol[col - 1] : J.rcol[col - 1 - J.nvl];
+        }
         const uint64_t j0 = (c - J.chunk_off) * BMAT_WROWS;
         mat_wave_chunk<BATCH_MAXNC, BMAT_RPT>(mj, j0, min(j0 + BMAT_WROWS, J.total));
     }

@@ -107,11 +107,18 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     mj.n = a.n;
     mj.n_left = a.n_left;
     mj.key_base = a.key_base;
-    mj.nl = a.nl;
-    mj.nr = a.nr;
-    mj.lcol = a.lcol;
-    mj.rcol = a.rcol;
-    mj.out = a.out;
+    mj.nl = NLC >= 0 ? NLC : a.nl;
+    mj.nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
+    mj.sorted_vals = a.use_sval != 0;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        mj.out[c] = a.out[c];
+        if (c >= 1) {
+            const bool left = c <= mj.nl;
+            mj.src[c] = left ? a.lcol[c - 1] : a.rcol[c - 1 - mj.nl];
+            mj.ssrc[c] = left ? a.sval[c - 1] : a.sval[c - 1 - mj.nl];
+        }
+    }
     const uint64_t nchunks = (a.row_end - a.row_begin + WROWS - 1) / WROWS;
     const uint64_t gw = (uint64_t)blockIdx.x * MQ_WAVES + threadIdx.x / MQ_WAVE;
     const uint64_t nw = (uint64_t)gridDim.x * MQ_WAVES;
@@ -119,6 +126,28 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
         const uint64_t j0 = a.row_begin + c * WROWS;
         mat_wave_chunk<NC, MatShape<NC>::RPT, NLC>(mj, j0, min(j0 + WROWS, a.row_end));
     }
+}
+
+// One pass over the sorted records: every record's value columns move into
+// sorted order, so that materialisation reads contiguous ranges instead of
+// gathering each output row's values through its record id.
+__global__ __launch_bounds__(MQ_BLOCK) void gather_values_kernel(GatherArgs g) {
+    const uint32_t stride = gridDim.x * MQ_BLOCK;
+    for (uint32_t i = blockIdx.x * MQ_BLOCK + threadIdx.x; i < g.n; i += stride) {
+        const uint32_t r = g.vals[i];
+        if (r < g.n_left) {
+            for (int c = 0; c < g.nl; c++) g.out[c][i] = g.lcol[c][r];
+        } else {
+            for (int c = 0; c < g.nr; c++) g.out[c][i] = g.rcol[c][r - g.n_left];
+        }
+    }
+}
+
+hipError_t launch_gather_values(const GatherArgs& g, hipStream_t stream) {
+    if (g.n == 0 || (g.nl == 0 && g.nr == 0)) return hipSuccess;
+    const uint32_t blocks = std::min((g.n + MQ_BLOCK * 4 - 1) / (MQ_BLOCK * 4), 8192u);
+    gather_values_kernel<<<blocks, MQ_BLOCK, 0, stream>>>(g);
+    return hipGetLastError();
 }
 
 hipError_t launch_materialize(const MatArgs& a, hipStream_t stream) {

@@ -49,6 +49,19 @@ hipError_t launch_seg_count(uint32_t n, const uint32_t* seg_start, const uint32_
                             const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, uint64_t* status,
                             uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
 
+// Value columns in sorted record order: for every record i, with
+// r = vals[i], out[c][i] = lcol[c][r] (a LEFT record, r < n_left, c < nl) or
+// rcol[c][r - n_left] (a RIGHT record, c < nr).
+struct GatherArgs {
+    const uint32_t* vals;
+    uint32_t n, n_left;
+    int32_t nl, nr;
+    const int32_t* lcol[16];
+    const int32_t* rcol[16];
+    int32_t* out[16];
+};
+hipError_t launch_gather_values(const GatherArgs& g, hipStream_t stream);
+
 struct MatArgs {
     const uint32_t* keys;      // sorted relative keys
     const uint32_t* vals;      // sorted payloads (record positions)
@@ -64,6 +77,8 @@ struct MatArgs {
     const int32_t* rcol[16];
     int32_t* out[16];          // 1 + nl + nr output columns
     uint64_t row_begin, row_end;  // materialise output rows [row_begin, row_end)
+    const int32_t* sval[16];   // value columns in sorted record order (GatherArgs.out), if use_sval
+    int32_t use_sval;
 };
 hipError_t launch_materialize(const MatArgs& a, hipStream_t stream);
 

@@ -689,8 +689,9 @@ mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name) {
     if (!t) return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + " is null");
     if (t->ncols < 1 || t->ncols > MAPSQ_MAX_COLS)
         return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": ncols must be in [1, 16]");
-    if (t->nrows < 0 || t->nrows >= (int64_t(1) << 31))
-        return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": nrows must be in [0, 2^31)");
+    if (t->nrows < 0) return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": negative nrows");
+    if (t->nrows >= (int64_t(1) << 31))
+        return ctx->fail(MAPSQ_ERR_TOO_LARGE, std::string(name) + ": a join input of 2^31 rows or more");
     for (int c = 0; c < t->ncols; c++) {
         if (t->nrows > 0 && !t->col[c]) return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + ": null column");
         for (int d = 0; d < c; d++)
@@ -850,12 +851,41 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     for (int c = 0; c < nc_mat; c++) a.out[c] = m.col[c];
     a.row_begin = 0;
     a.row_end = total;
+    // values in sorted record order when output rows outnumber records
+    // (each record's values are then read many times)
+    const int nv = std::max(a.nl, a.nr);
+    const double value_cells = a.nl * (double)nL + a.nr * (double)nR;
+    Block sval;
+    if (nv > 0 && total >= N) sval = alloc_block(ctx, size_t(nv) * nb4);
+    if (sval.ok()) {
+        GatherArgs g{};
+        g.vals = svals;
+        g.n = N;
+        g.n_left = nL;
+        g.nl = a.nl;
+        g.nr = a.nr;
+        for (int i = 0; i < a.nl; i++) g.lcol[i] = a.lcol[i];
+        for (int i = 0; i < a.nr; i++) g.rcol[i] = a.rcol[i];
+        for (int c = 0; c < nv; c++) {
+            g.out[c] = reinterpret_cast<int32_t*>(ctx->arena.ptr(sval.off) + c * nb4);
+            a.sval[c] = g.out[c];
+        }
+        a.use_sval = 1;
+        ph = ctx->prof_begin(7);
+        hipError_t ge = launch_gather_values(g, ctx->stream);
+        // reads every payload and each value cell once, writes nv cells per record
+        ctx->prof_end(ph, 4.0 * N + 4.0 * value_cells + 4.0 * nv * (double)N);
+        if (ge != hipSuccess) {
+            free_table(ctx, &m);
+            return ctx->fail(MAPSQ_ERR_HIP, std::string("gather: ") + hipGetErrorString(ge));
+        }
+    }
     ph = ctx->prof_begin(3);
     hipError_t e = launch_materialize(a, ctx->stream);
-    // writes 4 B per output cell; reads every record's payload once, each
-    // segment's key and table entries, and each value cell of both sides
-    ctx->prof_end(ph, 4.0 * nc_mat * (double)total + 4.0 * N + 20.0 * nseg +
-                          4.0 * (a.nl * (double)nL + a.nr * (double)nR));
+    // writes 4 B per output cell; reads each segment's key and table entries
+    // and each value cell once (from the gathered copy when there is one,
+    // else through every record's payload)
+    ctx->prof_end(ph, 4.0 * nc_mat * (double)total + 20.0 * nseg + 4.0 * value_cells + (a.use_sval ? 0.0 : 4.0 * N));
     ctx->acc.joins += 1;
     ctx->acc.rows_out += (int64_t)total;
     if (e != hipSuccess) {

@@ -41,10 +41,8 @@ struct SQuery {
     size_t next = 0;
     mapsq_table cur{};
     mapsq_table result{};
-    int retries = 0;  // rounds a step waited for memory
+    uint64_t admitted = 0;  // admission order (the latest is preempted first)
 };
-
-constexpr int MAX_RETRIES = 64;
 
 }  // namespace
 
@@ -56,6 +54,8 @@ struct Server {
     double budget = 0;  // 0: set from the arena at the first round
     double reserved = 0;
     int max_active = 256;
+    uint64_t admissions = 0;
+    bool hold = false;  // after a preemption: admit nothing until a query ends
 };
 
 void destroy_server(Ctx* ctx) {
@@ -243,6 +243,24 @@ static void fail_query(Ctx* ctx, Server* S, SQuery* q, mapsq_status err) {
     if (q->state == Q_ACTIVE) S->reserved -= q->predicted;
     q->state = Q_FAILED;
     q->err = err;
+    S->hold = false;
+}
+
+// Give back everything a stalled query holds and queue it again at the head:
+// it restarts from its partial matches once a running query has ended.
+static void preempt_query(Ctx* ctx, Server* S, SQuery* q) {
+    for (size_t i = 0; i < q->tabs.size(); i++)
+        if (!q->consumed[i]) free_table(ctx, &q->tabs[i]);
+    if (q->cur.owned) free_table(ctx, &q->cur);
+    std::memset(&q->cur, 0, sizeof(mapsq_table));
+    q->tabs.clear();
+    q->consumed.clear();
+    q->steps.clear();
+    q->next = 0;
+    S->reserved -= q->predicted;
+    q->state = Q_WAITING;
+    S->waiting.push_front(q);
+    S->hold = true;
 }
 
 static void finish_query(Server* S, SQuery* q) {
@@ -250,6 +268,7 @@ static void finish_query(Server* S, SQuery* q) {
     std::memset(&q->cur, 0, sizeof(mapsq_table));
     q->state = Q_DONE;
     S->reserved -= q->predicted;
+    S->hold = false;
 }
 
 // Map the patterns of a newly admitted query and fix its plan on the exact
@@ -283,28 +302,54 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
     if (S->budget <= 0) S->budget = 0.6 * (double)ctx->arena.free_bytes();
     // 1. sizes, plans and predictions of the waiting queries; FIFO admission
+    // while the admitted predictions fit the budget.  A query predicted
+    // above the whole budget is not refused on the estimate: it waits for
+    // the active set to drain and then runs alone.
     mapsq_status st = size_waiting(ctx, S);
     if (st) return st;
-    while (!S->waiting.empty()) {
+    auto live_others = [&](const SQuery* q) {
+        int k = 0;
+        for (const SQuery* o : S->active) k += o != q && o->state == Q_ACTIVE;
+        return k;
+    };
+    bool exclusive = false;
+    for (SQuery* q : S->active)
+        if (q->state == Q_ACTIVE && q->predicted > S->budget) exclusive = true;
+    while (!S->waiting.empty() && !S->hold && !exclusive) {
         SQuery* q = S->waiting.front();
         if (q->predicted == 0) predict(ctx, q);
-        if (q->predicted > S->budget) {
-            S->waiting.pop_front();
-            q->state = Q_FAILED;
-            q->err = MAPSQ_ERR_TOO_LARGE;
-            continue;
-        }
-        if ((int)S->active.size() >= S->max_active || S->reserved + q->predicted > S->budget) break;
+        const bool oversize = q->predicted > S->budget;
+        if (oversize ? !S->active.empty()
+                     : ((int)S->active.size() >= S->max_active || S->reserved + q->predicted > S->budget))
+            break;
         S->waiting.pop_front();
         S->reserved += q->predicted;
         S->active.push_back(q);
         q->state = Q_ACTIVE;
+        q->admitted = ++S->admissions;
+        exclusive = oversize;
         st = activate(ctx, S, q);
-        if (st) fail_query(ctx, S, q, st);
+        if (st == MAPSQ_ERR_CAPACITY && live_others(q) > 0)
+            preempt_query(ctx, S, q);  // its partial matches do not fit yet
+        else if (st)
+            fail_query(ctx, S, q, st == MAPSQ_ERR_CAPACITY ? MAPSQ_ERR_TOO_LARGE : st);
     }
     // 2. the next join step of every active query, in one batched launch
     std::vector<SQuery*> in_batch;
     std::vector<mapsq_join_desc> descs;
+    int progress = 0;
+    // a finished step: the intermediate must stay joinable (under 2^31 rows)
+    auto advance = [&](SQuery* q, const mapsq_table& nxt, int pick) {
+        free_table(ctx, &q->cur);
+        free_table(ctx, &q->tabs[pick]);
+        q->consumed[pick] = true;
+        q->cur = nxt;
+        progress++;
+        if (++q->next == q->steps.size())
+            finish_query(S, q);
+        else if (q->cur.nrows >= (int64_t(1) << 31))
+            fail_query(ctx, S, q, MAPSQ_ERR_TOO_LARGE);
+    };
     for (SQuery* q : S->active) {
         if (q->state != Q_ACTIVE || q->next >= q->steps.size()) continue;
         const PlanStep& ps = q->steps[q->next];
@@ -313,41 +358,44 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
             st = cross_join(ctx, q->cur, q->tabs[ps.pick], &nxt);
             if (st) {
                 fail_query(ctx, S, q, st);
+                progress++;
                 continue;
             }
-            free_table(ctx, &q->cur);
-            free_table(ctx, &q->tabs[ps.pick]);
-            q->consumed[ps.pick] = true;
-            q->cur = nxt;
-            if (++q->next == q->steps.size()) finish_query(S, q);
+            advance(q, nxt, ps.pick);
             continue;
         }
         in_batch.push_back(q);
         descs.push_back(mapsq_join_desc{&q->cur, &q->tabs[ps.pick], ps.key, 0});
     }
+    std::vector<SQuery*> stalled;
     if (!descs.empty()) {
         std::vector<mapsq_table> outs(descs.size());
         std::vector<mapsq_status> per(descs.size());
         st = join_batch(ctx, descs.data(), (int32_t)descs.size(), outs.data(), per.data());
         if (st) return st;
-        const bool others = S->active.size() > 1;
         for (size_t k = 0; k < in_batch.size(); k++) {
             SQuery* q = in_batch[k];
-            const PlanStep& ps = q->steps[q->next];
             if (per[k] != MAPSQ_OK) {
-                // memory may free up when other queries finish: retry next round
-                if ((per[k] == MAPSQ_ERR_CAPACITY || per[k] == MAPSQ_ERR_TOO_LARGE) && others &&
-                    ++q->retries < MAX_RETRIES)
+                const bool memory = per[k] == MAPSQ_ERR_CAPACITY || per[k] == MAPSQ_ERR_TOO_LARGE;
+                // memory held by other running queries comes back when they
+                // end: wait.  Alone, the query cannot fit: refuse it.
+                if (memory && live_others(q) > 0) {
+                    stalled.push_back(q);
                     continue;
-                fail_query(ctx, S, q, per[k]);
+                }
+                fail_query(ctx, S, q, memory ? MAPSQ_ERR_TOO_LARGE : per[k]);
+                progress++;
                 continue;
             }
-            free_table(ctx, &q->cur);
-            free_table(ctx, &q->tabs[ps.pick]);
-            q->consumed[ps.pick] = true;
-            q->cur = outs[k];
-            if (++q->next == q->steps.size()) finish_query(S, q);
+            advance(q, outs[k], q->steps[q->next].pick);
         }
+    }
+    // a round in which every step waited for memory: the latest admitted
+    // waiting query gives its memory back and restarts later
+    if (progress == 0 && !stalled.empty()) {
+        SQuery* v = *std::max_element(stalled.begin(), stalled.end(),
+                                      [](const SQuery* a, const SQuery* b) { return a->admitted < b->admitted; });
+        preempt_query(ctx, S, v);
     }
     // 3. retire finished queries from the active set
     S->active.erase(std::remove_if(S->active.begin(), S->active.end(),

@@ -316,18 +316,27 @@ __device__ __forceinline__ uint32_t seg_of(const uint64_t* __restrict__ off, uin
     return lo;
 }
 
+constexpr int MAT_MAXNC = 16;
+
+// One join as seen by materialisation.  Output column c >= 1 takes its
+// values from src[c] (a LEFT value column when c <= nl, else a RIGHT one),
+// indexed by record id, or, when ssrc[c] is set, from ssrc[c] indexed by
+// sorted record position (values gathered into sorted order beforehand).
+// Held by value and indexed only with compile-time column numbers, so the
+// pointers stay in registers.
 struct MatJoin {
     const uint32_t* keys;  // sorted relative keys
-    const uint32_t* vals;  // sorted payloads
+    const uint32_t* vals;  // sorted payloads (record ids)
     const uint32_t* seg_start;
     const uint32_t* seg_split;
     const uint64_t* seg_off;
     uint32_t ns, n, n_left;
     int32_t key_base;
     int32_t nl, nr;
-    const int32_t* const* lcol;
-    const int32_t* const* rcol;
-    int32_t* const* out;
+    bool sorted_vals;
+    const int32_t* src[MAT_MAXNC];
+    const int32_t* ssrc[MAT_MAXNC];
+    int32_t* out[MAT_MAXNC];
 };
 
 // Rows [j, j + nk) of one lane, in order, when they may run into later
@@ -346,7 +355,7 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint
     const uint64_t r = j - so;
     uint32_t li = (uint32_t)(r / cr), ri = (uint32_t)(r - (uint64_t)li * cr);
     int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
-    uint32_t lrow = has_l ? a.vals[st + li] : 0u;
+    uint32_t lrow = (has_l && !a.sorted_vals) ? a.vals[st + li] : 0u;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         if (k < nk) {
@@ -360,16 +369,22 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint
                 li = 0;
                 ri = 0;
                 key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
-                lrow = has_l ? a.vals[st] : 0u;
+                lrow = (has_l && !a.sorted_vals) ? a.vals[st] : 0u;
             }
-            const uint32_t rrow = has_r ? a.vals[sp + ri] - a.n_left : 0u;
             v[0][k] = key;
+            if (a.sorted_vals) {
 #pragma unroll
-            for (int col = 1; col < NC; col++)
-                if (col < nc) v[col][k] = col <= nl ? a.lcol[col - 1][lrow] : a.rcol[col - 1 - nl][rrow];
+                for (int col = 1; col < NC; col++)
+                    if (col < nc) v[col][k] = a.ssrc[col][col <= nl ? st + li : sp + ri];
+            } else {
+                const uint32_t rrow = has_r ? a.vals[sp + ri] - a.n_left : 0u;
+#pragma unroll
+                for (int col = 1; col < NC; col++)
+                    if (col < nc) v[col][k] = a.src[col][col <= nl ? lrow : rrow];
+            }
             if (++ri == cr) {
                 ri = 0;
-                if (++li < cl && has_l) lrow = a.vals[st + li];
+                if (++li < cl && has_l && !a.sorted_vals) lrow = a.vals[st + li];
             }
         }
     }
@@ -425,8 +440,10 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
             qfast[q] = j + 4 <= jend && r + 4 <= (uint64_t)cl * cr;
         }
     }
-    // phase 2: payloads of the fast sub-chunks (independent loads)
+    // phase 2: the LEFT and RIGHT sorted positions of every fast row; their
+    // payloads (record ids) only when values are gathered through them
     uint32_t lrow[Q][4], rrow[Q][4];
+    const bool direct = a.sorted_vals;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
 #pragma unroll
@@ -439,8 +456,13 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
                     ri -= qcr[q];
                     li++;
                 }
-                if (has_l) lrow[q][k] = a.vals[qst[q] + li];
-                if (has_r) rrow[q][k] = a.vals[qsp[q] + ri] - a.n_left;
+                if (direct) {
+                    lrow[q][k] = qst[q] + li;
+                    rrow[q][k] = qsp[q] + ri;
+                } else {
+                    if (has_l) lrow[q][k] = a.vals[qst[q] + li];
+                    if (has_r) rrow[q][k] = a.vals[qsp[q] + ri] - a.n_left;
+                }
             }
         }
     }
@@ -455,10 +477,15 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 v[0][k] = qkey[q];
+                if (direct) {
 #pragma unroll
-                for (int col = 1; col < NC; col++)
-                    if (col < nc)
-                        v[col][k] = col <= nl ? a.lcol[col - 1][lrow[q][k]] : a.rcol[col - 1 - nl][rrow[q][k]];
+                    for (int col = 1; col < NC; col++)
+                        if (col < nc) v[col][k] = a.ssrc[col][col <= nl ? lrow[q][k] : rrow[q][k]];
+                } else {
+#pragma unroll
+                    for (int col = 1; col < NC; col++)
+                        if (col < nc) v[col][k] = a.src[col][col <= nl ? lrow[q][k] : rrow[q][k]];
+                }
             }
         } else {
             nk = (int)min((uint64_t)4, jend - j);

@@ -67,21 +67,29 @@ def test_cfg3_full_size(sess):
     assert t.vars == [0, 1, 2, 3] and int(t.nrows) == sel["j3_rows"]
     cols = sess.to_numpy(t)
     sess.free(t)
-    # J3 = J2 (x-star of the first three patterns) JOIN P4 on ?y; the last
-    # join groups the rows by ?y
-    j2 = oracle.query(w.s, w.p, w.o, pats[:3])
+    # plan-agnostic checks: every value of ?x and of ?y gets exactly as many
+    # rows as the oracle's counting says, and sampled ?x values get exactly
+    # the oracle's rows.  Rows with a given (x, y) from P1 number
+    # cnt_P2(x) * cnt_P3(x) * cnt_P4(y).
+    x, y = cols[0].astype(np.int64), cols[1].astype(np.int64)
+    p1 = oracle.pmt(w.s, w.p, w.o, pats[0])
+    p2 = oracle.pmt(w.s, w.p, w.o, pats[1])
+    p3 = oracle.pmt(w.s, w.p, w.o, pats[2])
     p4 = oracle.pmt(w.s, w.p, w.o, pats[3], key_var=1)
-    keys, c2, c4 = oracle.join_key_counts(j2, p4, 1)
-    y = cols[1]
-    gk, glen = runs(y)
-    assert np.array_equal(gk, keys) and np.array_equal(glen, c2 * c4)
-    starts = np.concatenate([[0], np.cumsum(glen)[:-1]])
+    E = w.n_entities
+    c2 = np.bincount(p2.col(0), minlength=E).astype(np.int64)
+    c3 = np.bincount(p3.col(0), minlength=E).astype(np.int64)
+    c4 = np.bincount(p4.col(1), minlength=E).astype(np.int64)
+    wgt = c2[p1.col(0)] * c3[p1.col(0)] * c4[p1.col(1)]
+    assert int(wgt.sum()) == sel["j3_rows"]
+    assert np.array_equal(np.bincount(x, minlength=E), np.bincount(p1.col(0), weights=wgt, minlength=E).astype(np.int64))
+    assert np.array_equal(np.bincount(y, minlength=E), np.bincount(p1.col(1), weights=wgt, minlength=E).astype(np.int64))
+    j2 = oracle.query(w.s, w.p, w.o, pats[:3])
+    xs = np.unique(x)
     r = np.random.default_rng(1)
-    for i in list(r.choice(keys.size, size=min(30, keys.size), replace=False)) + [int(np.argmax(c2 * c4))]:
-        k = keys[i]
-        sl = slice(starts[i], starts[i] + glen[i])
-        got = Table([0, 1, 2, 3], [c[sl] for c in cols])
-        a = Table(j2.vars, [c[j2.col(1) == k] for c in j2.cols])
-        b = Table(p4.vars, [c[p4.col(1) == k] for c in p4.cols])
-        exp = oracle.join(a, b, 1)
+    for k in r.choice(xs, size=min(25, xs.size), replace=False):
+        m = x == k
+        got = Table([0, 1, 2, 3], [c[m] for c in cols])
+        a = Table(j2.vars, [c[j2.col(0) == k] for c in j2.cols])
+        exp = oracle.join(a, p4, 1)
         assert np.array_equal(oracle.canonical_rows(got, [0, 1, 2, 3]), oracle.canonical_rows(exp, [0, 1, 2, 3]))

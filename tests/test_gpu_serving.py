@@ -50,19 +50,26 @@ def test_results_alone_equal_results_in_the_mix(sess, served):
             gv, gc = got[j]
             av, ac = alone[j]
             assert gv == av
-            assert all(np.array_equal(a, b) for a, b in zip(gc, ac)), f"query {j} differs in the mix"
+            if not all(np.array_equal(a, b) for a, b in zip(gc, ac)):
+                same_bag = np.array_equal(oracle.canonical_rows(Table(gv, gc, n=len(gc[0]))),
+                                          oracle.canonical_rows(Table(av, ac, n=len(ac[0]))))
+                raise AssertionError(f"query {j} {qs[j]} differs in the mix: rows {len(gc[0])} vs {len(ac[0])}, "
+                                     f"same bag: {same_bag}")
 
 
 def test_served_results_match_the_oracle(sess, served):
     w, qs = served
-    announce("serving: small results against the oracle")
+    announce("serving: results up to 5M rows against the oracle")
     got = {}
     serving.run_continuous(sess, qs[:60], np.zeros(60), collect=got)
     checked = 0
     for j, (vs, cols) in got.items():
-        if cols and len(cols[0]) > 200_000:
+        if cols and len(cols[0]) > 5_000_000:
             continue
-        exp = oracle.query(w.s, w.p, w.o, qs[j])
+        try:
+            exp = oracle.query(w.s, w.p, w.o, qs[j], max_rows=20_000_000)
+        except OverflowError:  # the oracle's fixed order would build a huge intermediate
+            continue
         assert_same_bag(Table(vs, cols, n=len(cols[0]) if cols else 0), exp)
         checked += 1
     assert checked >= 20
