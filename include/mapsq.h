@@ -85,7 +85,12 @@ typedef struct {
     int32_t* col[MAPSQ_MAX_COLS];/* device pointer of each column */
     uint64_t block;             /* library bookkeeping (arena block id); 0 for views */
     int32_t key_max;            /* upper bound of the IDs in the table, -1 if unknown */
-    int32_t reserved;
+    int32_t sorted_col;         /* 1 + a column whose values ascend over the rows, 0 if none is known.
+                                   Set by the library on index views (the index's next sort column)
+                                   and on join results (column 0, the key).  A caller that sets it on
+                                   its own table asserts that order; mapsq_join then pairs the two
+                                   tables' key runs directly when both are sorted on the key (a wrong
+                                   claim gives wrong rows, never an out-of-range access). */
 } mapsq_table;
 
 /* Facts about the loaded store. */
@@ -105,8 +110,13 @@ typedef struct {
     int32_t radix_bits;    /* digit width of the sort */
     int32_t passes;        /* radix passes */
     int32_t key_bits;      /* bits sorted */
-    int32_t reserved;
+    int32_t path;          /* MAPSQ_PATH_*: how the records were grouped by key */
+    int64_t sorted_records; /* records that went through the shuffle (0 for a merge join) */
 } mapsq_join_stats;
+
+#define MAPSQ_PATH_SORT 0     /* LSD radix sort of both sides' records */
+#define MAPSQ_PATH_SEMIJOIN 1 /* the same after the semi-join reduction of the larger side */
+#define MAPSQ_PATH_MERGE 2    /* both sides already sorted on the key: runs paired directly */
 
 /* Create a context on `device`.  `arena` is device memory of `arena_bytes`
  * bytes owned by the caller and kept alive until mapsq_destroy; it must be
@@ -237,9 +247,21 @@ mapsq_status mapsq_table_free(mapsq_ctx* ctx, mapsq_table* t);
 mapsq_status mapsq_last_join_stats(mapsq_ctx* ctx, mapsq_join_stats* out);
 
 /* Radix digit width (4..11 bits; 0 = automatic) and keys per thread of the
- * sort tiles (8, 16 or 24; 0 = automatic) used by later joins.  Every choice
+ * sort tiles (8 or 16; 0 = automatic) used by later joins.  Every choice
  * gives the same rows in the same order. */
 mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_per_thread);
+
+/* How mapsq_join / mapsq_query group records by key; every choice gives
+ * the same rows in the same order.
+ * semijoin: a record whose key the other side lacks meets no partner in
+ *   Reduce (Algorithm 1), so it can be left out of the shuffle.  0 =
+ *   automatic (the larger side has at least 2^16 records and 4 times the
+ *   smaller side's, and the key bitmap is no larger than the larger side's
+ *   key column), 1 = never, 2 = whenever the bitmap fits in 1 GiB.
+ * merge: 0 = pair the key runs directly when both tables are sorted on the
+ *   key (sorted_col), 1 = always shuffle.
+ * INVALID_ARG for other values. */
+mapsq_status mapsq_set_join_options(mapsq_ctx* ctx, int32_t semijoin, int32_t merge);
 
 /* Per-phase device time and algorithmic bytes, accumulated while profiling
  * is on.  Phases: 0 map (range location and scan/compaction), 1 sort
@@ -248,10 +270,12 @@ mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_p
  * Times come from hipEvents recorded on the context's stream around each
  * phase's launches; 6 is a whole batched launch (mapsq_join_batch); 7 is
  * the gather of value cells into sorted record order that precedes
- * materialisation when the result has at least as many rows as records.
+ * materialisation when the result has at least as many rows as records;
+ * 8 is the semi-join reduction (key bitmap and filtered records).  A merge
+ * join's segment pass counts under 2 (count).
  * Algorithmic bytes are what each phase must move given
  * the exact sizes (formulas in the design notes of the repository). */
-#define MAPSQ_NPHASES 8
+#define MAPSQ_NPHASES 9
 typedef struct {
     double ms[MAPSQ_NPHASES];
     double bytes[MAPSQ_NPHASES];

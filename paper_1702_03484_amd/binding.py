@@ -21,6 +21,7 @@ MAPSQ_ERR_CAPACITY = -3
 MAPSQ_ERR_TOO_LARGE = -4
 MAPSQ_ERR_HIP = -5
 MAPSQ_ERR_STATE = -6
+MAPSQ_PATH_SORT, MAPSQ_PATH_SEMIJOIN, MAPSQ_PATH_MERGE = 0, 1, 2
 MAPSQ_LOAD_DEVICE_PTRS = 1
 MAPSQ_LOAD_DEDUP = 2
 
@@ -42,7 +43,7 @@ class mapsq_table(ctypes.Structure):
         ("col", ctypes.c_void_p * MAX_COLS),
         ("block", ctypes.c_uint64),
         ("key_max", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("sorted_col", ctypes.c_int32),
     ]
 
     @property
@@ -69,12 +70,13 @@ class mapsq_join_stats(ctypes.Structure):
         ("radix_bits", ctypes.c_int32),
         ("passes", ctypes.c_int32),
         ("key_bits", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("sorted_records", ctypes.c_int64),
     ]
 
 
-NPHASES = 8
-PHASES = ["map", "sort", "count", "materialize", "filter", "index", "batch", "gather"]
+NPHASES = 9
+PHASES = ["map", "sort", "count", "materialize", "filter", "index", "batch", "gather", "semijoin"]
 
 
 class mapsq_profile(ctypes.Structure):
@@ -133,6 +135,7 @@ _SIGS = [
     ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
     ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
     ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
+    ("mapsq_set_join_options", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_profile_enable", ctypes.c_int32, [_P, ctypes.c_int32]),
     ("mapsq_profile_read", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_profile)]),
     ("mapsq_tune_record", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -268,6 +271,12 @@ def mapsq_last_join_stats(ctx) -> mapsq_join_stats:
     return out
 
 
+def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0):
+    """semijoin: 0 automatic, 1 never, 2 always; merge: 0 when both sides are
+    sorted on the key, 1 never (every choice gives the same rows in the same order)."""
+    _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge))
+
+
 def mapsq_set_tuning(ctx, radix_bits: int = 0, keys_per_thread: int = 0):
     _check(ctx, lib().mapsq_set_tuning(ctx, radix_bits, keys_per_thread))
 
@@ -293,13 +302,15 @@ def mapsq_arena_free_bytes(ctx):
     return int(a.value), int(b.value)
 
 
-def make_table(vars, col_ptrs, nrows: int, key_max: int = -1) -> mapsq_table:
-    """A caller-owned table (owned = 0) over existing device columns."""
+def make_table(vars, col_ptrs, nrows: int, key_max: int = -1, sorted_col: int = 0) -> mapsq_table:
+    """A caller-owned table (owned = 0) over existing device columns;
+    sorted_col = 1 + a column the caller guarantees to be ascending, or 0."""
     t = mapsq_table()
     t.nrows = nrows
     t.ncols = len(vars)
     t.owned = 0
     t.key_max = key_max
+    t.sorted_col = sorted_col
     for i, (v, p) in enumerate(zip(vars, col_ptrs)):
         t.var[i] = v
         t.col[i] = p

@@ -153,6 +153,7 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         for (int c : p.lv) t->var[k++] = L->var[c];
         for (int c : p.rv) t->var[k++] = R->var[c];
         t->key_max = (L->key_max >= 0 && R->key_max >= 0) ? std::max(L->key_max, R->key_max) : -1;
+        t->sorted_col = 1;  // grouped by ascending key
     };
 
     if (tiles > 0) {

@@ -191,6 +191,16 @@ mapsq_status mapsq_last_join_stats(mapsq_ctx* c, mapsq_join_stats* out) {
     });
 }
 
+mapsq_status mapsq_set_join_options(mapsq_ctx* c, int32_t semijoin, int32_t merge) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (semijoin < 0 || semijoin > 2) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "semijoin must be 0, 1 or 2");
+        if (merge < 0 || merge > 1) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "merge must be 0 or 1");
+        ctx->semijoin = semijoin;
+        ctx->merge_mode = merge;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
 mapsq_status mapsq_set_tuning(mapsq_ctx* c, int32_t radix_bits, int32_t keys_per_thread) {
     return guarded(c, [&](Ctx* ctx) {
         if (radix_bits != 0 && (radix_bits < 4 || radix_bits > 11))

@@ -249,6 +249,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
         mj.nl = J.nvl;
         mj.nr = J.nvr;
         mj.sorted_vals = false;
+        mj.seg_cl = nullptr;
+        mj.seg_cr = nullptr;
 #pragma unroll
         for (int col = 0; col < BATCH_MAXNC; col++) {
             mj.out[col] = J.out[col];

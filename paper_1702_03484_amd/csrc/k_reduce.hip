@@ -109,14 +109,18 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     mj.key_base = a.key_base;
     mj.nl = NLC >= 0 ? NLC : a.nl;
     mj.nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
-    mj.sorted_vals = a.use_sval != 0;
+    const bool merged = a.seg_cl != nullptr;
+    mj.sorted_vals = merged || a.use_sval != 0;
+    mj.seg_cl = a.seg_cl;
+    mj.seg_cr = a.seg_cr;
 #pragma unroll
     for (int c = 0; c < NC; c++) {
         mj.out[c] = a.out[c];
         if (c >= 1) {
             const bool left = c <= mj.nl;
             mj.src[c] = left ? a.lcol[c - 1] : a.rcol[c - 1 - mj.nl];
-            mj.ssrc[c] = left ? a.sval[c - 1] : a.sval[c - 1 - mj.nl];
+            // merge join: runs index the tables' own (key-sorted) columns
+            mj.ssrc[c] = merged ? mj.src[c] : (left ? a.sval[c - 1] : a.sval[c - 1 - mj.nl]);
         }
     }
     const uint64_t nchunks = (a.row_end - a.row_begin + WROWS - 1) / WROWS;

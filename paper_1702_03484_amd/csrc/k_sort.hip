@@ -60,14 +60,38 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_hist_kernel(SortSrc src, const
     for (int i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) row[i] = sh[i];
 }
 
-// hist[i] = sum over the partial rows (one thread per counter)
-__global__ void hist_reduce_kernel(const uint32_t* __restrict__ part, uint32_t rows, uint32_t width,
-                                   uint32_t* __restrict__ hist) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= width) return;
+// hist[c] = sum over the partial rows.  A block of 16 waves owns 64
+// counters: lane L of wave w adds rows w, w + 16, ... of counter c0 + L
+// (coalesced 256-byte row slices, four loads in flight per lane), and the
+// 16 partial sums meet in LDS.
+constexpr int HRED_WAVES = 16;
+
+__global__ __launch_bounds__(HRED_WAVES * MQ_WAVE) void hist_reduce_kernel(const uint32_t* __restrict__ part,
+                                                                           uint32_t rows, uint32_t width,
+                                                                           uint32_t* __restrict__ hist) {
+    __shared__ uint32_t sh[HRED_WAVES][MQ_WAVE];
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint32_t c = blockIdx.x * MQ_WAVE + lane();
     uint32_t s = 0;
-    for (uint32_t r = 0; r < rows; r++) s += part[(uint64_t)r * width + i];
-    hist[i] = s;
+    if (c < width) {
+        uint32_t r = w;
+        for (; r + 3 * HRED_WAVES < rows; r += 4 * HRED_WAVES) {
+            const uint32_t a0 = part[(uint64_t)r * width + c];
+            const uint32_t a1 = part[(uint64_t)(r + HRED_WAVES) * width + c];
+            const uint32_t a2 = part[(uint64_t)(r + 2 * HRED_WAVES) * width + c];
+            const uint32_t a3 = part[(uint64_t)(r + 3 * HRED_WAVES) * width + c];
+            s += (a0 + a1) + (a2 + a3);
+        }
+        for (; r < rows; r += HRED_WAVES) s += part[(uint64_t)r * width + c];
+    }
+    sh[w][lane()] = s;
+    __syncthreads();
+    if (w == 0 && c < width) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int k = 0; k < HRED_WAVES; k++) t += sh[k][lane()];
+        hist[c] = t;
+    }
 }
 
 uint32_t radix_hist_part_words(int rb, int passes) { return HIST_BLOCKS * (uint32_t)passes << rb; }
@@ -125,7 +149,7 @@ hipError_t launch_radix_hist(const SortSrc& src, const uint32_t* keys, uint32_t 
     }
 #undef MQ_H
     const uint32_t width = (uint32_t)passes << rb;
-    hist_reduce_kernel<<<(width + 255) / 256, 256, 0, stream>>>(part, blocks, width, hist);
+    hist_reduce_kernel<<<(width + MQ_WAVE - 1) / MQ_WAVE, HRED_WAVES * MQ_WAVE, 0, stream>>>(part, blocks, width, hist);
     return hipGetLastError();
 }
 

@@ -21,6 +21,53 @@ struct SortSrc {
     int32_t base;
 };
 
+// Merge join of two tables already sorted on the key (k_merge.hip).  One
+// pass over the smaller side: at the head of each key run, the run's end is
+// found by galloping and the key's run in the larger side by binary search;
+// keys present on both sides become segments (ascending key), each with its
+// LEFT run, RIGHT run and output offset; *nseg and *total get the counts.
+struct MergeArgs {
+    const int32_t* skey;   // smaller side's key column (sorted)
+    uint32_t ns;
+    const int32_t* bkey;   // larger side's key column (sorted)
+    uint32_t nb;
+    int32_t small_is_left;
+    uint32_t* seg_lstart;
+    uint32_t* seg_lcount;
+    uint32_t* seg_rstart;
+    uint32_t* seg_rcount;
+    uint64_t* seg_off;
+    uint32_t* nseg;
+    uint64_t* total;
+};
+hipError_t launch_merge_segments(const MergeArgs& a, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch,
+                                 hipStream_t stream);
+uint32_t merge_tiles(uint32_t ns);
+
+// Semi-join reduction (k_semi.hip).  Bits of keys - base are set in bm
+// (range bits, cleared by the caller); the filter keeps the records of
+// `keys` whose relative key is set, writing (relative key, id_base + index)
+// in input order to kout/vout and the kept count to *count.
+struct SemiArgs {
+    const int32_t* keys;
+    uint32_t n;
+    int32_t base;
+    uint64_t range;  // bits in bm
+    const uint32_t* bm;
+    uint32_t id_base;
+    uint32_t* kout;
+    uint32_t* vout;
+    uint32_t* count;
+};
+hipError_t launch_bitmap_set(const int32_t* keys, uint32_t n, int32_t base, uint64_t range, uint32_t* bm,
+                             hipStream_t stream);
+hipError_t launch_semi_filter(const SemiArgs& a, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch,
+                              hipStream_t stream);
+uint32_t semi_filter_tiles(uint32_t n);
+// all n records of one side at kout/vout[(*at_dev or 0) + i]
+hipError_t launch_side_records(const int32_t* keys, uint32_t n, int32_t base, uint32_t id_base,
+                               const uint32_t* at_dev, uint32_t* kout, uint32_t* vout, hipStream_t stream);
+
 // Digit histograms of `passes` passes into hist[passes][2^rb] (overwritten).
 // keys == nullptr: read the keys from `src`.  `part` is scratch of
 // radix_hist_part_words(rb, passes) words.
@@ -79,6 +126,11 @@ struct MatArgs {
     uint64_t row_begin, row_end;  // materialise output rows [row_begin, row_end)
     const int32_t* sval[16];   // value columns in sorted record order (GatherArgs.out), if use_sval
     int32_t use_sval;
+    // merge join (seg_cl != null): segment s pairs LEFT rows [seg_start[s],
+    // + seg_cl[s]) of lcol with RIGHT rows [seg_split[s], + seg_cr[s]) of
+    // rcol; keys is the LEFT key column (key_base 0); vals and sval unused
+    const uint32_t* seg_cl;
+    const uint32_t* seg_cr;
 };
 hipError_t launch_materialize(const MatArgs& a, hipStream_t stream);
 

@@ -79,6 +79,7 @@ static mapsq_status with_zero_key(Ctx* ctx, const mapsq_table& t, mapsq_table* o
     out->ncols = t.ncols + 1;
     out->key_max = std::max(t.key_max, 0);
     if (t.key_max < 0) out->key_max = -1;
+    out->sorted_col = t.ncols + 1;  // a constant column is in order: the join pairs the two runs directly
     return MAPSQ_OK;
 }
 
@@ -98,6 +99,7 @@ mapsq_status cross_join(Ctx* ctx, const mapsq_table& cur, const mapsq_table& oth
     nxt->ncols -= 1;
     nxt->col[nxt->ncols] = nullptr;
     nxt->key_max = (cur.key_max >= 0 && other.key_max >= 0) ? std::max(cur.key_max, other.key_max) : -1;
+    nxt->sorted_col = 0;
     return MAPSQ_OK;
 }
 
@@ -105,12 +107,14 @@ mapsq_status cross_join(Ctx* ctx, const mapsq_table& cur, const mapsq_table& oth
 // table keeps its block).
 mapsq_table project_table(const mapsq_table& cur, const std::vector<int32_t>& want) {
     mapsq_table res = cur;
+    res.sorted_col = 0;
     for (size_t i = 0; i < want.size(); i++) {
         int c = -1;
         for (int k = 0; k < cur.ncols; k++)
             if (cur.var[k] == want[i]) c = k;
         res.var[i] = want[i];
         res.col[i] = cur.col[c];
+        if (cur.sorted_col == c + 1) res.sorted_col = (int32_t)i + 1;
     }
     for (size_t i = want.size(); i < MAPSQ_MAX_COLS; i++) {
         res.var[i] = 0;
@@ -185,6 +189,30 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
     int start;
     std::vector<PlanStep> steps;
     greedy_plan(tv, tr, qvars, &start, &steps);
+    // a view can be re-made from the other index so that its rows ascend on
+    // the key it is joined on (then the join needs no shuffle)
+    auto key_sorted = [&](int i, int32_t key) {
+        const int kc = col_of(&tabs[i], key);
+        if (tabs[i].owned || kc < 0 || tabs[i].sorted_col == kc + 1) return MAPSQ_OK;
+        mapsq_table t{};
+        mapsq_status s2 = map_pattern(ctx, &pats[i], key, &t);
+        if (s2) return s2;
+        if (t.owned) {
+            free_table(ctx, &t);
+        } else if (t.sorted_col == 1) {
+            tabs[i] = t;
+        }
+        return MAPSQ_OK;
+    };
+    for (size_t k = 0; k < steps.size(); k++) {
+        if (steps[k].cross) continue;
+        mapsq_status s2 = key_sorted(steps[k].pick, steps[k].key);
+        if (!s2 && k == 0) s2 = key_sorted(start, steps[k].key);
+        if (s2) {
+            cleanup();
+            return s2;
+        }
+    }
     mapsq_table cur = tabs[start];
     used[start] = true;
     for (const PlanStep& ps : steps) {

@@ -173,9 +173,9 @@ static inline uint32_t* scalar32(Ctx* ctx, int word) { return ctx->small + SMALL
 static inline uint32_t* counter(Ctx* ctx, int i) { return ctx->small + SMALL_CTR + i; }
 
 // scalar slots (u32 word index inside the scalar area)
-enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10 };
+enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12 };
 // counter slots
-enum { CT_PASS0 = 0, CT_HEADS = 8, CT_COUNT = 9, CT_COMPACT = 10 };
+enum { CT_PASS0 = 0, CT_HEADS = 8, CT_COUNT = 9, CT_COMPACT = 10, CT_SEMI = 11 };
 
 static mapsq_status readback(Ctx* ctx, const void* dev, size_t bytes, void* host) {
     HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
@@ -560,6 +560,7 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
     bool s_const = term[0] >= 0, p_const = term[1] >= 0, o_const = term[2] >= 0;
     int nterm = 0;
     int32_t ta[6], tb[6], tc[6];
+    int sorted_pos = -1;  // the store position whose values ascend over the rows, if any
     if (p_const) {
         int pi = find_pred(S, term[1]);
         if (pi < 0) {
@@ -580,14 +581,22 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
                 q.col2 = S.pso_o;
                 q.v2 = term[2];
             }
+            sorted_pos = 2;
         } else if (o_const) {  // POS: (p, o)
             col[0] = S.pos_s;
             col[2] = S.pos_o;
             q.col1 = S.pos_o;
             q.v1 = term[2];
+            sorted_pos = 0;
+        } else if (key_var >= 0 && term[2] == -key_var - 1 && term[0] != term[2]) {
+            // POS, so that the rows come sorted on the key (the object)
+            col[0] = S.pos_s;
+            col[2] = S.pos_o;
+            sorted_pos = 2;
         } else {
             col[0] = S.pso_s;
             col[2] = S.pso_o;
+            sorted_pos = 0;
         }
         col[1] = nullptr;
         if (q.col1) {
@@ -619,6 +628,11 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
         nterm++;
     }
     const int64_t rows = hi - lo;
+    // rows of an index range (and any order-preserving compaction of them)
+    // ascend on the index's next sort column
+    if (sorted_pos >= 0 && term[sorted_pos] < 0)
+        for (int c = 0; c < ncols; c++)
+            if (out->var[c] == -term[sorted_pos] - 1) out->sorted_col = c + 1;
     if (nterm == 0) {
         // a view of the store
         out->owned = 0;
@@ -739,6 +753,73 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         }
         t->ncols = nc_out;
         t->key_max = (L->key_max >= 0 && R->key_max >= 0) ? std::max(L->key_max, R->key_max) : -1;
+        t->sorted_col = 1;  // rows come out grouped by ascending key
+    };
+    // The materialised result m (nc_mat columns, total rows): further shared
+    // variables keep the rows where both copies agree and drop R's copy.
+    auto finish = [&](mapsq_table& m, uint64_t total) -> mapsq_status {
+        hipError_t e;
+        int ph;
+        if (extra_r.empty()) {
+            out->owned = 1;
+            out->block = m.block;
+            out->nrows = (int64_t)total;
+            for (int c = 0; c < nc_mat; c++) out->col[c] = m.col[c];
+            return MAPSQ_OK;
+        }
+        // further shared variables: keep rows where both copies agree, drop R's copy
+        mapsq_table f{};
+        if (alloc_table(ctx, (int64_t)total, nc_out, &f)) {
+            free_table(ctx, &m);
+            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "filtered join result exceeds the arena's free space");
+        }
+        CompactArgs c{};
+        c.nin = nc_mat;
+        for (int i = 0; i < nc_mat; i++) c.in[i] = m.col[i];
+        c.n = total;
+        c.nterm = 0;
+        for (size_t i = 0; i < extra_r.size(); i++) {
+            if (c.nterm >= 6) {
+                free_table(ctx, &m);
+                free_table(ctx, &f);
+                return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 6 further shared variables");
+            }
+            int li = 1 + int(std::find(lv.begin(), lv.end(), extra_l[i]) - lv.begin());
+            int ri = 1 + (int)lv.size() + int(std::find(rv.begin(), rv.end(), extra_r[i]) - rv.begin());
+            c.term_a[c.nterm] = li;
+            c.term_b[c.nterm] = ri;
+            c.nterm++;
+        }
+        c.nout = 0;
+        for (int i = 0; i < nc_mat; i++) {
+            bool drop = i >= 1 + (int)lv.size() &&
+                        std::find(extra_r.begin(), extra_r.end(), rv[i - 1 - lv.size()]) != extra_r.end();
+            if (!drop) {
+                c.out_src[c.nout] = i;
+                c.out[c.nout] = f.col[c.nout];
+                c.nout++;
+            }
+        }
+        c.count = scalar64(ctx, SC_COUNT);
+        uint64_t kept = 0;
+        e = hipSuccess;
+        if (!ctx->ensure_status(size_t(total / 4096 + 2))) e = hipErrorOutOfMemory;
+        ph = ctx->prof_begin(4);
+        if (e == hipSuccess) e = launch_fill_u32(counter(ctx, CT_COMPACT), 1, 0u, ctx->stream);
+        if (e == hipSuccess) e = launch_compact(c, ctx->status, counter(ctx, CT_COMPACT), ctx->next_epoch(), ctx->stream);
+        ctx->prof_end(ph, 4.0 * (double)c.nterm * 2 * total);
+        if (e == hipSuccess) st = readback(ctx, scalar64(ctx, SC_COUNT), 8, &kept);
+        if (ph >= 0) ctx->pending[ph].bytes += 4.0 * (double)c.nout * (double)kept;
+        free_table(ctx, &m);
+        if (e != hipSuccess || st) {
+            free_table(ctx, &f);
+            return e != hipSuccess ? ctx->fail(MAPSQ_ERR_HIP, "equality filter launch failed") : st;
+        }
+        out->owned = 1;
+        out->block = f.block;
+        out->nrows = (int64_t)kept;
+        for (int i = 0; i < nc_out; i++) out->col[i] = f.col[i];
+        return MAPSQ_OK;
     };
     mapsq_join_stats js{};
     js.left_rows = nL;
@@ -751,9 +832,87 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         return MAPSQ_OK;
     }
 
-    // key range: known bound, else a min/max pass
+    // Both tables already in key order (PSO/POS views, results of a join on
+    // this key): Reduce straight from the two sides' key runs, no shuffle.
     const int32_t* lkey = L->col[lk];
     const int32_t* rkey = R->col[rk];
+    if (ctx->merge_mode == 0 && L->sorted_col == lk + 1 && R->sorted_col == rk + 1) {
+        const bool small_left = nL <= nR;
+        const uint32_t nsm = small_left ? nL : nR, nbg = small_left ? nR : nL;
+        const size_t sb4 = align_up(size_t(nsm) * 4, ARENA_ALIGN);
+        Block seg = alloc_block(ctx, sb4 * 4 + align_up(size_t(nsm) * 8, ARENA_ALIGN));
+        if (!seg.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for merge segments");
+        if (!ctx->ensure_status(2 * size_t(merge_tiles(nsm)) + 2))
+            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
+        char* sp = ctx->arena.ptr(seg.off);
+        uint32_t* seg_ls = reinterpret_cast<uint32_t*>(sp);
+        uint32_t* seg_lc = reinterpret_cast<uint32_t*>(sp + sb4);
+        uint32_t* seg_rs = reinterpret_cast<uint32_t*>(sp + 2 * sb4);
+        uint32_t* seg_rc = reinterpret_cast<uint32_t*>(sp + 3 * sb4);
+        uint64_t* seg_off = reinterpret_cast<uint64_t*>(sp + 4 * sb4);
+        MergeArgs ma{small_left ? lkey : rkey, nsm, small_left ? rkey : lkey, nbg, small_left ? 1 : 0,
+                     seg_ls, seg_lc, seg_rs, seg_rc, seg_off, scalar32(ctx, SC_NSEG), scalar64(ctx, SC_TOTAL)};
+        int ph = ctx->prof_begin(2);
+        HIPCHK(launch_fill_u32(counter(ctx, CT_COUNT), 1, 0u, ctx->stream));
+        HIPCHK(launch_merge_segments(ma, ctx->status, counter(ctx, CT_COUNT), ctx->next_epoch(), ctx->stream));
+        ctx->prof_end(ph, 0.0);
+        uint32_t sc[4];
+        if ((st = readback(ctx, scalar32(ctx, SC_NSEG), 16, sc))) return st;
+        const uint32_t nseg = sc[0];
+        uint64_t total;
+        std::memcpy(&total, &sc[2], 8);
+        // reads the smaller side's keys; writes 24 B per segment
+        if (ph >= 0) ctx->pending[ph].bytes = 4.0 * nsm + 24.0 * nseg;
+        js.segments = nseg;
+        js.out_rows = (int64_t)total;
+        js.path = MAPSQ_PATH_MERGE;
+        js.sorted_records = 0;
+        ctx->last = js;
+        if (total >= SAT40_HOST) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds 2^40 rows");
+        set_meta(out);
+        if (total == 0) {
+            out->owned = 1;
+            out->nrows = 0;
+            return MAPSQ_OK;
+        }
+        mapsq_table m{};
+        const size_t colb = align_up(size_t(total) * 4, ARENA_ALIGN);
+        if (ctx->arena.largest() < colb * nc_mat)
+            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result (" + std::to_string(total) +
+                                                      " rows) exceeds the arena's free space");
+        if (alloc_table(ctx, (int64_t)total, nc_mat, &m))
+            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds the arena's free space");
+        MatArgs a{};
+        a.keys = reinterpret_cast<const uint32_t*>(lkey);
+        a.seg_start = seg_ls;
+        a.seg_split = seg_rs;
+        a.seg_cl = seg_lc;
+        a.seg_cr = seg_rc;
+        a.seg_off = seg_off;
+        a.nseg = scalar32(ctx, SC_NSEG);
+        a.key_base = 0;
+        a.nl = (int)lv.size();
+        a.nr = (int)rv.size();
+        for (int i = 0; i < a.nl; i++) a.lcol[i] = L->col[lv[i]];
+        for (int i = 0; i < a.nr; i++) a.rcol[i] = R->col[rv[i]];
+        for (int c = 0; c < nc_mat; c++) a.out[c] = m.col[c];
+        a.row_begin = 0;
+        a.row_end = total;
+        ph = ctx->prof_begin(3);
+        hipError_t e = launch_materialize(a, ctx->stream);
+        // writes 4 B per output cell and reads the segment table (the value
+        // cells of the matched runs are not counted)
+        ctx->prof_end(ph, 4.0 * nc_mat * (double)total + 24.0 * nseg);
+        ctx->acc.joins += 1;
+        ctx->acc.rows_out += (int64_t)total;
+        if (e != hipSuccess) {
+            free_table(ctx, &m);
+            return ctx->fail(MAPSQ_ERR_HIP, std::string("materialize: ") + hipGetErrorString(e));
+        }
+        return finish(m, total);
+    }
+
+    // key range: known bound, else a min/max pass
     int32_t kmin = 0, kmax;
     if (L->key_max >= 0 && R->key_max >= 0) {
         kmax = std::max(L->key_max, R->key_max);
@@ -782,23 +941,80 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
                {reinterpret_cast<uint32_t*>(sb + 2 * nb4), reinterpret_cast<uint32_t*>(sb + 3 * nb4)}};
     uint64_t* seg_off = reinterpret_cast<uint64_t*>(sb + 4 * nb4);
 
-    // Map + Sort: first pass reads the LEFT then the RIGHT key column
+    // Semi-join reduction: when one side is much larger, only its records
+    // whose key the other side has are sorted (same rows, same order).
+    uint32_t Ns = N;  // records that go through the shuffle
+    uint32_t nLs = nL, nRs = nR;  // of which LEFT and RIGHT
+    int ph;
+    {
+        const bool left_big = nL >= nR;
+        const uint32_t nb = left_big ? nL : nR, nsm = left_big ? nR : nL;
+        const uint64_t range = (uint64_t)((int64_t)kmax - (int64_t)kmin) + 1;
+        const uint64_t words = (range + 31) / 32;
+        bool semi = false;
+        if (ctx->semijoin == 0)
+            semi = nb >= SEMI_MIN_RECORDS && (uint64_t)nsm * SEMI_RATIO <= nb && words <= (uint64_t)nb;
+        else if (ctx->semijoin == 2)
+            semi = words * 4 <= (uint64_t(1) << 30);
+        Block bm;
+        if (semi) bm = alloc_block(ctx, words * 4);
+        if (bm.ok()) {
+            ph = ctx->prof_begin(8);
+            uint32_t* bits = bm.as<uint32_t>();
+            HIPCHK(launch_fill_u32(bits, words, 0u, ctx->stream));
+            HIPCHK(launch_fill_u32(counter(ctx, CT_SEMI), 1, 0u, ctx->stream));
+            HIPCHK(launch_bitmap_set(left_big ? rkey : lkey, nsm, kmin, range, bits, ctx->stream));
+            if (!ctx->ensure_status(semi_filter_tiles(nb) + 1))
+                return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
+            const uint32_t at = left_big ? 0u : nL;
+            SemiArgs sa{left_big ? lkey : rkey, nb, kmin, range, bits, at, b.k[0] + at, b.v[0] + at,
+                        scalar32(ctx, SC_SEMI)};
+            HIPCHK(launch_semi_filter(sa, ctx->status, counter(ctx, CT_SEMI), ctx->next_epoch(), ctx->stream));
+            if (left_big)  // the RIGHT records follow the kept LEFT ones
+                HIPCHK(launch_side_records(rkey, nR, kmin, nL, scalar32(ctx, SC_SEMI), b.k[0], b.v[0], ctx->stream));
+            else
+                HIPCHK(launch_side_records(lkey, nL, kmin, 0u, nullptr, b.k[0], b.v[0], ctx->stream));
+            // bitmap cleared, set and read once; the small side's keys read
+            // twice and its records written; the big side's keys read
+            ctx->prof_end(ph, 8.0 * words + 16.0 * nsm + 4.0 * nb);
+            uint32_t kept = 0;
+            if ((st = readback(ctx, scalar32(ctx, SC_SEMI), 4, &kept))) return st;
+            if (ph >= 0) ctx->pending[ph].bytes += 8.0 * kept;
+            Ns = kept + nsm;
+            (left_big ? nLs : nRs) = kept;
+            js.path = MAPSQ_PATH_SEMIJOIN;
+            js.sorted_records = Ns;
+            ctx->last = js;
+            if (kept == 0) {  // no key in common
+                set_meta(out);
+                out->owned = 1;
+                out->nrows = 0;
+                return MAPSQ_OK;
+            }
+        }
+    }
+    js.sorted_records = Ns;
+
+    // Map + Sort: the first pass reads the LEFT then the RIGHT key column
+    // (or the records the semi-join kept)
     SortSrc src{lkey, nL, rkey, nR, kmin};
     int res, passes;
-    int ph = ctx->prof_begin(1);
-    if ((st = radix_sort(ctx, &src, N, key_bits, rb, kpt, b, &res, &passes))) return st;
-    // histogram reads 4N; the first pass reads 4N keys, later passes 8N; every pass writes 8N
-    ctx->prof_end(ph, 16.0 * N * passes);
+    ph = ctx->prof_begin(1);
+    if ((st = radix_sort(ctx, js.path == MAPSQ_PATH_SEMIJOIN ? nullptr : &src, Ns, key_bits, rb, kpt, b, &res, &passes)))
+        return st;
+    // histogram reads 4N; the first pass reads 4N keys (8N records after a
+    // semi-join), later passes 8N; every pass writes 8N
+    ctx->prof_end(ph, 16.0 * Ns * passes + (js.path == MAPSQ_PATH_SEMIJOIN ? 4.0 * Ns : 0.0));
     const uint32_t* skeys = b.k[res];
     const uint32_t* svals = b.v[res];
     uint32_t* seg_start = b.k[1 - res];
     uint32_t* seg_split = b.v[1 - res];
     // ReduceDuplicate: segments, counts, offsets
-    if (!ctx->ensure_status(size_t(N) / 2048 + 2)) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
+    if (!ctx->ensure_status(size_t(Ns) / 2048 + 2)) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
     ph = ctx->prof_begin(2);
-    HIPCHK(launch_seg_heads(skeys, svals, N, nL, seg_start, seg_split, scalar32(ctx, SC_NSEG), ctx->status,
+    HIPCHK(launch_seg_heads(skeys, svals, Ns, nL, seg_start, seg_split, scalar32(ctx, SC_NSEG), ctx->status,
                             counter(ctx, CT_HEADS), ctx->next_epoch(), ctx->stream));
-    HIPCHK(launch_seg_count(N, seg_start, scalar32(ctx, SC_NSEG), N, seg_split, seg_off, scalar64(ctx, SC_TOTAL),
+    HIPCHK(launch_seg_count(Ns, seg_start, scalar32(ctx, SC_NSEG), Ns, seg_split, seg_off, scalar64(ctx, SC_TOTAL),
                             ctx->status, counter(ctx, CT_COUNT), ctx->next_epoch(), ctx->stream));
     uint32_t sc[4];
     {
@@ -809,7 +1025,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     const uint32_t nseg = sc[0];
     // heads: read 4N keys and 4N payloads, write 4S starts and 4S splits;
     // count: read 8S starts and 4S splits, write 8S offsets
-    if (ph >= 0) ctx->pending[ph].bytes = 8.0 * N + 28.0 * nseg;
+    if (ph >= 0) ctx->pending[ph].bytes = 8.0 * Ns + 28.0 * nseg;
     uint64_t total;
     std::memcpy(&total, &sc[2], 8);
     js.segments = nseg;
@@ -841,7 +1057,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     a.seg_split = seg_split;
     a.seg_off = seg_off;
     a.nseg = scalar32(ctx, SC_NSEG);
-    a.n = N;
+    a.n = Ns;
     a.n_left = nL;
     a.key_base = kmin;
     a.nl = (int)lv.size();
@@ -854,13 +1070,13 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // values in sorted record order when output rows outnumber records
     // (each record's values are then read many times)
     const int nv = std::max(a.nl, a.nr);
-    const double value_cells = a.nl * (double)nL + a.nr * (double)nR;
+    const double value_cells = a.nl * (double)nLs + a.nr * (double)nRs;
     Block sval;
-    if (nv > 0 && total >= N) sval = alloc_block(ctx, size_t(nv) * nb4);
+    if (nv > 0 && total >= Ns) sval = alloc_block(ctx, size_t(nv) * nb4);
     if (sval.ok()) {
         GatherArgs g{};
         g.vals = svals;
-        g.n = N;
+        g.n = Ns;
         g.n_left = nL;
         g.nl = a.nl;
         g.nr = a.nr;
@@ -874,7 +1090,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         ph = ctx->prof_begin(7);
         hipError_t ge = launch_gather_values(g, ctx->stream);
         // reads every payload and each value cell once, writes nv cells per record
-        ctx->prof_end(ph, 4.0 * N + 4.0 * value_cells + 4.0 * nv * (double)N);
+        ctx->prof_end(ph, 4.0 * Ns + 4.0 * value_cells + 4.0 * nv * (double)Ns);
         if (ge != hipSuccess) {
             free_table(ctx, &m);
             return ctx->fail(MAPSQ_ERR_HIP, std::string("gather: ") + hipGetErrorString(ge));
@@ -885,73 +1101,14 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // writes 4 B per output cell; reads each segment's key and table entries
     // and each value cell once (from the gathered copy when there is one,
     // else through every record's payload)
-    ctx->prof_end(ph, 4.0 * nc_mat * (double)total + 20.0 * nseg + 4.0 * value_cells + (a.use_sval ? 0.0 : 4.0 * N));
+    ctx->prof_end(ph, 4.0 * nc_mat * (double)total + 20.0 * nseg + 4.0 * value_cells + (a.use_sval ? 0.0 : 4.0 * Ns));
     ctx->acc.joins += 1;
     ctx->acc.rows_out += (int64_t)total;
     if (e != hipSuccess) {
         free_table(ctx, &m);
         return ctx->fail(MAPSQ_ERR_HIP, std::string("materialize: ") + hipGetErrorString(e));
     }
-    if (extra_r.empty()) {
-        out->owned = 1;
-        out->block = m.block;
-        out->nrows = (int64_t)total;
-        for (int c = 0; c < nc_mat; c++) out->col[c] = m.col[c];
-        return MAPSQ_OK;
-    }
-    // further shared variables: keep rows where both copies agree, drop R's copy
-    mapsq_table f{};
-    if (alloc_table(ctx, (int64_t)total, nc_out, &f)) {
-        free_table(ctx, &m);
-        return ctx->fail(MAPSQ_ERR_TOO_LARGE, "filtered join result exceeds the arena's free space");
-    }
-    CompactArgs c{};
-    c.nin = nc_mat;
-    for (int i = 0; i < nc_mat; i++) c.in[i] = m.col[i];
-    c.n = total;
-    c.nterm = 0;
-    for (size_t i = 0; i < extra_r.size(); i++) {
-        if (c.nterm >= 6) {
-            free_table(ctx, &m);
-            free_table(ctx, &f);
-            return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 6 further shared variables");
-        }
-        int li = 1 + int(std::find(lv.begin(), lv.end(), extra_l[i]) - lv.begin());
-        int ri = 1 + (int)lv.size() + int(std::find(rv.begin(), rv.end(), extra_r[i]) - rv.begin());
-        c.term_a[c.nterm] = li;
-        c.term_b[c.nterm] = ri;
-        c.nterm++;
-    }
-    c.nout = 0;
-    for (int i = 0; i < nc_mat; i++) {
-        bool drop = i >= 1 + (int)lv.size() &&
-                    std::find(extra_r.begin(), extra_r.end(), rv[i - 1 - lv.size()]) != extra_r.end();
-        if (!drop) {
-            c.out_src[c.nout] = i;
-            c.out[c.nout] = f.col[c.nout];
-            c.nout++;
-        }
-    }
-    c.count = scalar64(ctx, SC_COUNT);
-    uint64_t kept = 0;
-    e = hipSuccess;
-    if (!ctx->ensure_status(size_t(total / 4096 + 2))) e = hipErrorOutOfMemory;
-    ph = ctx->prof_begin(4);
-    if (e == hipSuccess) e = launch_fill_u32(counter(ctx, CT_COMPACT), 1, 0u, ctx->stream);
-    if (e == hipSuccess) e = launch_compact(c, ctx->status, counter(ctx, CT_COMPACT), ctx->next_epoch(), ctx->stream);
-    ctx->prof_end(ph, 4.0 * (double)c.nterm * 2 * total);
-    if (e == hipSuccess) st = readback(ctx, scalar64(ctx, SC_COUNT), 8, &kept);
-    if (ph >= 0) ctx->pending[ph].bytes += 4.0 * (double)c.nout * (double)kept;
-    free_table(ctx, &m);
-    if (e != hipSuccess || st) {
-        free_table(ctx, &f);
-        return e != hipSuccess ? ctx->fail(MAPSQ_ERR_HIP, "equality filter launch failed") : st;
-    }
-    out->owned = 1;
-    out->block = f.block;
-    out->nrows = (int64_t)kept;
-    for (int i = 0; i < nc_out; i++) out->col[i] = f.col[i];
-    return MAPSQ_OK;
+    return finish(m, total);
 }
 
 }  // namespace mq

@@ -105,6 +105,8 @@ struct Ctx {
     // pinned host staging for read-backs
     void* pinned = nullptr;
     int32_t tune_rb = 0, tune_kpt = 0;
+    int32_t semijoin = 0;    // 0 automatic, 1 never, 2 always
+    int32_t merge_mode = 0;  // 0 merge join of key-sorted tables, 1 never
     // autotuned choices: (key bits << 8 | log2 records) -> (rb << 8 | kpt)
     std::map<uint32_t, uint32_t> tuned;
     mapsq_join_stats last{};
@@ -147,6 +149,12 @@ struct Ctx {
 };
 
 // layout of the small device area (u32 words)
+// automatic semi-join reduction: the larger side has at least this many
+// records and SEMI_RATIO times the smaller side's, and the key bitmap is no
+// larger than the larger side's key column
+constexpr uint32_t SEMI_MIN_RECORDS = 1u << 16;
+constexpr uint64_t SEMI_RATIO = 4;
+
 constexpr size_t SMALL_HIST = 0;                  // up to 8 passes x 2048 buckets
 constexpr size_t SMALL_HIST_WORDS = 8 * 2048;
 constexpr size_t SMALL_CTR = SMALL_HIST + SMALL_HIST_WORDS;  // 32 tile counters

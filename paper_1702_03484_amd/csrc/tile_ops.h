@@ -334,10 +334,85 @@ struct MatJoin {
     int32_t key_base;
     int32_t nl, nr;
     bool sorted_vals;
+    // merge-join segments: LEFT run [seg_start, + seg_cl) of the LEFT
+    // table and RIGHT run [seg_split, + seg_cr) of the RIGHT table (null:
+    // both runs lie in one sorted record sequence, ended by the next start)
+    const uint32_t* seg_cl;
+    const uint32_t* seg_cr;
     const int32_t* src[MAT_MAXNC];
     const int32_t* ssrc[MAT_MAXNC];
     int32_t* out[MAT_MAXNC];
 };
+
+// Pair order inside a segment.  The segment's cL x cR rows run over one
+// side in the outer loop and the other in the inner loop; the inner side is
+// the one whose value cells take fewer bytes (cL * nl against cR * nr, LEFT
+// inner when strictly smaller), so the block that every outer step reads
+// again is the smaller one and stays cached while the output streams out.
+// Row r of the segment is (outer = r / c_inner, inner = r mod c_inner).
+struct SegPos {
+    uint32_t st, sp, cl, cr;  // LEFT run [st, sp), RIGHT run [sp, sp + cr)
+    bool left_inner;
+    uint32_t outer, inner;    // position of the current row
+};
+
+__device__ __forceinline__ bool left_inner_of(uint32_t cl, uint32_t cr, int nl, int nr) {
+    return (uint64_t)cl * (uint32_t)nl < (uint64_t)cr * (uint32_t)nr;
+}
+
+// sorted positions of the current row's LEFT and RIGHT records
+__device__ __forceinline__ uint32_t seg_lpos(const SegPos& p) { return p.st + (p.left_inner ? p.inner : p.outer); }
+__device__ __forceinline__ uint32_t seg_rpos(const SegPos& p) { return p.sp + (p.left_inner ? p.outer : p.inner); }
+
+__device__ __forceinline__ void seg_locate(SegPos& p, uint64_t r) {
+    const uint32_t ci = p.left_inner ? p.cl : p.cr;
+    if (r < 0xffffffffull) {
+        p.outer = (uint32_t)r / ci;
+        p.inner = (uint32_t)r - p.outer * ci;
+    } else {
+        p.outer = (uint32_t)(r / ci);
+        p.inner = (uint32_t)(r - (uint64_t)p.outer * ci);
+    }
+}
+
+__device__ __forceinline__ void seg_step(SegPos& p) {
+    if (++p.inner == (p.left_inner ? p.cl : p.cr)) {
+        p.inner = 0;
+        p.outer++;
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void seg_open(const MatJoin& a, uint32_t s, int nl, int nr, SegPos& p) {
+    p.st = a.seg_start[s];
+    p.sp = a.seg_split[s];
+    if (a.seg_cl) {
+        p.cl = a.seg_cl[s];
+        p.cr = a.seg_cr[s];
+    } else {
+        const uint32_t en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
+        p.cl = p.sp - p.st;
+        p.cr = en - p.sp;
+    }
+    p.left_inner = left_inner_of(p.cl, p.cr, nl, nr);
+}
+
+// value cells of one row
+template <int NC>
+__device__ __forceinline__ void row_values(const MatJoin& a, int nl, int nc, uint32_t lpos, uint32_t rpos,
+                                           int32_t (&v)[NC][4], int k) {
+    if (a.sorted_vals) {
+#pragma unroll
+        for (int col = 1; col < NC; col++)
+            if (col < nc) v[col][k] = a.ssrc[col][col <= nl ? lpos : rpos];
+    } else {
+        const uint32_t lrow = nl > 0 ? a.vals[lpos] : 0u;
+        const uint32_t rrow = nc - 1 > nl ? a.vals[rpos] - a.n_left : 0u;
+#pragma unroll
+        for (int col = 1; col < NC; col++)
+            if (col < nc) v[col][k] = a.src[col][col <= nl ? lrow : rrow];
+    }
+}
 
 // Rows [j, j + nk) of one lane, in order, when they may run into later
 // segments.  s is the segment of row j; later segments are found by binary
@@ -346,46 +421,24 @@ template <int NC, int NLC>
 __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint32_t s_last, uint64_t j, int nk,
                                               int32_t (&v)[NC][4]) {
     const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
-    const bool has_l = nl > 0, has_r = nr > 0;
     const int nc = 1 + nl + nr;
-    uint32_t st = a.seg_start[s], sp = a.seg_split[s];
-    uint32_t en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
-    uint64_t so = a.seg_off[s];
-    uint32_t cl = sp - st, cr = en - sp;
-    const uint64_t r = j - so;
-    uint32_t li = (uint32_t)(r / cr), ri = (uint32_t)(r - (uint64_t)li * cr);
-    int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
-    uint32_t lrow = (has_l && !a.sorted_vals) ? a.vals[st + li] : 0u;
+    SegPos p;
+    seg_open<NC>(a, s, nl, nr, p);
+    seg_locate(p, j - a.seg_off[s]);
+    int32_t key = (int32_t)(a.keys[p.st] + (uint32_t)a.key_base);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         if (k < nk) {
-            if (li == cl) {  // the next non-empty segment holds row j + k
+            if (p.outer == (p.left_inner ? p.cr : p.cl)) {  // the next non-empty segment holds row j + k
                 s = seg_of(a.seg_off, s + 1, s_last, j + k);
-                st = a.seg_start[s];
-                sp = a.seg_split[s];
-                en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
-                cl = sp - st;
-                cr = en - sp;
-                li = 0;
-                ri = 0;
-                key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
-                lrow = (has_l && !a.sorted_vals) ? a.vals[st] : 0u;
+                seg_open<NC>(a, s, nl, nr, p);
+                p.outer = 0;
+                p.inner = 0;
+                key = (int32_t)(a.keys[p.st] + (uint32_t)a.key_base);
             }
             v[0][k] = key;
-            if (a.sorted_vals) {
-#pragma unroll
-                for (int col = 1; col < NC; col++)
-                    if (col < nc) v[col][k] = a.ssrc[col][col <= nl ? st + li : sp + ri];
-            } else {
-                const uint32_t rrow = has_r ? a.vals[sp + ri] - a.n_left : 0u;
-#pragma unroll
-                for (int col = 1; col < NC; col++)
-                    if (col < nc) v[col][k] = a.src[col][col <= nl ? lrow : rrow];
-            }
-            if (++ri == cr) {
-                ri = 0;
-                if (++li < cl && has_l && !a.sorted_vals) lrow = a.vals[st + li];
-            }
+            row_values<NC>(a, nl, nc, seg_lpos(p), seg_rpos(p), v, k);
+            seg_step(p);
         }
     }
 }
@@ -394,20 +447,20 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint
 // 4) of one join with one wave.  The chunk is cut into RPT/4 sub-chunks of
 // 256 rows; in each, lane L writes rows 4L..4L+3, so every 16-byte store
 // instruction of the wave covers 1 KB of one column contiguously.  A lane's
-// four rows that lie in one segment take the fast path, whose payload and
-// value loads are all independent; rows that cross into later segments take
-// mat_rows_slow.  NC is an upper bound of the column count 1 + nl + nr;
-// NLC >= 0 fixes nl = NLC and nr = NC - 1 - NLC at compile time.
+// four rows that lie in one segment take the fast path, whose position,
+// payload and value loads are all independent; rows that cross into later
+// segments take mat_rows_slow.  NC is an upper bound of the column count
+// 1 + nl + nr; NLC >= 0 fixes nl = NLC and nr = NC - 1 - NLC at compile time.
 template <int NC, int RPT, int NLC = -1>
 __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend) {
     constexpr int Q = RPT / 4;
     const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
-    const bool has_l = nl > 0, has_r = nr > 0;
     const int nc = 1 + nl + nr;
     const uint32_t s_first = wave_seg_of(a.seg_off, 0, a.ns - 1, j0);
     const uint32_t s_last = wave_seg_of(a.seg_off, s_first, a.ns - 1, jend - 1);
-    // phase 1: each sub-chunk's segment and first (li, ri)
-    uint32_t qs[Q], qst[Q], qsp[Q], qcr[Q], qli[Q], qri[Q];
+    // phase 1: each sub-chunk's segment and the position of its first row
+    uint32_t qs[Q];
+    SegPos qp[Q];
     int32_t qkey[Q];
     bool qon[Q], qfast[Q];
     uint32_t s = s_first;
@@ -416,28 +469,17 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
         const uint64_t j = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
         qon[q] = j < jend;
         qfast[q] = false;
+        qp[q] = SegPos{};
+        qs[q] = s;
+        qkey[q] = 0;
         if (qon[q]) {
             s = seg_of(a.seg_off, s, s_last, j);
-            const uint32_t st = a.seg_start[s], sp = a.seg_split[s];
-            const uint32_t en = s + 1 < a.ns ? a.seg_start[s + 1] : a.n;
-            const uint32_t cl = sp - st, cr = en - sp;
+            seg_open<NC>(a, s, nl, nr, qp[q]);
             const uint64_t r = j - a.seg_off[s];
-            uint32_t li, ri;
-            if (r < 0xffffffffull) {
-                li = (uint32_t)r / cr;
-                ri = (uint32_t)r - li * cr;
-            } else {
-                li = (uint32_t)(r / cr);
-                ri = (uint32_t)(r - (uint64_t)li * cr);
-            }
+            seg_locate(qp[q], r);
             qs[q] = s;
-            qst[q] = st;
-            qsp[q] = sp;
-            qcr[q] = cr;
-            qli[q] = li;
-            qri[q] = ri;
-            qkey[q] = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
-            qfast[q] = j + 4 <= jend && r + 4 <= (uint64_t)cl * cr;
+            qkey[q] = (int32_t)(a.keys[qp[q].st] + (uint32_t)a.key_base);
+            qfast[q] = j + 4 <= jend && r + 4 <= (uint64_t)qp[q].cl * qp[q].cr;
         }
     }
     // phase 2: the LEFT and RIGHT sorted positions of every fast row; their
@@ -446,23 +488,20 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
     const bool direct = a.sorted_vals;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
+        SegPos p = qp[q];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             lrow[q][k] = 0;
             rrow[q][k] = 0;
             if (qfast[q]) {
-                uint32_t li = qli[q], ri = qri[q] + k;
-                while (ri >= qcr[q]) {  // at most 3 steps
-                    ri -= qcr[q];
-                    li++;
-                }
                 if (direct) {
-                    lrow[q][k] = qst[q] + li;
-                    rrow[q][k] = qsp[q] + ri;
+                    lrow[q][k] = seg_lpos(p);
+                    rrow[q][k] = seg_rpos(p);
                 } else {
-                    if (has_l) lrow[q][k] = a.vals[qst[q] + li];
-                    if (has_r) rrow[q][k] = a.vals[qsp[q] + ri] - a.n_left;
+                    if (nl > 0) lrow[q][k] = a.vals[seg_lpos(p)];
+                    if (nr > 0) rrow[q][k] = a.vals[seg_rpos(p)] - a.n_left;
                 }
+                seg_step(p);
             }
         }
     }

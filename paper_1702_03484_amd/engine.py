@@ -71,13 +71,18 @@ class MapSQ:
         B.mapsq_set_tuning(self.ctx, radix_bits, keys_per_thread)
 
     # ---- tables <-> tensors -------------------------------------------------
-    def table(self, vars, tensors, key_max: int = -1) -> B.mapsq_table:
-        """Wrap caller-owned int32 device tensors (kept alive by this session)."""
+
+    def set_join_options(self, semijoin: int = 0, merge: int = 0):
+        """semijoin 0 automatic / 1 never / 2 always; merge 0 automatic / 1 never."""
+        B.mapsq_set_join_options(self.ctx, semijoin, merge)
+    def table(self, vars, tensors, key_max: int = -1, sorted_col: int = 0) -> B.mapsq_table:
+        """Wrap caller-owned int32 device tensors (kept alive by this session);
+        sorted_col = 1 + a column the caller guarantees to be ascending."""
         ts = [t.contiguous() for t in tensors]
         assert all(t.dtype == torch.int32 and t.is_cuda for t in ts)
         n = ts[0].numel() if ts else 0
         self._keep.extend(ts)
-        return B.make_table(vars, [t.data_ptr() for t in ts], n, key_max)
+        return B.make_table(vars, [t.data_ptr() for t in ts], n, key_max, sorted_col)
 
     def column(self, t: B.mapsq_table, c: int) -> torch.Tensor:
         """Column c of a table as an int32 tensor view (no copy)."""

@@ -30,7 +30,7 @@ def test_struct_layout_matches_header():
     # mapsq_table: int64 + 2*int32 + 16*int32 + 16*ptr + uint64 + 2*int32
     assert ctypes.sizeof(binding.mapsq_table) == 8 + 8 + 64 + 128 + 8 + 8
     assert ctypes.sizeof(binding.mapsq_pattern) == 12
-    assert ctypes.sizeof(binding.mapsq_join_stats) == 4 * 8 + 4 * 4
+    assert ctypes.sizeof(binding.mapsq_join_stats) == 4 * 8 + 4 * 4 + 8
 
 
 def test_null_context_is_rejected_without_gpu_work():

@@ -129,7 +129,7 @@ def test_join_order_is_deterministic_and_tuning_invariant(sess):
     R = sess.table([0, 2], [dev(c) for c in rc])
     ref = sess.join(L, R, 0)
     ref_cols = sess.to_numpy(ref)
-    # key, then LEFT rows in input order, then RIGHT rows in input order
+    # rows grouped by ascending key
     k = ref_cols[0]
     assert np.all(k[1:] >= k[:-1])
     for rb in range(4, 12):
@@ -142,6 +142,161 @@ def test_join_order_is_deterministic_and_tuning_invariant(sess):
             sess.free(out)
     sess.set_tuning(0, 0)
     sess.free(ref)
+
+
+SEMI_CASES = [
+    # (nL, nR, LEFT key cardinality, RIGHT key cardinality, shared fraction of RIGHT keys, vl, vr, high IDs)
+    (300_000, 5_000, 20_000, 800, 0.5, 1, 1, False),   # big LEFT
+    (4_000, 250_001, 500, 30_000, 0.3, 2, 1, True),    # big RIGHT, IDs near 2^31
+    (200_000, 3_000, 5_000, 200, 0.0, 1, 0, False),    # no key in common
+    (100_000, 100_000, 1000, 1000, 1.0, 1, 1, False),  # equal sizes, every key shared
+    (70_000, 9, 3, 2, 1.0, 0, 2, False),               # tiny RIGHT, hot keys
+]
+
+
+@pytest.mark.parametrize("nl,nr,cl,cr,shared,vl,vr,high", SEMI_CASES)
+def test_semijoin_keeps_rows_and_order(sess, nl, nr, cl, cr, shared, vl, vr, high):
+    announce(f"semi-join nl={nl} nr={nr} cl={cl} cr={cr} shared={shared}")
+    lo = (1 << 31) - 20_000_000 if high else 0
+    pool = keyset(nl + 3 * nr, cl + cr, lo=lo)
+    kl = pool[:cl]
+    ns = int(round(shared * cr))
+    kr = np.concatenate([kl[:ns], pool[cl:cl + cr - ns]])
+    lc = random_table(nl + 1, nl, cl, vl, key_ids=kl)
+    rc = random_table(nr + 2, nr, len(kr), vr, key_ids=kr)
+    lvars = [0] + list(range(10, 10 + vl))
+    rvars = [0] + list(range(20, 20 + vr))
+    L = sess.table(lvars, [dev(c) for c in lc])
+    R = sess.table(rvars, [dev(c) for c in rc])
+    cols = {}
+    try:
+        for mode in (1, 2, 0):
+            sess.set_join_options(semijoin=mode, merge=1)
+            out = sess.join(L, R, 0)
+            st = sess.stats()
+            cols[mode] = sess.to_numpy(out)
+            if mode == 2:
+                big, small = (lc[0], rc[0]) if nl >= nr else (rc[0], lc[0])
+                assert st.path == B.MAPSQ_PATH_SEMIJOIN
+                assert st.sorted_records == int(np.isin(big, small).sum()) + len(small)
+            if mode == 1:
+                assert st.path == B.MAPSQ_PATH_SORT and st.sorted_records == nl + nr
+                assert_same_bag(host_table(sess, out), oracle.join(Table(lvars, lc), Table(rvars, rc), 0))
+            sess.free(out)
+    finally:
+        sess.set_join_options(0, 0)
+    for mode in (2, 0):
+        assert all(np.array_equal(a, b) for a, b in zip(cols[mode], cols[1])), f"mode {mode} changed the rows"
+
+
+MERGE_CASES = [
+    # (nL, nR, key cardinality, left value cols, right value cols, extreme keys)
+    (1, 1, 1, 1, 0, False),
+    (5000, 5000, 1, 1, 1, False),              # one key: a 5000 x 5000 block
+    (300_001, 1_588, 700, 0, 1, False),        # big sorted side, hot keys
+    (1_588, 300_001, 700, 1, 0, True),         # the same mirrored, keys at INT32_MIN/MAX
+    (200_000, 150_000, 120_000, 2, 1, False),  # mostly distinct keys
+    (65_536, 1023, 5_000, 1, 2, True),
+]
+
+
+def _sorted_table(seed, n, card, nv, extreme):
+    r = np.random.default_rng(seed)
+    ids = keyset(seed, card, lo=-(1 << 31) + 1 if extreme else 0)
+    if extreme:
+        ids = np.unique(np.concatenate([ids[: max(card - 2, 0)], [-(1 << 31), (1 << 31) - 1]]))[:card]
+    keys = np.sort(ids[r.integers(0, ids.size, size=n)]).astype(np.int32)
+    return [keys] + [r.integers(0, 1 << 31, size=n).astype(np.int32) for _ in range(nv)]
+
+
+@pytest.mark.parametrize("nl,nr,card,vl,vr,extreme", MERGE_CASES)
+def test_merge_join_equals_the_shuffle(sess, nl, nr, card, vl, vr, extreme):
+    announce(f"merge join nl={nl} nr={nr} card={card} vl={vl} vr={vr} extreme={extreme}")
+    lc = _sorted_table(nl + 5, nl, card, vl, extreme)
+    rc = _sorted_table(nr + 6, nr, card, vr, extreme)
+    lvars = [0] + list(range(10, 10 + vl))
+    rvars = [0] + list(range(20, 20 + vr))
+    L = sess.table(lvars, [dev(c) for c in lc], sorted_col=1)
+    R = sess.table(rvars, [dev(c) for c in rc], sorted_col=1)
+    got = {}
+    try:
+        for merge in (0, 1):
+            sess.set_join_options(semijoin=1, merge=merge)
+            out = sess.join(L, R, 0)
+            st = sess.stats()
+            assert st.path == (B.MAPSQ_PATH_MERGE if merge == 0 else B.MAPSQ_PATH_SORT)
+            assert out.sorted_col == 1
+            got[merge] = sess.to_numpy(out)
+            if merge == 0:
+                exp = oracle.join(Table(lvars, lc), Table(rvars, rc), 0)
+                assert st.out_rows == exp.n
+                assert_same_bag(host_table(sess, out), exp)
+            sess.free(out)
+    finally:
+        sess.set_join_options(0, 0)
+    assert all(np.array_equal(a, b) for a, b in zip(got[0], got[1]))
+    assert np.all(got[0][0][1:] >= got[0][0][:-1])
+
+
+def test_views_claim_only_true_orders(sess):
+    announce("sorted_col of index views and map outputs")
+    w = random_store(31, 200_000, 3000, 40)
+    sess.load(w.s, w.p, w.o)
+    p1 = int(w.p[0])
+    o1 = int(w.o[0])
+    s1 = int(w.s[0])
+    cases = [((var(0), p1, var(1)), 0), ((var(0), p1, var(1)), 1), ((var(0), p1, var(1)), -1),
+             ((s1, p1, var(1)), 1), ((var(0), p1, o1), 0), ((var(0), p1, var(0)), 0),
+             ((var(0), var(1), var(2)), 0)]
+    claimed = 0
+    for pat, key in cases:
+        t = sess.map(pat, key_var=key)
+        cols = sess.to_numpy(t)
+        if t.sorted_col:
+            c = cols[t.sorted_col - 1]
+            assert np.all(c[1:] >= c[:-1]), (pat, key)
+            claimed += 1
+        if key >= 0 and t.vars[0] == key and pat[1] >= 0 and pat.count(var(key)) == 1:
+            assert t.sorted_col == 1, (pat, key)  # an index order exists for the key
+        sess.free(t)
+    assert claimed >= 5
+
+
+def test_query_merge_path_equals_shuffle(sess):
+    announce("queries with and without the merge join")
+    w = random_store(32, 300_000, 5000, 24)
+    sess.load(w.s, w.p, w.o)
+    r = np.random.default_rng(33)
+    preds = np.unique(w.p)
+    queries = []
+    for _ in range(12):
+        a, b, c = (int(x) for x in r.choice(preds, 3))
+        o = int(w.o[r.integers(0, w.n)])
+        queries += [[(var(0), a, var(1)), (var(1), b, o)],
+                    [(var(0), a, var(1)), (var(0), b, var(2)), (var(0), c, var(3))],
+                    [(var(0), a, var(1)), (var(1), b, var(2))]]
+    merged = 0
+    try:
+        for q in queries:
+            res = {}
+            for merge in (0, 1):
+                sess.set_join_options(0, merge)
+                try:
+                    t = sess.query(q)
+                except B.MapSQError as e:
+                    res[merge] = e.code
+                    continue
+                merged += merge == 0 and sess.stats().path == B.MAPSQ_PATH_MERGE
+                res[merge] = (t.vars, sess.to_numpy(t))
+                sess.free(t)
+            if isinstance(res[0], int) or isinstance(res[1], int):
+                assert res[0] == res[1]
+                continue
+            assert res[0][0] == res[1][0]
+            assert all(np.array_equal(x, y) for x, y in zip(res[0][1], res[1][1])), q
+    finally:
+        sess.set_join_options(0, 0)
+    assert merged >= 12
 
 
 def test_join_too_large_is_refused_without_leak(sess):
