@@ -33,6 +33,8 @@ def tune_class(sess, key_bits: int, nrec: int, reps: int = 3, seed: int = 0):
     rk = torch.full((max(1, nrec - nl),), hi - 1, device="cuda", dtype=torch.int32)
     L = sess.table([0], [lk], key_max=hi - 1)
     R = sess.table([0], [rk], key_max=hi - 1)
+    # every record through the shuffle: no semi-join reduction, no merge join
+    sess.set_join_options(semijoin=1, merge=1)
     times = {}
     for rb, kpt in CANDIDATES:
         sess.set_tuning(rb, kpt)
@@ -45,6 +47,7 @@ def tune_class(sess, key_bits: int, nrec: int, reps: int = 3, seed: int = 0):
         prof = B.mapsq_profile_read(sess.ctx)
         times[(rb, kpt)] = prof.ms[1] / max(1, prof.launches[1])
     sess.set_tuning(0, 0)
+    sess.set_join_options(0, 0)
     B.mapsq_profile_enable(sess.ctx, False)
     best = min(times, key=times.get)
     return best, times
@@ -77,3 +80,28 @@ def install(sess, path):
     for k, v in load_cache(path).items():
         kb, lg = (int(x) for x in k.split(":"))
         B.mapsq_tune_record(sess.ctx, kb, lg, v["radix_bits"], v["keys_per_thread"])
+
+
+DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+DEFAULT_CLASSES = [(kb, 3 << (lg - 2)) for kb in (20, 24, 26, 31) for lg in range(11, 26)]
+
+
+def main(argv=None):
+    import argparse
+
+    from .engine import MapSQ
+
+    ap = argparse.ArgumentParser(description="time every (digit width, keys per thread) per size class")
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--arena-gb", type=float, default=16.0)
+    args = ap.parse_args(argv)
+    with MapSQ(arena_bytes=int(args.arena_gb * (1 << 30)), tuning=None) as sess:
+        for kb, n in DEFAULT_CLASSES:
+            autotune(sess, [(kb, n)], cache_path=args.out)
+            e = load_cache(args.out)[f"{kb}:{_bitlen(n)}"]
+            print(f"key bits {kb:2d}  records {n:9d}  ->  {e['radix_bits']} bits x {e['keys_per_thread']} keys/thread",
+                  flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -257,7 +257,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
             if (col >= 1) mj.src[col] = col <= J.nvl ? J.lcol[col - 1] : J.rcol[col - 1 - J.nvl];
         }
         const uint64_t j0 = (c - J.chunk_off) * BMAT_WROWS;
-        mat_wave_chunk<BATCH_MAXNC, BMAT_RPT>(mj, j0, min(j0 + BMAT_WROWS, J.total));
+        uint32_t hint = 0;  // chunks of a wave may belong to different joins
+        mat_wave_chunk<BATCH_MAXNC, BMAT_RPT>(mj, j0, min(j0 + BMAT_WROWS, J.total), hint);
     }
 }
 

@@ -51,6 +51,50 @@ __device__ __forceinline__ uint32_t run_end(const int32_t* __restrict__ a, uint3
     }
 }
 
+// Both bounds of v in b[0, n) at once: lower (first b[i] >= v) and upper
+// (first b[i] > v).  A table of MRG_SAMPLES evenly spaced keys in LDS gives
+// each bound's bracket; the two global binary searches then run
+// interleaved, so their loads overlap.
+constexpr int MRG_SAMPLES = 2048;
+
+__device__ __forceinline__ uint32_t sample_pos(uint32_t j, uint32_t n) {
+    return (uint32_t)(((uint64_t)j * n) / MRG_SAMPLES);
+}
+
+__device__ __forceinline__ void bounds_i32(const int32_t* __restrict__ b, uint32_t n, const int32_t* samp, int32_t v,
+                                           uint32_t& lower, uint32_t& upper) {
+    // samples below v (jl) and at most v (ju), by binary search in LDS
+    uint32_t jl = 0, jh = MRG_SAMPLES, ul = 0, uh = MRG_SAMPLES;
+    while (jl < jh) {
+        const uint32_t m = (jl + jh) >> 1;
+        if (samp[m] < v) jl = m + 1;
+        else jh = m;
+    }
+    while (ul < uh) {
+        const uint32_t m = (ul + uh) >> 1;
+        if (samp[m] <= v) ul = m + 1;
+        else uh = m;
+    }
+    // the bound lies in (pos(j - 1), pos(j)], with pos(-1) = -1 and pos(S) = n
+    uint32_t l0 = jl == 0 ? 0u : sample_pos(jl - 1, n) + 1, l1 = jl == MRG_SAMPLES ? n : sample_pos(jl, n);
+    uint32_t u0 = ul == 0 ? 0u : sample_pos(ul - 1, n) + 1, u1 = ul == MRG_SAMPLES ? n : sample_pos(ul, n);
+    while (l0 < l1 || u0 < u1) {
+        const uint32_t lm = l0 + ((l1 - l0) >> 1), um = u0 + ((u1 - u0) >> 1);
+        const bool lgo = l0 < l1, ugo = u0 < u1;
+        const int32_t lv = lgo ? b[lm] : 0, uv = ugo ? b[um] : 0;
+        if (lgo) {
+            if (lv < v) l0 = lm + 1;
+            else l1 = lm;
+        }
+        if (ugo) {
+            if (uv <= v) u0 = um + 1;
+            else u1 = um;
+        }
+    }
+    lower = l0;
+    upper = u0;
+}
+
 __global__ __launch_bounds__(MQ_BLOCK) void merge_segments_kernel(MergeArgs a, uint64_t* __restrict__ status,
                                                                   uint32_t* __restrict__ tile_ctr, uint32_t epoch) {
     constexpr uint32_t TILE = MQ_BLOCK * MRG_IPT;
@@ -58,11 +102,15 @@ __global__ __launch_bounds__(MQ_BLOCK) void merge_segments_kernel(MergeArgs a, u
     __shared__ uint32_t s_wseg[MQ_WAVES];
     __shared__ uint64_t s_wrow[MQ_WAVES];
     __shared__ uint64_t s_ex[2];
+    __shared__ int32_t s_samp[MRG_SAMPLES];
     const uint32_t ntiles = (a.ns + TILE - 1) / TILE;
     uint64_t* st_seg = status;           // segment counts
     uint64_t* st_row = status + ntiles;  // output rows
     const uint32_t w = threadIdx.x / MQ_WAVE;
     const uint64_t lt = lanemask_lt();
+    // nb >= 1: the caller returns early on an empty side
+    for (uint32_t j = threadIdx.x; j < MRG_SAMPLES; j += MQ_BLOCK) s_samp[j] = a.bkey[sample_pos(j, a.nb)];
+    __syncthreads();
     for (;;) {
         const uint32_t tile = next_tile(tile_ctr, &s_tile);
         if (tile >= ntiles) break;
@@ -80,16 +128,17 @@ __global__ __launch_bounds__(MQ_BLOCK) void merge_segments_kernel(MergeArgs a, u
             if (idx < a.ns) {
                 const int32_t key = a.skey[idx];
                 if (idx == 0 || a.skey[idx - 1] != key) {
-                    const uint32_t lb = lower_bound_i32(a.bkey, 0, a.nb, key);
-                    if (lb < a.nb && a.bkey[lb] == key) {
+                    uint32_t lb, ub;
+                    bounds_i32(a.bkey, a.nb, s_samp, key, lb, ub);
+                    if (ub > lb) {
                         bl[k] = lb;
-                        bc[k] = upper_bound_i32(a.bkey, lb + 1, a.nb, key) - lb;
+                        bc[k] = ub - lb;
                         sc[k] = run_end(a.skey, idx, a.ns, key) - idx;
                         keep = true;
                     }
                 }
             }
-            km[k] = __ballot(keep);
+        km[k] = __ballot(keep);
             rows[k] = keep ? (uint64_t)sc[k] * bc[k] : 0ull;
             wseg += (uint32_t)__popcll(km[k]);
             wrow += wave_sum(rows[k]);

@@ -26,8 +26,9 @@ __device__ __forceinline__ uint32_t src_key(const SortSrc& s, uint32_t idx) {
 }
 
 // Digit histograms of every pass in two launches: each block counts its
-// keys into LDS (all loads of a tile in flight at once) and stores its
-// counts to its own row of a partial table; a second kernel sums the rows.
+// keys into LDS (all loads of a tile in flight at once, one atomic per run
+// of equal digits) and stores its counts to its own row of a partial table;
+// a second kernel sums the rows.
 // No device-wide atomics: they serialise on the few hundred counters.
 constexpr int HIST_IPT = 16;
 constexpr uint32_t HIST_BLOCKS = 512;
@@ -42,17 +43,33 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_hist_kernel(SortSrc src, const
     constexpr uint32_t TILE = MQ_BLOCK * HIST_IPT;
     const uint32_t ntiles = (n + TILE - 1) / TILE;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        // each thread takes HIST_IPT consecutive keys: runs of one digit
+        // (index-ordered keys have long ones) cost one LDS atomic per run
+        // instead of one per key
+        const uint32_t first = t * TILE + threadIdx.x * HIST_IPT;
         uint32_t k[HIST_IPT];
 #pragma unroll
         for (int i = 0; i < HIST_IPT; i++) {
-            const uint32_t idx = t * TILE + i * MQ_BLOCK + threadIdx.x;
+            const uint32_t idx = first + i;
             k[i] = idx < n ? (GEN ? src_key(src, idx) : keys[idx]) : 0u;
         }
+        const int cnt = first >= n ? 0 : (int)min((uint32_t)HIST_IPT, n - first);
+        for (int p = 0; p < passes; p++) {
+            const int sh_p = p * RB;
+            uint32_t cur = (k[0] >> sh_p) & R::MASK, run = 0;
 #pragma unroll
-        for (int i = 0; i < HIST_IPT; i++) {
-            const uint32_t idx = t * TILE + i * MQ_BLOCK + threadIdx.x;
-            if (idx < n)
-                for (int p = 0; p < passes; p++) atomicAdd(&sh[p * R::BUCKETS + ((k[i] >> (p * RB)) & R::MASK)], 1u);
+            for (int i = 0; i < HIST_IPT; i++) {
+                if (i < cnt) {
+                    const uint32_t d = (k[i] >> sh_p) & R::MASK;
+                    if (d != cur) {
+                        atomicAdd(&sh[p * R::BUCKETS + cur], run);
+                        cur = d;
+                        run = 0;
+                    }
+                    run++;
+                }
+            }
+            if (run) atomicAdd(&sh[p * R::BUCKETS + cur], run);
         }
     }
     __syncthreads();

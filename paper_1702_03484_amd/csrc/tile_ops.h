@@ -451,13 +451,31 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint
 // payload and value loads are all independent; rows that cross into later
 // segments take mat_rows_slow.  NC is an upper bound of the column count
 // 1 + nl + nr; NLC >= 0 fixes nl = NLC and nr = NC - 1 - NLC at compile time.
+// The segment of row j (the last s with seg_off[s] <= j), given a guess:
+// the segment of an earlier row of the same wave, or 0.  When j still lies
+// in the guess's segment or the next one, three independent loads settle
+// it; otherwise a 64-ary search from the guess on.
+__device__ __forceinline__ uint32_t seg_from_hint(const MatJoin& a, uint32_t hint, uint64_t j) {
+    const uint64_t o0 = a.seg_off[hint];
+    const uint64_t o1 = hint + 1 < a.ns ? a.seg_off[hint + 1] : ~0ull;
+    const uint64_t o2 = hint + 2 < a.ns ? a.seg_off[hint + 2] : ~0ull;
+    if (o0 <= j) {
+        if (j < o1) return hint;
+        if (j < o2) return hint + 1;
+    }
+    return wave_seg_of(a.seg_off, o0 <= j ? hint : 0, a.ns - 1, j);
+}
+
 template <int NC, int RPT, int NLC = -1>
-__device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend) {
+__device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend, uint32_t& hint) {
     constexpr int Q = RPT / 4;
     const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
     const int nc = 1 + nl + nr;
-    const uint32_t s_first = wave_seg_of(a.seg_off, 0, a.ns - 1, j0);
-    const uint32_t s_last = wave_seg_of(a.seg_off, s_first, a.ns - 1, jend - 1);
+    const uint32_t s_first = seg_from_hint(a, hint, j0);
+    const uint32_t s_last = (s_first + 1 >= a.ns || jend - 1 < a.seg_off[s_first + 1])
+                                ? s_first
+                                : wave_seg_of(a.seg_off, s_first, a.ns - 1, jend - 1);
+    hint = s_last;
     // phase 1: each sub-chunk's segment and the position of its first row
     uint32_t qs[Q];
     SegPos qp[Q];

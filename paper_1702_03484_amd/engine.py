@@ -11,8 +11,14 @@ import torch
 from . import binding as B
 
 
+_DEFAULT_TUNING = "default"
+
+
 class MapSQ:
-    def __init__(self, arena_bytes: int = 8 << 30, device: int = 0, stream: torch.cuda.Stream | None = None):
+    def __init__(self, arena_bytes: int = 8 << 30, device: int = 0, stream: torch.cuda.Stream | None = None,
+                 tuning: str | None = _DEFAULT_TUNING):
+        """tuning: a JSON table written by ``python -m paper_1702_03484_amd.autotune``
+        (default: the one shipped with the package, if present; None: no table)."""
         if not torch.cuda.is_available():
             raise RuntimeError("MapSQ needs a GPU (gfx950); there is no CPU path")
         self.device = device
@@ -20,6 +26,10 @@ class MapSQ:
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.ctx = B.mapsq_create(device, self.arena.data_ptr(), self.arena.numel(), self.stream.cuda_stream)
         self._keep = []
+        if tuning is not None:
+            from . import autotune
+
+            autotune.install(self, autotune.DEFAULT_TABLE if tuning == _DEFAULT_TUNING else tuning)
 
     def close(self):
         if self.ctx is not None:
