@@ -123,15 +123,14 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
             mj.ssrc[c] = merged ? mj.src[c] : (left ? a.sval[c - 1] : a.sval[c - 1 - mj.nl]);
         }
     }
-    // each wave takes a contiguous run of chunks, so the segment found for
-    // one chunk is the starting guess for the next
+    // chunks strided over the waves (the rows being written at any moment
+    // stay in one window of the output); a wave's previous segment is the
+    // starting guess for its next chunk
     const uint64_t nchunks = (a.row_end - a.row_begin + WROWS - 1) / WROWS;
     const uint64_t gw = (uint64_t)blockIdx.x * MQ_WAVES + threadIdx.x / MQ_WAVE;
     const uint64_t nw = (uint64_t)gridDim.x * MQ_WAVES;
-    const uint64_t per = (nchunks + nw - 1) / nw;
-    const uint64_t c_end = min(nchunks, (gw + 1) * per);
     uint32_t hint = 0;
-    for (uint64_t c = gw * per; c < c_end; c++) {
+    for (uint64_t c = gw; c < nchunks; c += nw) {
         const uint64_t j0 = a.row_begin + c * WROWS;
         mat_wave_chunk<NC, MatShape<NC>::RPT, NLC>(mj, j0, min(j0 + WROWS, a.row_end), hint);
     }

@@ -443,18 +443,11 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint
     }
 }
 
-// Materialise output rows [j0, jend) (at most 64*RPT rows, j0 a multiple of
-// 4) of one join with one wave.  The chunk is cut into RPT/4 sub-chunks of
-// 256 rows; in each, lane L writes rows 4L..4L+3, so every 16-byte store
-// instruction of the wave covers 1 KB of one column contiguously.  A lane's
-// four rows that lie in one segment take the fast path, whose position,
-// payload and value loads are all independent; rows that cross into later
-// segments take mat_rows_slow.  NC is an upper bound of the column count
-// 1 + nl + nr; NLC >= 0 fixes nl = NLC and nr = NC - 1 - NLC at compile time.
 // The segment of row j (the last s with seg_off[s] <= j), given a guess:
 // the segment of an earlier row of the same wave, or 0.  When j still lies
 // in the guess's segment or the next one, three independent loads settle
-// it; otherwise a 64-ary search from the guess on.
+// it; otherwise a 64-ary search from the guess on.  Every lane of the wave
+// calls it with the same arguments.
 __device__ __forceinline__ uint32_t seg_from_hint(const MatJoin& a, uint32_t hint, uint64_t j) {
     const uint64_t o0 = a.seg_off[hint];
     const uint64_t o1 = hint + 1 < a.ns ? a.seg_off[hint + 1] : ~0ull;
@@ -466,101 +459,161 @@ __device__ __forceinline__ uint32_t seg_from_hint(const MatJoin& a, uint32_t hin
     return wave_seg_of(a.seg_off, o0 <= j ? hint : 0, a.ns - 1, j);
 }
 
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
+// Materialise output rows [j0, jend) (at most 64*RPT rows, j0 a multiple of
+// 4) of one join with one wave.  The chunk is cut into sub-chunks of 256
+// rows; in each, lane L writes rows 4L..4L+3, so every 16-byte store
+// instruction of the wave covers 1 KB of one column contiguously.
+//
+// A sub-chunk that lies inside one segment (the common case: the output of a
+// hot key spans many sub-chunks) takes the wave-uniform path: the segment,
+// its pair order and the divide of the sub-chunk's first row into (outer,
+// inner) are computed once for the wave (scalar registers); each lane then
+// needs only its offset 4L past that row, whose quotient by the inner run
+// length is one compare when the run has at least 256 rows and a small
+// exact divide otherwise.  Sub-chunks that cross segment boundaries take
+// mat_rows_slow per lane.  NC is an upper bound of the column count
+// 1 + nl + nr; NLC >= 0 fixes nl = NLC and nr = NC - 1 - NLC at compile
+// time.  `hint` carries the wave's current segment from chunk to chunk.
 template <int NC, int RPT, int NLC = -1>
 __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend, uint32_t& hint) {
     constexpr int Q = RPT / 4;
     const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
     const int nc = 1 + nl + nr;
-    const uint32_t s_first = seg_from_hint(a, hint, j0);
-    const uint32_t s_last = (s_first + 1 >= a.ns || jend - 1 < a.seg_off[s_first + 1])
-                                ? s_first
-                                : wave_seg_of(a.seg_off, s_first, a.ns - 1, jend - 1);
-    hint = s_last;
-    // phase 1: each sub-chunk's segment and the position of its first row
-    uint32_t qs[Q];
-    SegPos qp[Q];
-    int32_t qkey[Q];
-    bool qon[Q], qfast[Q];
-    uint32_t s = s_first;
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-        const uint64_t j = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
-        qon[q] = j < jend;
-        qfast[q] = false;
-        qp[q] = SegPos{};
-        qs[q] = s;
-        qkey[q] = 0;
-        if (qon[q]) {
-            s = seg_of(a.seg_off, s, s_last, j);
-            seg_open<NC>(a, s, nl, nr, qp[q]);
-            const uint64_t r = j - a.seg_off[s];
-            seg_locate(qp[q], r);
-            qs[q] = s;
-            qkey[q] = (int32_t)(a.keys[qp[q].st] + (uint32_t)a.key_base);
-            qfast[q] = j + 4 <= jend && r + 4 <= (uint64_t)qp[q].cl * qp[q].cr;
-        }
-    }
-    // phase 2: the LEFT and RIGHT sorted positions of every fast row; their
-    // payloads (record ids) only when values are gathered through them
-    uint32_t lrow[Q][4], rrow[Q][4];
-    const bool direct = a.sorted_vals;
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-        SegPos p = qp[q];
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            lrow[q][k] = 0;
-            rrow[q][k] = 0;
-            if (qfast[q]) {
-                if (direct) {
-                    lrow[q][k] = seg_lpos(p);
-                    rrow[q][k] = seg_rpos(p);
-                } else {
-                    if (nl > 0) lrow[q][k] = a.vals[seg_lpos(p)];
-                    if (nr > 0) rrow[q][k] = a.vals[seg_rpos(p)] - a.n_left;
-                }
-                seg_step(p);
+    uint32_t s = uni(seg_from_hint(a, uni(hint), j0));
+    {
+        SegPos p;
+        seg_open<NC>(a, s, nl, nr, p);
+        const uint32_t st = uni(p.st), sp = uni(p.sp), cl = uni(p.cl), cr = uni(p.cr);
+        const uint64_t off = uni64(a.seg_off[s]);
+        const uint64_t send = off + (uint64_t)cl * cr;
+        if (j0 + (uint64_t)Q * (4 * MQ_WAVE) <= (send < jend ? send : jend)) {
+            // the whole chunk lies in segment s: one uniform divide, then
+            // every lane's rows of all sub-chunks, all loads before any store
+            const bool left_in = left_inner_of(cl, cr, nl, nr);
+            const uint32_t ci = left_in ? cl : cr;
+            const uint64_t r0 = j0 - off;
+            uint32_t o0, i0;
+            if (r0 <= 0xffffffffull) {
+                o0 = uni((uint32_t)r0 / ci);
+                i0 = uni((uint32_t)r0 - o0 * ci);
+            } else {
+                o0 = uni((uint32_t)(r0 / ci));
+                i0 = uni((uint32_t)(r0 - (uint64_t)o0 * ci));
             }
+            const int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
+            int32_t v[Q][NC][4];
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+                // this lane's first row of sub-chunk q: offset t past (o0, i0)
+                const uint32_t t = i0 + (uint32_t)q * (4 * MQ_WAVE) + 4u * lane();  // < ci + 64 * RPT
+                uint32_t dq, inner;
+                if (ci >= (uint32_t)(4 * MQ_WAVE * Q)) {
+                    dq = t >= ci ? 1u : 0u;
+                    inner = t - (dq ? ci : 0u);
+                } else {
+                    dq = t / ci;
+                    inner = t - dq * ci;
+                }
+                uint32_t outer = o0 + dq;
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    v[q][0][k] = key;
+                    row_values<NC>(a, nl, nc, st + (left_in ? inner : outer), sp + (left_in ? outer : inner), v[q], k);
+                    if (++inner == ci) {
+                        inner = 0;
+                        outer++;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+                const uint64_t jl = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
+#pragma unroll
+                for (int col = 0; col < NC; col++)
+                    if (col < nc)
+                        *reinterpret_cast<int4*>(a.out[col] + jl) =
+                            make_int4(v[q][col][0], v[q][col][1], v[q][col][2], v[q][col][3]);
+            }
+            hint = s;
+            return;
         }
     }
-    // phase 3: values and 16-byte stores
-#pragma unroll
+    // the chunk crosses segment boundaries: sub-chunk by sub-chunk
+#pragma unroll 1
     for (int q = 0; q < Q; q++) {
-        if (!qon[q]) continue;
-        const uint64_t j = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
+        const uint64_t jq = j0 + (uint64_t)q * (4 * MQ_WAVE);
+        if (jq >= jend) break;
+        s = uni(seg_from_hint(a, s, jq));
+        SegPos p;
+        seg_open<NC>(a, s, nl, nr, p);
+        const uint32_t st = uni(p.st), sp = uni(p.sp), cl = uni(p.cl), cr = uni(p.cr);
+        const uint64_t off = uni64(a.seg_off[s]);
+        const uint64_t send = off + (uint64_t)cl * cr;
+        const uint64_t jl = jq + 4ull * lane();
         int32_t v[NC][4];
         int nk = 4;
-        if (qfast[q]) {
+        if (jq + 4 * MQ_WAVE <= (send < jend ? send : jend)) {
+            // wave-uniform: the whole sub-chunk lies in segment s
+            const bool left_in = left_inner_of(cl, cr, nl, nr);
+            const uint32_t ci = left_in ? cl : cr;
+            const uint64_t r0 = jq - off;
+            uint32_t o0, i0;
+            if (r0 <= 0xffffffffull) {
+                o0 = uni((uint32_t)r0 / ci);
+                i0 = uni((uint32_t)r0 - o0 * ci);
+            } else {
+                o0 = uni((uint32_t)(r0 / ci));
+                i0 = uni((uint32_t)(r0 - (uint64_t)o0 * ci));
+            }
+            const uint32_t t = i0 + 4u * lane();  // < ci + 256
+            uint32_t dq, inner;
+            if (ci >= 4 * MQ_WAVE) {
+                dq = t >= ci ? 1u : 0u;
+                inner = t - (dq ? ci : 0u);
+            } else {
+                dq = t / ci;  // t < 512
+                inner = t - dq * ci;
+            }
+            uint32_t outer = o0 + dq;
+            const int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
 #pragma unroll
             for (int k = 0; k < 4; k++) {
-                v[0][k] = qkey[q];
-                if (direct) {
-#pragma unroll
-                    for (int col = 1; col < NC; col++)
-                        if (col < nc) v[col][k] = a.ssrc[col][col <= nl ? lrow[q][k] : rrow[q][k]];
-                } else {
-#pragma unroll
-                    for (int col = 1; col < NC; col++)
-                        if (col < nc) v[col][k] = a.src[col][col <= nl ? lrow[q][k] : rrow[q][k]];
+                const uint32_t lpos = st + (left_in ? inner : outer);
+                const uint32_t rpos = sp + (left_in ? outer : inner);
+                v[0][k] = key;
+                row_values<NC>(a, nl, nc, lpos, rpos, v, k);
+                if (++inner == ci) {
+                    inner = 0;
+                    outer++;
                 }
             }
         } else {
-            nk = (int)min((uint64_t)4, jend - j);
-            mat_rows_slow<NC, NLC>(a, qs[q], s_last, j, nk, v);
+            // the sub-chunk's last segment (every lane takes part in the
+            // search), then each lane's own segment and rows
+            const uint64_t jlast = (jend < jq + 4 * MQ_WAVE ? jend : jq + 4 * MQ_WAVE) - 1;
+            const uint32_t s_last = wave_seg_of(a.seg_off, s, a.ns - 1, jlast);
+            nk = jl < jend ? (int)min((uint64_t)4, jend - jl) : 0;
+            if (nk > 0) mat_rows_slow<NC, NLC>(a, seg_of(a.seg_off, s, s_last, jl), s_last, jl, nk, v);
         }
         if (nk == 4) {
 #pragma unroll
             for (int col = 0; col < NC; col++)
-                if (col < nc) *reinterpret_cast<int4*>(a.out[col] + j) = make_int4(v[col][0], v[col][1], v[col][2], v[col][3]);
-        } else {
+                if (col < nc) *reinterpret_cast<int4*>(a.out[col] + jl) = make_int4(v[col][0], v[col][1], v[col][2], v[col][3]);
+        } else if (nk > 0) {
 #pragma unroll
             for (int col = 0; col < NC; col++)
                 if (col < nc)
 #pragma unroll
                     for (int k = 0; k < 4; k++)
-                        if (k < nk) a.out[col][j + k] = v[col][k];
+                        if (k < nk) a.out[col][jl + k] = v[col][k];
         }
     }
+    hint = s;
 }
 
 }  // namespace mq
