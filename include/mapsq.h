@@ -208,19 +208,23 @@ mapsq_status mapsq_join_batch(mapsq_ctx* ctx, const mapsq_join_desc* joins, int3
  * Queries are queued by mapsq_submit.  Each mapsq_serve_step is one
  * scheduling round: waiting queries get exact pattern sizes from the index
  * ranges and a predicted intermediate-byte cost (greedy plan, join sizes
- * estimated from per-predicate distinct counts); queries are admitted in
+ * estimated from per-predicate distinct counts); they are admitted in
  * arrival order while the predicted bytes of all admitted queries stay
- * within the budget; a query predicted above the whole budget waits until
- * nothing else is in flight and then runs alone.  Newly admitted queries
- * map their patterns; then the next join step of every admitted query runs
- * in one batched launch.  A step that finds no memory waits while other
- * queries in flight hold memory; when a round makes no progress at all, the
- * most recently admitted waiting query frees what it holds and is queued
- * again at the head, and nothing is admitted until some query ends.  A
- * query fails with TOO_LARGE only when it does not fit with nothing else in
- * flight, or when an intermediate reaches 2^31 rows.  A query that arrives
- * while others are in flight joins the next round.  Each result is exactly
- * what mapsq_query returns for the query alone.  Serving calls use
+ * within the budget, a later query that fits going ahead of one that does
+ * not (at most 8 rounds in a row, then admission waits for the older one).
+ * A query predicted above the whole budget reserves nothing: the exact size
+ * of each of its joins decides.  Newly admitted queries map their patterns;
+ * then the next join step of every admitted query runs: small steps
+ * together in one batched launch, steps of 2^20 records or more and steps
+ * whose inputs are already in key order through the plain join path.  A
+ * step that finds no memory waits while other queries hold memory, unless
+ * its exact output could not fit even if they let go of everything; when a
+ * round makes no progress at all, the most recently admitted waiting query
+ * frees what it holds and is queued again at the head, and nothing is
+ * admitted until some query ends.  A query fails with TOO_LARGE when a join
+ * output cannot fit or an intermediate reaches 2^31 rows.  A query that
+ * arrives while others are in flight joins the next round.  Each result is
+ * exactly what mapsq_query returns for the query alone.  Serving calls use
  * the context like every other call: one thread at a time. */
 
 /* Budget of predicted intermediate bytes (0: 60% of the arena's free space

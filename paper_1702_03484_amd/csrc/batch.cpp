@@ -46,11 +46,13 @@ struct Plan {
 }  // namespace
 
 mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_table* outs,
-                        mapsq_status* per_join) {
+                        mapsq_status* per_join, int64_t* need_rows) {
     if (n < 0 || (n > 0 && (!d || !outs))) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "bad batch arguments");
     for (int i = 0; i < n; i++) std::memset(&outs[i], 0, sizeof(mapsq_table));
     if (per_join)
         for (int i = 0; i < n; i++) per_join[i] = MAPSQ_OK;
+    if (need_rows)
+        for (int i = 0; i < n; i++) need_rows[i] = 0;
     if (n == 0) return MAPSQ_OK;
     std::vector<Plan> plan(n);
     int32_t kmax = 0;
@@ -270,6 +272,7 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
             if (plan[i].batched && !plan[i].empty && J[i].status == 2) {
                 if (!per_join) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join " + std::to_string(i) + ": over 2^40 rows");
                 per_join[i] = MAPSQ_ERR_TOO_LARGE;
+                if (need_rows) need_rows[i] = (int64_t)J[i].total;
                 done[i] = true;
             }
         // results in the output region share its block
@@ -318,6 +321,7 @@ plain_rest:
             std::string msg = ctx->err;
             if (!per_join) return fail_all(st, "join " + std::to_string(i) + ": " + msg);
             per_join[i] = st;
+            if (need_rows) need_rows[i] = ctx->last.out_rows;
             std::memset(&res[i], 0, sizeof(mapsq_table));
         }
         done[i] = true;

@@ -158,6 +158,32 @@ mapsq_status query_vars(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, cons
     return MAPSQ_OK;
 }
 
+// Views re-made from the other index where that puts their rows in the
+// order of the key they are joined on (the first step's key for the start
+// table), so that the join pairs key runs without a shuffle.  Owned tables
+// and views already in key order are left alone.
+mapsq_status key_sort_views(Ctx* ctx, const mapsq_pattern* pats, mapsq_table* tabs, int start,
+                            const std::vector<PlanStep>& steps) {
+    auto one = [&](int i, int32_t key) -> mapsq_status {
+        const int kc = col_of(&tabs[i], key);
+        if (tabs[i].owned || kc < 0 || tabs[i].sorted_col == kc + 1) return MAPSQ_OK;
+        mapsq_table t{};
+        if (mapsq_status st = map_pattern(ctx, &pats[i], key, &t)) return st;
+        if (t.owned)
+            free_table(ctx, &t);
+        else if (t.sorted_col == 1)
+            tabs[i] = t;
+        return MAPSQ_OK;
+    };
+    for (size_t k = 0; k < steps.size(); k++) {
+        if (steps[k].cross) continue;
+        if (mapsq_status st = one(steps[k].pick, steps[k].key)) return st;
+        if (k == 0)
+            if (mapsq_status st = one(start, steps[k].key)) return st;
+    }
+    return MAPSQ_OK;
+}
+
 mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
                    mapsq_table* out) {
     std::memset(out, 0, sizeof(*out));
@@ -189,29 +215,9 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
     int start;
     std::vector<PlanStep> steps;
     greedy_plan(tv, tr, qvars, &start, &steps);
-    // a view can be re-made from the other index so that its rows ascend on
-    // the key it is joined on (then the join needs no shuffle)
-    auto key_sorted = [&](int i, int32_t key) {
-        const int kc = col_of(&tabs[i], key);
-        if (tabs[i].owned || kc < 0 || tabs[i].sorted_col == kc + 1) return MAPSQ_OK;
-        mapsq_table t{};
-        mapsq_status s2 = map_pattern(ctx, &pats[i], key, &t);
-        if (s2) return s2;
-        if (t.owned) {
-            free_table(ctx, &t);
-        } else if (t.sorted_col == 1) {
-            tabs[i] = t;
-        }
-        return MAPSQ_OK;
-    };
-    for (size_t k = 0; k < steps.size(); k++) {
-        if (steps[k].cross) continue;
-        mapsq_status s2 = key_sorted(steps[k].pick, steps[k].key);
-        if (!s2 && k == 0) s2 = key_sorted(start, steps[k].key);
-        if (s2) {
-            cleanup();
-            return s2;
-        }
+    if (mapsq_status s2 = key_sort_views(ctx, pats, tabs.data(), start, steps)) {
+        cleanup();
+        return s2;
     }
     mapsq_table cur = tabs[start];
     used[start] = true;

@@ -186,9 +186,10 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
                    mapsq_table* out);
 // per_join == nullptr: any failing join fails the whole batch.  Otherwise a
 // join that fails leaves its status there (and a zeroed table) while the
-// others complete.
+// others complete, and need_rows (if given) gets each failed join's exact
+// output row count when it was counted (0 otherwise).
 mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_table* outs,
-                        mapsq_status* per_join = nullptr);
+                        mapsq_status* per_join = nullptr, int64_t* need_rows = nullptr);
 struct PlanStep {
     int pick;     // table joined at this step
     int32_t key;  // join variable (-1 for a cross product)
@@ -198,6 +199,8 @@ void greedy_plan(const std::vector<std::vector<int32_t>>& vars, const std::vecto
                  const std::vector<int32_t>& qvars, int* start, std::vector<PlanStep>* steps);
 mapsq_status cross_join(Ctx* ctx, const mapsq_table& a, const mapsq_table& b, mapsq_table* out);
 mapsq_table project_table(const mapsq_table& cur, const std::vector<int32_t>& want);
+mapsq_status key_sort_views(Ctx* ctx, const mapsq_pattern* pats, mapsq_table* tabs, int start,
+                            const std::vector<PlanStep>& steps);
 bool ensure_stage(Ctx* ctx, size_t bytes);
 // serving (serve.cpp)
 mapsq_status serve_config(Ctx* ctx, uint64_t budget_bytes, int32_t max_active);

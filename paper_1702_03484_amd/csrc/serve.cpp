@@ -42,7 +42,16 @@ struct SQuery {
     mapsq_table cur{};
     mapsq_table result{};
     uint64_t admitted = 0;  // admission order (the latest is preempted first)
+    double reserve = 0;     // budget bytes held while admitted
+    int passed_over = 0;    // rounds in which later queries were admitted first
 };
+
+// a waiting query may be passed over by later ones this many rounds, then
+// admission waits for it (no starvation)
+constexpr int MAX_PASSED_OVER = 8;
+// join steps of at least this many records run through the plain join path
+// (merge join, semi-join reduction) rather than the batched kernels
+constexpr int64_t PLAIN_STEP_RECORDS = int64_t(1) << 20;
 
 }  // namespace
 
@@ -240,7 +249,7 @@ static void fail_query(Ctx* ctx, Server* S, SQuery* q, mapsq_status err) {
         if (!q->consumed[i]) free_table(ctx, &q->tabs[i]);
     if (q->cur.owned) free_table(ctx, &q->cur);
     std::memset(&q->cur, 0, sizeof(mapsq_table));
-    if (q->state == Q_ACTIVE) S->reserved -= q->predicted;
+    if (q->state == Q_ACTIVE) S->reserved -= q->reserve;
     q->state = Q_FAILED;
     q->err = err;
     S->hold = false;
@@ -257,7 +266,7 @@ static void preempt_query(Ctx* ctx, Server* S, SQuery* q) {
     q->consumed.clear();
     q->steps.clear();
     q->next = 0;
-    S->reserved -= q->predicted;
+    S->reserved -= q->reserve;
     q->state = Q_WAITING;
     S->waiting.push_front(q);
     S->hold = true;
@@ -267,7 +276,7 @@ static void finish_query(Server* S, SQuery* q) {
     q->result = project_table(q->cur, q->want);
     std::memset(&q->cur, 0, sizeof(mapsq_table));
     q->state = Q_DONE;
-    S->reserved -= q->predicted;
+    S->reserved -= q->reserve;
     S->hold = false;
 }
 
@@ -289,6 +298,7 @@ static mapsq_status activate(Ctx* ctx, Server* S, SQuery* q) {
         rows[i] = q->tabs[i].nrows;
     }
     greedy_plan(vars, rows, q->qvars, &q->start, &q->steps);
+    if (mapsq_status st = key_sort_views(ctx, q->pats.data(), q->tabs.data(), q->start, q->steps)) return st;
     q->cur = q->tabs[q->start];
     q->consumed[q->start] = true;
     q->next = 0;
@@ -301,10 +311,11 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     Server* S = server(ctx);
     if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
     if (S->budget <= 0) S->budget = 0.6 * (double)ctx->arena.free_bytes();
-    // 1. sizes, plans and predictions of the waiting queries; FIFO admission
-    // while the admitted predictions fit the budget.  A query predicted
-    // above the whole budget is not refused on the estimate: it waits for
-    // the active set to drain and then runs alone.
+    // 1. sizes, plans and predictions of the waiting queries; admission in
+    // arrival order while the admitted predictions fit the budget, later
+    // queries that fit going first (a query passed over MAX_PASSED_OVER
+    // rounds stops that).  A prediction above the whole budget reserves
+    // nothing: the exact size of each of its joins decides (step 2).
     mapsq_status st = size_waiting(ctx, S);
     if (st) return st;
     auto live_others = [&](const SQuery* q) {
@@ -312,30 +323,32 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         for (const SQuery* o : S->active) k += o != q && o->state == Q_ACTIVE;
         return k;
     };
-    bool exclusive = false;
-    for (SQuery* q : S->active)
-        if (q->state == Q_ACTIVE && q->predicted > S->budget) exclusive = true;
-    while (!S->waiting.empty() && !S->hold && !exclusive) {
-        SQuery* q = S->waiting.front();
+    for (auto it = S->waiting.begin(); it != S->waiting.end() && !S->hold;) {
+        SQuery* q = *it;
+        if ((int)S->active.size() >= S->max_active) break;
         if (q->predicted == 0) predict(ctx, q);
-        const bool oversize = q->predicted > S->budget;
-        if (oversize ? !S->active.empty()
-                     : ((int)S->active.size() >= S->max_active || S->reserved + q->predicted > S->budget))
-            break;
-        S->waiting.pop_front();
-        S->reserved += q->predicted;
+        const double r = q->predicted > S->budget ? 0.0 : q->predicted;
+        if (S->reserved + r > S->budget) {
+            if (++q->passed_over > MAX_PASSED_OVER) break;
+            ++it;
+            continue;
+        }
+        it = S->waiting.erase(it);
+        q->reserve = r;
+        S->reserved += r;
         S->active.push_back(q);
         q->state = Q_ACTIVE;
         q->admitted = ++S->admissions;
-        exclusive = oversize;
         st = activate(ctx, S, q);
         if (st == MAPSQ_ERR_CAPACITY && live_others(q) > 0)
             preempt_query(ctx, S, q);  // its partial matches do not fit yet
         else if (st)
             fail_query(ctx, S, q, st == MAPSQ_ERR_CAPACITY ? MAPSQ_ERR_TOO_LARGE : st);
+        if (S->hold) break;
     }
-    // 2. the next join step of every active query, in one batched launch
-    std::vector<SQuery*> in_batch;
+    // 2. the next join step of every active query: small ones together in
+    // one batched launch, large or key-sorted ones through the plain path
+    std::vector<SQuery*> in_batch, in_plain;
     std::vector<mapsq_join_desc> descs;
     int progress = 0;
     // a finished step: the intermediate must stay joinable (under 2^31 rows)
@@ -350,45 +363,80 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         else if (q->cur.nrows >= (int64_t(1) << 31))
             fail_query(ctx, S, q, MAPSQ_ERR_TOO_LARGE);
     };
+    // bytes the query could use if every other active query let go of its tables
+    auto room_alone = [&](const SQuery* q) {
+        double b = (double)ctx->arena.free_bytes();
+        for (const SQuery* o : S->active) {
+            if (o == q || o->state != Q_ACTIVE) continue;
+            auto held = [&](const mapsq_table& t) {
+                return t.owned ? 4.0 * (double)t.nrows * t.ncols + 256.0 * t.ncols : 0.0;
+            };
+            b += held(o->cur);
+            for (size_t i = 0; i < o->tabs.size(); i++)
+                if (!o->consumed[i]) b += held(o->tabs[i]);
+        }
+        return b;
+    };
+    std::vector<SQuery*> stalled;
+    // a failed step: wait for memory while others hold some, unless the
+    // exact output could not fit even then
+    auto failed = [&](SQuery* q, mapsq_status e, int64_t need_rows) {
+        const bool memory = e == MAPSQ_ERR_CAPACITY || e == MAPSQ_ERR_TOO_LARGE;
+        if (memory && live_others(q) > 0) {
+            const PlanStep& ps = q->steps[q->next];
+            const double cols = q->cur.ncols + q->tabs[ps.pick].ncols - 1;
+            const double need = 4.0 * (double)need_rows * cols;
+            if (need_rows < SAT40_HOST && need <= room_alone(q)) {
+                stalled.push_back(q);
+                return;
+            }
+        }
+        fail_query(ctx, S, q, memory ? MAPSQ_ERR_TOO_LARGE : e);
+        progress++;
+    };
     for (SQuery* q : S->active) {
         if (q->state != Q_ACTIVE || q->next >= q->steps.size()) continue;
         const PlanStep& ps = q->steps[q->next];
         if (ps.cross) {  // rare: run it now through the plain path
             mapsq_table nxt{};
             st = cross_join(ctx, q->cur, q->tabs[ps.pick], &nxt);
-            if (st) {
-                fail_query(ctx, S, q, st);
-                progress++;
-                continue;
-            }
-            advance(q, nxt, ps.pick);
+            if (st)
+                failed(q, st, ctx->last.out_rows);
+            else
+                advance(q, nxt, ps.pick);
             continue;
         }
-        in_batch.push_back(q);
-        descs.push_back(mapsq_join_desc{&q->cur, &q->tabs[ps.pick], ps.key, 0});
+        const mapsq_table& R = q->tabs[ps.pick];
+        const bool sorted = q->cur.sorted_col == col_of(&q->cur, ps.key) + 1 && R.sorted_col == col_of(&R, ps.key) + 1;
+        if (sorted || q->cur.nrows + R.nrows >= PLAIN_STEP_RECORDS) {
+            in_plain.push_back(q);
+        } else {
+            in_batch.push_back(q);
+            descs.push_back(mapsq_join_desc{&q->cur, &q->tabs[ps.pick], ps.key, 0});
+        }
     }
-    std::vector<SQuery*> stalled;
     if (!descs.empty()) {
         std::vector<mapsq_table> outs(descs.size());
         std::vector<mapsq_status> per(descs.size());
-        st = join_batch(ctx, descs.data(), (int32_t)descs.size(), outs.data(), per.data());
+        std::vector<int64_t> need(descs.size());
+        st = join_batch(ctx, descs.data(), (int32_t)descs.size(), outs.data(), per.data(), need.data());
         if (st) return st;
         for (size_t k = 0; k < in_batch.size(); k++) {
             SQuery* q = in_batch[k];
-            if (per[k] != MAPSQ_OK) {
-                const bool memory = per[k] == MAPSQ_ERR_CAPACITY || per[k] == MAPSQ_ERR_TOO_LARGE;
-                // memory held by other running queries comes back when they
-                // end: wait.  Alone, the query cannot fit: refuse it.
-                if (memory && live_others(q) > 0) {
-                    stalled.push_back(q);
-                    continue;
-                }
-                fail_query(ctx, S, q, memory ? MAPSQ_ERR_TOO_LARGE : per[k]);
-                progress++;
-                continue;
-            }
-            advance(q, outs[k], q->steps[q->next].pick);
+            if (per[k] != MAPSQ_OK)
+                failed(q, per[k], need[k]);
+            else
+                advance(q, outs[k], q->steps[q->next].pick);
         }
+    }
+    for (SQuery* q : in_plain) {
+        const PlanStep& ps = q->steps[q->next];
+        mapsq_table nxt{};
+        st = join_tables(ctx, &q->cur, &q->tabs[ps.pick], ps.key, &nxt);
+        if (st)
+            failed(q, st, ctx->last.out_rows);
+        else
+            advance(q, nxt, ps.pick);
     }
     // a round in which every step waited for memory: the latest admitted
     // waiting query gives its memory back and restarts later
