@@ -214,8 +214,18 @@ def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1
     warm_q, qs = qs[:warm], qs[warm:]
     serving.run_plain(sess, warm_q, np.zeros(len(warm_q)))
     serving.run_continuous(sess, warm_q, np.zeros(len(warm_q)))
-    sat_plain, _, _ = serving.run_plain(sess, qs, np.zeros(len(qs)))
+    sat_plain, lat_p, st_p = serving.run_plain(sess, qs, np.zeros(len(qs)))
     sat_cont, _, _ = serving.run_continuous(sess, qs, np.zeros(len(qs)))
+    # one query at a time from t = 0: the gaps between completions are service times
+    order = np.argsort(lat_p)
+    svc = np.diff(np.concatenate([[0.0], lat_p[order]]))
+    svc_of = np.empty_like(svc)
+    svc_of[order] = svc
+    ok = st_p == 0
+    log(f"[cfg5] plain service time: completed {svc_of[ok].sum():.3f} s over {ok.sum()} queries, "
+        f"refused {svc_of[~ok].sum():.3f} s over {(~ok).sum()}")
+    for j in np.argsort(-svc_of)[:8]:
+        log(f"[cfg5]   {svc_of[j] * 1e3:8.2f} ms status {int(st_p[j])}: {qs[j]}")
     log(f"[cfg5] saturated: plain {sat_plain['qps']:.0f} q/s, continuous {sat_cont['qps']:.0f} q/s")
     rows = []
     for f in loads:

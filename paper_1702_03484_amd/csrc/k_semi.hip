@@ -128,3 +128,92 @@ hipError_t launch_side_records(const int32_t* keys, uint32_t n, int32_t base, ui
 }
 
 }  // namespace mq
+
+namespace mq {
+
+// Exact |RS| before any shuffle: the smaller side's keys are counted into a
+// dense array over the key range, then every record of the larger side
+// adds the count of its key (sum over keys of cL * cR, Algorithm 1's
+// ReduceDuplicate without grouping).  Keys outside [base, base + range)
+// count nothing.
+// Each thread counts 16 consecutive keys, one atomic per run of equal keys;
+// when the wave's 1024 keys are all one key (a hot key of a key-sorted
+// side) one atomic counts them all, so hot keys do not serialise.
+constexpr int KC_IPT = 16;
+
+__global__ __launch_bounds__(MQ_BLOCK) void key_count_kernel(const int32_t* __restrict__ keys, uint32_t n, int32_t base,
+                                                             uint64_t range, uint32_t* __restrict__ cnt) {
+    constexpr uint32_t TILE = MQ_BLOCK * KC_IPT;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * TILE; t0 < n; t0 += (uint64_t)gridDim.x * TILE) {
+        const uint64_t first = t0 + (uint64_t)threadIdx.x * KC_IPT;
+        uint32_t k[KC_IPT];
+#pragma unroll
+        for (int i = 0; i < KC_IPT; i++)
+            k[i] = first + i < n ? (uint32_t)keys[first + i] - (uint32_t)base : 0xffffffffu;
+        const int cnt_here = first >= n ? 0 : (int)min((uint64_t)KC_IPT, n - first);
+        const bool full = __ballot(cnt_here == KC_IPT) == ~0ull;
+        const uint32_t k0 = __shfl(k[0], 0, MQ_WAVE), k1 = __shfl(k[KC_IPT - 1], MQ_WAVE - 1, MQ_WAVE);
+        if (full && k0 == k1) {
+            // sorted input, one key over the whole wave (unsorted input with
+            // this property is one key too: the test is exact either way)
+            bool same = true;
+#pragma unroll
+            for (int i = 0; i < KC_IPT; i++) same = same && k[i] == k0;
+            if (__ballot(!same) == 0ull) {
+                if (lane() == 0 && k0 < range) atomicAdd(&cnt[k0], (uint32_t)(MQ_WAVE * KC_IPT));
+                continue;
+            }
+        }
+        uint32_t cur = k[0], run = 0;
+#pragma unroll
+        for (int i = 0; i < KC_IPT; i++) {
+            if (i < cnt_here) {
+                if (k[i] != cur) {
+                    if (cur < range) atomicAdd(&cnt[cur], run);
+                    cur = k[i];
+                    run = 0;
+                }
+                run++;
+            }
+        }
+        if (run && cur < range) atomicAdd(&cnt[cur], run);
+    }
+}
+
+__global__ __launch_bounds__(MQ_BLOCK) void key_dot_kernel(const int32_t* __restrict__ keys, uint32_t n, int32_t base,
+                                                           uint64_t range, const uint32_t* __restrict__ cnt,
+                                                           unsigned long long* __restrict__ total) {
+    __shared__ uint64_t s_w[MQ_WAVES];
+    uint64_t acc = 0;
+    for (uint32_t i = blockIdx.x * MQ_BLOCK + threadIdx.x; i < n; i += gridDim.x * MQ_BLOCK) {
+        const uint32_t k = (uint32_t)keys[i] - (uint32_t)base;
+        if (k < range) acc += cnt[k];
+    }
+    acc = wave_sum(acc);
+    if (lane() == 0) s_w[threadIdx.x / MQ_WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < MQ_WAVES; w++) t += s_w[w];
+        if (t) atomicAdd(total, (unsigned long long)t);
+    }
+}
+
+hipError_t launch_key_count(const int32_t* keys, uint32_t n, int32_t base, uint64_t range, uint32_t* cnt,
+                            hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint32_t blocks = std::min<uint32_t>((n + MQ_BLOCK * KC_IPT - 1) / (MQ_BLOCK * KC_IPT), 4096u);
+    key_count_kernel<<<blocks, MQ_BLOCK, 0, stream>>>(keys, n, base, range, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_dot(const int32_t* keys, uint32_t n, int32_t base, uint64_t range, const uint32_t* cnt,
+                          uint64_t* total, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint32_t blocks = std::min<uint32_t>((n + MQ_BLOCK * 8 - 1) / (MQ_BLOCK * 8), 4096u);
+    key_dot_kernel<<<blocks, MQ_BLOCK, 0, stream>>>(keys, n, base, range, cnt,
+                                                    reinterpret_cast<unsigned long long*>(total));
+    return hipGetLastError();
+}
+
+}  // namespace mq

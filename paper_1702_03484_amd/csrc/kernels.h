@@ -64,6 +64,13 @@ hipError_t launch_bitmap_set(const int32_t* keys, uint32_t n, int32_t base, uint
 hipError_t launch_semi_filter(const SemiArgs& a, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch,
                               hipStream_t stream);
 uint32_t semi_filter_tiles(uint32_t n);
+// Exact join size: cnt[k - base] += 1 over one side's keys (cnt cleared by
+// the caller, range entries), then *total += sum of cnt[k - base] over the
+// other side's keys (*total cleared by the caller).
+hipError_t launch_key_count(const int32_t* keys, uint32_t n, int32_t base, uint64_t range, uint32_t* cnt,
+                            hipStream_t stream);
+hipError_t launch_key_dot(const int32_t* keys, uint32_t n, int32_t base, uint64_t range, const uint32_t* cnt,
+                          uint64_t* total, hipStream_t stream);
 // all n records of one side at kout/vout[(*at_dev or 0) + i]
 hipError_t launch_side_records(const int32_t* keys, uint32_t n, int32_t base, uint32_t id_base,
                                const uint32_t* at_dev, uint32_t* kout, uint32_t* vout, hipStream_t stream);

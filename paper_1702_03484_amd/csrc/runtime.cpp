@@ -173,7 +173,7 @@ static inline uint32_t* scalar32(Ctx* ctx, int word) { return ctx->small + SMALL
 static inline uint32_t* counter(Ctx* ctx, int i) { return ctx->small + SMALL_CTR + i; }
 
 // scalar slots (u32 word index inside the scalar area)
-enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12 };
+enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12, SC_PRECOUNT = 14 };
 // counter slots
 enum { CT_PASS0 = 0, CT_HEADS = 8, CT_COUNT = 9, CT_COMPACT = 10, CT_SEMI = 11 };
 
@@ -930,6 +930,45 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     const int key_bits = bitlen((uint64_t)((int64_t)kmax - (int64_t)kmin));
     int rb, kpt;
     pick_tuning(ctx, key_bits, rb, kpt, (uint64_t)nL + nR);
+
+    // A large shuffle first gets the exact |RS| from two passes over the keys
+    // (dense key counts of the smaller side, summed over the larger side's
+    // records): a join with no key in common, or whose output cannot fit in
+    // the arena's free space at all, ends here without sorting anything.
+    if ((uint64_t)N >= PRECOUNT_MIN_RECORDS) {
+        const uint64_t range = (uint64_t)((int64_t)kmax - (int64_t)kmin) + 1;
+        Block cnt;
+        if (range <= PRECOUNT_MAX_RANGE) cnt = alloc_block(ctx, size_t(range) * 4);
+        if (cnt.ok()) {
+            // count a side sorted on the key (its hot keys come in runs), else the smaller one
+            const bool ls = L->sorted_col == lk + 1, rs = R->sorted_col == rk + 1;
+            const bool count_left = ls && rs ? nL <= nR : (ls || (!rs && nL <= nR));
+            const int ph = ctx->prof_begin(2);
+            HIPCHK(launch_fill_u32(cnt.as<uint32_t>(), range, 0u, ctx->stream));
+            HIPCHK(launch_fill_u32(scalar32(ctx, SC_PRECOUNT), 2, 0u, ctx->stream));
+            HIPCHK(launch_key_count(count_left ? lkey : rkey, count_left ? nL : nR, kmin, range, cnt.as<uint32_t>(),
+                                    ctx->stream));
+            HIPCHK(launch_key_dot(count_left ? rkey : lkey, count_left ? nR : nL, kmin, range, cnt.as<uint32_t>(),
+                                  scalar64(ctx, SC_PRECOUNT), ctx->stream));
+            // clears the counts, reads both key columns and one count per record of the other side
+            ctx->prof_end(ph, 4.0 * range + 4.0 * N + 4.0 * (count_left ? nR : nL));
+            uint64_t total = 0;
+            if ((st = readback(ctx, scalar64(ctx, SC_PRECOUNT), 8, &total))) return st;
+            cnt.reset();
+            js.out_rows = (int64_t)std::min<uint64_t>(total, SAT40_HOST);
+            ctx->last = js;
+            if (total >= SAT40_HOST) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds 2^40 rows");
+            if (total == 0) {
+                set_meta(out);
+                out->owned = 1;
+                out->nrows = 0;
+                return MAPSQ_OK;
+            }
+            if ((double)align_up(size_t(total) * 4, ARENA_ALIGN) * nc_mat > (double)ctx->arena.free_bytes())
+                return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result (" + std::to_string(total) +
+                                                          " rows) exceeds the arena's free space");
+        }
+    }
 
     // scratch: sort buffers (16 N) and segment offsets (8 N); the spare sort
     // buffers later hold the segment starts and splits

@@ -154,6 +154,10 @@ struct Ctx {
 // larger than the larger side's key column
 constexpr uint32_t SEMI_MIN_RECORDS = 1u << 16;
 constexpr uint64_t SEMI_RATIO = 4;
+// exact output size before the shuffle of at least this many records, when
+// the key range needs at most PRECOUNT_MAX_RANGE counters
+constexpr uint64_t PRECOUNT_MIN_RECORDS = uint64_t(1) << 24;
+constexpr uint64_t PRECOUNT_MAX_RANGE = uint64_t(1) << 28;
 
 constexpr size_t SMALL_HIST = 0;                  // up to 8 passes x 2048 buckets
 constexpr size_t SMALL_HIST_WORDS = 8 * 2048;

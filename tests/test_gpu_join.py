@@ -299,6 +299,48 @@ def test_query_merge_path_equals_shuffle(sess):
     assert merged >= 12
 
 
+def test_large_join_counts_exactly_before_sorting(sess):
+    announce("joins of 2^24+ records: exact count first (normal, empty, too large)")
+    r = np.random.default_rng(41)
+    n_big, n_small = (1 << 24) + 12345, 1_000_003
+    kl = r.integers(0, 1 << 20, size=n_big).astype(np.int32)
+    kr = r.integers(0, 1 << 20, size=n_small).astype(np.int32)
+    vl = r.integers(0, 1 << 31, size=n_big).astype(np.int32)
+    vr = r.integers(0, 1 << 31, size=n_small).astype(np.int32)
+    L = sess.table([0, 1], [dev(kl), dev(vl)])
+    R = sess.table([0, 2], [dev(kr), dev(vr)])
+    sess.set_join_options(semijoin=1, merge=1)
+    try:
+        out = sess.join(L, R, 0)
+        exp_rows = int(np.bincount(kl, minlength=1 << 20).astype(np.int64) @ np.bincount(kr, minlength=1 << 20))
+        assert out.nrows == exp_rows == sess.stats().out_rows
+        k, a, b = sess.to_numpy(out)
+        assert np.array_equal(np.bincount(k, minlength=1 << 20),
+                              np.bincount(kl, minlength=1 << 20) * np.bincount(kr, minlength=1 << 20))
+        # exact rows of a few keys
+        for key in r.choice(np.unique(kr), 5, replace=False):
+            got = Table([0, 1, 2], [k[k == key], a[k == key], b[k == key]])
+            exp = oracle.join(Table([0, 1], [kl[kl == key], vl[kl == key]]), Table([0, 2], [kr[kr == key], vr[kr == key]]), 0)
+            assert np.array_equal(oracle.canonical_rows(got), oracle.canonical_rows(exp))
+        sess.free(out)
+        # no key in common: empty, nothing sorted
+        R2 = sess.table([0, 2], [dev(kr + (1 << 20)), dev(vr)])
+        out = sess.join(L, R2, 0)
+        assert out.nrows == 0 and sess.stats().out_rows == 0 and sess.stats().sorted_records == 0
+        sess.free(out)
+        # one hot key on both sides: far more rows than the arena holds
+        free0 = B.mapsq_arena_free_bytes(sess.ctx)[0]
+        L3 = sess.table([0, 1], [dev(np.zeros(n_big, np.int32)), dev(vl)])
+        R3 = sess.table([0, 2], [dev(np.zeros(3000, np.int32)), dev(vr[:3000])])
+        with pytest.raises(B.MapSQError) as ei:
+            sess.join(L3, R3, 0)
+        assert ei.value.code == B.MAPSQ_ERR_TOO_LARGE
+        assert sess.stats().out_rows == n_big * 3000
+        assert B.mapsq_arena_free_bytes(sess.ctx)[0] == free0
+    finally:
+        sess.set_join_options(0, 0)
+
+
 def test_join_too_large_is_refused_without_leak(sess):
     announce("TOO_LARGE: over 2^40 rows and over the arena")
     free0 = None
