@@ -4,14 +4,24 @@ Workload (default): the plain 2-pattern join ``?x p1 ?y . ?y p2 c`` over
 50M dictionary-encoded int32 triples (32 predicates, Zipf(1.0); subject and
 object IDs Zipf(1.1) over 10M entities), about 194M output rows.  The store
 and its indexes are built once and stay resident in HBM; one step is one
-``mapsq_query`` call: map both patterns, sort, count/scan, materialise the
-result table in HBM, free it.  ``value`` is joined output rows per second.
+``mapsq_query`` call: map both patterns, group the records by key (here both
+patterns come from the index sorted on the key, so the join pairs key runs
+directly), count/scan, materialise the result table in HBM, free it.
+``value`` is joined output rows per second.
 
 The roofline entry is for the dominant kernel (materialisation): its
 algorithmic bytes per launch divided by its average launch time, timed with
 HIP events recorded by the library on the stream it launches on.
 
+Two more measurements go into the same JSON line: "batched" (512
+independent subqueries, plain one-join-per-call against one batched launch
+per chain step, exact row-for-row agreement checked) and "serving" (a
+resident 500M-triple store, random-walk queries, one query at a time against
+continuous batching, saturated and at Poisson arrival rates, p50/p99).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-batched] [--no-serving]
+       python bench.py --cfg4-only | --cfg5-only   (one of the two extra measurements)
        python bench.py --copy-calibration   (plain copy of a known size, for PMC scaling)
 """
 from __future__ import annotations
@@ -250,9 +260,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--n", type=int, default=50_000_000, help="triples (default: the full workload)")
-    ap.add_argument("--batched", action="store_true", help="add the 512-subquery batched-vs-plain measurement")
+    ap.add_argument("--no-batched", action="store_true", help="leave out the 512-subquery batched-vs-plain measurement")
     ap.add_argument("--cfg4-only", action="store_true")
-    ap.add_argument("--serving", action="store_true", help="add the serving measurement (500M-triple store)")
+    ap.add_argument("--no-serving", action="store_true", help="leave out the serving measurement (500M-triple store)")
     ap.add_argument("--cfg5-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -341,8 +351,20 @@ def main():
         log(f"[bench] oracle: {cpu['value']:.3e} rows/s")
 
     sess.close()
-    batched = run_cfg4() if args.batched else None
-    served = run_cfg5() if args.serving else None
+    del sess
+    torch.cuda.empty_cache()
+
+    def guarded(fn, name):
+        try:
+            return fn()
+        except Exception as e:  # the main line must still come out
+            log(f"[bench] {name} failed: {e!r}")
+            return {"error": repr(e)}
+        finally:
+            torch.cuda.empty_cache()
+
+    batched = None if args.no_batched else guarded(run_cfg4, "batched measurement")
+    served = None if args.no_serving else guarded(run_cfg5, "serving measurement")
     out = {
         "metric": "joined output rows/s",
         "value": rows * args.steps / el,

@@ -107,33 +107,62 @@ __device__ __forceinline__ uint64_t lookback(const uint64_t* status, uint32_t ti
 }
 
 // Wave-parallel look-back over one status column (stride 1): each probe
-// reads the 64 predecessors below `top` at once and stops at the nearest
-// inclusive prefix.  Every lane of the calling wave must call it; all lanes
-// return the exclusive prefix of `tile` (saturating at 2^40 - 1).
+// reads the LB_PER_LANE * 64 predecessors below `top` at once (lane L the
+// LB_PER_LANE nearest after those of lanes < L) and stops at the nearest
+// inclusive prefix.  When many tiles finish together, a tile walks back over
+// aggregates until it meets an inclusive prefix, so a wide window keeps that
+// walk short.  Every lane of the calling wave must call it; all lanes return
+// the exclusive prefix of `tile` (saturating at 2^40 - 1).
+constexpr int LB_PER_LANE = 4;
+
 __device__ __forceinline__ uint64_t wave_lookback(const uint64_t* status, uint32_t tile, uint32_t first_tile,
                                                   uint32_t epoch) {
+    constexpr int64_t WIN = (int64_t)LB_PER_LANE * MQ_WAVE;
     uint64_t excl = 0;
     int64_t top = (int64_t)tile - 1;
     while (top >= (int64_t)first_tile) {
-        const int64_t t = top - (int64_t)lane();
-        const bool inr = t >= (int64_t)first_tile;
-        const uint64_t w = inr ? st_load(status + t) : 0ull;
-        const uint32_t flag = (uint32_t)(w >> 40) & 3u;
-        const bool valid = !inr || ((uint32_t)(w >> 42) == epoch && flag != 0);
-        const bool inc = !inr || (valid && flag == ST_INC);
-        const uint64_t incm = __ballot(inc);
-        const uint64_t invm = __ballot(!valid);
+        uint64_t w[LB_PER_LANE];
+        bool inr[LB_PER_LANE];
+#pragma unroll
+        for (int j = 0; j < LB_PER_LANE; j++) {
+            const int64_t t = top - (int64_t)lane() * LB_PER_LANE - j;
+            inr[j] = t >= (int64_t)first_tile;
+            w[j] = inr[j] ? st_load(status + t) : 0ull;
+        }
+        // this lane: the first of its words that is an inclusive prefix (or
+        // out of range), and whether any word before it is unpublished
+        int jinc = LB_PER_LANE;
+        bool pending = false;
+#pragma unroll
+        for (int j = LB_PER_LANE - 1; j >= 0; j--) {
+            const uint32_t flag = (uint32_t)(w[j] >> 40) & 3u;
+            const bool valid = !inr[j] || ((uint32_t)(w[j] >> 42) == epoch && flag != 0);
+            const bool inc = !inr[j] || (valid && flag == ST_INC);
+            if (inc) jinc = j;
+        }
+#pragma unroll
+        for (int j = 0; j < LB_PER_LANE; j++) {
+            const uint32_t flag = (uint32_t)(w[j] >> 40) & 3u;
+            const bool valid = !inr[j] || ((uint32_t)(w[j] >> 42) == epoch && flag != 0);
+            if (j <= jinc && !valid) pending = true;
+        }
+        const uint64_t incm = __ballot(jinc < LB_PER_LANE);
         const uint32_t stop = incm ? (uint32_t)__builtin_ctzll(incm) : 64u;  // lanes 0..stop count
         const uint64_t need = stop >= 63 ? ~0ull : ((2ull << stop) - 1ull);
-        if (invm & need) {
+        if (__ballot(pending) & need) {
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        uint64_t v = (lane() <= stop && inr) ? (w & ST_VAL_MASK) : 0ull;
-        v = wave_sum(v);  // at most 64 * 2^40: no overflow
+        uint64_t v = 0;
+        if (lane() <= stop) {
+#pragma unroll
+            for (int j = 0; j < LB_PER_LANE; j++)
+                if (inr[j] && (lane() < stop || j <= jinc)) v += w[j] & ST_VAL_MASK;
+        }
+        v = wave_sum(v);  // at most 256 * 2^40: no overflow
         excl = sat_add(excl, v > SAT40 ? SAT40 : v);
         if (stop < 64) break;
-        top -= MQ_WAVE;
+        top -= WIN;
     }
     return excl;
 }

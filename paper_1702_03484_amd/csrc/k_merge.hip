@@ -15,7 +15,9 @@
 
 namespace mq {
 
-constexpr int MRG_IPT = 4;
+// one smaller-side record per thread: the searches of a thread cannot
+// overlap, those of different threads do
+constexpr int MRG_IPT = 1;
 
 // first index in [lo, hi) with a[i] >= v (a ascending)
 __device__ __forceinline__ uint32_t lower_bound_i32(const int32_t* __restrict__ a, uint32_t lo, uint32_t hi,
@@ -205,3 +207,4 @@ hipError_t launch_merge_segments(const MergeArgs& a, uint64_t* status, uint32_t*
 }
 
 }  // namespace mq
+

@@ -32,9 +32,12 @@ class MapSQ:
             autotune.install(self, autotune.DEFAULT_TABLE if tuning == _DEFAULT_TUNING else tuning)
 
     def close(self):
+        """Destroy the context and drop the arena and kept tensors."""
         if self.ctx is not None:
             B.mapsq_destroy(self.ctx)
             self.ctx = None
+        self.arena = None
+        self._keep.clear()
 
     def __enter__(self):
         return self
