@@ -228,6 +228,7 @@ __device__ __forceinline__ uint32_t wave_join_of(const BatchJoin* __restrict__ j
 }
 
 __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restrict__ h) {
+    __shared__ uint64_t s_segs[MQ_WAVES][MAT_LDS_SEGS];
     const uint64_t nchunks = h->total_chunks;
     const uint32_t passes = h->passes;
     const int fin = (passes - 1) & 1;
@@ -258,7 +259,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
         }
         const uint64_t j0 = (c - J.chunk_off) * BMAT_WROWS;
         uint32_t hint = 0;  // chunks of a wave may belong to different joins
-        mat_wave_chunk<BATCH_MAXNC, BMAT_RPT>(mj, j0, min(j0 + BMAT_WROWS, J.total), hint);
+        mat_wave_chunk<BATCH_MAXNC, BMAT_RPT>(mj, j0, min(j0 + BMAT_WROWS, J.total), hint,
+                                              s_segs[threadIdx.x / MQ_WAVE]);
     }
 }
 

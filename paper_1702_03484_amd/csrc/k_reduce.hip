@@ -97,6 +97,7 @@ struct MatShape {
 template <int NC, int NLC>
 __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     constexpr uint32_t WROWS = MatShape<NC>::WROWS;
+    __shared__ uint64_t s_segs[MQ_WAVES][MAT_LDS_SEGS];
     MatJoin mj;
     mj.keys = a.keys;
     mj.vals = a.vals;
@@ -132,7 +133,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     uint32_t hint = 0;
     for (uint64_t c = gw; c < nchunks; c += nw) {
         const uint64_t j0 = a.row_begin + c * WROWS;
-        mat_wave_chunk<NC, MatShape<NC>::RPT, NLC>(mj, j0, min(j0 + WROWS, a.row_end), hint);
+        mat_wave_chunk<NC, MatShape<NC>::RPT, NLC>(mj, j0, min(j0 + WROWS, a.row_end), hint,
+                                                   s_segs[threadIdx.x / MQ_WAVE]);
     }
 }
 

@@ -39,14 +39,34 @@ hipError_t launch_gather(const int32_t* src, const uint32_t* idx, int32_t* out, 
     return hipGetLastError();
 }
 
-__global__ void minmax_kernel(const int32_t* __restrict__ a, uint64_t na, const int32_t* __restrict__ b,
-                              uint64_t nb, int32_t* __restrict__ mm) {
+// Min and max of a[0..na) and b[0..nb): 8 independent loads in flight per
+// thread, a block-level reduction, then one atomic pair per block (atomics
+// on one address serialise, so there are few blocks).
+constexpr int MM_UNROLL = 8;
+constexpr uint32_t MM_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void minmax_kernel(const int32_t* __restrict__ a, uint64_t na,
+                                                     const int32_t* __restrict__ b, uint64_t nb,
+                                                     int32_t* __restrict__ mm) {
+    __shared__ int32_t s_lo[256 / MQ_WAVE], s_hi[256 / MQ_WAVE];
     int32_t lo = INT32_MAX, hi = INT32_MIN;
     const uint64_t n = na + nb;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        int32_t v = i < na ? a[i] : b[i - na];
-        lo = min(lo, v);
-        hi = max(hi, v);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i0 < n; i0 += stride * MM_UNROLL) {
+        int32_t v[MM_UNROLL];
+        bool ok[MM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < MM_UNROLL; u++) {
+            const uint64_t i = i0 + (uint64_t)u * stride;
+            ok[u] = i < n;
+            v[u] = i < na ? a[i] : (ok[u] ? b[i - na] : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < MM_UNROLL; u++)
+            if (ok[u]) {
+                lo = min(lo, v[u]);
+                hi = max(hi, v[u]);
+            }
     }
 #pragma unroll
     for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
@@ -54,6 +74,15 @@ __global__ void minmax_kernel(const int32_t* __restrict__ a, uint64_t na, const 
         hi = max(hi, __shfl_xor(hi, o, MQ_WAVE));
     }
     if (mq::lane() == 0) {
+        s_lo[threadIdx.x / MQ_WAVE] = lo;
+        s_hi[threadIdx.x / MQ_WAVE] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / MQ_WAVE; w++) {
+            lo = min(lo, s_lo[w]);
+            hi = max(hi, s_hi[w]);
+        }
         atomicMin(&mm[0], lo);
         atomicMax(&mm[1], hi);
     }
@@ -61,7 +90,8 @@ __global__ void minmax_kernel(const int32_t* __restrict__ a, uint64_t na, const 
 hipError_t launch_minmax(const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int32_t* minmax,
                          hipStream_t stream) {
     if (na + nb == 0) return hipSuccess;
-    minmax_kernel<<<grid_for(na + nb, 256 * 16, 2048), 256, 0, stream>>>(a, na, b, nb, minmax);
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((na + nb + 255) / 256, MM_BLOCKS);
+    minmax_kernel<<<blocks, 256, 0, stream>>>(a, na, b, nb, minmax);
     return hipGetLastError();
 }
 

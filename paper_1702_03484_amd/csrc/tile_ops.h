@@ -416,21 +416,23 @@ __device__ __forceinline__ void row_values(const MatJoin& a, int nl, int nc, uin
 
 // Rows [j, j + nk) of one lane, in order, when they may run into later
 // segments.  s is the segment of row j; later segments are found by binary
-// search in (s, s_last] (empty segments are skipped, never walked).
+// search in (s, s_last] (empty segments are skipped, never walked).  The
+// offsets are read from off[t] = seg_off[off0 + t]: the global array
+// (off0 = 0), or a copy of the sub-chunk's range in LDS.
 template <int NC, int NLC>
-__device__ __forceinline__ void mat_rows_slow(const MatJoin& a, uint32_t s, uint32_t s_last, uint64_t j, int nk,
-                                              int32_t (&v)[NC][4]) {
+__device__ __forceinline__ void mat_rows_slow(const MatJoin& a, const uint64_t* off, uint32_t off0, uint32_t s,
+                                              uint32_t s_last, uint64_t j, int nk, int32_t (&v)[NC][4]) {
     const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
     const int nc = 1 + nl + nr;
     SegPos p;
     seg_open<NC>(a, s, nl, nr, p);
-    seg_locate(p, j - a.seg_off[s]);
+    seg_locate(p, j - off[s - off0]);
     int32_t key = (int32_t)(a.keys[p.st] + (uint32_t)a.key_base);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         if (k < nk) {
             if (p.outer == (p.left_inner ? p.cr : p.cl)) {  // the next non-empty segment holds row j + k
-                s = seg_of(a.seg_off, s + 1, s_last, j + k);
+                s = seg_of(off, s + 1 - off0, s_last - off0, j + k) + off0;
                 seg_open<NC>(a, s, nl, nr, p);
                 p.outer = 0;
                 p.inner = 0;
@@ -479,8 +481,13 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
 // mat_rows_slow per lane.  NC is an upper bound of the column count
 // 1 + nl + nr; NLC >= 0 fixes nl = NLC and nr = NC - 1 - NLC at compile
 // time.  `hint` carries the wave's current segment from chunk to chunk.
+// Offsets of at most this many segments spanned by one 256-row sub-chunk are
+// staged in the wave's slice of LDS before the per-lane searches.
+constexpr uint32_t MAT_LDS_SEGS = 512;
+
 template <int NC, int RPT, int NLC = -1>
-__device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend, uint32_t& hint) {
+__device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend, uint32_t& hint,
+                                               uint64_t* lds) {
     constexpr int Q = RPT / 4;
     const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
     const int nc = 1 + nl + nr;
@@ -597,8 +604,24 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
             // search), then each lane's own segment and rows
             const uint64_t jlast = (jend < jq + 4 * MQ_WAVE ? jend : jq + 4 * MQ_WAVE) - 1;
             const uint32_t s_last = wave_seg_of(a.seg_off, s, a.ns - 1, jlast);
+            // many segments (a sparse stretch of the output): their offsets in
+            // LDS, so that each lane's searches stay on chip
+            const uint32_t m = s_last - s + 1;
+            const uint64_t* off = a.seg_off;
+            uint32_t off0 = 0;
+            if (lds && m > 2 && m <= MAT_LDS_SEGS) {
+                __builtin_amdgcn_wave_barrier();
+                for (uint32_t t = lane(); t < m; t += MQ_WAVE) lds[t] = a.seg_off[s + t];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                off = lds;
+                off0 = s;
+            }
             nk = jl < jend ? (int)min((uint64_t)4, jend - jl) : 0;
-            if (nk > 0) mat_rows_slow<NC, NLC>(a, seg_of(a.seg_off, s, s_last, jl), s_last, jl, nk, v);
+            if (nk > 0)
+                mat_rows_slow<NC, NLC>(a, off, off0, seg_of(off, s - off0, s_last - off0, jl) + off0, s_last, jl,
+                                       nk, v);
         }
         if (nk == 4) {
 #pragma unroll
