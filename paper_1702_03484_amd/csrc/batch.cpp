@@ -178,6 +178,15 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
             goto plain_rest;
         }
         char* sb = ctx->arena.ptr(scratch.off);
+        // value columns in sorted record order (joins with more output rows
+        // than records use them); without room, materialisation gathers
+        uint32_t nsval = 0;
+        for (int i = 0; i < n; i++)
+            if (plan[i].batched && !plan[i].empty)
+                nsval = std::max(nsval, (uint32_t)std::max(J[i].nvl, J[i].nvr));
+        Block svb;
+        if (nsval) svb = alloc_block(ctx, nb4 * nsval);
+        if (!svb.ok()) nsval = 0;
         // the output region: the largest free block that is left
         const size_t cap_bytes = ctx->arena.largest() / ARENA_ALIGN * ARENA_ALIGN;
         Block region;
@@ -203,6 +212,9 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         H.ctr = ctx->small + SMALL_CTR;
         H.status = ctx->status;
         H.out_base = region.ok() ? region.as<int32_t>() : nullptr;
+        H.nsval = nsval;
+        for (uint32_t c = 0; c < nsval; c++)
+            H.sval[c] = reinterpret_cast<int32_t*>(ctx->arena.ptr(svb.off) + c * nb4);
         H.out_cap_words = region.ok() ? cap_bytes / 4 : 0;
         // upload header, descriptors and the tile map through pinned staging
         const size_t up = sizeof(BatchHdr) + sizeof(BatchJoin) * n + tiles * 4;
@@ -260,9 +272,13 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
                 if (!plan[i].batched || plan[i].empty) continue;
                 const double N = double(b.nl) + b.nr;
                 bytes += 16.0 * N * passes + 8.0 * N + 28.0 * b.nseg;
-                if (b.status == 0)
-                    bytes += 4.0 * (1 + b.nvl + b.nvr) * double(b.total) + 4.0 * N + 20.0 * b.nseg +
-                             4.0 * (b.nvl * double(b.nl) + b.nvr * double(b.nr));
+                if (b.status == 0) {
+                    const double cells = b.nvl * double(b.nl) + b.nvr * double(b.nr);
+                    const uint32_t nv = (uint32_t)std::max(b.nvl, b.nvr);
+                    bytes += 4.0 * (1 + b.nvl + b.nvr) * double(b.total) + 4.0 * N + 20.0 * b.nseg + 4.0 * cells;
+                    if (nv && nv <= nsval && double(b.total) >= N)  // the sorted-order copy of the values
+                        bytes += 4.0 * cells + 4.0 * nv * N;
+                }
                 ctx->acc.rows_out += (int64_t)b.total;
                 ctx->acc.joins += 1;
             }

@@ -227,6 +227,39 @@ __device__ __forceinline__ uint32_t wave_join_of(const BatchJoin* __restrict__ j
     return lo;
 }
 
+// A join whose output has at least as many rows as records reads each
+// record's values many times: they move into sorted record order first
+// (one pass over the sorted payloads), and materialisation reads them in
+// place of the record-id gathers.
+__device__ __forceinline__ bool bjoin_uses_sval(const BatchHdr* h, const BatchJoin& J) {
+    const uint32_t nv = (uint32_t)max(J.nvl, J.nvr);
+    return J.status == 0 && nv > 0 && nv <= h->nsval && J.total >= (uint64_t)J.nl + J.nr;
+}
+
+template <int KPT>
+__global__ __launch_bounds__(MQ_BLOCK) void bgather_kernel(const BatchHdr* __restrict__ h) {
+    constexpr uint32_t TILE = MQ_BLOCK * KPT;
+    const int fin = (h->passes - 1) & 1;
+    for (uint32_t t = blockIdx.x; t < h->total_tiles; t += gridDim.x) {
+        const BatchJoin& J = h->joins[h->tile_join[t]];
+        if (!bjoin_uses_sval(h, J)) continue;
+        const uint32_t n = J.nl + J.nr;
+        const uint32_t i0 = (t - J.tile_off) * TILE;
+        const uint32_t i1 = min(i0 + TILE, n);
+        const uint32_t* vals = h->vals[fin] + J.rec_off;
+        for (uint32_t i = i0 + threadIdx.x; i < i1; i += MQ_BLOCK) {
+            const uint32_t r = vals[i];
+            if (r < J.nl) {
+                for (int c = 0; c < J.nvl; c++) h->sval[c][J.rec_off + i] = J.lcol[c][r];
+            } else {
+                for (int c = 0; c < J.nvr; c++) h->sval[c][J.rec_off + i] = J.rcol[c][r - J.nl];
+            }
+        }
+    }
+}
+
+// Materialisation of every join of the batch: chunks strided over the
+// waves, each chunk's join found by a 64-ary search over the joins.
 __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restrict__ h) {
     __shared__ uint64_t s_segs[MQ_WAVES][MAT_LDS_SEGS];
     const uint64_t nchunks = h->total_chunks;
@@ -249,13 +282,17 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
         mj.key_base = J.key_base;
         mj.nl = J.nvl;
         mj.nr = J.nvr;
-        mj.sorted_vals = false;
+        mj.sorted_vals = bjoin_uses_sval(h, J);
         mj.seg_cl = nullptr;
         mj.seg_cr = nullptr;
 #pragma unroll
         for (int col = 0; col < BATCH_MAXNC; col++) {
             mj.out[col] = J.out[col];
-            if (col >= 1) mj.src[col] = col <= J.nvl ? J.lcol[col - 1] : J.rcol[col - 1 - J.nvl];
+            if (col >= 1) {
+                mj.src[col] = col <= J.nvl ? J.lcol[col - 1] : J.rcol[col - 1 - J.nvl];
+                const int sc = col <= J.nvl ? col - 1 : col - 1 - J.nvl;
+                mj.ssrc[col] = mj.sorted_vals && sc < (int)h->nsval ? h->sval[sc] + J.rec_off : nullptr;
+            }
         }
         const uint64_t j0 = (c - J.chunk_off) * BMAT_WROWS;
         uint32_t hint = 0;  // chunks of a wave may belong to different joins
@@ -276,6 +313,7 @@ static hipError_t launch_batch_t(const BatchHdr* hdr, int passes, hipStream_t st
     bheads_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(h);
     bcount_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(h);
     bplace_kernel<<<1, MQ_BLOCK, 0, stream>>>(h);
+    bgather_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
     bmat_kernel<<<BMAT_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
     return hipGetLastError();
 }

@@ -215,6 +215,10 @@ struct BatchHdr {
     uint64_t out_cap_words;
     uint64_t out_used_words;    // result
     uint64_t total_chunks;      // result
+    // value columns in sorted record order (record slots as keys/vals), used
+    // by joins with at least as many output rows as records; nsval = 0: none
+    int32_t* sval[BATCH_MAXNC - 1];
+    uint32_t nsval;
 };
 
 // The whole batch in kernel launches (a graph capture records them).
