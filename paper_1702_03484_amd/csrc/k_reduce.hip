@@ -127,14 +127,16 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     // chunks strided over the waves (the rows being written at any moment
     // stay in one window of the output); a wave's previous segment is the
     // starting guess for its next chunk
-    const uint64_t nchunks = (a.row_end - a.row_begin + WROWS - 1) / WROWS;
+    const int qn = a.sparse ? 1 : MatShape<NC>::RPT / 4;
+    const uint32_t crows = a.sparse ? 4 * MQ_WAVE : WROWS;
+    const uint64_t nchunks = (a.row_end - a.row_begin + crows - 1) / crows;
     const uint64_t gw = (uint64_t)blockIdx.x * MQ_WAVES + threadIdx.x / MQ_WAVE;
     const uint64_t nw = (uint64_t)gridDim.x * MQ_WAVES;
     uint32_t hint = 0;
     for (uint64_t c = gw; c < nchunks; c += nw) {
-        const uint64_t j0 = a.row_begin + c * WROWS;
-        mat_wave_chunk<NC, MatShape<NC>::RPT, NLC>(mj, j0, min(j0 + WROWS, a.row_end), hint,
-                                                   s_segs[threadIdx.x / MQ_WAVE]);
+        const uint64_t j0 = a.row_begin + c * crows;
+        mat_wave_chunk<NC, MatShape<NC>::RPT, NLC>(mj, j0, min(j0 + crows, a.row_end), hint,
+                                                   s_segs[threadIdx.x / MQ_WAVE], qn);
     }
 }
 
@@ -168,7 +170,8 @@ hipError_t launch_materialize(const MatArgs& a, hipStream_t stream) {
     // narrow joins get the value-column split fixed at compile time
 #define MQ_LAUNCH(C, L)                                                                             \
     {                                                                                               \
-        uint64_t chunks = (rows + MatShape<C>::WROWS - 1) / MatShape<C>::WROWS;                     \
+        const uint64_t crows = a.sparse ? 4 * MQ_WAVE : MatShape<C>::WROWS;                         \
+        uint64_t chunks = (rows + crows - 1) / crows;                                               \
         uint32_t blocks = (uint32_t)std::min<uint64_t>((chunks + MQ_WAVES - 1) / MQ_WAVES, 256ull * 32); \
         materialize_kernel<C, L><<<blocks, MQ_BLOCK, 0, stream>>>(a);                               \
     }

@@ -138,6 +138,9 @@ struct MatArgs {
     // rcol; keys is the LEFT key column (key_base 0); vals and sval unused
     const uint32_t* seg_cl;
     const uint32_t* seg_cr;
+    // 1: one 256-row sub-chunk per wave (a sparse output: few rows per
+    // segment, so the per-row searches want many waves); 0: the default
+    int32_t sparse;
 };
 hipError_t launch_materialize(const MatArgs& a, hipStream_t stream);
 

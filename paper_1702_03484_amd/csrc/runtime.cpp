@@ -898,6 +898,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         for (int c = 0; c < nc_mat; c++) a.out[c] = m.col[c];
         a.row_begin = 0;
         a.row_end = total;
+        a.sparse = total < SPARSE_ROWS_PER_SEG * (uint64_t)nseg ? 1 : 0;
         ph = ctx->prof_begin(3);
         hipError_t e = launch_materialize(a, ctx->stream);
         // writes 4 B per output cell and reads the segment table (the value
@@ -1106,6 +1107,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     for (int c = 0; c < nc_mat; c++) a.out[c] = m.col[c];
     a.row_begin = 0;
     a.row_end = total;
+    a.sparse = total < SPARSE_ROWS_PER_SEG * (uint64_t)nseg ? 1 : 0;
     // values in sorted record order when output rows outnumber records
     // (each record's values are then read many times)
     const int nv = std::max(a.nl, a.nr);

@@ -158,6 +158,9 @@ constexpr uint64_t SEMI_RATIO = 4;
 // the key range needs at most PRECOUNT_MAX_RANGE counters
 constexpr uint64_t PRECOUNT_MIN_RECORDS = uint64_t(1) << 24;
 constexpr uint64_t PRECOUNT_MAX_RANGE = uint64_t(1) << 28;
+// materialisation with one 256-row sub-chunk per wave when the output has
+// fewer rows than this per segment on average (per-row segment searches)
+constexpr uint64_t SPARSE_ROWS_PER_SEG = 64;
 
 constexpr size_t SMALL_HIST = 0;                  // up to 8 passes x 2048 buckets
 constexpr size_t SMALL_HIST_WORDS = 8 * 2048;

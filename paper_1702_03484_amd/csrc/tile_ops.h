@@ -414,9 +414,10 @@ __device__ __forceinline__ void row_values(const MatJoin& a, int nl, int nc, uin
     }
 }
 
-// Rows [j, j + nk) of one lane, in order, when they may run into later
-// segments.  s is the segment of row j; later segments are found by binary
-// search in (s, s_last] (empty segments are skipped, never walked).  The
+// Rows [j, j + nk) of one lane when they may lie in different segments (a
+// sparse stretch of the output).  s is the segment of row j; each row's
+// segment is found by its own binary search in [s, s_last] (empty segments
+// are skipped, never walked), so the rows' searches and loads overlap.  The
 // offsets are read from off[t] = seg_off[off0 + t]: the global array
 // (off0 = 0), or a copy of the sub-chunk's range in LDS.
 template <int NC, int NLC>
@@ -424,23 +425,18 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, const uint64_t* 
                                               uint32_t s_last, uint64_t j, int nk, int32_t (&v)[NC][4]) {
     const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
     const int nc = 1 + nl + nr;
-    SegPos p;
-    seg_open<NC>(a, s, nl, nr, p);
-    seg_locate(p, j - off[s - off0]);
-    int32_t key = (int32_t)(a.keys[p.st] + (uint32_t)a.key_base);
+    uint32_t sk[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) sk[k] = k == 0 || k >= nk ? s : seg_of(off, s - off0, s_last - off0, j + k) + off0;
+    SegPos p[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) seg_open<NC>(a, sk[k], nl, nr, p[k]);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         if (k < nk) {
-            if (p.outer == (p.left_inner ? p.cr : p.cl)) {  // the next non-empty segment holds row j + k
-                s = seg_of(off, s + 1 - off0, s_last - off0, j + k) + off0;
-                seg_open<NC>(a, s, nl, nr, p);
-                p.outer = 0;
-                p.inner = 0;
-                key = (int32_t)(a.keys[p.st] + (uint32_t)a.key_base);
-            }
-            v[0][k] = key;
-            row_values<NC>(a, nl, nc, seg_lpos(p), seg_rpos(p), v, k);
-            seg_step(p);
+            seg_locate(p[k], j + k - off[sk[k] - off0]);
+            v[0][k] = (int32_t)(a.keys[p[k].st] + (uint32_t)a.key_base);
+            row_values<NC>(a, nl, nc, seg_lpos(p[k]), seg_rpos(p[k]), v, k);
         }
     }
 }
@@ -487,8 +483,8 @@ constexpr uint32_t MAT_LDS_SEGS = 512;
 
 template <int NC, int RPT, int NLC = -1>
 __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, uint64_t jend, uint32_t& hint,
-                                               uint64_t* lds) {
-    constexpr int Q = RPT / 4;
+                                               uint64_t* lds, int qn = RPT / 4) {
+    constexpr int Q = RPT / 4;  // sub-chunks of 256 rows per chunk; qn <= Q of them are used
     const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
     const int nc = 1 + nl + nr;
     uint32_t s = uni(seg_from_hint(a, uni(hint), j0));
@@ -498,7 +494,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
         const uint32_t st = uni(p.st), sp = uni(p.sp), cl = uni(p.cl), cr = uni(p.cr);
         const uint64_t off = uni64(a.seg_off[s]);
         const uint64_t send = off + (uint64_t)cl * cr;
-        if (j0 + (uint64_t)Q * (4 * MQ_WAVE) <= (send < jend ? send : jend)) {
+        if (j0 + (uint64_t)qn * (4 * MQ_WAVE) <= (send < jend ? send : jend)) {
             // the whole chunk lies in segment s: one uniform divide, then
             // every lane's rows of all sub-chunks, all loads before any store
             const bool left_in = left_inner_of(cl, cr, nl, nr);
@@ -516,6 +512,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
             int32_t v[Q][NC][4];
 #pragma unroll
             for (int q = 0; q < Q; q++) {
+                if (q >= qn) break;
                 // this lane's first row of sub-chunk q: offset t past (o0, i0)
                 const uint32_t t = i0 + (uint32_t)q * (4 * MQ_WAVE) + 4u * lane();  // < ci + 64 * RPT
                 uint32_t dq, inner;
@@ -539,6 +536,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
             }
 #pragma unroll
             for (int q = 0; q < Q; q++) {
+                if (q >= qn) break;
                 const uint64_t jl = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
 #pragma unroll
                 for (int col = 0; col < NC; col++)
@@ -552,7 +550,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
     }
     // the chunk crosses segment boundaries: sub-chunk by sub-chunk
 #pragma unroll 1
-    for (int q = 0; q < Q; q++) {
+    for (int q = 0; q < qn; q++) {
         const uint64_t jq = j0 + (uint64_t)q * (4 * MQ_WAVE);
         if (jq >= jend) break;
         s = uni(seg_from_hint(a, s, jq));
