@@ -82,6 +82,62 @@ def cpu_baseline(w):
                       f"{rs.n} rows in {el:.2f} s (numpy, single thread)"}, rs.n
 
 
+def phase_table(prof):
+    """Per-phase average launch time, algorithmic bytes and GB/s (fraction of peak)."""
+    from paper_1702_03484_amd import binding as B
+
+    out = {}
+    for k, name in enumerate(B.PHASES):
+        if name in ("index", "batch"):
+            continue
+        n = prof.launches[k]
+        if n == 0:
+            continue
+        ms = prof.ms[k] / n
+        by = prof.bytes[k] / n
+        gbs = by / (ms * 1e-3) / 1e9 if ms > 0 else None
+        out[name] = {"avg_ms": round(ms, 4), "bytes_per_launch": int(by),
+                     "gbs": round(gbs, 1) if gbs else None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None}
+    return out
+
+
+def run_shuffle(n=16_000_000, key_bits=24, reps=5):
+    """The shuffle path on its own: a join of two n-row tables with uniform
+    random keys over 2^key_bits values and one value column each, with the
+    merge join and the semi-join reduction turned off, so every record goes
+    through the histogram, radix passes, segment heads and counts."""
+    import numpy as np
+    import torch
+
+    from paper_1702_03484_amd import binding as B
+    from paper_1702_03484_amd.engine import MapSQ
+
+    r = np.random.default_rng(11)
+    with MapSQ(arena_bytes=32 << 30) as sess:
+        cols = [torch.from_numpy(r.integers(0, 1 << key_bits, n).astype(np.int32)).cuda() for _ in range(2)]
+        vals = [torch.from_numpy(r.integers(0, 1 << 31, n).astype(np.int32)).cuda() for _ in range(2)]
+        L = sess.table([0, 1], [cols[0], vals[0]], key_max=(1 << key_bits) - 1)
+        R = sess.table([0, 2], [cols[1], vals[1]], key_max=(1 << key_bits) - 1)
+        sess.set_join_options(semijoin=1, merge=1)
+        for _ in range(2):
+            sess.free(sess.join(L, R, 0))
+        torch.cuda.synchronize()
+        B.mapsq_profile_enable(sess.ctx, True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            t = sess.join(L, R, 0)
+            rows = int(t.nrows)
+            sess.free(t)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        st = sess.stats()
+        phases = phase_table(B.mapsq_profile_read(sess.ctx))
+    return {"workload": f"join of two {n}-row tables, uniform keys over 2^{key_bits}, one value column each, "
+                       "merge join and semi-join off", "records": 2 * n, "rows": rows, "radix_bits": st.radix_bits,
+            "passes": st.passes, "ms_per_join": round(el * 1e3, 3), "phases": phases}
+
+
 def run_cfg4(seed=1, n_sub=512, reps=2):
     """Batched form vs plain one-join-per-call form on the 512-subquery
     batch workload; exactness: every batched result equals the plain result
@@ -283,7 +339,7 @@ def main():
 
     from paper_1702_03484_amd import binding as B
     from paper_1702_03484_amd.engine import MapSQ
-    from synth import store_cfg2
+    from synth import store_cfg2, var
 
     full = args.n == 50_000_000
     log(f"[bench] generating the workload ({args.n} triples)")
@@ -323,17 +379,19 @@ def main():
     prof = B.mapsq_profile_read(sess.ctx)
     log(f"[bench] timed {args.steps} steps in {el:.4f} s")
 
-    phases = {}
-    for k, name in enumerate(B.PHASES):
-        if name in ("index", "batch"):
-            continue
-        n = prof.launches[k]
-        if n == 0:
-            continue
-        ms = prof.ms[k] / n
-        by = prof.bytes[k] / n
-        phases[name] = {"avg_ms": round(ms, 4), "bytes_per_launch": int(by),
-                        "gbs": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
+    phases = phase_table(prof)
+    # Map of a pattern with only a constant object over the whole store: a
+    # scan of the raw columns with ballot compaction (the paper's Map)
+    c = w.patterns[1][2]
+    B.mapsq_profile_enable(sess.ctx, False)
+    B.mapsq_profile_enable(sess.ctx, True)
+    for _ in range(5):
+        t = sess.map((var(0), var(1), c))
+        sess.free(t)
+    torch.cuda.synchronize()
+    mp = phase_table(B.mapsq_profile_read(sess.ctx)).get("map")
+    if mp:
+        mp["pattern"] = "?s ?p c over the 50M-triple store (variable predicate: full scan + compaction)"
     mat = phases["materialize"]
     achieved = mat["gbs"]
     traffic = traffic_from_profile()
@@ -363,6 +421,7 @@ def main():
         finally:
             torch.cuda.empty_cache()
 
+    shuffle = guarded(run_shuffle, "shuffle measurement")
     batched = None if args.no_batched else guarded(run_cfg4, "batched measurement")
     served = None if args.no_serving else guarded(run_cfg5, "serving measurement")
     out = {
@@ -386,6 +445,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phases,
+        "map": mp,
+        "shuffle": shuffle,
         "batched": batched,
         "serving": served,
     }

@@ -43,7 +43,7 @@ hipError_t launch_gather(const int32_t* src, const uint32_t* idx, int32_t* out, 
 // thread, a block-level reduction, then one atomic pair per block (atomics
 // on one address serialise, so there are few blocks).
 constexpr int MM_UNROLL = 8;
-constexpr uint32_t MM_BLOCKS = 256;
+constexpr uint32_t MM_BLOCKS = 1024;
 
 __global__ __launch_bounds__(256) void minmax_kernel(const int32_t* __restrict__ a, uint64_t na,
                                                      const int32_t* __restrict__ b, uint64_t nb,
