@@ -1,9 +1,14 @@
 // Map of Algorithm 1 on gfx950: scan a range of the store (or any SoA
 // table), keep the rows that pass the pattern's equality tests, and emit
-// the variable columns.  Single pass: each wave takes one __ballot per row
-// slot, the block scans the wave totals, and the tile's output offset comes
-// from a decoupled look-back, so kept rows stay in input order.
-// The same kernel filters join results on further shared variables.
+// the variable columns in input order.  Two passes with no ordering between
+// blocks (no tile counter, no look-back).  In the test pass block b owns a
+// contiguous run of tiles; it reads only the columns the tests use and
+// stores one __ballot word per 64 rows, the kept rows of its run before
+// each tile, and its run's total.  The write pass takes one tile per block
+// (so clustered output spreads over the whole grid): its offset is the sum
+// of the run totals before its run plus its in-run offset, and it copies
+// the output columns of the rows its mask words mark.
+// The same kernels filter join results on further shared variables.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -11,72 +16,180 @@
 
 namespace mq {
 
-constexpr int CMP_IPT = 16;
+constexpr int CMP_IPT = 16;                                // row slots per thread per tile
+constexpr uint64_t CMP_TILE = (uint64_t)MQ_BLOCK * CMP_IPT;  // rows per tile
+constexpr uint64_t CMP_TILE_WORDS = CMP_TILE / 64;          // mask words per tile
+constexpr uint64_t CMP_MAX_BLOCKS = 1024;                   // 4 blocks per CU: one resident wave of blocks
 
-__global__ __launch_bounds__(MQ_BLOCK) void compact_kernel(CompactArgs a, uint64_t* __restrict__ status,
-                                                           uint32_t* __restrict__ tile_ctr, uint32_t epoch) {
-    constexpr uint64_t TILE = MQ_BLOCK * CMP_IPT;
-    __shared__ uint32_t s_tile;
+struct CompactGrid {
+    uint64_t ntiles, chunk, blocks;
+};
+
+__host__ __device__ inline CompactGrid compact_grid(uint64_t n) {
+    CompactGrid g;
+    g.ntiles = (n + CMP_TILE - 1) / CMP_TILE;
+    const uint64_t want = g.ntiles < CMP_MAX_BLOCKS ? g.ntiles : CMP_MAX_BLOCKS;
+    g.chunk = want ? (g.ntiles + want - 1) / want : 0;
+    g.blocks = g.chunk ? (g.ntiles + g.chunk - 1) / g.chunk : 0;
+    return g;
+}
+
+// the kept count of the calling wave's 64-row slot i sits in lane i of `mine`
+__device__ __forceinline__ uint64_t pick_slot(const uint64_t (&km)[CMP_IPT]) {
+    uint64_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < CMP_IPT; i++) mine = lane() == (uint32_t)i ? km[i] : mine;
+    return mine;
+}
+
+__global__ __launch_bounds__(MQ_BLOCK) void compact_test_kernel(CompactArgs a, uint64_t* __restrict__ counts,
+                                                                uint32_t* __restrict__ tloc,
+                                                                uint64_t* __restrict__ mask, CompactGrid g) {
     __shared__ uint32_t s_wtot[MQ_WAVES];
-    __shared__ uint64_t s_excl;
-    const uint64_t ntiles = (a.n + TILE - 1) / TILE;
     const uint32_t w = threadIdx.x / MQ_WAVE;
-    const uint64_t lt = lanemask_lt();
-    for (;;) {
-        const uint32_t tile = next_tile(tile_ctr, &s_tile);
-        if (tile >= ntiles) break;
-        const uint64_t base = (uint64_t)tile * TILE;
+    const uint64_t t0 = (uint64_t)blockIdx.x * g.chunk;
+    const uint64_t t1 = t0 + g.chunk < g.ntiles ? t0 + g.chunk : g.ntiles;
+    __shared__ uint32_t s_run;  // kept rows of the run's tiles so far
+    if (threadIdx.x == 0) s_run = 0;
+    for (uint64_t tile = t0; tile < t1; tile++) {
+        const uint64_t base = tile * CMP_TILE;
+        // the first test's operands of every row slot are loaded before any
+        // compare, so each wave keeps CMP_IPT loads in flight; further tests
+        // (a repeated variable next to a constant) load per slot
+        bool ok[CMP_IPT];
+        {
+            const int32_t* A = a.nterm > 0 ? a.in[a.term_a[0]] : nullptr;
+            const int32_t* B = a.nterm > 0 && a.term_b[0] >= 0 ? a.in[a.term_b[0]] : nullptr;
+            const int32_t c0 = a.nterm > 0 ? a.term_c[0] : 0;
+            int32_t va[CMP_IPT], vb[CMP_IPT];
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++) {
+                const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
+                ok[i] = idx < a.n;
+                va[i] = A && ok[i] ? A[idx] : 0;
+                vb[i] = B && ok[i] ? B[idx] : c0;
+            }
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++) ok[i] = ok[i] && (!A || va[i] == vb[i]);
+        }
+        for (int t = 1; t < a.nterm; t++) {
+            const int32_t* A = a.in[a.term_a[t]];
+            const int32_t* B = a.term_b[t] >= 0 ? a.in[a.term_b[t]] : nullptr;
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++) {
+                const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
+                if (ok[i]) ok[i] = A[idx] == (B ? B[idx] : a.term_c[t]);
+            }
+        }
         uint64_t km[CMP_IPT];
         uint32_t run = 0;
 #pragma unroll
         for (int i = 0; i < CMP_IPT; i++) {
-            uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
-            bool ok = idx < a.n;
-            if (ok) {
-                for (int t = 0; t < a.nterm; t++) {
-                    int32_t va = a.in[a.term_a[t]][idx];
-                    int32_t vb = a.term_b[t] >= 0 ? a.in[a.term_b[t]][idx] : a.term_c[t];
-                    ok = ok && va == vb;
-                }
-            }
-            km[i] = __ballot(ok);
+            km[i] = __ballot(ok[i]);
             run += (uint32_t)__popcll(km[i]);
         }
+        // slot i of wave w covers rows base + (w * CMP_IPT + i) * 64 + [0, 64)
+        const uint64_t mine = pick_slot(km);
+        if (lane() < (uint32_t)CMP_IPT) mask[tile * CMP_TILE_WORDS + w * CMP_IPT + lane()] = mine;
         if (lane() == 0) s_wtot[w] = run;
         __syncthreads();
-        uint32_t wex = 0, ttot = 0;
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
 #pragma unroll
-        for (int i = 0; i < MQ_WAVES; i++) {
-            if ((uint32_t)i < w) wex += s_wtot[i];
-            ttot += s_wtot[i];
+            for (int i = 0; i < MQ_WAVES; i++) tot += s_wtot[i];
+            tloc[tile] = s_run;
+            s_run += tot;
         }
-        if (w == 0) {
-            const uint64_t ex = tile_prefix_wave0(status, tile, epoch, ttot);
-            if (lane() == 0) {
-                s_excl = ex;
-                if (tile == ntiles - 1) *a.count = ex + ttot;
-            }
-        }
-        __syncthreads();
-        uint64_t pos = s_excl + wex;
+        __syncthreads();  // s_wtot is rewritten by the next tile
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = s_run;
+}
+
+__global__ __launch_bounds__(MQ_BLOCK) void compact_write_kernel(CompactArgs a, const uint64_t* __restrict__ counts,
+                                                                 const uint32_t* __restrict__ tloc,
+                                                                 const uint64_t* __restrict__ mask, CompactGrid g) {
+    __shared__ uint64_t s_red[MQ_WAVES];
+    __shared__ uint32_t s_wtot[MQ_WAVES];
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint64_t lt = lanemask_lt();
+    const uint64_t tile = blockIdx.x;
+    const uint64_t run_of = tile / g.chunk;  // the test-pass block that owned this tile
+    const uint64_t base = tile * CMP_TILE;
+    const uint64_t mine = lane() < (uint32_t)CMP_IPT ? mask[tile * CMP_TILE_WORDS + w * CMP_IPT + lane()] : 0ull;
+    // rows kept before this tile: the runs before its run, then its in-run offset
+    uint64_t before = 0;
+    for (uint64_t b = threadIdx.x; b < run_of; b += MQ_BLOCK) before += counts[b];
+    uint32_t run = (uint32_t)__popcll(mine);
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
+        before += __shfl_xor(before, o);
+        run += __shfl_xor(run, o);
+    }
+    if (lane() == 0) {
+        s_red[w] = before;
+        s_wtot[w] = run;
+    }
+    __syncthreads();
+    uint64_t pos0 = tloc[tile];
+    uint32_t wex = 0, ttot = 0;
+#pragma unroll
+    for (int i = 0; i < MQ_WAVES; i++) {
+        pos0 += s_red[i];
+        if ((uint32_t)i < w) wex += s_wtot[i];
+        ttot += s_wtot[i];
+    }
+    if (tile == g.ntiles - 1 && threadIdx.x == 0) *a.count = pos0 + ttot;
+    const uint64_t pos = pos0 + wex;
+    if (run == 0) return;
+    {
+        // slot masks as wave-uniform values, and each lane's output row per slot
+        uint64_t km[CMP_IPT];
+        uint32_t rel[CMP_IPT];
+        uint32_t acc = 0;
 #pragma unroll
         for (int i = 0; i < CMP_IPT; i++) {
-            if ((km[i] >> lane()) & 1ull) {
-                uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
-                uint64_t at = pos + (uint64_t)__popcll(km[i] & lt);
-                for (int c = 0; c < a.nout; c++) a.out[c][at] = a.in[a.out_src[c]][idx];
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, i);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine >> 32), i);
+            km[i] = (uint64_t)hi << 32 | lo;
+            rel[i] = acc + (uint32_t)__popcll(km[i] & lt);
+            acc += (uint32_t)__popcll(km[i]);
+        }
+        // per column, every slot's gather is issued before any store, so a
+        // sparse tile waits for one load latency per column, not one per slot
+        for (int c = 0; c < a.nout; c++) {
+            const int32_t* __restrict__ src = a.in[a.out_src[c]];
+            int32_t* __restrict__ dst = a.out[c];
+            int32_t v[CMP_IPT];
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++) {
+                const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
+                v[i] = (km[i] >> lane()) & 1ull ? src[idx] : 0;
             }
-            pos += (uint64_t)__popcll(km[i]);
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++)
+                if ((km[i] >> lane()) & 1ull) dst[pos + rel[i]] = v[i];
         }
     }
 }
 
-hipError_t launch_compact(const CompactArgs& a, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch,
-                          hipStream_t stream) {
+size_t compact_scratch_words(uint64_t n) {
+    const CompactGrid g = compact_grid(n);
+    return (size_t)(g.blocks + (g.ntiles + 1) / 2 + g.ntiles * CMP_TILE_WORDS);
+}
+
+hipError_t launch_compact(const CompactArgs& a, uint64_t* scratch, hipStream_t stream) {
     if (a.n == 0) return hipSuccess;
-    uint64_t tiles = (a.n + MQ_BLOCK * CMP_IPT - 1) / (MQ_BLOCK * CMP_IPT);
-    uint32_t blocks = (uint32_t)std::min<uint64_t>(tiles, 256ull * 8);
-    compact_kernel<<<blocks, MQ_BLOCK, 0, stream>>>(a, status, tile_ctr, epoch);
+    const CompactGrid g = compact_grid(a.n);
+    if (g.ntiles * MQ_BLOCK > 0xffffffffull) return hipErrorInvalidValue;  // grid size in work-items is 32-bit
+    // scratch: run totals (u64 per test block), in-run tile offsets (u32 per
+    // tile), then the mask words of whole tiles
+    uint64_t* counts = scratch;
+    uint32_t* tloc = reinterpret_cast<uint32_t*>(scratch + g.blocks);
+    uint64_t* mask = scratch + g.blocks + (g.ntiles + 1) / 2;
+    compact_test_kernel<<<(uint32_t)g.blocks, MQ_BLOCK, 0, stream>>>(a, counts, tloc, mask, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    compact_write_kernel<<<(uint32_t)g.ntiles, MQ_BLOCK, 0, stream>>>(a, counts, tloc, mask, g);
     return hipGetLastError();
 }
 

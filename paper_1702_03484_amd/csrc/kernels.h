@@ -161,8 +161,10 @@ struct CompactArgs {
     int32_t* out[16];
     uint64_t* count;           // device: rows kept
 };
-hipError_t launch_compact(const CompactArgs& a, uint64_t* status, uint32_t* tile_ctr, uint32_t epoch,
-                          hipStream_t stream);
+// u64 words of device scratch launch_compact needs for n rows (block
+// counts, then one mask word per 64 rows of whole tiles)
+size_t compact_scratch_words(uint64_t n);
+hipError_t launch_compact(const CompactArgs& a, uint64_t* scratch, hipStream_t stream);
 
 // Range location in sorted columns: for query q, lo/hi start as the given
 // range; level 1 narrows it to rows whose col1 value equals v1, level 2

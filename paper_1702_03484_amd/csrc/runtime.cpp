@@ -175,7 +175,7 @@ static inline uint32_t* counter(Ctx* ctx, int i) { return ctx->small + SMALL_CTR
 // scalar slots (u32 word index inside the scalar area)
 enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12, SC_PRECOUNT = 14 };
 // counter slots
-enum { CT_PASS0 = 0, CT_HEADS = 8, CT_COUNT = 9, CT_COMPACT = 10, CT_SEMI = 11 };
+enum { CT_PASS0 = 0, CT_HEADS = 8, CT_COUNT = 9, CT_SEMI = 11 };
 
 static mapsq_status readback(Ctx* ctx, const void* dev, size_t bytes, void* host) {
     HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
@@ -421,13 +421,13 @@ mapsq_status load_triples(Ctx* ctx, const int32_t* s, const int32_t* p, const in
         c.out[1] = np_.as<int32_t>();
         c.out[2] = no.as<int32_t>();
         c.count = scalar64(ctx, SC_COUNT);
-        if (!ctx->ensure_status(size_t(n / 4096 + 2))) {
+        Block cs = alloc_block(ctx, compact_scratch_words((uint64_t)n) * 8);
+        if (!cs.ok()) {
             free_store(ctx);
-            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
+            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for de-duplication");
         }
-        LHIP(launch_fill_u32(counter(ctx, CT_COMPACT), 1, 0u, ctx->stream));
         LHIP(launch_fill_u32(scalar32(ctx, SC_COUNT), 2, 0u, ctx->stream));
-        LHIP(launch_compact(c, ctx->status, counter(ctx, CT_COMPACT), ctx->next_epoch(), ctx->stream));
+        LHIP(launch_compact(c, cs.as<uint64_t>(), ctx->stream));
         uint64_t kept = 0;
         LCHK(readback(ctx, scalar64(ctx, SC_COUNT), 8, &kept));
         LHIP(hipMemcpyAsync(S.s, ns.as<int32_t>(), kept * 4, hipMemcpyDeviceToDevice, ctx->stream));
@@ -659,18 +659,24 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
         a.out[c] = t.col[c];
     }
     a.count = scalar64(ctx, SC_COUNT);
-    if (!ctx->ensure_status(size_t(rows / 4096 + 2))) {
+    Block cs = alloc_block(ctx, compact_scratch_words((uint64_t)rows) * 8);
+    if (!cs.ok()) {
         free_table(ctx, &t);
-        return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for status words");
+        return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the map's row masks");
     }
     int ph = ctx->prof_begin(0);
-    hipError_t e = launch_fill_u32(ctx->small + SMALL_CTR, 32, 0u, ctx->stream);
-    if (e == hipSuccess) e = launch_fill_u32(scalar32(ctx, SC_COUNT), 2, 0u, ctx->stream);
-    if (e == hipSuccess) e = launch_compact(a, ctx->status, counter(ctx, CT_COMPACT), ctx->next_epoch(), ctx->stream);
+    hipError_t e = launch_fill_u32(scalar32(ctx, SC_COUNT), 2, 0u, ctx->stream);
+    if (e == hipSuccess) e = launch_compact(a, cs.as<uint64_t>(), ctx->stream);
     {
-        int ncol_read = 0;
-        for (int pos = 0; pos < 3; pos++) ncol_read += a.in[pos] ? 1 : 0;
-        ctx->prof_end(ph, 4.0 * ncol_read * (double)rows);
+        // every row reads the columns its equality tests use; kept rows also
+        // read and write their output columns (added after the count)
+        bool used[3] = {false, false, false};
+        for (int i = 0; i < nterm; i++) {
+            used[ta[i]] = true;
+            if (tb[i] >= 0) used[tb[i]] = true;
+        }
+        const int ncol_test = (int)used[0] + (int)used[1] + (int)used[2];
+        ctx->prof_end(ph, 4.0 * ncol_test * (double)rows);
     }
     if (e != hipSuccess) {
         free_table(ctx, &t);
@@ -682,7 +688,7 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
         free_table(ctx, &t);
         return st;
     }
-    if (ph >= 0) ctx->pending[ph].bytes += 4.0 * ncols * (double)kept;
+    if (ph >= 0) ctx->pending[ph].bytes += 8.0 * ncols * (double)kept;
     // columns were laid out for `rows`; keep the layout, only the row count changes
     out->owned = 1;
     out->block = t.block;
@@ -803,13 +809,14 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         c.count = scalar64(ctx, SC_COUNT);
         uint64_t kept = 0;
         e = hipSuccess;
-        if (!ctx->ensure_status(size_t(total / 4096 + 2))) e = hipErrorOutOfMemory;
+        Block cs = alloc_block(ctx, compact_scratch_words((uint64_t)total) * 8);
+        if (!cs.ok()) e = hipErrorOutOfMemory;
         ph = ctx->prof_begin(4);
-        if (e == hipSuccess) e = launch_fill_u32(counter(ctx, CT_COMPACT), 1, 0u, ctx->stream);
-        if (e == hipSuccess) e = launch_compact(c, ctx->status, counter(ctx, CT_COMPACT), ctx->next_epoch(), ctx->stream);
+        if (e == hipSuccess) e = launch_fill_u32(scalar32(ctx, SC_COUNT), 2, 0u, ctx->stream);
+        if (e == hipSuccess) e = launch_compact(c, cs.as<uint64_t>(), ctx->stream);
         ctx->prof_end(ph, 4.0 * (double)c.nterm * 2 * total);
         if (e == hipSuccess) st = readback(ctx, scalar64(ctx, SC_COUNT), 8, &kept);
-        if (ph >= 0) ctx->pending[ph].bytes += 4.0 * (double)c.nout * (double)kept;
+        if (ph >= 0) ctx->pending[ph].bytes += 8.0 * (double)c.nout * (double)kept;
         free_table(ctx, &m);
         if (e != hipSuccess || st) {
             free_table(ctx, &f);

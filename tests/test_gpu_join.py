@@ -409,6 +409,23 @@ def test_map_matches_oracle(sess):
                 sess.free(got)
 
 
+def test_map_large_scans(sess):
+    """Scans longer than one tile per block (the map's blocks then own runs of
+    several tiles) with a ragged tail: dense, sparse, two-test and empty
+    selections must each give exactly the oracle's bag."""
+    w = _store_with_repeats(23, 9_000_037, 200_000, 5)
+    sess.load(w.s, w.p, w.o)
+    hot = int(np.bincount(w.o).argmax())
+    for pat in [(var(0), var(1), hot), (var(0), var(1), var(0)), (var(0), var(0), var(1)),
+                (var(0), var(1), int(w.p[0])), (var(0), var(0), 10**9)]:
+        announce(f"map over 9M triples {pat}")
+        exp = oracle.match_pattern(w.s, w.p, w.o, pat)
+        got = sess.map(pat)
+        assert int(got.nrows) == exp.n
+        assert_same_bag(host_table(sess, got), exp)
+        sess.free(got)
+
+
 def test_map_dedup_load(sess):
     announce("load with MAPSQ_LOAD_DEDUP")
     w = random_store(31, 50_000, 50, 3)
