@@ -256,7 +256,7 @@ mapsq_status mapsq_last_join_stats(mapsq_ctx* ctx, mapsq_join_stats* out);
 mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_per_thread);
 
 /* How mapsq_join / mapsq_query group records by key; every choice gives
- * the same rows in the same order.
+ * the same rows in the same order (or the same error).
  * semijoin: a record whose key the other side lacks meets no partner in
  *   Reduce (Algorithm 1), so it can be left out of the shuffle.  0 =
  *   automatic (the larger side has at least 2^16 records and 4 times the
@@ -264,8 +264,14 @@ mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_p
  *   key column), 1 = never, 2 = whenever the bitmap fits in 1 GiB.
  * merge: 0 = pair the key runs directly when both tables are sorted on the
  *   key (sorted_col), 1 = always shuffle.
+ * precount: before a shuffle of at least 2^24 records, count |RS| exactly
+ *   from dense per-key counts (two passes over the keys), so that a join
+ *   with no key in common, or whose result cannot fit in the arena, ends
+ *   without sorting.  0 = automatic (only for the join steps that
+ *   mapsq_serve_step runs through the single-join path), 1 = never,
+ *   2 = always.  Without it the same outcome comes after the sort.
  * INVALID_ARG for other values. */
-mapsq_status mapsq_set_join_options(mapsq_ctx* ctx, int32_t semijoin, int32_t merge);
+mapsq_status mapsq_set_join_options(mapsq_ctx* ctx, int32_t semijoin, int32_t merge, int32_t precount);
 
 /* Per-phase device time and algorithmic bytes, accumulated while profiling
  * is on.  Phases: 0 map (range location and scan/compaction), 1 sort

@@ -135,7 +135,7 @@ _SIGS = [
     ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
     ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
     ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
-    ("mapsq_set_join_options", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
+    ("mapsq_set_join_options", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_profile_enable", ctypes.c_int32, [_P, ctypes.c_int32]),
     ("mapsq_profile_read", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_profile)]),
     ("mapsq_tune_record", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -271,10 +271,12 @@ def mapsq_last_join_stats(ctx) -> mapsq_join_stats:
     return out
 
 
-def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0):
+def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0, precount: int = 0):
     """semijoin: 0 automatic, 1 never, 2 always; merge: 0 when both sides are
-    sorted on the key, 1 never (every choice gives the same rows in the same order)."""
-    _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge))
+    sorted on the key, 1 never; precount (exact |RS| before shuffles of 2^24+
+    records): 0 serving steps only, 1 never, 2 always.  Every choice gives the
+    same rows in the same order."""
+    _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge, precount))
 
 
 def mapsq_set_tuning(ctx, radix_bits: int = 0, keys_per_thread: int = 0):

@@ -1,12 +1,18 @@
 // ReduceDuplicate of Algorithm 1 on gfx950: after the shuffle, records with
 // equal keys are contiguous, LEFT records (payload < n_left) ahead of RIGHT
-// records within each key.  Three kernels:
-//   seg_heads    compacts the first position of every distinct key,
-//   seg_count    finds each key's LEFT/RIGHT split, counts cL*cR pairs and
-//                scans the counts into exact output offsets,
-//   materialize  writes the per-key cross products, LEFT-major, with the
-//                output rows split evenly over the grid (a key with a huge
-//                product is spread over many blocks).
+// records within each key.  Three phases:
+//   heads        compacts the first position of every distinct key and its
+//                LEFT/RIGHT split,
+//   count        counts cL*cR pairs per key and scans the counts into exact
+//                output offsets,
+//   materialize  writes the per-key cross products, with the output rows
+//                split evenly over the grid (a key with a huge product is
+//                spread over many blocks).
+// Heads and count each run as two kernels with no ordering between blocks
+// (no tile counter, no look-back): a sum pass in which block b owns a
+// contiguous run of tiles and stores each tile's offset within the run and
+// the run's total, then a write pass with one tile per block whose offset is
+// the totals of the runs before its run plus its in-run offset.
 #include "device_common.h"
 #include "kernels.h"
 #include "tile_ops.h"
@@ -16,72 +22,285 @@
 namespace mq {
 
 constexpr int HEADS_IPT = 16;
+constexpr uint32_t HEADS_TILE = MQ_BLOCK * HEADS_IPT;
 constexpr int COUNT_IPT = 8;
-constexpr uint32_t PERSIST_BLOCKS = 256 * 8;
+constexpr uint32_t COUNT_TILE = MQ_BLOCK * COUNT_IPT;
+constexpr uint32_t RUN_BLOCKS = 1024;  // blocks of a sum pass
 
-__global__ __launch_bounds__(MQ_BLOCK) void seg_heads_kernel(const uint32_t* __restrict__ keys,
-                                                             const uint32_t* __restrict__ vals, uint32_t n,
-                                                             uint32_t n_left, uint32_t* __restrict__ seg_start,
-                                                             uint32_t* __restrict__ seg_split,
-                                                             uint32_t* __restrict__ nseg,
-                                                             uint64_t* __restrict__ status,
-                                                             uint32_t* __restrict__ tile_ctr, uint32_t epoch) {
-    constexpr uint32_t TILE = MQ_BLOCK * HEADS_IPT;
-    __shared__ HeadsSmem sm;
-    __shared__ uint32_t s_tile;
-    const uint32_t ntiles = (n + TILE - 1) / TILE;
-    for (;;) {
-        const uint32_t tile = next_tile(tile_ctr, &s_tile);
-        if (tile >= ntiles) break;
-        heads_tile<HEADS_IPT>(sm, keys, vals, n, n_left, tile * TILE, tile, 0, tile == ntiles - 1, seg_start,
-                              seg_split, nseg, status, epoch);
+struct RunGrid {
+    uint32_t ntiles, chunk, blocks;
+};
+
+__host__ __device__ inline RunGrid run_grid(uint32_t ntiles) {
+    RunGrid g;
+    g.ntiles = ntiles;
+    const uint32_t want = ntiles < RUN_BLOCKS ? ntiles : RUN_BLOCKS;
+    g.chunk = want ? (ntiles + want - 1) / want : 0;
+    g.blocks = g.chunk ? (ntiles + g.chunk - 1) / g.chunk : 0;
+    return g;
+}
+
+// Key and payload of record idx and of its neighbours, for every lane of a
+// wave that covers 64 consecutive records (lanes past n see key ~0u).
+struct RecView {
+    uint32_t k, v, kprev, vprev, knext;
+};
+
+__device__ __forceinline__ RecView rec_view(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                            uint32_t n, uint32_t idx) {
+    RecView r;
+    const bool in = idx < n;
+    r.k = in ? keys[idx] : ~0u;
+    r.v = in ? vals[idx] : 0u;
+    // neighbours from the adjacent lanes; the wave's edge lanes load them
+    r.kprev = __shfl_up(r.k, 1, MQ_WAVE);
+    r.vprev = __shfl_up(r.v, 1, MQ_WAVE);
+    r.knext = __shfl_down(r.k, 1, MQ_WAVE);
+    if (lane() == 0 && in && idx > 0) {
+        r.kprev = keys[idx - 1];
+        r.vprev = vals[idx - 1];
     }
+    if (lane() == MQ_WAVE - 1 && idx + 1 < n) r.knext = keys[idx + 1];
+    return r;
+}
+
+__device__ __forceinline__ bool rec_is_head(const RecView& r, uint32_t idx, uint32_t n) {
+    return idx < n && (idx == 0 || r.kprev != r.k);
+}
+
+// sum pass: heads of every tile of the block's run
+__global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __restrict__ keys, uint32_t n,
+                                                             uint32_t* __restrict__ run_tot,
+                                                             uint32_t* __restrict__ tloc, RunGrid g) {
+    __shared__ uint32_t s_wtot[MQ_WAVES];
+    __shared__ uint32_t s_run;
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    if (threadIdx.x == 0) s_run = 0;
+    const uint32_t t0 = blockIdx.x * g.chunk;
+    const uint32_t t1 = min(t0 + g.chunk, g.ntiles);
+    for (uint32_t tile = t0; tile < t1; tile++) {
+        const uint32_t base = tile * HEADS_TILE;
+        uint32_t k[HEADS_IPT];
+#pragma unroll
+        for (int i = 0; i < HEADS_IPT; i++) {
+            const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
+            k[i] = idx < n ? keys[idx] : 0u;
+        }
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < HEADS_IPT; i++) {
+            const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
+            uint32_t kp = __shfl_up(k[i], 1, MQ_WAVE);
+            if (lane() == 0 && idx > 0 && idx < n) kp = keys[idx - 1];
+            run += (uint32_t)__popcll(__ballot(idx < n && (idx == 0 || kp != k[i])));
+        }
+        if (lane() == 0) s_wtot[w] = run;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int i = 0; i < MQ_WAVES; i++) tot += s_wtot[i];
+            tloc[tile] = s_run;
+            s_run += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) run_tot[blockIdx.x] = s_run;
+}
+
+// write pass: one tile per block
+__global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* __restrict__ keys,
+                                                               const uint32_t* __restrict__ vals, uint32_t n,
+                                                               uint32_t n_left, const uint32_t* __restrict__ run_tot,
+                                                               const uint32_t* __restrict__ tloc, RunGrid g,
+                                                               uint32_t* __restrict__ seg_start,
+                                                               uint32_t* __restrict__ seg_split,
+                                                               uint32_t* __restrict__ nseg) {
+    __shared__ uint32_t s_red[MQ_WAVES];
+    __shared__ uint32_t s_wtot[MQ_WAVES];
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint64_t lt = lanemask_lt();
+    const uint32_t tile = blockIdx.x;
+    const uint32_t base = tile * HEADS_TILE;
+    RecView r[HEADS_IPT];
+#pragma unroll
+    for (int i = 0; i < HEADS_IPT; i++) r[i] = rec_view(keys, vals, n, base + (w * HEADS_IPT + i) * MQ_WAVE + lane());
+    uint32_t before = 0;
+    for (uint32_t b = threadIdx.x; b < tile / g.chunk; b += MQ_BLOCK) before += run_tot[b];
+    uint64_t hm[HEADS_IPT];
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < HEADS_IPT; i++) {
+        hm[i] = __ballot(rec_is_head(r[i], base + (w * HEADS_IPT + i) * MQ_WAVE + lane(), n));
+        run += (uint32_t)__popcll(hm[i]);
+    }
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) before += __shfl_xor(before, o);
+    if (lane() == 0) {
+        s_red[w] = before;
+        s_wtot[w] = run;
+    }
+    __syncthreads();
+    uint32_t pos = tloc[tile], ttot = 0;
+#pragma unroll
+    for (int i = 0; i < MQ_WAVES; i++) {
+        pos += s_red[i] + ((uint32_t)i < w ? s_wtot[i] : 0u);
+        ttot += s_wtot[i];
+    }
+    if (tile == g.ntiles - 1 && threadIdx.x == 0) *nseg = pos + ttot;  // thread 0: pos is the tile's first head
+#pragma unroll
+    for (int i = 0; i < HEADS_IPT; i++) {
+        const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
+        const bool h = (hm[i] >> lane()) & 1ull;
+        const uint32_t bef = pos + (uint32_t)__popcll(hm[i] & lt);  // heads before this record
+        if (idx < n) {
+            const bool is_r = r[i].v >= n_left;
+            const bool last = idx + 1 == n || r[i].knext != r[i].k;
+            const bool first_r = is_r && (h || r[i].vprev < n_left);
+            if (h) seg_start[bef] = idx;
+            if (first_r || (last && !is_r)) {
+                const uint32_t sid = h ? bef : bef - 1u;  // record 0 is always a head
+                seg_split[sid] = first_r ? idx : idx + 1;
+            }
+        }
+        pos += (uint32_t)__popcll(hm[i]);
+    }
+}
+
+size_t seg_scratch_bytes(uint32_t n) {
+    const RunGrid gh = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
+    const RunGrid gc = run_grid(std::max(1u, (n + COUNT_TILE - 1) / COUNT_TILE));
+    return 4ull * (gh.blocks + gh.ntiles) + 8ull * (gc.blocks + gc.ntiles) + 8;
 }
 
 hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
-                            uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, uint64_t* status,
-                            uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream) {
+                            uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, void* scratch,
+                            hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    uint32_t tiles = (n + MQ_BLOCK * HEADS_IPT - 1) / (MQ_BLOCK * HEADS_IPT);
-    uint32_t blocks = std::min(tiles, PERSIST_BLOCKS);
-    seg_heads_kernel<<<blocks, MQ_BLOCK, 0, stream>>>(keys, vals, n, n_left, seg_start, seg_split, nseg, status,
-                                                      tile_ctr, epoch);
+    const RunGrid g = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
+    uint32_t* run_tot = static_cast<uint32_t*>(scratch);
+    uint32_t* tloc = run_tot + g.blocks;
+    heads_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, n, run_tot, tloc, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    heads_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, vals, n, n_left, run_tot, tloc, g, seg_start,
+                                                         seg_split, nseg);
     return hipGetLastError();
 }
 
-// cnt[s] = (split - start) * (end - split), scanned into exact output
-// offsets (saturating at 2^40 - 1); *total = the sum.
-__global__ __launch_bounds__(MQ_BLOCK) void seg_count_kernel(uint32_t n, const uint32_t* __restrict__ seg_start,
+__device__ __forceinline__ uint64_t block_reduce_sum(uint64_t v, uint64_t* tmp) {
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane() == 0) tmp[threadIdx.x / MQ_WAVE] = v;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < MQ_WAVES; i++) t += tmp[i];
+    __syncthreads();
+    return t;
+}
+
+// pairs of segment s: (split - start) * (end - split), capped at 2^40 - 1
+__device__ __forceinline__ uint64_t seg_pairs(const uint32_t* __restrict__ seg_start,
+                                              const uint32_t* __restrict__ seg_split, uint32_t n, uint32_t ns,
+                                              uint32_t s) {
+    if (s >= ns) return 0;
+    const uint32_t st = seg_start[s];
+    const uint32_t en = s + 1 < ns ? seg_start[s + 1] : n;
+    const uint32_t sp = seg_split[s];
+    const uint64_t c = (uint64_t)(sp - st) * (uint64_t)(en - sp);
+    return c > SAT40 ? SAT40 : c;
+}
+
+// The segment count lives on the device; both count kernels are sized for
+// max_seg segments and treat tiles past the real count as empty.
+__global__ __launch_bounds__(MQ_BLOCK) void count_sum_kernel(uint32_t n, const uint32_t* __restrict__ seg_start,
                                                              const uint32_t* __restrict__ nseg_p,
                                                              const uint32_t* __restrict__ seg_split,
-                                                             uint64_t* __restrict__ seg_off,
-                                                             uint64_t* __restrict__ total,
-                                                             uint64_t* __restrict__ status,
-                                                             uint32_t* __restrict__ tile_ctr, uint32_t epoch) {
-    constexpr uint32_t TILE = MQ_BLOCK * COUNT_IPT;
-    __shared__ CountSmem sm;
-    __shared__ uint32_t s_tile;
+                                                             uint64_t* __restrict__ run_tot,
+                                                             uint64_t* __restrict__ tloc, RunGrid g) {
+    __shared__ uint64_t s_tmp[MQ_WAVES];
+    __shared__ uint64_t s_run;
     const uint32_t ns = n == 0 ? 0u : *nseg_p;
-    const uint32_t ntiles = (ns + TILE - 1) / TILE;
+    if (threadIdx.x == 0) s_run = 0;
+    const uint32_t t0 = blockIdx.x * g.chunk;
+    const uint32_t t1 = min(t0 + g.chunk, g.ntiles);
+    for (uint32_t tile = t0; tile < t1; tile++) {
+        const uint32_t first = tile * COUNT_TILE + threadIdx.x * COUNT_IPT;
+        uint64_t sum = 0;
+        if (first < ns) {
+#pragma unroll
+            for (int i = 0; i < COUNT_IPT; i++) sum += seg_pairs(seg_start, seg_split, n, ns, first + i);
+        }
+        const uint64_t tot = block_reduce_sum(sum, s_tmp);
+        if (threadIdx.x == 0) {
+            tloc[tile] = s_run;
+            s_run = sat_add(s_run, tot > SAT40 ? SAT40 : tot);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) run_tot[blockIdx.x] = s_run;
+}
+
+__global__ __launch_bounds__(MQ_BLOCK) void count_write_kernel(uint32_t n, const uint32_t* __restrict__ seg_start,
+                                                               const uint32_t* __restrict__ nseg_p,
+                                                               const uint32_t* __restrict__ seg_split,
+                                                               const uint64_t* __restrict__ run_tot,
+                                                               const uint64_t* __restrict__ tloc, RunGrid g,
+                                                               uint64_t* __restrict__ seg_off,
+                                                               uint64_t* __restrict__ total) {
+    __shared__ uint64_t s_tmp[MQ_WAVES];
+    __shared__ uint64_t s_red[MQ_WAVES];
+    const uint32_t ns = n == 0 ? 0u : *nseg_p;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t ntiles = (ns + COUNT_TILE - 1) / COUNT_TILE;
     if (ns == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *total = 0;
+        if (tile == 0 && threadIdx.x == 0) *total = 0;
         return;
     }
-    for (;;) {
-        const uint32_t tile = next_tile(tile_ctr, &s_tile);
-        if (tile >= ntiles) break;
-        count_tile<COUNT_IPT>(sm, n, ns, tile * TILE, tile, 0, tile == ntiles - 1, seg_start, seg_split, seg_off,
-                              total, status, epoch);
+    if (tile >= ntiles) return;
+    const uint32_t first = tile * COUNT_TILE + threadIdx.x * COUNT_IPT;
+    uint64_t cnt[COUNT_IPT];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < COUNT_IPT; i++) {
+        cnt[i] = seg_pairs(seg_start, seg_split, n, ns, first + i);
+        sum += cnt[i];
+    }
+    // totals of the runs before this tile's run (saturating)
+    uint64_t before = 0;
+    for (uint32_t b = threadIdx.x; b < tile / g.chunk; b += MQ_BLOCK) before = sat_add(before, run_tot[b]);
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) before = sat_add(before, (uint64_t)__shfl_xor(before, o));
+    if (lane() == 0) s_red[threadIdx.x / MQ_WAVE] = before;
+    uint64_t ttot;
+    const uint64_t ex_in = block_excl_scan<uint64_t>(sum, s_tmp, &ttot);  // syncs after s_red is written
+    uint64_t off = tloc[tile];
+#pragma unroll
+    for (int i = 0; i < MQ_WAVES; i++) off = sat_add(off, s_red[i]);
+    if (tile == ntiles - 1 && threadIdx.x == 0) *total = sat_add(off, ttot > SAT40 ? SAT40 : ttot);
+    off = sat_add(off, ex_in > SAT40 ? SAT40 : ex_in);
+#pragma unroll
+    for (int i = 0; i < COUNT_IPT; i++) {
+        if (first + i < ns) seg_off[first + i] = off;
+        off = sat_add(off, cnt[i]);
     }
 }
 
 hipError_t launch_seg_count(uint32_t n, const uint32_t* seg_start, const uint32_t* nseg, uint32_t max_seg,
-                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, uint64_t* status,
-                            uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream) {
-    uint32_t tiles = (max_seg + MQ_BLOCK * COUNT_IPT - 1) / (MQ_BLOCK * COUNT_IPT);
-    uint32_t blocks = std::max(1u, std::min(tiles, PERSIST_BLOCKS));
-    seg_count_kernel<<<blocks, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, seg_off, total, status,
-                                                      tile_ctr, epoch);
+                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, void* scratch,
+                            hipStream_t stream) {
+    const RunGrid gh = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
+    const RunGrid g = run_grid(std::max(1u, (max_seg + COUNT_TILE - 1) / COUNT_TILE));
+    // after the heads pass's words, 8-byte aligned
+    uint64_t* run_tot = reinterpret_cast<uint64_t*>(
+        (reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(scratch) + gh.blocks + gh.ntiles) + 7) & ~uintptr_t(7));
+    uint64_t* tloc = run_tot + g.blocks;
+    count_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, run_tot, tloc, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    count_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, run_tot, tloc, g, seg_off,
+                                                         total);
     return hipGetLastError();
 }
 

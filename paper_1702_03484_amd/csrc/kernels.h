@@ -93,15 +93,18 @@ uint32_t radix_tiles(uint32_t n, int kpt);
 // Segment heads of the sorted records: seg_start[s] = first position of the
 // s-th distinct key, seg_split[s] = position of its first RIGHT record
 // (payload >= n_left), or its end when it has none; *nseg = segments.
+// scratch: seg_scratch_bytes(n) bytes of device memory shared by the two
+// launches below (run totals and per-tile offsets; no clearing needed).
 hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
-                            uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, uint64_t* status,
-                            uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
+                            uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, void* scratch,
+                            hipStream_t stream);
 // count[s] = (split - start) * (end - split); seg_off = exclusive scan of the
 // counts (saturating at 2^40-1); *total = the full sum.  max_seg bounds the
-// device count *nseg (sizes the persistent grid).
+// device count *nseg (sizes the grids).
 hipError_t launch_seg_count(uint32_t n, const uint32_t* seg_start, const uint32_t* nseg, uint32_t max_seg,
-                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, uint64_t* status,
-                            uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
+                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, void* scratch,
+                            hipStream_t stream);
+size_t seg_scratch_bytes(uint32_t n);
 
 // Value columns in sorted record order: for every record i, with
 // r = vals[i], out[c][i] = lcol[c][r] (a LEFT record, r < n_left, c < nl) or

@@ -175,7 +175,7 @@ static inline uint32_t* counter(Ctx* ctx, int i) { return ctx->small + SMALL_CTR
 // scalar slots (u32 word index inside the scalar area)
 enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12, SC_PRECOUNT = 14 };
 // counter slots
-enum { CT_PASS0 = 0, CT_HEADS = 8, CT_COUNT = 9, CT_SEMI = 11 };
+enum { CT_PASS0 = 0, CT_COUNT = 9, CT_SEMI = 11 };
 
 static mapsq_status readback(Ctx* ctx, const void* dev, size_t bytes, void* host) {
     HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
@@ -939,11 +939,14 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     int rb, kpt;
     pick_tuning(ctx, key_bits, rb, kpt, (uint64_t)nL + nR);
 
-    // A large shuffle first gets the exact |RS| from two passes over the keys
-    // (dense key counts of the smaller side, summed over the larger side's
+    // A large shuffle may first get the exact |RS| from two passes over the
+    // keys (dense key counts of one side, summed over the other side's
     // records): a join with no key in common, or whose output cannot fit in
-    // the arena's free space at all, ends here without sorting anything.
-    if ((uint64_t)N >= PRECOUNT_MIN_RECORDS) {
+    // the arena's free space at all, then ends without sorting anything.
+    // It costs about as much as the count phase after the sort, so by
+    // default only the server's steps (which may fail and retry) use it.
+    const bool precount = ctx->precount == 2 || (ctx->precount == 0 && ctx->serving_step);
+    if (precount && (uint64_t)N >= PRECOUNT_MIN_RECORDS) {
         const uint64_t range = (uint64_t)((int64_t)kmax - (int64_t)kmin) + 1;
         Block cnt;
         if (range <= PRECOUNT_MAX_RANGE) cnt = alloc_block(ctx, size_t(range) * 4);
@@ -1057,12 +1060,13 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     uint32_t* seg_start = b.k[1 - res];
     uint32_t* seg_split = b.v[1 - res];
     // ReduceDuplicate: segments, counts, offsets
-    if (!ctx->ensure_status(size_t(Ns) / 2048 + 2)) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: status words");
+    Block ss = alloc_block(ctx, seg_scratch_bytes(Ns));
+    if (!ss.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the segment scans");
     ph = ctx->prof_begin(2);
-    HIPCHK(launch_seg_heads(skeys, svals, Ns, nL, seg_start, seg_split, scalar32(ctx, SC_NSEG), ctx->status,
-                            counter(ctx, CT_HEADS), ctx->next_epoch(), ctx->stream));
+    HIPCHK(launch_seg_heads(skeys, svals, Ns, nL, seg_start, seg_split, scalar32(ctx, SC_NSEG), ss.as<void>(),
+                            ctx->stream));
     HIPCHK(launch_seg_count(Ns, seg_start, scalar32(ctx, SC_NSEG), Ns, seg_split, seg_off, scalar64(ctx, SC_TOTAL),
-                            ctx->status, counter(ctx, CT_COUNT), ctx->next_epoch(), ctx->stream));
+                            ss.as<void>(), ctx->stream));
     uint32_t sc[4];
     {
         // bytes are filled in once the segment count is known (below)

@@ -85,9 +85,10 @@ class MapSQ:
 
     # ---- tables <-> tensors -------------------------------------------------
 
-    def set_join_options(self, semijoin: int = 0, merge: int = 0):
-        """semijoin 0 automatic / 1 never / 2 always; merge 0 automatic / 1 never."""
-        B.mapsq_set_join_options(self.ctx, semijoin, merge)
+    def set_join_options(self, semijoin: int = 0, merge: int = 0, precount: int = 0):
+        """semijoin 0 automatic / 1 never / 2 always; merge 0 automatic / 1 never;
+        precount 0 serving steps / 1 never / 2 always."""
+        B.mapsq_set_join_options(self.ctx, semijoin, merge, precount)
     def table(self, vars, tensors, key_max: int = -1, sorted_col: int = 0) -> B.mapsq_table:
         """Wrap caller-owned int32 device tensors (kept alive by this session);
         sorted_col = 1 + a column the caller guarantees to be ascending."""

@@ -309,7 +309,7 @@ def test_large_join_counts_exactly_before_sorting(sess):
     vr = r.integers(0, 1 << 31, size=n_small).astype(np.int32)
     L = sess.table([0, 1], [dev(kl), dev(vl)])
     R = sess.table([0, 2], [dev(kr), dev(vr)])
-    sess.set_join_options(semijoin=1, merge=1)
+    sess.set_join_options(semijoin=1, merge=1, precount=2)
     try:
         out = sess.join(L, R, 0)
         exp_rows = int(np.bincount(kl, minlength=1 << 20).astype(np.int64) @ np.bincount(kr, minlength=1 << 20))
@@ -332,6 +332,16 @@ def test_large_join_counts_exactly_before_sorting(sess):
         free0 = B.mapsq_arena_free_bytes(sess.ctx)[0]
         L3 = sess.table([0, 1], [dev(np.zeros(n_big, np.int32)), dev(vl)])
         R3 = sess.table([0, 2], [dev(np.zeros(3000, np.int32)), dev(vr[:3000])])
+        with pytest.raises(B.MapSQError) as ei:
+            sess.join(L3, R3, 0)
+        assert ei.value.code == B.MAPSQ_ERR_TOO_LARGE
+        assert sess.stats().out_rows == n_big * 3000
+        assert B.mapsq_arena_free_bytes(sess.ctx)[0] == free0
+        # without the count first: the same outcomes, found after the sort
+        sess.set_join_options(semijoin=1, merge=1, precount=1)
+        out = sess.join(L, R2, 0)
+        assert out.nrows == 0 and sess.stats().out_rows == 0 and sess.stats().sorted_records == n_big + n_small
+        sess.free(out)
         with pytest.raises(B.MapSQError) as ei:
             sess.join(L3, R3, 0)
         assert ei.value.code == B.MAPSQ_ERR_TOO_LARGE
