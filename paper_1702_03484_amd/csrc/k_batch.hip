@@ -280,6 +280,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
         mj.n = J.nl + J.nr;
         mj.n_left = J.nl;
         mj.key_base = J.key_base;
+        mj.key_shift = 0;
         mj.nl = J.nvl;
         mj.nr = J.nvr;
         mj.sorted_vals = bjoin_uses_sval(h, J);

@@ -64,13 +64,14 @@ __device__ __forceinline__ RecView rec_view(const uint32_t* __restrict__ keys, c
     return r;
 }
 
-__device__ __forceinline__ bool rec_is_head(const RecView& r, uint32_t idx, uint32_t n) {
-    return idx < n && (idx == 0 || r.kprev != r.k);
+// fs = 1 when the key's low bit is the side (segments group keys >> 1)
+__device__ __forceinline__ bool rec_is_head(const RecView& r, uint32_t idx, uint32_t n, uint32_t fs) {
+    return idx < n && (idx == 0 || (r.kprev >> fs) != (r.k >> fs));
 }
 
 // sum pass: heads of every tile of the block's run
 __global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __restrict__ keys, uint32_t n,
-                                                             uint32_t* __restrict__ run_tot,
+                                                             uint32_t fs, uint32_t* __restrict__ run_tot,
                                                              uint32_t* __restrict__ tloc, RunGrid g) {
     __shared__ uint32_t s_wtot[MQ_WAVES];
     __shared__ uint32_t s_run;
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __r
             const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
             uint32_t kp = __shfl_up(k[i], 1, MQ_WAVE);
             if (lane() == 0 && idx > 0 && idx < n) kp = keys[idx - 1];
-            run += (uint32_t)__popcll(__ballot(idx < n && (idx == 0 || kp != k[i])));
+            run += (uint32_t)__popcll(__ballot(idx < n && (idx == 0 || (kp >> fs) != (k[i] >> fs))));
         }
         if (lane() == 0) s_wtot[w] = run;
         __syncthreads();
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __r
 // write pass: one tile per block
 __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* __restrict__ keys,
                                                                const uint32_t* __restrict__ vals, uint32_t n,
-                                                               uint32_t n_left, const uint32_t* __restrict__ run_tot,
+                                                               uint32_t n_left, uint32_t fs,
+                                                               const uint32_t* __restrict__ run_tot,
                                                                const uint32_t* __restrict__ tloc, RunGrid g,
                                                                uint32_t* __restrict__ seg_start,
                                                                uint32_t* __restrict__ seg_split,
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
     uint32_t run = 0;
 #pragma unroll
     for (int i = 0; i < HEADS_IPT; i++) {
-        hm[i] = __ballot(rec_is_head(r[i], base + (w * HEADS_IPT + i) * MQ_WAVE + lane(), n));
+        hm[i] = __ballot(rec_is_head(r[i], base + (w * HEADS_IPT + i) * MQ_WAVE + lane(), n, fs));
         run += (uint32_t)__popcll(hm[i]);
     }
 #pragma unroll
@@ -154,9 +156,10 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
         const bool h = (hm[i] >> lane()) & 1ull;
         const uint32_t bef = pos + (uint32_t)__popcll(hm[i] & lt);  // heads before this record
         if (idx < n) {
-            const bool is_r = r[i].v >= n_left;
-            const bool last = idx + 1 == n || r[i].knext != r[i].k;
-            const bool first_r = is_r && (h || r[i].vprev < n_left);
+            const bool is_r = fs ? (r[i].k & 1u) != 0 : r[i].v >= n_left;
+            const bool prev_r = fs ? (r[i].kprev & 1u) != 0 : r[i].vprev >= n_left;
+            const bool last = idx + 1 == n || (r[i].knext >> fs) != (r[i].k >> fs);
+            const bool first_r = is_r && (h || !prev_r);
             if (h) seg_start[bef] = idx;
             if (first_r || (last && !is_r)) {
                 const uint32_t sid = h ? bef : bef - 1u;  // record 0 is always a head
@@ -174,16 +177,17 @@ size_t seg_scratch_bytes(uint32_t n) {
 }
 
 hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
-                            uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, void* scratch,
+                            int side_bit, uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, void* scratch,
                             hipStream_t stream) {
+    const uint32_t fs = side_bit ? 1u : 0u;
     if (n == 0) return hipSuccess;
     const RunGrid g = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
     uint32_t* run_tot = static_cast<uint32_t*>(scratch);
     uint32_t* tloc = run_tot + g.blocks;
-    heads_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, n, run_tot, tloc, g);
+    heads_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, n, fs, run_tot, tloc, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    heads_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, vals, n, n_left, run_tot, tloc, g, seg_start,
+    heads_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, vals, n, n_left, fs, run_tot, tloc, g, seg_start,
                                                          seg_split, nseg);
     return hipGetLastError();
 }
@@ -327,6 +331,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     mj.n = a.n;
     mj.n_left = a.n_left;
     mj.key_base = a.key_base;
+    mj.key_shift = a.key_shift;
     mj.nl = NLC >= 0 ? NLC : a.nl;
     mj.nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
     const bool merged = a.seg_cl != nullptr;

@@ -10,8 +10,10 @@
 //
 // First-pass ("gen") mode reads the keys of two input segments (the LEFT
 // then the RIGHT partial-match table of a join), subtracts a base and
-// generates the payload as the record's position in that concatenation, so
-// the intermediate records are never written out before the first scatter.
+// generates the payload as the record's position in that concatenation, or
+// reads it from the record's one value column (the side then rides in the
+// key's low bit), so the intermediate records are never written out before
+// the first scatter.
 #include "device_common.h"
 #include "kernels.h"
 #include "tile_ops.h"
@@ -21,8 +23,17 @@
 namespace mq {
 
 __device__ __forceinline__ uint32_t src_key(const SortSrc& s, uint32_t idx) {
-    int32_t k = idx < s.n0 ? s.k0[idx] : s.k1[idx - s.n0];
-    return (uint32_t)k - (uint32_t)s.base;
+    const bool right = idx >= s.n0;
+    const int32_t k = right ? s.k1[idx - s.n0] : s.k0[idx];
+    const uint32_t rel = (uint32_t)k - (uint32_t)s.base;
+    return s.carry ? rel << 1 | (right ? 1u : 0u) : rel;
+}
+
+__device__ __forceinline__ uint32_t src_payload(const SortSrc& s, uint32_t idx) {
+    if (!s.carry) return idx;
+    const bool right = idx >= s.n0;
+    const int32_t* v = right ? s.v1 : s.v0;
+    return v ? (uint32_t)v[right ? idx - s.n0 : idx] : 0u;
 }
 
 // Digit histograms of every pass in two launches: each block counts its
@@ -137,7 +148,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
         const bool ok = off < valid_n;
         if (GEN) {
             key[i] = ok ? src_key(src, idx) : 0u;
-            val[i] = idx;
+            val[i] = ok ? src_payload(src, idx) : 0u;
         } else {
             key[i] = ok ? kin[idx] : 0u;
             val[i] = ok ? vin[idx] : 0u;

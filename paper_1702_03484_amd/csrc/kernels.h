@@ -13,12 +13,21 @@ constexpr uint32_t BLOCK_THREADS = 256;  // threads per block of every tiled ker
 // Keys of a first pass come from two int32 segments (k0[0..n0) then
 // k1[0..n1)), minus `base`; the payload is the position in that
 // concatenation.
+// First-pass source of a join's shuffle: the LEFT key column k0 (n0 rows)
+// then the RIGHT one k1 (n1 rows), keys relative to base.  carry = 0: the
+// payload is the record's position in that concatenation (RIGHT records
+// from n0 on).  carry = 1: the payload is the record's value cell (v0 or v1,
+// 0 when null) and the key is (relative key << 1) | side, so LEFT records
+// still sort ahead of RIGHT ones within a key.
 struct SortSrc {
     const int32_t* k0;
     uint32_t n0;
     const int32_t* k1;
     uint32_t n1;
     int32_t base;
+    const int32_t* v0;
+    const int32_t* v1;
+    int32_t carry;
 };
 
 // Merge join of two tables already sorted on the key (k_merge.hip).  One
@@ -95,8 +104,10 @@ uint32_t radix_tiles(uint32_t n, int kpt);
 // (payload >= n_left), or its end when it has none; *nseg = segments.
 // scratch: seg_scratch_bytes(n) bytes of device memory shared by the two
 // launches below (run totals and per-tile offsets; no clearing needed).
+// side_bit: the side is the key's low bit (a carried shuffle) instead of
+// payload >= n_left; segments then group keys >> 1.
 hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
-                            uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, void* scratch,
+                            int side_bit, uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, void* scratch,
                             hipStream_t stream);
 // count[s] = (split - start) * (end - split); seg_off = exclusive scan of the
 // counts (saturating at 2^40-1); *total = the full sum.  max_seg bounds the
@@ -144,6 +155,8 @@ struct MatArgs {
     // 1: one 256-row sub-chunk per wave (a sparse output: few rows per
     // segment, so the per-row searches want many waves); 0: the default
     int32_t sparse;
+    // 1: keys carry the side in their low bit (output key = (key >> 1) + base)
+    int32_t key_shift;
 };
 hipError_t launch_materialize(const MatArgs& a, hipStream_t stream);
 

@@ -1046,15 +1046,28 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     js.sorted_records = Ns;
 
     // Map + Sort: the first pass reads the LEFT then the RIGHT key column
-    // (or the records the semi-join kept)
-    SortSrc src{lkey, nL, rkey, nR, kmin};
+    // (or the records the semi-join kept).  When each side has at most one
+    // value column the records carry that value instead of their position
+    // (the side moves into the key's low bit), so Reduce reads the values
+    // in sorted order instead of gathering them through the positions.
+    const bool carry = js.path != MAPSQ_PATH_SEMIJOIN && lv.size() <= 1 && rv.size() <= 1 && key_bits <= 31;
+    const int sort_bits = carry ? key_bits + 1 : key_bits;
+    if (carry) pick_tuning(ctx, sort_bits, rb, kpt, (uint64_t)Ns);
+    SortSrc src{lkey, nL, rkey, nR, kmin, nullptr, nullptr, carry ? 1 : 0};
+    if (carry) {
+        src.v0 = lv.empty() ? nullptr : L->col[lv[0]];
+        src.v1 = rv.empty() ? nullptr : R->col[rv[0]];
+    }
     int res, passes;
     ph = ctx->prof_begin(1);
-    if ((st = radix_sort(ctx, js.path == MAPSQ_PATH_SEMIJOIN ? nullptr : &src, Ns, key_bits, rb, kpt, b, &res, &passes)))
+    if ((st = radix_sort(ctx, js.path == MAPSQ_PATH_SEMIJOIN ? nullptr : &src, Ns, sort_bits, rb, kpt, b, &res,
+                         &passes)))
         return st;
     // histogram reads 4N; the first pass reads 4N keys (8N records after a
-    // semi-join), later passes 8N; every pass writes 8N
-    ctx->prof_end(ph, 16.0 * Ns * passes + (js.path == MAPSQ_PATH_SEMIJOIN ? 4.0 * Ns : 0.0));
+    // semi-join, plus the carried value cells), later passes 8N; every pass
+    // writes 8N
+    ctx->prof_end(ph, 16.0 * Ns * passes + (js.path == MAPSQ_PATH_SEMIJOIN ? 4.0 * Ns : 0.0) +
+                          (carry ? 4.0 * (lv.size() * (double)nL + rv.size() * (double)nR) : 0.0));
     const uint32_t* skeys = b.k[res];
     const uint32_t* svals = b.v[res];
     uint32_t* seg_start = b.k[1 - res];
@@ -1063,8 +1076,8 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     Block ss = alloc_block(ctx, seg_scratch_bytes(Ns));
     if (!ss.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the segment scans");
     ph = ctx->prof_begin(2);
-    HIPCHK(launch_seg_heads(skeys, svals, Ns, nL, seg_start, seg_split, scalar32(ctx, SC_NSEG), ss.as<void>(),
-                            ctx->stream));
+    HIPCHK(launch_seg_heads(skeys, svals, Ns, nL, carry ? 1 : 0, seg_start, seg_split, scalar32(ctx, SC_NSEG),
+                            ss.as<void>(), ctx->stream));
     HIPCHK(launch_seg_count(Ns, seg_start, scalar32(ctx, SC_NSEG), Ns, seg_split, seg_off, scalar64(ctx, SC_TOTAL),
                             ss.as<void>(), ctx->stream));
     uint32_t sc[4];
@@ -1111,6 +1124,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     a.n = Ns;
     a.n_left = nL;
     a.key_base = kmin;
+    a.key_shift = carry ? 1 : 0;
     a.nl = (int)lv.size();
     a.nr = (int)rv.size();
     for (int i = 0; i < a.nl; i++) a.lcol[i] = L->col[lv[i]];
@@ -1124,7 +1138,13 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     const int nv = std::max(a.nl, a.nr);
     const double value_cells = a.nl * (double)nLs + a.nr * (double)nRs;
     Block sval;
-    if (nv > 0 && total >= Ns) sval = alloc_block(ctx, size_t(nv) * nb4);
+    if (carry) {
+        // both sides' value cells are the sorted payloads themselves
+        a.sval[0] = reinterpret_cast<const int32_t*>(svals);
+        a.use_sval = 1;
+    } else if (nv > 0 && total >= Ns) {
+        sval = alloc_block(ctx, size_t(nv) * nb4);
+    }
     if (sval.ok()) {
         GatherArgs g{};
         g.vals = svals;

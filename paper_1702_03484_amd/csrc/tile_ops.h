@@ -332,6 +332,7 @@ struct MatJoin {
     const uint64_t* seg_off;
     uint32_t ns, n, n_left;
     int32_t key_base;
+    int32_t key_shift;  // 1: the side rides in the key's low bit
     int32_t nl, nr;
     bool sorted_vals;
     // merge-join segments: LEFT run [seg_start, + seg_cl) of the LEFT
@@ -435,7 +436,7 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, const uint64_t* 
     for (int k = 0; k < 4; k++) {
         if (k < nk) {
             seg_locate(p[k], j + k - off[sk[k] - off0]);
-            v[0][k] = (int32_t)(a.keys[p[k].st] + (uint32_t)a.key_base);
+            v[0][k] = (int32_t)((a.keys[p[k].st] >> a.key_shift) + (uint32_t)a.key_base);
             row_values<NC>(a, nl, nc, seg_lpos(p[k]), seg_rpos(p[k]), v, k);
         }
     }
@@ -508,7 +509,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
                 o0 = uni((uint32_t)(r0 / ci));
                 i0 = uni((uint32_t)(r0 - (uint64_t)o0 * ci));
             }
-            const int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
+            const int32_t key = (int32_t)((a.keys[st] >> a.key_shift) + (uint32_t)a.key_base);
             int32_t v[Q][NC][4];
 #pragma unroll
             for (int q = 0; q < Q; q++) {
@@ -585,7 +586,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
                 inner = t - dq * ci;
             }
             uint32_t outer = o0 + dq;
-            const int32_t key = (int32_t)(a.keys[st] + (uint32_t)a.key_base);
+            const int32_t key = (int32_t)((a.keys[st] >> a.key_shift) + (uint32_t)a.key_base);
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 const uint32_t lpos = st + (left_in ? inner : outer);
