@@ -320,10 +320,11 @@ def main():
     ap.add_argument("--cfg4-only", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="leave out the serving measurement (500M-triple store)")
     ap.add_argument("--cfg5-only", action="store_true")
+    ap.add_argument("--shuffle-only", action="store_true", help="only the 16M + 16M-record shuffle join")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build runs the join on "
-              "a single MI355X and has no multi-GPU path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the join runs on a single "
+              "MI355X and there is no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
@@ -333,6 +334,9 @@ def main():
         return
     if args.cfg5_only:
         print(json.dumps(run_cfg5()), flush=True)
+        return
+    if args.shuffle_only:
+        print(json.dumps(run_shuffle()), flush=True)
         return
 
     import torch

@@ -46,19 +46,20 @@ struct RecView {
     uint32_t k, v, kprev, vprev, knext;
 };
 
+// vals may be null (the side rides in the key): payloads then read as 0.
 __device__ __forceinline__ RecView rec_view(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                             uint32_t n, uint32_t idx) {
     RecView r;
     const bool in = idx < n;
     r.k = in ? keys[idx] : ~0u;
-    r.v = in ? vals[idx] : 0u;
+    r.v = in && vals ? vals[idx] : 0u;
     // neighbours from the adjacent lanes; the wave's edge lanes load them
     r.kprev = __shfl_up(r.k, 1, MQ_WAVE);
     r.vprev = __shfl_up(r.v, 1, MQ_WAVE);
     r.knext = __shfl_down(r.k, 1, MQ_WAVE);
     if (lane() == 0 && in && idx > 0) {
         r.kprev = keys[idx - 1];
-        r.vprev = vals[idx - 1];
+        r.vprev = vals ? vals[idx - 1] : 0u;
     }
     if (lane() == MQ_WAVE - 1 && idx + 1 < n) r.knext = keys[idx + 1];
     return r;
@@ -187,8 +188,8 @@ hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t
     heads_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, n, fs, run_tot, tloc, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    heads_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, vals, n, n_left, fs, run_tot, tloc, g, seg_start,
-                                                         seg_split, nseg);
+    heads_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, fs ? nullptr : vals, n, n_left, fs, run_tot, tloc,
+                                                         g, seg_start, seg_split, nseg);
     return hipGetLastError();
 }
 
@@ -230,11 +231,12 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_sum_kernel(uint32_t n, const u
     const uint32_t t0 = blockIdx.x * g.chunk;
     const uint32_t t1 = min(t0 + g.chunk, g.ntiles);
     for (uint32_t tile = t0; tile < t1; tile++) {
-        const uint32_t first = tile * COUNT_TILE + threadIdx.x * COUNT_IPT;
+        // any order within the tile: coalesced, segment base + i * 256 + thread
+        const uint32_t base = tile * COUNT_TILE;
         uint64_t sum = 0;
-        if (first < ns) {
+        if (base < ns) {
 #pragma unroll
-            for (int i = 0; i < COUNT_IPT; i++) sum += seg_pairs(seg_start, seg_split, n, ns, first + i);
+            for (int i = 0; i < COUNT_IPT; i++) sum += seg_pairs(seg_start, seg_split, n, ns, base + i * MQ_BLOCK + threadIdx.x);
         }
         const uint64_t tot = block_reduce_sum(sum, s_tmp);
         if (threadIdx.x == 0) {
@@ -263,31 +265,54 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_write_kernel(uint32_t n, const
         return;
     }
     if (tile >= ntiles) return;
-    const uint32_t first = tile * COUNT_TILE + threadIdx.x * COUNT_IPT;
-    uint64_t cnt[COUNT_IPT];
-    uint64_t sum = 0;
+    // wave-striped: slot i of wave w holds segments base + (w * IPT + i) * 64 + lane
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint32_t base = tile * COUNT_TILE + w * COUNT_IPT * MQ_WAVE;
+    uint32_t st[COUNT_IPT], sp[COUNT_IPT];
 #pragma unroll
     for (int i = 0; i < COUNT_IPT; i++) {
-        cnt[i] = seg_pairs(seg_start, seg_split, n, ns, first + i);
-        sum += cnt[i];
+        const uint32_t s = base + i * MQ_WAVE + lane();
+        st[i] = s < ns ? seg_start[s] : n;
+        sp[i] = s < ns ? seg_split[s] : n;
+    }
+    uint64_t cnt[COUNT_IPT];
+    uint64_t wsum = 0;  // this wave's pairs before slot i
+    uint64_t excl[COUNT_IPT];
+#pragma unroll
+    for (int i = 0; i < COUNT_IPT; i++) {
+        const uint32_t s = base + i * MQ_WAVE + lane();
+        uint32_t en = __shfl_down(st[i], 1, MQ_WAVE);
+        if (lane() == MQ_WAVE - 1) en = s + 1 < ns ? seg_start[s + 1] : n;
+        if (s + 1 >= ns) en = n;
+        const uint64_t c = s < ns ? (uint64_t)(sp[i] - st[i]) * (uint64_t)(en - sp[i]) : 0ull;
+        cnt[i] = c > SAT40 ? SAT40 : c;
+        const uint64_t inc = wave_incl_scan<uint64_t>(cnt[i]);
+        excl[i] = wsum + inc - cnt[i];
+        wsum += (uint64_t)__shfl(inc, MQ_WAVE - 1, MQ_WAVE);
     }
     // totals of the runs before this tile's run (saturating)
     uint64_t before = 0;
     for (uint32_t b = threadIdx.x; b < tile / g.chunk; b += MQ_BLOCK) before = sat_add(before, run_tot[b]);
 #pragma unroll
     for (int o = MQ_WAVE / 2; o > 0; o >>= 1) before = sat_add(before, (uint64_t)__shfl_xor(before, o));
-    if (lane() == 0) s_red[threadIdx.x / MQ_WAVE] = before;
-    uint64_t ttot;
-    const uint64_t ex_in = block_excl_scan<uint64_t>(sum, s_tmp, &ttot);  // syncs after s_red is written
-    uint64_t off = tloc[tile];
+    if (lane() == 0) {
+        s_red[w] = before;
+        s_tmp[w] = wsum;
+    }
+    __syncthreads();
+    uint64_t off = tloc[tile], ttot = 0, wex = 0;
 #pragma unroll
-    for (int i = 0; i < MQ_WAVES; i++) off = sat_add(off, s_red[i]);
+    for (int i = 0; i < MQ_WAVES; i++) {
+        off = sat_add(off, s_red[i]);
+        if ((uint32_t)i < w) wex += s_tmp[i];
+        ttot += s_tmp[i];
+    }
     if (tile == ntiles - 1 && threadIdx.x == 0) *total = sat_add(off, ttot > SAT40 ? SAT40 : ttot);
-    off = sat_add(off, ex_in > SAT40 ? SAT40 : ex_in);
+    off = sat_add(off, wex > SAT40 ? SAT40 : wex);
 #pragma unroll
     for (int i = 0; i < COUNT_IPT; i++) {
-        if (first + i < ns) seg_off[first + i] = off;
-        off = sat_add(off, cnt[i]);
+        const uint32_t s = base + i * MQ_WAVE + lane();
+        if (s < ns) seg_off[s] = sat_add(off, excl[i] > SAT40 ? SAT40 : excl[i]);
     }
 }
 
