@@ -19,8 +19,12 @@ constexpr uint32_t BMAT_WROWS = MQ_WAVE * BMAT_RPT;
 
 uint32_t batch_chunk_rows() { return BMAT_WROWS; }
 
+// Relative key of record idx (< nl + nr) of a join: the column is selected
+// per lane before one load, and callers clamp idx into range instead of
+// branching, so a thread's loads are all in flight together.
 __device__ __forceinline__ uint32_t bsrc_key(const BatchJoin& J, uint32_t idx) {
-    const int32_t k = idx < J.nl ? J.lkey[idx] : J.rkey[idx - J.nl];
+    const bool right = idx >= J.nl;
+    const int32_t k = (right ? J.rkey : J.lkey)[right ? idx - J.nl : idx];
     return (uint32_t)k - (uint32_t)J.key_base;
 }
 
@@ -65,8 +69,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void bhist_kernel(const BatchHdr* __restr
         uint32_t k[KPT];
 #pragma unroll
         for (int i = 0; i < KPT; i++) {
-            const uint32_t idx = base + i * MQ_BLOCK + threadIdx.x;
-            k[i] = idx < n ? bsrc_key(J, idx) : 0u;
+            k[i] = bsrc_key(J, min(base + i * MQ_BLOCK + threadIdx.x, n - 1));
         }
 #pragma unroll
         for (int i = 0; i < KPT; i++) {
@@ -110,7 +113,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void bpass_kernel(const BatchHdr* __restr
             const uint32_t idx = base + off;
             const bool ok = off < valid_n;
             if (GEN) {
-                key[i] = ok ? bsrc_key(J, idx) : 0u;
+                const uint32_t k = bsrc_key(J, min(idx, n - 1));
+                key[i] = ok ? k : 0u;
                 val[i] = idx;
             } else {
                 key[i] = ok ? kin[idx] : 0u;

@@ -22,18 +22,17 @@
 
 namespace mq {
 
-__device__ __forceinline__ uint32_t src_key(const SortSrc& s, uint32_t idx) {
-    const bool right = idx >= s.n0;
-    const int32_t k = right ? s.k1[idx - s.n0] : s.k0[idx];
-    const uint32_t rel = (uint32_t)k - (uint32_t)s.base;
-    return s.carry ? rel << 1 | (right ? 1u : 0u) : rel;
+// Cell idx of the concatenation c0 (n0 cells) ++ c1.  Callers clamp idx
+// into range and load unconditionally, then transform: a load (or its use)
+// inside a divergent branch makes every load wait for the one before.
+__device__ __forceinline__ int32_t src_load(const int32_t* c0, const int32_t* c1, uint32_t n0, uint32_t idx) {
+    const bool right = idx >= n0;
+    return (right ? c1 : c0)[right ? idx - n0 : idx];
 }
 
-__device__ __forceinline__ uint32_t src_payload(const SortSrc& s, uint32_t idx) {
-    if (!s.carry) return idx;
-    const bool right = idx >= s.n0;
-    const int32_t* v = right ? s.v1 : s.v0;
-    return v ? (uint32_t)v[right ? idx - s.n0 : idx] : 0u;
+__device__ __forceinline__ uint32_t src_key_of(const SortSrc& s, int32_t raw, uint32_t idx) {
+    const uint32_t rel = (uint32_t)raw - (uint32_t)s.base;
+    return s.carry ? rel << 1 | (idx >= s.n0 ? 1u : 0u) : rel;
 }
 
 // Digit histograms of every pass in two launches: each block counts its
@@ -62,7 +61,14 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_hist_kernel(SortSrc src, const
 #pragma unroll
         for (int i = 0; i < HIST_IPT; i++) {
             const uint32_t idx = first + i;
-            k[i] = idx < n ? (GEN ? src_key(src, idx) : keys[idx]) : 0u;
+            if (GEN)
+                k[i] = (uint32_t)src_load(src.k0, src.k1, src.n0, min(idx, n - 1));
+            else
+                k[i] = idx < n ? keys[idx] : 0u;
+        }
+        if (GEN) {
+#pragma unroll
+            for (int i = 0; i < HIST_IPT; i++) k[i] = src_key_of(src, (int32_t)k[i], first + i);
         }
         const int cnt = first >= n ? 0 : (int)min((uint32_t)HIST_IPT, n - first);
         for (int p = 0; p < passes; p++) {
@@ -141,15 +147,29 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
     const uint32_t w = threadIdx.x / MQ_WAVE;
     // wave-striped slice: element i of this lane is base + (w*KPT + i)*64 + lane
     uint32_t key[KPT], val[KPT];
+    if (GEN) {
+        // every load first (clamped into range), then the keys and payloads
+        int32_t rk[KPT], rv[KPT];
 #pragma unroll
-    for (int i = 0; i < KPT; i++) {
-        const uint32_t off = (w * KPT + i) * MQ_WAVE + lane();
-        const uint32_t idx = base + off;
-        const bool ok = off < valid_n;
-        if (GEN) {
-            key[i] = ok ? src_key(src, idx) : 0u;
-            val[i] = ok ? src_payload(src, idx) : 0u;
-        } else {
+        for (int i = 0; i < KPT; i++) {
+            const uint32_t idx = min(base + (w * KPT + i) * MQ_WAVE + lane(), n - 1);
+            rk[i] = src_load(src.k0, src.k1, src.n0, idx);
+            rv[i] = src.carry ? src_load(src.v0, src.v1, src.n0, idx) : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < KPT; i++) {
+            const uint32_t off = (w * KPT + i) * MQ_WAVE + lane();
+            const uint32_t idx = base + off;
+            const bool ok = off < valid_n;
+            key[i] = ok ? src_key_of(src, rk[i], idx) : 0u;
+            val[i] = ok ? (src.carry ? (uint32_t)rv[i] : idx) : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < KPT; i++) {
+            const uint32_t off = (w * KPT + i) * MQ_WAVE + lane();
+            const uint32_t idx = base + off;
+            const bool ok = off < valid_n;
             key[i] = ok ? kin[idx] : 0u;
             val[i] = ok ? vin[idx] : 0u;
         }

@@ -16,9 +16,10 @@ constexpr uint32_t BLOCK_THREADS = 256;  // threads per block of every tiled ker
 // First-pass source of a join's shuffle: the LEFT key column k0 (n0 rows)
 // then the RIGHT one k1 (n1 rows), keys relative to base.  carry = 0: the
 // payload is the record's position in that concatenation (RIGHT records
-// from n0 on).  carry = 1: the payload is the record's value cell (v0 or v1,
-// 0 when null) and the key is (relative key << 1) | side, so LEFT records
-// still sort ahead of RIGHT ones within a key.
+// from n0 on).  carry = 1: the payload is the record's value cell (v0 or v1;
+// a side without a value column points at any column of its rows and its
+// payloads go unused) and the key is (relative key << 1) | side, so LEFT
+// records still sort ahead of RIGHT ones within a key.
 struct SortSrc {
     const int32_t* k0;
     uint32_t n0;

@@ -1055,8 +1055,8 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     if (carry) pick_tuning(ctx, sort_bits, rb, kpt, (uint64_t)Ns);
     SortSrc src{lkey, nL, rkey, nR, kmin, nullptr, nullptr, carry ? 1 : 0};
     if (carry) {
-        src.v0 = lv.empty() ? nullptr : L->col[lv[0]];
-        src.v1 = rv.empty() ? nullptr : R->col[rv[0]];
+        src.v0 = lv.empty() ? lkey : L->col[lv[0]];  // payloads of a side without values go unused
+        src.v1 = rv.empty() ? rkey : R->col[rv[0]];
     }
     int res, passes;
     ph = ctx->prof_begin(1);
