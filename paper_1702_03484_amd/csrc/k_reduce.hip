@@ -174,7 +174,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
 size_t seg_scratch_bytes(uint32_t n) {
     const RunGrid gh = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
     const RunGrid gc = run_grid(std::max(1u, (n + COUNT_TILE - 1) / COUNT_TILE));
-    return 4ull * (gh.blocks + gh.ntiles) + 8ull * (gc.blocks + gc.ntiles) + 8;
+    return 4ull * (gh.blocks + gh.ntiles) + 8ull * (2 * gc.blocks + gc.ntiles) + 8;
 }
 
 hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
@@ -223,9 +223,11 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_sum_kernel(uint32_t n, const u
                                                              const uint32_t* __restrict__ nseg_p,
                                                              const uint32_t* __restrict__ seg_split,
                                                              uint64_t* __restrict__ run_tot,
+                                                             uint64_t* __restrict__ run_max,
                                                              uint64_t* __restrict__ tloc, RunGrid g) {
     __shared__ uint64_t s_tmp[MQ_WAVES];
     __shared__ uint64_t s_run;
+    uint64_t mx = 0;  // this thread's largest count
     const uint32_t ns = n == 0 ? 0u : *nseg_p;
     if (threadIdx.x == 0) s_run = 0;
     const uint32_t t0 = blockIdx.x * g.chunk;
@@ -236,7 +238,11 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_sum_kernel(uint32_t n, const u
         uint64_t sum = 0;
         if (base < ns) {
 #pragma unroll
-            for (int i = 0; i < COUNT_IPT; i++) sum += seg_pairs(seg_start, seg_split, n, ns, base + i * MQ_BLOCK + threadIdx.x);
+            for (int i = 0; i < COUNT_IPT; i++) {
+                const uint64_t c = seg_pairs(seg_start, seg_split, n, ns, base + i * MQ_BLOCK + threadIdx.x);
+                sum += c;
+                mx = c > mx ? c : mx;
+            }
         }
         const uint64_t tot = block_reduce_sum(sum, s_tmp);
         if (threadIdx.x == 0) {
@@ -245,26 +251,59 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_sum_kernel(uint32_t n, const u
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) run_tot[blockIdx.x] = s_run;
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor(mx, o);
+        mx = y > mx ? y : mx;
+    }
+    if (lane() == 0) s_tmp[threadIdx.x / MQ_WAVE] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        run_tot[blockIdx.x] = s_run;
+        for (int i = 0; i < MQ_WAVES; i++) mx = s_tmp[i] > mx ? s_tmp[i] : mx;
+        run_max[blockIdx.x] = mx;
+    }
 }
 
 __global__ __launch_bounds__(MQ_BLOCK) void count_write_kernel(uint32_t n, const uint32_t* __restrict__ seg_start,
                                                                const uint32_t* __restrict__ nseg_p,
                                                                const uint32_t* __restrict__ seg_split,
                                                                const uint64_t* __restrict__ run_tot,
+                                                               const uint64_t* __restrict__ run_max,
                                                                const uint64_t* __restrict__ tloc, RunGrid g,
                                                                uint64_t* __restrict__ seg_off,
-                                                               uint64_t* __restrict__ total) {
+                                                               uint64_t* __restrict__ total,
+                                                               uint64_t* __restrict__ max_pairs) {
     __shared__ uint64_t s_tmp[MQ_WAVES];
     __shared__ uint64_t s_red[MQ_WAVES];
     const uint32_t ns = n == 0 ? 0u : *nseg_p;
     const uint32_t tile = blockIdx.x;
     const uint32_t ntiles = (ns + COUNT_TILE - 1) / COUNT_TILE;
     if (ns == 0) {
-        if (tile == 0 && threadIdx.x == 0) *total = 0;
+        if (tile == 0 && threadIdx.x == 0) {
+            *total = 0;
+            *max_pairs = 0;
+        }
         return;
     }
     if (tile >= ntiles) return;
+    if (tile == ntiles - 1) {
+        // the sum pass has finished: the largest count over every run
+        __shared__ uint64_t s_mx[MQ_WAVES];
+        uint64_t mx = 0;
+        for (uint32_t b = threadIdx.x; b < g.blocks; b += MQ_BLOCK) mx = run_max[b] > mx ? run_max[b] : mx;
+#pragma unroll
+        for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
+            const uint64_t y = __shfl_xor(mx, o);
+            mx = y > mx ? y : mx;
+        }
+        if (lane() == 0) s_mx[threadIdx.x / MQ_WAVE] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < MQ_WAVES; i++) mx = s_mx[i] > mx ? s_mx[i] : mx;
+            *max_pairs = mx;
+        }
+    }
     // wave-striped: slot i of wave w holds segments base + (w * IPT + i) * 64 + lane
     const uint32_t w = threadIdx.x / MQ_WAVE;
     const uint32_t base = tile * COUNT_TILE + w * COUNT_IPT * MQ_WAVE;
@@ -317,19 +356,20 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_write_kernel(uint32_t n, const
 }
 
 hipError_t launch_seg_count(uint32_t n, const uint32_t* seg_start, const uint32_t* nseg, uint32_t max_seg,
-                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, void* scratch,
-                            hipStream_t stream) {
+                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, uint64_t* max_pairs,
+                            void* scratch, hipStream_t stream) {
     const RunGrid gh = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
     const RunGrid g = run_grid(std::max(1u, (max_seg + COUNT_TILE - 1) / COUNT_TILE));
     // after the heads pass's words, 8-byte aligned
     uint64_t* run_tot = reinterpret_cast<uint64_t*>(
         (reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(scratch) + gh.blocks + gh.ntiles) + 7) & ~uintptr_t(7));
-    uint64_t* tloc = run_tot + g.blocks;
-    count_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, run_tot, tloc, g);
+    uint64_t* run_max = run_tot + g.blocks;
+    uint64_t* tloc = run_max + g.blocks;
+    count_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, run_tot, run_max, tloc, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    count_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, run_tot, tloc, g, seg_off,
-                                                         total);
+    count_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, run_tot, run_max, tloc, g,
+                                                         seg_off, total, max_pairs);
     return hipGetLastError();
 }
 
@@ -343,9 +383,7 @@ struct MatShape {
 };
 
 template <int NC, int NLC>
-__global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
-    constexpr uint32_t WROWS = MatShape<NC>::WROWS;
-    __shared__ uint64_t s_segs[MQ_WAVES][MAT_LDS_SEGS];
+__device__ __forceinline__ MatJoin mat_join_of(const MatArgs& a) {
     MatJoin mj;
     mj.keys = a.keys;
     mj.vals = a.vals;
@@ -373,6 +411,14 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
             mj.ssrc[c] = merged ? mj.src[c] : (left ? a.sval[c - 1] : a.sval[c - 1 - mj.nl]);
         }
     }
+    return mj;
+}
+
+template <int NC, int NLC>
+__global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
+    constexpr uint32_t WROWS = MatShape<NC>::WROWS;
+    __shared__ uint64_t s_segs[MQ_WAVES][MAT_LDS_SEGS];
+    const MatJoin mj = mat_join_of<NC, NLC>(a);
     // chunks strided over the waves (the rows being written at any moment
     // stay in one window of the output); a wave's previous segment is the
     // starting guess for its next chunk
@@ -386,6 +432,85 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
         const uint64_t j0 = a.row_begin + c * crows;
         mat_wave_chunk<NC, MatShape<NC>::RPT, NLC>(mj, j0, min(j0 + crows, a.row_end), hint,
                                                    s_segs[threadIdx.x / MQ_WAVE], qn);
+    }
+}
+
+// Segment-major materialisation of sparse outputs (every key product at
+// most MAT_SEG_MAX_PAIRS): one wave per group of 64 consecutive segments.
+// The group's starts, splits, offsets and keys are loaded once, coalesced,
+// into LDS; its rows (at most 64 * MAT_SEG_MAX_PAIRS) go out lane-strided,
+// each row finding its segment by a binary search over the group's
+// offsets, so consecutive lanes store consecutive rows.
+template <int NC, int NLC>
+__global__ __launch_bounds__(MQ_BLOCK) void mat_seg_kernel(MatArgs a) {
+    __shared__ uint64_t s_off[MQ_WAVES][MQ_WAVE + 1];
+    __shared__ uint32_t s_st[MQ_WAVES][MQ_WAVE];
+    __shared__ uint32_t s_sp[MQ_WAVES][MQ_WAVE];
+    __shared__ uint32_t s_en[MQ_WAVES][MQ_WAVE];
+    __shared__ int32_t s_key[MQ_WAVES][MQ_WAVE];
+    const MatJoin mj = mat_join_of<NC, NLC>(a);
+    const int nl = NLC >= 0 ? NLC : mj.nl, nr = NLC >= 0 ? NC - 1 - NLC : mj.nr;
+    const int nc = 1 + nl + nr;
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint32_t ns = mj.ns;
+    const uint32_t ngroups = (ns + MQ_WAVE - 1) / MQ_WAVE;
+    const uint32_t nw = gridDim.x * MQ_WAVES;
+    for (uint32_t grp = blockIdx.x * MQ_WAVES + w; grp < ngroups; grp += nw) {
+        const uint32_t s0 = grp * MQ_WAVE;
+        const uint32_t s = s0 + lane();
+        const bool in = s < ns;
+        const uint32_t st = in ? mj.seg_start[s] : mj.n;
+        const uint32_t sp = in ? mj.seg_split[s] : mj.n;
+        uint32_t en = __shfl_down(st, 1, MQ_WAVE);
+        if (lane() == MQ_WAVE - 1 && s + 1 < ns) en = mj.seg_start[s + 1];
+        if (s + 1 >= ns) en = mj.n;
+        // segments past the end sit at the end of the output: no row finds them
+        const uint64_t off = in ? mj.seg_off[s] : a.row_end;
+        const uint64_t off_end = s0 + MQ_WAVE < ns ? mj.seg_off[s0 + MQ_WAVE] : a.row_end;
+        const int32_t key = in ? (int32_t)((mj.keys[st] >> mj.key_shift) + (uint32_t)mj.key_base) : 0;
+        __builtin_amdgcn_wave_barrier();  // the previous group's reads of the LDS rows are done
+        s_off[w][lane()] = off;
+        if (lane() == 0) s_off[w][MQ_WAVE] = off_end;
+        s_st[w][lane()] = st;
+        s_sp[w][lane()] = sp;
+        s_en[w][lane()] = en;
+        s_key[w][lane()] = key;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint64_t off0 = s_off[w][0];
+        const uint32_t rows = (uint32_t)(off_end - off0);
+        for (uint32_t r = lane(); r < rows; r += MQ_WAVE) {
+            const uint64_t j = off0 + r;
+            // the last segment of the group starting at or before row j
+            // (empty segments share the next one's offset and lose the tie)
+            uint32_t lo = 0, hi = MQ_WAVE - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (s_off[w][mid] <= j) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t kst = s_st[w][lo], ksp = s_sp[w][lo], ken = s_en[w][lo];
+            const uint32_t cl = ksp - kst, cr = ken - ksp;
+            const bool left_in = left_inner_of(cl, cr, nl, nr);
+            const uint32_t ci = left_in ? cl : cr;
+            const uint32_t rr = (uint32_t)(j - s_off[w][lo]);  // < MAT_SEG_MAX_PAIRS
+            const uint32_t outer = rr / ci, inner = rr - outer * ci;
+            const uint32_t lpos = kst + (left_in ? inner : outer);
+            const uint32_t rpos = ksp + (left_in ? outer : inner);
+            mj.out[0][j] = s_key[w][lo];
+            if (mj.sorted_vals) {
+#pragma unroll
+                for (int col = 1; col < NC; col++)
+                    if (col < nc) mj.out[col][j] = mj.ssrc[col][col <= nl ? lpos : rpos];
+            } else {
+                const uint32_t lrow = nl > 0 ? mj.vals[lpos] : 0u;
+                const uint32_t rrow = nc - 1 > nl ? mj.vals[rpos] - mj.n_left : 0u;
+#pragma unroll
+                for (int col = 1; col < NC; col++)
+                    if (col < nc) mj.out[col][j] = mj.src[col][col <= nl ? lrow : rrow];
+            }
+        }
     }
 }
 
@@ -414,11 +539,16 @@ hipError_t launch_gather_values(const GatherArgs& g, hipStream_t stream) {
 hipError_t launch_materialize(const MatArgs& a, hipStream_t stream) {
     if (a.row_end <= a.row_begin) return hipSuccess;
     if (a.row_begin % 16) return hipErrorInvalidValue;
+    if (a.seg_major && (a.row_begin != 0 || a.seg_cl != nullptr)) return hipErrorInvalidValue;
     const int nc = 1 + a.nl + a.nr;
     const uint64_t rows = a.row_end - a.row_begin;
     // narrow joins get the value-column split fixed at compile time
 #define MQ_LAUNCH(C, L)                                                                             \
-    {                                                                                               \
+    if (a.seg_major) {                                                                              \
+        const uint64_t groups = (a.seg_count + MQ_WAVE - 1) / MQ_WAVE;                              \
+        uint32_t blocks = (uint32_t)std::min<uint64_t>((groups + MQ_WAVES - 1) / MQ_WAVES, 256ull * 32); \
+        mat_seg_kernel<C, L><<<std::max(blocks, 1u), MQ_BLOCK, 0, stream>>>(a);                     \
+    } else {                                                                                        \
         const uint64_t crows = a.sparse ? 4 * MQ_WAVE : MatShape<C>::WROWS;                         \
         uint64_t chunks = (rows + crows - 1) / crows;                                               \
         uint32_t blocks = (uint32_t)std::min<uint64_t>((chunks + MQ_WAVES - 1) / MQ_WAVES, 256ull * 32); \

@@ -113,9 +113,10 @@ hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t
 // count[s] = (split - start) * (end - split); seg_off = exclusive scan of the
 // counts (saturating at 2^40-1); *total = the full sum.  max_seg bounds the
 // device count *nseg (sizes the grids).
+// *max_pairs gets the largest single count.
 hipError_t launch_seg_count(uint32_t n, const uint32_t* seg_start, const uint32_t* nseg, uint32_t max_seg,
-                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, void* scratch,
-                            hipStream_t stream);
+                            const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, uint64_t* max_pairs,
+                            void* scratch, hipStream_t stream);
 size_t seg_scratch_bytes(uint32_t n);
 
 // Value columns in sorted record order: for every record i, with
@@ -158,7 +159,13 @@ struct MatArgs {
     int32_t sparse;
     // 1: keys carry the side in their low bit (output key = (key >> 1) + base)
     int32_t key_shift;
+    // 1: segment-major writing for sparse outputs whose largest key product
+    // is at most MAT_SEG_MAX_PAIRS (one wave per 64 segments); needs
+    // row_begin == 0, row_end == |RS| and seg_cl == null
+    int32_t seg_major;
+    uint32_t seg_count;  // host copy of *nseg (sizes the segment-major grid)
 };
+constexpr uint64_t MAT_SEG_MAX_PAIRS = 64;
 hipError_t launch_materialize(const MatArgs& a, hipStream_t stream);
 
 // ---- map and filters (k_map.hip) -----------------------------------------

@@ -173,7 +173,7 @@ static inline uint32_t* scalar32(Ctx* ctx, int word) { return ctx->small + SMALL
 static inline uint32_t* counter(Ctx* ctx, int i) { return ctx->small + SMALL_CTR + i; }
 
 // scalar slots (u32 word index inside the scalar area)
-enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12, SC_PRECOUNT = 14 };
+enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12, SC_PRECOUNT = 14, SC_MAXPAIRS = 16 };
 // counter slots
 enum { CT_PASS0 = 0, CT_COUNT = 9, CT_SEMI = 11 };
 
@@ -1079,13 +1079,15 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     HIPCHK(launch_seg_heads(skeys, svals, Ns, nL, carry ? 1 : 0, seg_start, seg_split, scalar32(ctx, SC_NSEG),
                             ss.as<void>(), ctx->stream));
     HIPCHK(launch_seg_count(Ns, seg_start, scalar32(ctx, SC_NSEG), Ns, seg_split, seg_off, scalar64(ctx, SC_TOTAL),
-                            ss.as<void>(), ctx->stream));
-    uint32_t sc[4];
+                            scalar64(ctx, SC_MAXPAIRS), ss.as<void>(), ctx->stream));
+    uint32_t sc[SC_MAXPAIRS + 2];  // scalar words 0 .. SC_MAXPAIRS + 1
     {
         // bytes are filled in once the segment count is known (below)
         ctx->prof_end(ph, 0.0);
     }
-    if ((st = readback(ctx, scalar32(ctx, SC_NSEG), 16, sc))) return st;
+    if ((st = readback(ctx, scalar32(ctx, SC_NSEG), sizeof(sc), sc))) return st;
+    uint64_t max_pairs;
+    std::memcpy(&max_pairs, &sc[SC_MAXPAIRS], 8);
     const uint32_t nseg = sc[0];
     // heads: read 4N keys and 4N payloads, write 4S starts and 4S splits;
     // count: read 8S starts and 4S splits, write 8S offsets
@@ -1133,6 +1135,8 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     a.row_begin = 0;
     a.row_end = total;
     a.sparse = total < SPARSE_ROWS_PER_SEG * (uint64_t)nseg ? 1 : 0;
+    a.seg_major = a.sparse && max_pairs <= MAT_SEG_MAX_PAIRS ? 1 : 0;
+    a.seg_count = nseg;
     // values in sorted record order when output rows outnumber records
     // (each record's values are then read many times)
     const int nv = std::max(a.nl, a.nr);
