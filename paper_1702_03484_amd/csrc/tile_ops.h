@@ -85,13 +85,18 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t 
         const uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
         const bool ok = off < valid_n;
         const uint32_t dg = (key[i] >> shift) & R::MASK;
-        uint64_t peers = __ballot(ok);
+        // lanes whose digit differs in some bit: per bit, the ballot of
+        // that bit xor this lane's bit spread over 64 bits (0 or all ones)
+        uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
         for (int b = 0; b < RB; b++) {
-            const uint32_t bit = (dg >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+            const int32_t top = (int32_t)(dg << (31 - b));  // digit bit b in the sign bit
+            const uint64_t m = __ballot(top < 0);
+            const uint32_t spread = (uint32_t)(top >> 31);
+            diff_lo |= (uint32_t)m ^ spread;
+            diff_hi |= (uint32_t)(m >> 32) ^ spread;
         }
+        const uint64_t peers = __ballot(ok) & ~((uint64_t)diff_hi << 32 | diff_lo);
         const uint32_t below = __popcll(peers & lt);
         const uint32_t old = ok ? sm.wcnt[w][dg] : 0u;
         if (ok && below == 0) sm.wcnt[w][dg] = old + (uint32_t)__popcll(peers);
