@@ -116,29 +116,30 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_write_kernel(CompactArgs a, 
     const uint64_t run_of = tile / g.chunk;  // the test-pass block that owned this tile
     const uint64_t base = tile * CMP_TILE;
     const uint64_t mine = lane() < (uint32_t)CMP_IPT ? mask[tile * CMP_TILE_WORDS + w * CMP_IPT + lane()] : 0ull;
-    // rows kept before this tile: the runs before its run, then its in-run offset
-    uint64_t before = 0;
-    for (uint64_t b = threadIdx.x; b < run_of; b += MQ_BLOCK) before += counts[b];
     uint32_t run = (uint32_t)__popcll(mine);
 #pragma unroll
-    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
-        before += __shfl_xor(before, o);
-        run += __shfl_xor(run, o);
-    }
-    if (lane() == 0) {
-        s_red[w] = before;
-        s_wtot[w] = run;
-    }
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) run += __shfl_xor(run, o);
+    if (lane() == 0) s_wtot[w] = run;
     __syncthreads();
-    uint64_t pos0 = tloc[tile];
     uint32_t wex = 0, ttot = 0;
 #pragma unroll
     for (int i = 0; i < MQ_WAVES; i++) {
-        pos0 += s_red[i];
         if ((uint32_t)i < w) wex += s_wtot[i];
         ttot += s_wtot[i];
     }
-    if (tile == g.ntiles - 1 && threadIdx.x == 0) *a.count = pos0 + ttot;
+    const bool last = tile == g.ntiles - 1;
+    if (ttot == 0 && !last) return;  // nothing kept here (most tiles of a selective scan)
+    // rows kept before this tile: the runs before its run, then its in-run offset
+    uint64_t before = 0;
+    for (uint64_t b = threadIdx.x; b < run_of; b += MQ_BLOCK) before += counts[b];
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) before += __shfl_xor(before, o);
+    if (lane() == 0) s_red[w] = before;
+    __syncthreads();
+    uint64_t pos0 = tloc[tile];
+#pragma unroll
+    for (int i = 0; i < MQ_WAVES; i++) pos0 += s_red[i];
+    if (last && threadIdx.x == 0) *a.count = pos0 + ttot;
     const uint64_t pos = pos0 + wex;
     if (run == 0) return;
     {
