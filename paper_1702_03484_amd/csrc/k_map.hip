@@ -4,10 +4,11 @@
 // blocks (no tile counter, no look-back).  In the test pass block b owns a
 // contiguous run of tiles; it reads only the columns the tests use and
 // stores one __ballot word per 64 rows, the kept rows of its run before
-// each tile, and its run's total.  The write pass takes one tile per block
-// (so clustered output spreads over the whole grid): its offset is the sum
-// of the run totals before its run plus its in-run offset, and it copies
-// the output columns of the rows its mask words mark.
+// each tile, and its run's total.  One block turns the run totals into
+// their prefix sums.  The write pass takes one tile per block (so clustered
+// output spreads over the whole grid): its offset is its run's prefix plus
+// its in-run offset, and it copies the output columns of the rows its mask
+// words mark.
 // The same kernels filter join results on further shared variables.
 #include "device_common.h"
 #include "kernels.h"
@@ -108,7 +109,6 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_test_kernel(CompactArgs a, u
 __global__ __launch_bounds__(MQ_BLOCK) void compact_write_kernel(CompactArgs a, const uint64_t* __restrict__ counts,
                                                                  const uint32_t* __restrict__ tloc,
                                                                  const uint64_t* __restrict__ mask, CompactGrid g) {
-    __shared__ uint64_t s_red[MQ_WAVES];
     __shared__ uint32_t s_wtot[MQ_WAVES];
     const uint32_t w = threadIdx.x / MQ_WAVE;
     const uint64_t lt = lanemask_lt();
@@ -127,19 +127,10 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_write_kernel(CompactArgs a, 
         if ((uint32_t)i < w) wex += s_wtot[i];
         ttot += s_wtot[i];
     }
-    const bool last = tile == g.ntiles - 1;
-    if (ttot == 0 && !last) return;  // nothing kept here (most tiles of a selective scan)
-    // rows kept before this tile: the runs before its run, then its in-run offset
-    uint64_t before = 0;
-    for (uint64_t b = threadIdx.x; b < run_of; b += MQ_BLOCK) before += counts[b];
-#pragma unroll
-    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) before += __shfl_xor(before, o);
-    if (lane() == 0) s_red[w] = before;
-    __syncthreads();
-    uint64_t pos0 = tloc[tile];
-#pragma unroll
-    for (int i = 0; i < MQ_WAVES; i++) pos0 += s_red[i];
-    if (last && threadIdx.x == 0) *a.count = pos0 + ttot;
+    if (ttot == 0) return;  // nothing kept here (most tiles of a selective scan)
+    // rows kept before this tile: the runs before its run (counts holds their
+    // exclusive prefix by now), then its offset within the run
+    const uint64_t pos0 = counts[run_of] + tloc[tile];
     const uint64_t pos = pos0 + wex;
     if (run == 0) return;
     {
@@ -189,6 +180,7 @@ hipError_t launch_compact(const CompactArgs& a, uint64_t* scratch, hipStream_t s
     uint64_t* mask = scratch + g.blocks + (g.ntiles + 1) / 2;
     compact_test_kernel<<<(uint32_t)g.blocks, MQ_BLOCK, 0, stream>>>(a, counts, tloc, mask, g);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_scan_runs(counts, (uint32_t)g.blocks, a.count, nullptr, nullptr, nullptr, stream);
     if (e != hipSuccess) return e;
     compact_write_kernel<<<(uint32_t)g.ntiles, MQ_BLOCK, 0, stream>>>(a, counts, tloc, mask, g);
     return hipGetLastError();

@@ -11,8 +11,9 @@
 // Heads and count each run as two kernels with no ordering between blocks
 // (no tile counter, no look-back): a sum pass in which block b owns a
 // contiguous run of tiles and stores each tile's offset within the run and
-// the run's total, then a write pass with one tile per block whose offset is
-// the totals of the runs before its run plus its in-run offset.
+// the run's total, one block that turns the run totals into prefix sums,
+// then a write pass with one tile per block whose offset is its run's
+// prefix plus its in-run offset.
 #include "device_common.h"
 #include "kernels.h"
 #include "tile_ops.h"
@@ -72,7 +73,7 @@ __device__ __forceinline__ bool rec_is_head(const RecView& r, uint32_t idx, uint
 
 // sum pass: heads of every tile of the block's run
 __global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __restrict__ keys, uint32_t n,
-                                                             uint32_t fs, uint32_t* __restrict__ run_tot,
+                                                             uint32_t fs, uint64_t* __restrict__ run_tot,
                                                              uint32_t* __restrict__ tloc, RunGrid g) {
     __shared__ uint32_t s_wtot[MQ_WAVES];
     __shared__ uint32_t s_run;
@@ -114,12 +115,10 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __r
 __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* __restrict__ keys,
                                                                const uint32_t* __restrict__ vals, uint32_t n,
                                                                uint32_t n_left, uint32_t fs,
-                                                               const uint32_t* __restrict__ run_tot,
+                                                               const uint64_t* __restrict__ run_excl,
                                                                const uint32_t* __restrict__ tloc, RunGrid g,
                                                                uint32_t* __restrict__ seg_start,
-                                                               uint32_t* __restrict__ seg_split,
-                                                               uint32_t* __restrict__ nseg) {
-    __shared__ uint32_t s_red[MQ_WAVES];
+                                                               uint32_t* __restrict__ seg_split) {
     __shared__ uint32_t s_wtot[MQ_WAVES];
     const uint32_t w = threadIdx.x / MQ_WAVE;
     const uint64_t lt = lanemask_lt();
@@ -128,8 +127,6 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
     RecView r[HEADS_IPT];
 #pragma unroll
     for (int i = 0; i < HEADS_IPT; i++) r[i] = rec_view(keys, vals, n, base + (w * HEADS_IPT + i) * MQ_WAVE + lane());
-    uint32_t before = 0;
-    for (uint32_t b = threadIdx.x; b < tile / g.chunk; b += MQ_BLOCK) before += run_tot[b];
     uint64_t hm[HEADS_IPT];
     uint32_t run = 0;
 #pragma unroll
@@ -137,20 +134,12 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
         hm[i] = __ballot(rec_is_head(r[i], base + (w * HEADS_IPT + i) * MQ_WAVE + lane(), n, fs));
         run += (uint32_t)__popcll(hm[i]);
     }
-#pragma unroll
-    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) before += __shfl_xor(before, o);
-    if (lane() == 0) {
-        s_red[w] = before;
-        s_wtot[w] = run;
-    }
+    if (lane() == 0) s_wtot[w] = run;
     __syncthreads();
-    uint32_t pos = tloc[tile], ttot = 0;
+    // heads before this tile: its run's prefix, then its offset within the run
+    uint32_t pos = (uint32_t)run_excl[tile / g.chunk] + tloc[tile];
 #pragma unroll
-    for (int i = 0; i < MQ_WAVES; i++) {
-        pos += s_red[i] + ((uint32_t)i < w ? s_wtot[i] : 0u);
-        ttot += s_wtot[i];
-    }
-    if (tile == g.ntiles - 1 && threadIdx.x == 0) *nseg = pos + ttot;  // thread 0: pos is the tile's first head
+    for (int i = 0; i < MQ_WAVES; i++) pos += (uint32_t)i < w ? s_wtot[i] : 0u;
 #pragma unroll
     for (int i = 0; i < HEADS_IPT; i++) {
         const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
@@ -171,10 +160,31 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
     }
 }
 
+// Scratch of the heads and count phases (u64 words first): heads run
+// totals, count run totals, count run maxima, count per-tile offsets, then
+// heads per-tile offsets (u32).
+struct SegScratch {
+    uint64_t *h_run, *c_run, *c_max, *c_tloc;
+    uint32_t* h_tloc;
+};
+
+static RunGrid heads_grid(uint32_t n) { return run_grid((n + HEADS_TILE - 1) / HEADS_TILE); }
+static RunGrid count_grid(uint32_t max_seg) { return run_grid(std::max(1u, (max_seg + COUNT_TILE - 1) / COUNT_TILE)); }
+
+static SegScratch seg_scratch(void* p, uint32_t n) {
+    const RunGrid gh = heads_grid(n), gc = count_grid(n);
+    SegScratch s;
+    s.h_run = static_cast<uint64_t*>(p);
+    s.c_run = s.h_run + gh.blocks;
+    s.c_max = s.c_run + gc.blocks;
+    s.c_tloc = s.c_max + gc.blocks;
+    s.h_tloc = reinterpret_cast<uint32_t*>(s.c_tloc + gc.ntiles);
+    return s;
+}
+
 size_t seg_scratch_bytes(uint32_t n) {
-    const RunGrid gh = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
-    const RunGrid gc = run_grid(std::max(1u, (n + COUNT_TILE - 1) / COUNT_TILE));
-    return 4ull * (gh.blocks + gh.ntiles) + 8ull * (2 * gc.blocks + gc.ntiles) + 8;
+    const RunGrid gh = heads_grid(n), gc = count_grid(n);
+    return 8ull * (gh.blocks + 2ull * gc.blocks + gc.ntiles) + 4ull * gh.ntiles;
 }
 
 hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
@@ -182,14 +192,14 @@ hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t
                             hipStream_t stream) {
     const uint32_t fs = side_bit ? 1u : 0u;
     if (n == 0) return hipSuccess;
-    const RunGrid g = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
-    uint32_t* run_tot = static_cast<uint32_t*>(scratch);
-    uint32_t* tloc = run_tot + g.blocks;
-    heads_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, n, fs, run_tot, tloc, g);
+    const RunGrid g = heads_grid(n);
+    const SegScratch ss = seg_scratch(scratch, n);
+    heads_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, n, fs, ss.h_run, ss.h_tloc, g);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_scan_runs(ss.h_run, g.blocks, nullptr, nseg, nullptr, nullptr, stream);
     if (e != hipSuccess) return e;
-    heads_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, fs ? nullptr : vals, n, n_left, fs, run_tot, tloc,
-                                                         g, seg_start, seg_split, nseg);
+    heads_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, fs ? nullptr : vals, n, n_left, fs, ss.h_run,
+                                                         ss.h_tloc, g, seg_start, seg_split);
     return hipGetLastError();
 }
 
@@ -268,42 +278,14 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_sum_kernel(uint32_t n, const u
 __global__ __launch_bounds__(MQ_BLOCK) void count_write_kernel(uint32_t n, const uint32_t* __restrict__ seg_start,
                                                                const uint32_t* __restrict__ nseg_p,
                                                                const uint32_t* __restrict__ seg_split,
-                                                               const uint64_t* __restrict__ run_tot,
-                                                               const uint64_t* __restrict__ run_max,
+                                                               const uint64_t* __restrict__ run_excl,
                                                                const uint64_t* __restrict__ tloc, RunGrid g,
-                                                               uint64_t* __restrict__ seg_off,
-                                                               uint64_t* __restrict__ total,
-                                                               uint64_t* __restrict__ max_pairs) {
+                                                               uint64_t* __restrict__ seg_off) {
     __shared__ uint64_t s_tmp[MQ_WAVES];
-    __shared__ uint64_t s_red[MQ_WAVES];
     const uint32_t ns = n == 0 ? 0u : *nseg_p;
     const uint32_t tile = blockIdx.x;
     const uint32_t ntiles = (ns + COUNT_TILE - 1) / COUNT_TILE;
-    if (ns == 0) {
-        if (tile == 0 && threadIdx.x == 0) {
-            *total = 0;
-            *max_pairs = 0;
-        }
-        return;
-    }
     if (tile >= ntiles) return;
-    if (tile == ntiles - 1) {
-        // the sum pass has finished: the largest count over every run
-        __shared__ uint64_t s_mx[MQ_WAVES];
-        uint64_t mx = 0;
-        for (uint32_t b = threadIdx.x; b < g.blocks; b += MQ_BLOCK) mx = run_max[b] > mx ? run_max[b] : mx;
-#pragma unroll
-        for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
-            const uint64_t y = __shfl_xor(mx, o);
-            mx = y > mx ? y : mx;
-        }
-        if (lane() == 0) s_mx[threadIdx.x / MQ_WAVE] = mx;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int i = 0; i < MQ_WAVES; i++) mx = s_mx[i] > mx ? s_mx[i] : mx;
-            *max_pairs = mx;
-        }
-    }
     // wave-striped: slot i of wave w holds segments base + (w * IPT + i) * 64 + lane
     const uint32_t w = threadIdx.x / MQ_WAVE;
     const uint32_t base = tile * COUNT_TILE + w * COUNT_IPT * MQ_WAVE;
@@ -329,24 +311,12 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_write_kernel(uint32_t n, const
         excl[i] = wsum + inc - cnt[i];
         wsum += (uint64_t)__shfl(inc, MQ_WAVE - 1, MQ_WAVE);
     }
-    // totals of the runs before this tile's run (saturating)
-    uint64_t before = 0;
-    for (uint32_t b = threadIdx.x; b < tile / g.chunk; b += MQ_BLOCK) before = sat_add(before, run_tot[b]);
-#pragma unroll
-    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) before = sat_add(before, (uint64_t)__shfl_xor(before, o));
-    if (lane() == 0) {
-        s_red[w] = before;
-        s_tmp[w] = wsum;
-    }
+    if (lane() == 0) s_tmp[w] = wsum;
     __syncthreads();
-    uint64_t off = tloc[tile], ttot = 0, wex = 0;
+    // pairs before this tile: its run's prefix (capped), then its offset within the run
+    uint64_t off = sat_add(run_excl[tile / g.chunk], tloc[tile]), wex = 0;
 #pragma unroll
-    for (int i = 0; i < MQ_WAVES; i++) {
-        off = sat_add(off, s_red[i]);
-        if ((uint32_t)i < w) wex += s_tmp[i];
-        ttot += s_tmp[i];
-    }
-    if (tile == ntiles - 1 && threadIdx.x == 0) *total = sat_add(off, ttot > SAT40 ? SAT40 : ttot);
+    for (int i = 0; i < MQ_WAVES; i++) wex += (uint32_t)i < w ? s_tmp[i] : 0ull;
     off = sat_add(off, wex > SAT40 ? SAT40 : wex);
 #pragma unroll
     for (int i = 0; i < COUNT_IPT; i++) {
@@ -358,18 +328,16 @@ __global__ __launch_bounds__(MQ_BLOCK) void count_write_kernel(uint32_t n, const
 hipError_t launch_seg_count(uint32_t n, const uint32_t* seg_start, const uint32_t* nseg, uint32_t max_seg,
                             const uint32_t* seg_split, uint64_t* seg_off, uint64_t* total, uint64_t* max_pairs,
                             void* scratch, hipStream_t stream) {
-    const RunGrid gh = run_grid((n + HEADS_TILE - 1) / HEADS_TILE);
-    const RunGrid g = run_grid(std::max(1u, (max_seg + COUNT_TILE - 1) / COUNT_TILE));
-    // after the heads pass's words, 8-byte aligned
-    uint64_t* run_tot = reinterpret_cast<uint64_t*>(
-        (reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(scratch) + gh.blocks + gh.ntiles) + 7) & ~uintptr_t(7));
-    uint64_t* run_max = run_tot + g.blocks;
-    uint64_t* tloc = run_max + g.blocks;
-    count_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, run_tot, run_max, tloc, g);
+    if (max_seg > n) return hipErrorInvalidValue;  // the scratch is laid out for n
+    const RunGrid g = count_grid(max_seg);
+    const SegScratch ss = seg_scratch(scratch, n);
+    count_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, ss.c_run, ss.c_max, ss.c_tloc,
+                                                       g);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_scan_runs(ss.c_run, g.blocks, total, nullptr, ss.c_max, max_pairs, stream);
     if (e != hipSuccess) return e;
-    count_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, run_tot, run_max, tloc, g,
-                                                         seg_off, total, max_pairs);
+    count_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(n, seg_start, nseg, seg_split, ss.c_run, ss.c_tloc, g,
+                                                         seg_off);
     return hipGetLastError();
 }
 

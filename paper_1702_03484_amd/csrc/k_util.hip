@@ -16,6 +16,55 @@ __global__ void fill_kernel(T* __restrict__ p, uint64_t n, T v) {
         p[i] = v;
 }
 
+constexpr uint32_t SCAN_RUNS_MAX = 4 * 256;
+
+__global__ __launch_bounds__(256) void scan_runs_kernel(uint64_t* __restrict__ tot, uint32_t nruns,
+                                                        uint64_t* __restrict__ total64,
+                                                        uint32_t* __restrict__ total32,
+                                                        const uint64_t* __restrict__ run_max,
+                                                        uint64_t* __restrict__ max_out) {
+    __shared__ uint64_t tmp[MQ_WAVES];
+    __shared__ uint64_t s_mx[MQ_WAVES];
+    uint64_t v[4], sum = 0, mx = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const uint32_t i = threadIdx.x * 4 + k;
+        v[k] = i < nruns ? tot[i] : 0ull;
+        sum += v[k];
+        if (run_max && i < nruns) mx = run_max[i] > mx ? run_max[i] : mx;
+    }
+    uint64_t all;
+    uint64_t ex = block_excl_scan<uint64_t>(sum, tmp, &all);  // each total < 2^41: no overflow
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const uint32_t i = threadIdx.x * 4 + k;
+        if (i < nruns) tot[i] = ex > SAT40 ? SAT40 : ex;
+        ex += v[k];
+    }
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor(mx, o);
+        mx = y > mx ? y : mx;
+    }
+    if (lane() == 0) s_mx[threadIdx.x / MQ_WAVE] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (total64) *total64 = all > SAT40 ? SAT40 : all;
+        if (total32) *total32 = (uint32_t)all;
+        if (run_max) {
+            for (int i = 0; i < MQ_WAVES; i++) mx = s_mx[i] > mx ? s_mx[i] : mx;
+            *max_out = mx;
+        }
+    }
+}
+
+hipError_t launch_scan_runs(uint64_t* tot, uint32_t nruns, uint64_t* total64, uint32_t* total32,
+                            const uint64_t* run_max, uint64_t* max_out, hipStream_t stream) {
+    if (nruns > SCAN_RUNS_MAX) return hipErrorInvalidValue;
+    scan_runs_kernel<<<1, 256, 0, stream>>>(tot, nruns, total64, total32, run_max, max_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     fill_kernel<uint32_t><<<grid_for(n, 256 * 4, 4096), 256, 0, stream>>>(p, n, v);

@@ -256,6 +256,12 @@ hipError_t launch_batch(const BatchHdr* hdr_dev, int rb, int kpt, int passes, hi
 uint32_t batch_chunk_rows();
 
 // ---- utilities (k_util.hip) -----------------------------------------------
+// Between the two passes of a two-pass scan: the run totals tot[0..nruns)
+// (nruns <= 1024) become their exclusive prefix sums, in place, capped at
+// 2^40 - 1; the sum goes to *total64 and/or *total32 (either may be null)
+// and, when run_max is given, the largest of run_max[0..nruns) to *max_out.
+hipError_t launch_scan_runs(uint64_t* tot, uint32_t nruns, uint64_t* total64, uint32_t* total32,
+                            const uint64_t* run_max, uint64_t* max_out, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t stream);
 // out[i] = src[idx[i]] - base

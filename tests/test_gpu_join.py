@@ -63,6 +63,33 @@ JOIN_CASES = [
 ]
 
 
+@pytest.mark.parametrize("hot", [(8, 8), (5, 13)])
+@pytest.mark.parametrize("vl,vr", [(1, 1), (2, 1)])
+def test_sparse_join_around_the_segment_major_bound(sess, hot, vl, vr):
+    """A sparse shuffled join (about one row per key) plus one hot key whose
+    product is 64 rows (segment-major materialisation) or 65 (row-chunk
+    kernel); value-carrying (1 + 1 columns) and id-payload (2 + 1) records."""
+    announce(f"sparse join, hot key {hot[0]}x{hot[1]}, vl={vl} vr={vr}")
+    r = np.random.default_rng(hot[0] * 100 + vl)
+    n = 200_003
+    keys = r.permutation(np.arange(1, 4 * n, 2))[:n].astype(np.int32)
+    lk = np.concatenate([keys, np.zeros(hot[0], np.int32)])
+    rk = np.concatenate([r.permutation(keys)[: n - 1000], np.zeros(hot[1], np.int32)])
+    lc = [lk] + [r.integers(0, 1 << 31, lk.size).astype(np.int32) for _ in range(vl)]
+    rc = [rk] + [r.integers(0, 1 << 31, rk.size).astype(np.int32) for _ in range(vr)]
+    lvars = [0] + list(range(10, 10 + vl))
+    rvars = [0] + list(range(20, 20 + vr))
+    sess.set_join_options(semijoin=1, merge=1)
+    try:
+        out = sess.join(sess.table(lvars, [dev(c) for c in lc]), sess.table(rvars, [dev(c) for c in rc]), 0)
+        exp = oracle.join(Table(lvars, lc), Table(rvars, rc), 0)
+        assert out.nrows == exp.n == n - 1000 + hot[0] * hot[1]
+        assert_same_bag(host_table(sess, out), exp)
+        sess.free(out)
+    finally:
+        sess.set_join_options(0, 0)
+
+
 @pytest.mark.parametrize("nl,nr,card,vl,vr,known", JOIN_CASES)
 def test_join_matches_oracle(sess, nl, nr, card, vl, vr, known):
     announce(f"join nl={nl} nr={nr} card={card} vl={vl} vr={vr} known={known}")
