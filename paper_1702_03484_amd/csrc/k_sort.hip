@@ -150,11 +150,25 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
     if (GEN) {
         // every load first (clamped into range), then the keys and payloads
         int32_t rk[KPT], rv[KPT];
+        if (base + (uint32_t)TILE <= src.n0 || base >= src.n0) {
+            // the whole tile on one side: loads from a uniform base
+            const bool right = base >= src.n0;
+            const uint32_t b0 = right ? base - src.n0 : base;
+            const int32_t* kt = (right ? src.k1 : src.k0) + b0;
+            const int32_t* vt = (right ? src.v1 : src.v0) + b0;
 #pragma unroll
-        for (int i = 0; i < KPT; i++) {
-            const uint32_t idx = min(base + (w * KPT + i) * MQ_WAVE + lane(), n - 1);
-            rk[i] = src_load(src.k0, src.k1, src.n0, idx);
-            rv[i] = src.carry ? src_load(src.v0, src.v1, src.n0, idx) : 0;
+            for (int i = 0; i < KPT; i++) {
+                const uint32_t off = min((w * KPT + i) * MQ_WAVE + lane(), valid_n - 1);
+                rk[i] = kt[off];
+                rv[i] = src.carry ? vt[off] : 0;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < KPT; i++) {
+                const uint32_t idx = min(base + (w * KPT + i) * MQ_WAVE + lane(), n - 1);
+                rk[i] = src_load(src.k0, src.k1, src.n0, idx);
+                rv[i] = src.carry ? src_load(src.v0, src.v1, src.n0, idx) : 0;
+            }
         }
 #pragma unroll
         for (int i = 0; i < KPT; i++) {
@@ -165,13 +179,15 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
             val[i] = ok ? (src.carry ? (uint32_t)rv[i] : idx) : 0u;
         }
     } else {
+        // from the tile's (uniform) base with 32-bit offsets: scalar-base loads
+        const uint32_t* kt = kin + base;
+        const uint32_t* vt = vin + base;
 #pragma unroll
         for (int i = 0; i < KPT; i++) {
             const uint32_t off = (w * KPT + i) * MQ_WAVE + lane();
-            const uint32_t idx = base + off;
             const bool ok = off < valid_n;
-            key[i] = ok ? kin[idx] : 0u;
-            val[i] = ok ? vin[idx] : 0u;
+            key[i] = ok ? kt[off] : 0u;
+            val[i] = ok ? vt[off] : 0u;
         }
     }
     sort_tile<RB, KPT>(sm, key, val, valid_n, shift, ghist, status, tile, 0, epoch, kout, vout);

@@ -78,7 +78,9 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t 
     scan_buckets<RB>(sm.goff, sm.goff, sm.tmp);
 
     // stable rank within the wave, digit by digit through the wave counters
-    uint32_t rank[KPT];
+    // (ranks are below the tile size, 2^16: two per register)
+    static_assert(MQ_BLOCK * KPT <= 65536 && KPT % 2 == 0, "16-bit ranks");
+    uint32_t rank2[KPT / 2];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int i = 0; i < KPT; i++) {
@@ -100,7 +102,10 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t 
         const uint32_t below = __popcll(peers & lt);
         const uint32_t old = ok ? sm.wcnt[w][dg] : 0u;
         if (ok && below == 0) sm.wcnt[w][dg] = old + (uint32_t)__popcll(peers);
-        rank[i] = old + below;
+        if (i % 2 == 0)
+            rank2[i / 2] = old + below;
+        else
+            rank2[i / 2] |= (old + below) << 16;
     }
     __syncthreads();
 
@@ -148,7 +153,7 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t 
         const uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
         if (off < valid_n) {
             const uint32_t dg = (key[i] >> shift) & R::MASK;
-            const uint32_t pos = sm.local[dg] + sm.wcnt[w][dg] + rank[i];
+            const uint32_t pos = sm.local[dg] + sm.wcnt[w][dg] + ((rank2[i / 2] >> (16 * (i % 2))) & 0xffffu);
             sm.keys[pos] = key[i];
             sm.vals[pos] = val[i];
         }
