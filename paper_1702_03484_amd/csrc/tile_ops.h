@@ -30,25 +30,29 @@ struct SortSmem {
 };
 
 // Exclusive scan of the BUCKETS values in LDS `in` into LDS `out` (may
-// alias).  Thread t owns the BPT consecutive buckets t*BPT...
+// alias), by wave 0 alone (lane L owns buckets L*PER ... L*PER + PER - 1),
+// then one barrier: the other waves only wait once.
 template <int RB>
 __device__ __forceinline__ void scan_buckets(const uint32_t* in, uint32_t* out, uint32_t* tmp) {
     using R = Radix<RB>;
-    uint32_t loc[R::BPT];
-    uint32_t sum = 0;
+    constexpr int PER = (R::BUCKETS + MQ_WAVE - 1) / MQ_WAVE;
+    (void)tmp;
+    if (threadIdx.x < MQ_WAVE) {
+        uint32_t loc[PER];
+        uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < R::BPT; k++) {
-        uint32_t d = threadIdx.x * R::BPT + k;
-        loc[k] = d < (uint32_t)R::BUCKETS ? in[d] : 0u;
-        sum += loc[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(sum, tmp, &tot);
+        for (int k = 0; k < PER; k++) {
+            const uint32_t d = lane() * PER + k;
+            loc[k] = d < (uint32_t)R::BUCKETS ? in[d] : 0u;
+            sum += loc[k];
+        }
+        uint32_t ex = wave_incl_scan(sum) - sum;
 #pragma unroll
-    for (int k = 0; k < R::BPT; k++) {
-        uint32_t d = threadIdx.x * R::BPT + k;
-        if (d < (uint32_t)R::BUCKETS) out[d] = ex;
-        ex += loc[k];
+        for (int k = 0; k < PER; k++) {
+            const uint32_t d = lane() * PER + k;
+            if (d < (uint32_t)R::BUCKETS) out[d] = ex;
+            ex += loc[k];
+        }
     }
     __syncthreads();
 }
