@@ -105,8 +105,9 @@ def phase_table(prof):
 def run_shuffle(n=16_000_000, key_bits=24, reps=5):
     """The shuffle path on its own: a join of two n-row tables with uniform
     random keys over 2^key_bits values and one value column each, with the
-    merge join and the semi-join reduction turned off, so every record goes
-    through the histogram, radix passes, segment heads and counts."""
+    merge join, the semi-join reduction and the exact count before sorting
+    turned off, so every record goes through the histogram, radix passes,
+    segment heads and counts, and nothing else is timed."""
     import numpy as np
     import torch
 
@@ -119,7 +120,7 @@ def run_shuffle(n=16_000_000, key_bits=24, reps=5):
         vals = [torch.from_numpy(r.integers(0, 1 << 31, n).astype(np.int32)).cuda() for _ in range(2)]
         L = sess.table([0, 1], [cols[0], vals[0]], key_max=(1 << key_bits) - 1)
         R = sess.table([0, 2], [cols[1], vals[1]], key_max=(1 << key_bits) - 1)
-        sess.set_join_options(semijoin=1, merge=1)
+        sess.set_join_options(semijoin=1, merge=1, precount=1)
         for _ in range(2):
             sess.free(sess.join(L, R, 0))
         torch.cuda.synchronize()
@@ -134,7 +135,7 @@ def run_shuffle(n=16_000_000, key_bits=24, reps=5):
         st = sess.stats()
         phases = phase_table(B.mapsq_profile_read(sess.ctx))
     return {"workload": f"join of two {n}-row tables, uniform keys over 2^{key_bits}, one value column each, "
-                       "merge join and semi-join off", "records": 2 * n, "rows": rows, "radix_bits": st.radix_bits,
+                       "merge join, semi-join and exact pre-count off", "records": 2 * n, "rows": rows, "radix_bits": st.radix_bits,
             "passes": st.passes, "ms_per_join": round(el * 1e3, 3), "phases": phases}
 
 

@@ -264,12 +264,11 @@ mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_p
  *   key column), 1 = never, 2 = whenever the bitmap fits in 1 GiB.
  * merge: 0 = pair the key runs directly when both tables are sorted on the
  *   key (sorted_col), 1 = always shuffle.
- * precount: before a shuffle of at least 2^24 records, count |RS| exactly
- *   from dense per-key counts (two passes over the keys), so that a join
- *   with no key in common, or whose result cannot fit in the arena, ends
- *   without sorting.  0 = automatic (only for the join steps that
- *   mapsq_serve_step runs through the single-join path), 1 = never,
- *   2 = always.  Without it the same outcome comes after the sort.
+ * precount: before a shuffle, count |RS| exactly from dense per-key counts
+ *   (two passes over the keys), so that a join with no key in common, or
+ *   whose result cannot fit in the arena, ends without sorting.  0 =
+ *   automatic (shuffles of at least 2^24 records), 1 = never, 2 = every
+ *   shuffle.  Without it the same outcome comes after the sort.
  * INVALID_ARG for other values. */
 mapsq_status mapsq_set_join_options(mapsq_ctx* ctx, int32_t semijoin, int32_t merge, int32_t precount);
 

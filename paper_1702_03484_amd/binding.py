@@ -273,9 +273,9 @@ def mapsq_last_join_stats(ctx) -> mapsq_join_stats:
 
 def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0, precount: int = 0):
     """semijoin: 0 automatic, 1 never, 2 always; merge: 0 when both sides are
-    sorted on the key, 1 never; precount (exact |RS| before shuffles of 2^24+
-    records): 0 serving steps only, 1 never, 2 always.  Every choice gives the
-    same rows in the same order."""
+    sorted on the key, 1 never; precount (exact |RS| before sorting): 0 for
+    shuffles of 2^24+ records, 1 never, 2 always.  Every choice gives the same
+    rows in the same order."""
     _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge, precount))
 
 

@@ -939,14 +939,13 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     int rb, kpt;
     pick_tuning(ctx, key_bits, rb, kpt, (uint64_t)nL + nR);
 
-    // A large shuffle may first get the exact |RS| from two passes over the
+    // A large shuffle first gets the exact |RS| from two passes over the
     // keys (dense key counts of one side, summed over the other side's
     // records): a join with no key in common, or whose output cannot fit in
     // the arena's free space at all, then ends without sorting anything.
-    // It costs about as much as the count phase after the sort, so by
-    // default only the server's steps (which may fail and retry) use it.
-    const bool precount = ctx->precount == 2 || (ctx->precount == 0 && ctx->serving_step);
-    if (precount && (uint64_t)N >= PRECOUNT_MIN_RECORDS) {
+    // On a join that fits it costs about as much as the count phase.
+    const bool precount = ctx->precount == 2 || (ctx->precount == 0 && (uint64_t)N >= PRECOUNT_MIN_RECORDS);
+    if (precount) {
         const uint64_t range = (uint64_t)((int64_t)kmax - (int64_t)kmin) + 1;
         Block cnt;
         if (range <= PRECOUNT_MAX_RANGE) cnt = alloc_block(ctx, size_t(range) * 4);

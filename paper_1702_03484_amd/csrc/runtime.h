@@ -107,8 +107,7 @@ struct Ctx {
     int32_t tune_rb = 0, tune_kpt = 0;
     int32_t semijoin = 0;    // 0 automatic, 1 never, 2 always
     int32_t merge_mode = 0;  // 0 merge join of key-sorted tables, 1 never
-    int32_t precount = 0;    // exact |RS| before large shuffles: 0 serving steps, 1 never, 2 always
-    bool serving_step = false;  // set while the server runs a step through join_tables
+    int32_t precount = 0;    // exact |RS| before shuffles: 0 of 2^24+ records, 1 never, 2 always
     // autotuned choices: (key bits << 8 | log2 records) -> (rb << 8 | kpt)
     std::map<uint32_t, uint32_t> tuned;
     mapsq_join_stats last{};

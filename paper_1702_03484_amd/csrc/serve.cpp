@@ -432,9 +432,7 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     for (SQuery* q : in_plain) {
         const PlanStep& ps = q->steps[q->next];
         mapsq_table nxt{};
-        ctx->serving_step = true;
         st = join_tables(ctx, &q->cur, &q->tabs[ps.pick], ps.key, &nxt);
-        ctx->serving_step = false;
         if (st)
             failed(q, st, ctx->last.out_rows);
         else

@@ -87,7 +87,7 @@ class MapSQ:
 
     def set_join_options(self, semijoin: int = 0, merge: int = 0, precount: int = 0):
         """semijoin 0 automatic / 1 never / 2 always; merge 0 automatic / 1 never;
-        precount 0 serving steps / 1 never / 2 always."""
+        precount 0 shuffles of 2^24+ records / 1 never / 2 always."""
         B.mapsq_set_join_options(self.ctx, semijoin, merge, precount)
     def table(self, vars, tensors, key_max: int = -1, sorted_col: int = 0) -> B.mapsq_table:
         """Wrap caller-owned int32 device tensors (kept alive by this session);
