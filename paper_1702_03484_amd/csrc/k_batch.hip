@@ -165,7 +165,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void bcount_kernel(BatchHdr* __restrict__
         if (lt * TILE >= ns) continue;  // beyond the join's segments (block-uniform)
         const uint32_t last = (ns + TILE - 1) / TILE - 1;
         count_tile<KPT>(sm, J.nl + J.nr, ns, lt * TILE, t, J.tile_off, lt == last, h->keys[1 - fin] + J.rec_off,
-                        h->vals[1 - fin] + J.rec_off, h->seg_off + J.rec_off, &J.total, h->status, epoch);
+                        h->vals[1 - fin] + J.rec_off, h->seg_off + J.rec_off, &J.total, h->status, epoch,
+                        &J.max_pairs);
     }
 }
 
@@ -179,11 +180,14 @@ __global__ __launch_bounds__(MQ_BLOCK) void bplace_kernel(BatchHdr* __restrict__
     for (uint32_t b = 0; b < nj; b += MQ_BLOCK) {
         const uint32_t j = b + threadIdx.x;
         uint64_t words = 0, cw = 0, tot = 0;
-        uint32_t st = 0;
+        uint32_t st = 0, ns = 0;
+        bool seg = false;
         int nc = 0;
         if (j < nj) {
             const BatchJoin& J = h->joins[j];
             tot = J.total;
+            ns = J.nseg;
+            seg = mat_seg_use(tot, ns, J.max_pairs);
             nc = 1 + J.nvl + J.nvr;
             if (tot >= SAT40) {
                 st = 2;
@@ -196,12 +200,14 @@ __global__ __launch_bounds__(MQ_BLOCK) void bplace_kernel(BatchHdr* __restrict__
         const uint64_t wex = block_excl_scan<uint64_t>(words, s_tmp, &wsum);
         const uint64_t at = run_words + wex;
         if (st == 0 && at + words > h->out_cap_words) st = 1;
-        const uint64_t chunks = (st == 0) ? (tot + BMAT_WROWS - 1) / BMAT_WROWS : 0;
+        // work items: groups of 64 keys (segment-major) or chunks of rows
+        const uint64_t chunks = st != 0 ? 0 : (seg ? (ns + MQ_WAVE - 1) / MQ_WAVE : (tot + BMAT_WROWS - 1) / BMAT_WROWS);
         uint64_t csum;
         const uint64_t cex = block_excl_scan<uint64_t>(chunks, s_tmp, &csum);
         if (j < nj) {
             BatchJoin& J = h->joins[j];
             J.status = st;
+            J.seg_major = seg ? 1u : 0u;
             J.out_word = at;
             J.col_words = cw;
             J.chunk_off = run_chunks + cex;
@@ -264,6 +270,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void bgather_kernel(const BatchHdr* __res
 
 // Materialisation of every join of the batch: chunks strided over the
 // waves, each chunk's join found by a 64-ary search over the joins.
+static_assert(MAT_SEG_LDS_WORDS <= (int)MAT_LDS_SEGS, "a wave's LDS rows hold a key group");
+
 __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restrict__ h) {
     __shared__ uint64_t s_segs[MQ_WAVES][MAT_LDS_SEGS];
     const uint64_t nchunks = h->total_chunks;
@@ -298,6 +306,10 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
                 const int sc = col <= J.nvl ? col - 1 : col - 1 - J.nvl;
                 mj.ssrc[col] = mj.sorted_vals && sc < (int)h->nsval ? h->sval[sc] + J.rec_off : nullptr;
             }
+        }
+        if (J.seg_major) {
+            mat_seg_group<BATCH_MAXNC, -1>(mj, (uint32_t)(c - J.chunk_off), J.total, s_segs[threadIdx.x / MQ_WAVE]);
+            continue;
         }
         const uint64_t j0 = (c - J.chunk_off) * BMAT_WROWS;
         uint32_t hint = 0;  // chunks of a wave may belong to different joins

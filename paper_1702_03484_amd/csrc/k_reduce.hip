@@ -403,83 +403,16 @@ __global__ __launch_bounds__(MQ_BLOCK) void materialize_kernel(MatArgs a) {
     }
 }
 
-// Segment-major materialisation of sparse outputs (every key product at
-// most MAT_SEG_MAX_PAIRS): one wave per group of 64 consecutive segments.
-// The group's starts, splits, offsets and keys are loaded once, coalesced,
-// into LDS; its rows (at most 64 * MAT_SEG_MAX_PAIRS) go out lane-strided,
-// each row finding its segment by a binary search over the group's
-// offsets, so consecutive lanes store consecutive rows.
+// Segment-major materialisation (mat_seg_group): one wave per group of 64
+// keys, for outputs whose key products are small.
 template <int NC, int NLC>
 __global__ __launch_bounds__(MQ_BLOCK) void mat_seg_kernel(MatArgs a) {
-    __shared__ uint64_t s_off[MQ_WAVES][MQ_WAVE + 1];
-    __shared__ uint32_t s_st[MQ_WAVES][MQ_WAVE];
-    __shared__ uint32_t s_sp[MQ_WAVES][MQ_WAVE];
-    __shared__ uint32_t s_en[MQ_WAVES][MQ_WAVE];
-    __shared__ int32_t s_key[MQ_WAVES][MQ_WAVE];
+    __shared__ uint64_t s_grp[MQ_WAVES][MAT_SEG_LDS_WORDS];
     const MatJoin mj = mat_join_of<NC, NLC>(a);
-    const int nl = NLC >= 0 ? NLC : mj.nl, nr = NLC >= 0 ? NC - 1 - NLC : mj.nr;
-    const int nc = 1 + nl + nr;
-    const uint32_t w = threadIdx.x / MQ_WAVE;
-    const uint32_t ns = mj.ns;
-    const uint32_t ngroups = (ns + MQ_WAVE - 1) / MQ_WAVE;
+    const uint32_t ngroups = (mj.ns + MQ_WAVE - 1) / MQ_WAVE;
     const uint32_t nw = gridDim.x * MQ_WAVES;
-    for (uint32_t grp = blockIdx.x * MQ_WAVES + w; grp < ngroups; grp += nw) {
-        const uint32_t s0 = grp * MQ_WAVE;
-        const uint32_t s = s0 + lane();
-        const bool in = s < ns;
-        const uint32_t st = in ? mj.seg_start[s] : mj.n;
-        const uint32_t sp = in ? mj.seg_split[s] : mj.n;
-        uint32_t en = __shfl_down(st, 1, MQ_WAVE);
-        if (lane() == MQ_WAVE - 1 && s + 1 < ns) en = mj.seg_start[s + 1];
-        if (s + 1 >= ns) en = mj.n;
-        // segments past the end sit at the end of the output: no row finds them
-        const uint64_t off = in ? mj.seg_off[s] : a.row_end;
-        const uint64_t off_end = s0 + MQ_WAVE < ns ? mj.seg_off[s0 + MQ_WAVE] : a.row_end;
-        const int32_t key = in ? (int32_t)((mj.keys[st] >> mj.key_shift) + (uint32_t)mj.key_base) : 0;
-        __builtin_amdgcn_wave_barrier();  // the previous group's reads of the LDS rows are done
-        s_off[w][lane()] = off;
-        if (lane() == 0) s_off[w][MQ_WAVE] = off_end;
-        s_st[w][lane()] = st;
-        s_sp[w][lane()] = sp;
-        s_en[w][lane()] = en;
-        s_key[w][lane()] = key;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint64_t off0 = s_off[w][0];
-        const uint32_t rows = (uint32_t)(off_end - off0);
-        for (uint32_t r = lane(); r < rows; r += MQ_WAVE) {
-            const uint64_t j = off0 + r;
-            // the last segment of the group starting at or before row j
-            // (empty segments share the next one's offset and lose the tie)
-            uint32_t lo = 0, hi = MQ_WAVE - 1;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (s_off[w][mid] <= j) lo = mid;
-                else hi = mid - 1;
-            }
-            const uint32_t kst = s_st[w][lo], ksp = s_sp[w][lo], ken = s_en[w][lo];
-            const uint32_t cl = ksp - kst, cr = ken - ksp;
-            const bool left_in = left_inner_of(cl, cr, nl, nr);
-            const uint32_t ci = left_in ? cl : cr;
-            const uint32_t rr = (uint32_t)(j - s_off[w][lo]);  // < MAT_SEG_MAX_PAIRS
-            const uint32_t outer = rr / ci, inner = rr - outer * ci;
-            const uint32_t lpos = kst + (left_in ? inner : outer);
-            const uint32_t rpos = ksp + (left_in ? outer : inner);
-            mj.out[0][j] = s_key[w][lo];
-            if (mj.sorted_vals) {
-#pragma unroll
-                for (int col = 1; col < NC; col++)
-                    if (col < nc) mj.out[col][j] = mj.ssrc[col][col <= nl ? lpos : rpos];
-            } else {
-                const uint32_t lrow = nl > 0 ? mj.vals[lpos] : 0u;
-                const uint32_t rrow = nc - 1 > nl ? mj.vals[rpos] - mj.n_left : 0u;
-#pragma unroll
-                for (int col = 1; col < NC; col++)
-                    if (col < nc) mj.out[col][j] = mj.src[col][col <= nl ? lrow : rrow];
-            }
-        }
-    }
+    for (uint32_t grp = blockIdx.x * MQ_WAVES + threadIdx.x / MQ_WAVE; grp < ngroups; grp += nw)
+        mat_seg_group<NC, NLC>(mj, grp, a.row_end, s_grp[threadIdx.x / MQ_WAVE]);
 }
 
 // One pass over the sorted records: every record's value columns move into

@@ -1134,7 +1134,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     a.row_begin = 0;
     a.row_end = total;
     a.sparse = total < SPARSE_ROWS_PER_SEG * (uint64_t)nseg ? 1 : 0;
-    a.seg_major = a.sparse && max_pairs <= MAT_SEG_MAX_PAIRS ? 1 : 0;
+    a.seg_major = mat_seg_use(total, nseg, max_pairs) ? 1 : 0;
     a.seg_count = nseg;
     // values in sorted record order when output rows outnumber records
     // (each record's values are then read many times)

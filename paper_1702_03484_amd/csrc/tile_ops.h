@@ -249,6 +249,7 @@ __device__ __forceinline__ void heads_tile(HeadsSmem& sm, const uint32_t* __rest
 
 struct CountSmem {
     uint64_t tmp[MQ_WAVES];
+    uint64_t mx[MQ_WAVES];
     uint64_t excl;
 };
 
@@ -260,10 +261,10 @@ __device__ __forceinline__ void count_tile(CountSmem& sm, uint32_t n, uint32_t n
                                            const uint32_t* __restrict__ seg_start,
                                            const uint32_t* __restrict__ seg_split, uint64_t* __restrict__ seg_off,
                                            uint64_t* __restrict__ total, uint64_t* __restrict__ status,
-                                           uint32_t epoch) {
+                                           uint32_t epoch, uint64_t* __restrict__ max_pairs) {
     const uint32_t first = base + threadIdx.x * IPT;
     uint64_t cnt[IPT];
-    uint64_t sum = 0;
+    uint64_t sum = 0, mx = 0;
 #pragma unroll
     for (int i = 0; i < IPT; i++) {
         const uint32_t s = first + i;
@@ -276,7 +277,15 @@ __device__ __forceinline__ void count_tile(CountSmem& sm, uint32_t n, uint32_t n
             cnt[i] = c > SAT40 ? SAT40 : c;
         }
         sum += cnt[i];
+        mx = cnt[i] > mx ? cnt[i] : mx;
     }
+    // the tile's largest count raises the join's maximum (one atomic per tile)
+#pragma unroll
+    for (int o = MQ_WAVE / 2; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor(mx, o);
+        mx = y > mx ? y : mx;
+    }
+    if (lane() == 0) sm.mx[threadIdx.x / MQ_WAVE] = mx;
     uint64_t ttot;
     const uint64_t ex_in = block_excl_scan<uint64_t>(sum, sm.tmp, &ttot);
     if (threadIdx.x < MQ_WAVE) {
@@ -287,6 +296,12 @@ __device__ __forceinline__ void count_tile(CountSmem& sm, uint32_t n, uint32_t n
         }
     }
     __syncthreads();
+    if (threadIdx.x == 0 && max_pairs) {
+        uint64_t m = 0;
+#pragma unroll
+        for (int w = 0; w < MQ_WAVES; w++) m = sm.mx[w] > m ? sm.mx[w] : m;
+        atomicMax(reinterpret_cast<unsigned long long*>(max_pairs), (unsigned long long)m);
+    }
     uint64_t off = sm.excl + ex_in;
 #pragma unroll
     for (int i = 0; i < IPT; i++) {
@@ -650,6 +665,83 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
         }
     }
     hint = s;
+}
+
+// Segment-major materialisation of one group of 64 consecutive keys
+// [64 * grp, 64 * grp + 64) for outputs whose key products are small: the
+// group's starts, splits, offsets and output keys are loaded once,
+// coalesced, into the wave's LDS rows; its rows (at most 64 times the
+// largest product) go out lane-strided, each row finding its key by a
+// binary search over the group's offsets, so consecutive lanes store
+// consecutive rows.  row_end = |RS|.  lds: MAT_SEG_LDS_WORDS words of this
+// wave's LDS.  Every lane of the wave calls it.
+constexpr int MAT_SEG_LDS_WORDS = MQ_WAVE + 1 + 2 * MQ_WAVE;  // offsets, then 4 x 64 u32
+
+template <int NC, int NLC>
+__device__ __forceinline__ void mat_seg_group(const MatJoin& mj, uint32_t grp, uint64_t row_end, uint64_t* lds) {
+    const int nl = NLC >= 0 ? NLC : mj.nl, nr = NLC >= 0 ? NC - 1 - NLC : mj.nr;
+    const int nc = 1 + nl + nr;
+    uint64_t* s_off = lds;
+    uint32_t* s_st = reinterpret_cast<uint32_t*>(lds + MQ_WAVE + 1);
+    uint32_t* s_sp = s_st + MQ_WAVE;
+    uint32_t* s_en = s_sp + MQ_WAVE;
+    int32_t* s_key = reinterpret_cast<int32_t*>(s_en + MQ_WAVE);
+    const uint32_t ns = mj.ns;
+    const uint32_t s0 = grp * MQ_WAVE;
+    const uint32_t s = s0 + lane();
+    const bool in = s < ns;
+    const uint32_t st = in ? mj.seg_start[s] : mj.n;
+    const uint32_t sp = in ? mj.seg_split[s] : mj.n;
+    uint32_t en = __shfl_down(st, 1, MQ_WAVE);
+    if (lane() == MQ_WAVE - 1 && s + 1 < ns) en = mj.seg_start[s + 1];
+    if (s + 1 >= ns) en = mj.n;
+    // keys past the end sit at the end of the output: no row finds them
+    const uint64_t off = in ? mj.seg_off[s] : row_end;
+    const uint64_t off_end = s0 + MQ_WAVE < ns ? mj.seg_off[s0 + MQ_WAVE] : row_end;
+    const int32_t key = in ? (int32_t)((mj.keys[st] >> mj.key_shift) + (uint32_t)mj.key_base) : 0;
+    __builtin_amdgcn_wave_barrier();  // the previous group's reads of these LDS rows are done
+    s_off[lane()] = off;
+    if (lane() == 0) s_off[MQ_WAVE] = off_end;
+    s_st[lane()] = st;
+    s_sp[lane()] = sp;
+    s_en[lane()] = en;
+    s_key[lane()] = key;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t off0 = s_off[0];
+    const uint32_t rows = (uint32_t)(off_end - off0);
+    for (uint32_t r = lane(); r < rows; r += MQ_WAVE) {
+        const uint64_t j = off0 + r;
+        // the last key of the group starting at or before row j (empty keys
+        // share the next one's offset and lose the tie)
+        uint32_t lo = 0, hi = MQ_WAVE - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t kst = s_st[lo], ksp = s_sp[lo], ken = s_en[lo];
+        const uint32_t cl = ksp - kst, cr = ken - ksp;
+        const bool left_in = left_inner_of(cl, cr, nl, nr);
+        const uint32_t ci = left_in ? cl : cr;
+        const uint32_t rr = (uint32_t)(j - s_off[lo]);  // below the key's product
+        const uint32_t outer = rr / ci, inner = rr - outer * ci;
+        const uint32_t lpos = kst + (left_in ? inner : outer);
+        const uint32_t rpos = ksp + (left_in ? outer : inner);
+        mj.out[0][j] = s_key[lo];
+        if (mj.sorted_vals) {
+#pragma unroll
+            for (int col = 1; col < NC; col++)
+                if (col < nc) mj.out[col][j] = mj.ssrc[col][col <= nl ? lpos : rpos];
+        } else {
+            const uint32_t lrow = nl > 0 ? mj.vals[lpos] : 0u;
+            const uint32_t rrow = nc - 1 > nl ? mj.vals[rpos] - mj.n_left : 0u;
+#pragma unroll
+            for (int col = 1; col < NC; col++)
+                if (col < nc) mj.out[col][j] = mj.src[col][col <= nl ? lrow : rrow];
+        }
+    }
 }
 
 }  // namespace mq

@@ -69,6 +69,30 @@ def test_batch_matches_oracle_and_plain(sess):
         sess.free(t)
 
 
+def test_batch_sparse_joins_segment_major(sess):
+    """Sparse joins (about one output row per key; segment-major work items)
+    beside one with a 65-row key (row chunks), 0-3 value columns a side,
+    against the oracle and row for row against mapsq_join."""
+    announce("batch of sparse joins (segment-major work items)")
+    r = np.random.default_rng(5)
+    joins, host = [], []
+    for i, (n, hot, vl, vr) in enumerate([(50_000, (8, 8), 1, 1), (120_000, (5, 13), 2, 1), (3_000, (1, 1), 0, 3),
+                                          (70_001, (8, 8), 3, 2), (999, (2, 3), 1, 0)]):
+        keys = r.permutation(np.arange(1, 4 * n, 2))[:n].astype(np.int32)
+        lk = np.concatenate([keys, np.zeros(hot[0], np.int32)])
+        rk = np.concatenate([r.permutation(keys)[: n - n // 10], np.zeros(hot[1], np.int32)])
+        lc = [lk] + [r.integers(0, 1 << 31, lk.size).astype(np.int32) for _ in range(vl)]
+        rc = [rk] + [r.integers(0, 1 << 31, rk.size).astype(np.int32) for _ in range(vr)]
+        lv = [0] + [10 + k for k in range(vl)]
+        rv = [0] + [20 + k for k in range(vr)]
+        joins.append((sess.table(lv, [dev(c) for c in lc]), sess.table(rv, [dev(c) for c in rc]), 0))
+        host.append((Table(lv, lc), Table(rv, rc)))
+    outs = sess.join_batch(joins)
+    check_against_plain_and_oracle(sess, joins, host, outs)
+    for t in outs:
+        sess.free(t)
+
+
 def test_batch_graph_replay_and_direct_launch_agree(sess, monkeypatch):
     announce("batch: graph replays and direct launches agree")
     joins, host = make_batch(sess, 2, 25, max_rows=100_000)
