@@ -320,9 +320,19 @@ __device__ __forceinline__ void count_tile(CountSmem& sm, uint32_t n, uint32_t n
 // 16-byte stores.
 
 // last s in [lo, hi] with off[s] <= j; off is non-decreasing and off[lo] <= j.
-// Wave-uniform arguments; every lane of the wave must call it.
+// Wave-uniform arguments; every lane of the wave must call it.  near: the
+// answer is likely within 64 of lo, so the 64 offsets from lo are probed
+// first (one round trip when it is) before the 64-ary search of the rest.
 __device__ __forceinline__ uint32_t wave_seg_of(const uint64_t* __restrict__ off, uint32_t lo, uint32_t hi,
-                                                uint64_t j) {
+                                                uint64_t j, bool near = false) {
+    if (near && hi > lo) {
+        const uint32_t pos = lo + lane();
+        const bool ok = pos <= hi && off[pos] <= j;
+        const uint64_t m = __ballot(ok);  // a prefix of lanes, lane 0 always set
+        const uint32_t top = 63u - (uint32_t)__clzll(m);
+        if (top < MQ_WAVE - 1 || hi - lo <= MQ_WAVE - 1) return lo + top;
+        lo += MQ_WAVE - 1;  // off[lo + 63] <= j: the answer is at or past it
+    }
     while (hi > lo) {
         const uint32_t step = (hi - lo + MQ_WAVE) / MQ_WAVE;  // ceil(span / 64)
         const uint32_t pos = lo + lane() * step;
@@ -631,7 +641,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
             // the sub-chunk's last segment (every lane takes part in the
             // search), then each lane's own segment and rows
             const uint64_t jlast = (jend < jq + 4 * MQ_WAVE ? jend : jq + 4 * MQ_WAVE) - 1;
-            const uint32_t s_last = wave_seg_of(a.seg_off, s, a.ns - 1, jlast);
+            const uint32_t s_last = wave_seg_of(a.seg_off, s, a.ns - 1, jlast, true);
             // many segments (a sparse stretch of the output): their offsets in
             // LDS, so that each lane's searches stay on chip
             const uint32_t m = s_last - s + 1;
