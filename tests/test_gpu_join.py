@@ -122,6 +122,33 @@ def test_join_high_ids_and_negative_base(sess):
     sess.free(out)
 
 
+@pytest.mark.parametrize("lo,hi", [(0, (1 << 31) - 2), (-(1 << 31), (1 << 31) - 1), (-5, 4)])
+@pytest.mark.parametrize("vl,vr", [(1, 1), (0, 2)])
+def test_join_key_range_extremes(sess, lo, hi, vl, vr):
+    """Key ranges of 31 bits (values carried, 32-bit sort keys with the side
+    bit), the full 32 bits (record positions instead) and a tiny negative
+    range; keys at both ends of the range occur on both sides."""
+    announce(f"join keys in [{lo}, {hi}] vl={vl} vr={vr}")
+    r = np.random.default_rng(abs(lo) % 1000 + hi % 1000 + vl)
+    mid = r.integers(lo, hi, size=3000, endpoint=True)
+    keys = np.unique(np.concatenate([[lo, hi, lo + 1, hi - 1], mid])).astype(np.int64)
+    lc = random_table(11 + vl, 40_000, keys.size, vl, key_ids=keys.astype(np.int32))
+    rc = random_table(12 + vr, 30_000, keys.size, vr, key_ids=keys.astype(np.int32))
+    lc[0][:2] = [lo, hi]
+    rc[0][:2] = [hi, lo]
+    lv = [0] + [10 + k for k in range(vl)]
+    rv = [0] + [20 + k for k in range(vr)]
+    sess.set_join_options(semijoin=1, merge=1)
+    try:
+        out = sess.join(sess.table(lv, [dev(c) for c in lc]), sess.table(rv, [dev(c) for c in rc]), 0)
+        exp = oracle.join(Table(lv, lc), Table(rv, rc), 0)
+        assert out.nrows == exp.n
+        assert_same_bag(host_table(sess, out), exp)
+        sess.free(out)
+    finally:
+        sess.set_join_options(0, 0)
+
+
 def test_join_further_shared_variable(sess):
     announce("join with a second shared variable (equality filter)")
     keys = keyset(3, 500)
