@@ -359,13 +359,14 @@ constexpr int MAT_MAXNC = 16;
 
 // One join as seen by materialisation.  Output column c >= 1 takes its
 // values from src[c] (a LEFT value column when c <= nl, else a RIGHT one),
-// indexed by record id, or, when ssrc[c] is set, from ssrc[c] indexed by
-// sorted record position (values gathered into sorted order beforehand).
+// indexed by record id, or, when sorted_vals is set, from ssrc[c] indexed
+// by sorted record position (values gathered into sorted order beforehand,
+// or carried through the sort as the payload itself).
 // Held by value and indexed only with compile-time column numbers, so the
 // pointers stay in registers.
 struct MatJoin {
     const uint32_t* keys;  // sorted relative keys
-    const uint32_t* vals;  // sorted payloads (record ids)
+    const uint32_t* vals;  // sorted payloads (record ids unless values were carried)
     const uint32_t* seg_start;
     const uint32_t* seg_split;
     const uint64_t* seg_off;
