@@ -436,6 +436,11 @@ def test_invalid_arguments(sess):
     with pytest.raises(B.MapSQError) as ei:
         B.mapsq_set_tuning(sess.ctx, 3, 0)
     assert ei.value.code == B.MAPSQ_ERR_INVALID_ARG
+    for bad in [(3, 0, 0), (0, 2, 0), (0, 0, 3), (-1, 0, 0), (0, 0, -1)]:
+        with pytest.raises(B.MapSQError) as ei:
+            B.mapsq_set_join_options(sess.ctx, *bad)
+        assert ei.value.code == B.MAPSQ_ERR_INVALID_ARG, bad
+    B.mapsq_set_join_options(sess.ctx, 0, 0, 0)
 
 
 # ----------------------------------------------------------------------- map
