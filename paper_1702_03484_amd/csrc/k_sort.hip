@@ -130,16 +130,21 @@ __global__ __launch_bounds__(HRED_WAVES * MQ_WAVE) void hist_reduce_kernel(const
 
 uint32_t radix_hist_part_words(int rb, int passes) { return HIST_BLOCKS * (uint32_t)passes << rb; }
 
-template <int RB, int KPT, bool GEN>
-__global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const uint32_t* __restrict__ kin,
-                                                              const uint32_t* __restrict__ vin,
-                                                              uint32_t* __restrict__ kout,
-                                                              uint32_t* __restrict__ vout, uint32_t n, int shift,
-                                                              const uint32_t* __restrict__ ghist,
-                                                              uint64_t* __restrict__ status,
-                                                              uint32_t* __restrict__ tile_ctr, uint32_t epoch) {
-    constexpr int TILE = MQ_BLOCK * KPT;
-    __shared__ SortSmem<RB, KPT> sm;
+// Waves per block of a radix pass: 8 (8,192-record tiles, half the tile-id
+// atomics and look-backs of 4-wave blocks; two blocks still fit a CU's LDS)
+// for digits of up to 8 bits at 16 keys per thread, else 4.
+__host__ __device__ constexpr int sort_waves(int rb, int kpt) { return rb <= 8 && kpt == 16 ? 8 : 4; }
+
+template <int RB, int KPT, bool GEN, int NW = sort_waves(RB, KPT)>
+__global__ __launch_bounds__(NW * MQ_WAVE) void radix_pass_kernel(SortSrc src, const uint32_t* __restrict__ kin,
+                                                                  const uint32_t* __restrict__ vin,
+                                                                  uint32_t* __restrict__ kout,
+                                                                  uint32_t* __restrict__ vout, uint32_t n, int shift,
+                                                                  const uint32_t* __restrict__ ghist,
+                                                                  uint64_t* __restrict__ status,
+                                                                  uint32_t* __restrict__ tile_ctr, uint32_t epoch) {
+    constexpr int TILE = NW * MQ_WAVE * KPT;
+    __shared__ SortSmem<RB, KPT, NW> sm;
     __shared__ uint32_t s_tile;
     const uint32_t tile = next_tile(tile_ctr, &s_tile);
     const uint32_t base = tile * (uint32_t)TILE;
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void radix_pass_kernel(SortSrc src, const
             val[i] = ok ? vt[off] : 0u;
         }
     }
-    sort_tile<RB, KPT>(sm, key, val, valid_n, shift, ghist, status, tile, 0, epoch, kout, vout);
+    sort_tile<RB, KPT, NW>(sm, key, val, valid_n, shift, ghist, status, tile, 0, epoch, kout, vout);
 }
 
 #define MQ_RB_LIST(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
@@ -225,13 +230,14 @@ hipError_t launch_radix_pass(int rb, int kpt, const SortSrc& src, const uint32_t
     int shift = pass * rb;
 #define MQ_P(B, K)                                                                                          \
     {                                                                                                       \
-        uint32_t tiles = (n + MQ_BLOCK * K - 1) / (MQ_BLOCK * K);                                           \
+        constexpr uint32_t NT = sort_waves(B, K) * MQ_WAVE;                                                 \
+        uint32_t tiles = radix_tiles(n, K, B);                                                              \
         if (gen)                                                                                            \
-            radix_pass_kernel<B, K, true><<<tiles, MQ_BLOCK, 0, stream>>>(src, kin, vin, kout, vout, n, shift, \
-                                                                          hist_pass, status, tile_ctr, epoch); \
+            radix_pass_kernel<B, K, true><<<tiles, NT, 0, stream>>>(src, kin, vin, kout, vout, n, shift,    \
+                                                                    hist_pass, status, tile_ctr, epoch);    \
         else                                                                                                \
-            radix_pass_kernel<B, K, false><<<tiles, MQ_BLOCK, 0, stream>>>(src, kin, vin, kout, vout, n, shift, \
-                                                                           hist_pass, status, tile_ctr, epoch); \
+            radix_pass_kernel<B, K, false><<<tiles, NT, 0, stream>>>(src, kin, vin, kout, vout, n, shift,   \
+                                                                     hist_pass, status, tile_ctr, epoch);   \
     }
 #define MQ_PK(B)                     \
     case B:                          \
@@ -247,6 +253,9 @@ hipError_t launch_radix_pass(int rb, int kpt, const SortSrc& src, const uint32_t
     return hipGetLastError();
 }
 
-uint32_t radix_tiles(uint32_t n, int kpt) { return (n + MQ_BLOCK * kpt - 1) / (MQ_BLOCK * kpt); }
+uint32_t radix_tiles(uint32_t n, int kpt, int rb) {
+    const uint32_t tile = (uint32_t)(sort_waves(rb, kpt) * MQ_WAVE * kpt);
+    return (n + tile - 1) / tile;
+}
 
 }  // namespace mq

@@ -18,15 +18,16 @@ struct Radix {
     static constexpr int BPT = (BUCKETS + MQ_BLOCK - 1) / MQ_BLOCK;  // buckets per thread
 };
 
-template <int RB, int KPT>
+// NW waves per block (a tile is NW * 64 * KPT records)
+template <int RB, int KPT, int NW = MQ_WAVES>
 struct SortSmem {
-    static constexpr int TILE = MQ_BLOCK * KPT;
+    static constexpr int TILE = NW * MQ_WAVE * KPT;
     uint32_t keys[TILE];
     uint32_t vals[TILE];
-    uint32_t wcnt[MQ_WAVES][Radix<RB>::BUCKETS];
+    uint32_t wcnt[NW][Radix<RB>::BUCKETS];
     uint32_t local[Radix<RB>::BUCKETS];
     uint32_t goff[Radix<RB>::BUCKETS];
-    uint32_t tmp[MQ_WAVES];
+    uint32_t tmp[NW];
 };
 
 // Exclusive scan of the BUCKETS values in LDS `in` into LDS `out` (may
@@ -64,26 +65,28 @@ __device__ __forceinline__ void scan_buckets(const uint32_t* in, uint32_t* out, 
 // earlier tiles, and scatters the tile to kout/vout (join-relative).
 // `ghist` is the join's digit histogram of this pass.  Every thread of the
 // block calls it.
-template <int RB, int KPT>
-__device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t (&key)[KPT],
+template <int RB, int KPT, int NW = MQ_WAVES>
+__device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint32_t (&key)[KPT],
                                           const uint32_t (&val)[KPT], uint32_t valid_n, int shift,
                                           const uint32_t* __restrict__ ghist, uint64_t* __restrict__ status,
                                           uint32_t tile, uint32_t first_tile, uint32_t epoch,
                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
     using R = Radix<RB>;
+    constexpr int NT = NW * MQ_WAVE;                       // threads of the block
+    constexpr int BPT = (R::BUCKETS + NT - 1) / NT;        // buckets per thread
     const uint32_t w = threadIdx.x / MQ_WAVE;
     const uint32_t ln = lane();
-    for (int d = threadIdx.x; d < R::BUCKETS; d += MQ_BLOCK) {
+    for (int d = threadIdx.x; d < R::BUCKETS; d += NT) {
         sm.goff[d] = ghist[d];
 #pragma unroll
-        for (int i = 0; i < MQ_WAVES; i++) sm.wcnt[i][d] = 0;
+        for (int i = 0; i < NW; i++) sm.wcnt[i][d] = 0;
     }
     __syncthreads();
     scan_buckets<RB>(sm.goff, sm.goff, sm.tmp);
 
     // stable rank within the wave, digit by digit through the wave counters
     // (ranks are below the tile size, 2^16: two per register)
-    static_assert(MQ_BLOCK * KPT <= 65536 && KPT % 2 == 0, "16-bit ranks");
+    static_assert(NT * KPT <= 65536 && KPT % 2 == 0, "16-bit ranks");
     uint32_t rank2[KPT / 2];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -114,14 +117,14 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t 
     __syncthreads();
 
     // per digit: exclusive prefix over waves, tile total, local digit starts
-    uint32_t tot[R::BPT];
+    uint32_t tot[BPT];
 #pragma unroll
-    for (int k = 0; k < R::BPT; k++) {
-        const uint32_t d = threadIdx.x * R::BPT + k;
+    for (int k = 0; k < BPT; k++) {
+        const uint32_t d = threadIdx.x * BPT + k;
         uint32_t run = 0;
         if (d < (uint32_t)R::BUCKETS) {
 #pragma unroll
-            for (int i = 0; i < MQ_WAVES; i++) {
+            for (int i = 0; i < NW; i++) {
                 const uint32_t c = sm.wcnt[i][d];
                 sm.wcnt[i][d] = run;
                 run += c;
@@ -136,14 +139,14 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t 
     // publish this tile's digit totals, then look back for the prefix
     uint64_t* st = status + (uint64_t)tile * R::BUCKETS;
 #pragma unroll
-    for (int k = 0; k < R::BPT; k++) {
-        const uint32_t d = threadIdx.x * R::BPT + k;
+    for (int k = 0; k < BPT; k++) {
+        const uint32_t d = threadIdx.x * BPT + k;
         if (d < (uint32_t)R::BUCKETS) st_store(st + d, st_pack(epoch, tile == first_tile ? ST_INC : ST_AGG, tot[k]));
     }
     if (tile > first_tile) {
 #pragma unroll
-        for (int k = 0; k < R::BPT; k++) {
-            const uint32_t d = threadIdx.x * R::BPT + k;
+        for (int k = 0; k < BPT; k++) {
+            const uint32_t d = threadIdx.x * BPT + k;
             if (d < (uint32_t)R::BUCKETS) {
                 const uint64_t ex = lookback(status + d, tile, first_tile, R::BUCKETS, epoch);
                 st_store(st + d, st_pack(epoch, ST_INC, ex + tot[k]));
@@ -163,7 +166,7 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT>& sm, const uint32_t 
         }
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < valid_n; j += MQ_BLOCK) {
+    for (uint32_t j = threadIdx.x; j < valid_n; j += NT) {
         const uint32_t k = sm.keys[j];
         const uint32_t dg = (k >> shift) & R::MASK;
         const uint32_t g = sm.goff[dg] + (j - sm.local[dg]);
