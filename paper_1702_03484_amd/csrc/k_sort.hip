@@ -132,10 +132,14 @@ uint32_t radix_hist_part_words(int rb, int passes) { return HIST_BLOCKS * (uint3
 
 // Waves per block of a radix pass: 8 (8,192-record tiles, half the tile-id
 // atomics and look-backs of 4-wave blocks; two blocks still fit a CU's LDS)
-// for digits of up to 8 bits at 16 keys per thread, else 4.
-__host__ __device__ constexpr int sort_waves(int rb, int kpt) { return rb <= 8 && kpt == 16 ? 8 : 4; }
+// for digits of up to 8 bits at 16 keys per thread, else 4.  The first pass
+// (reading the input columns) needs more registers: at 3 waves per SIMD only
+// one 8-wave block would fit a CU, so it keeps 4-wave blocks.
+__host__ __device__ constexpr int sort_waves(int rb, int kpt, bool gen) {
+    return rb <= 8 && kpt == 16 && !gen ? 8 : 4;
+}
 
-template <int RB, int KPT, bool GEN, int NW = sort_waves(RB, KPT)>
+template <int RB, int KPT, bool GEN, int NW = sort_waves(RB, KPT, GEN)>
 __global__ __launch_bounds__(NW * MQ_WAVE) void radix_pass_kernel(SortSrc src, const uint32_t* __restrict__ kin,
                                                                   const uint32_t* __restrict__ vin,
                                                                   uint32_t* __restrict__ kout,
@@ -230,14 +234,13 @@ hipError_t launch_radix_pass(int rb, int kpt, const SortSrc& src, const uint32_t
     int shift = pass * rb;
 #define MQ_P(B, K)                                                                                          \
     {                                                                                                       \
-        constexpr uint32_t NT = sort_waves(B, K) * MQ_WAVE;                                                 \
-        uint32_t tiles = radix_tiles(n, K, B);                                                              \
+        const uint32_t tiles = radix_tiles(n, K, B, gen);                                                   \
         if (gen)                                                                                            \
-            radix_pass_kernel<B, K, true><<<tiles, NT, 0, stream>>>(src, kin, vin, kout, vout, n, shift,    \
-                                                                    hist_pass, status, tile_ctr, epoch);    \
+            radix_pass_kernel<B, K, true><<<tiles, sort_waves(B, K, true) * MQ_WAVE, 0, stream>>>(          \
+                src, kin, vin, kout, vout, n, shift, hist_pass, status, tile_ctr, epoch);                   \
         else                                                                                                \
-            radix_pass_kernel<B, K, false><<<tiles, NT, 0, stream>>>(src, kin, vin, kout, vout, n, shift,   \
-                                                                     hist_pass, status, tile_ctr, epoch);   \
+            radix_pass_kernel<B, K, false><<<tiles, sort_waves(B, K, false) * MQ_WAVE, 0, stream>>>(        \
+                src, kin, vin, kout, vout, n, shift, hist_pass, status, tile_ctr, epoch);                   \
     }
 #define MQ_PK(B)                     \
     case B:                          \
@@ -253,8 +256,8 @@ hipError_t launch_radix_pass(int rb, int kpt, const SortSrc& src, const uint32_t
     return hipGetLastError();
 }
 
-uint32_t radix_tiles(uint32_t n, int kpt, int rb) {
-    const uint32_t tile = (uint32_t)(sort_waves(rb, kpt) * MQ_WAVE * kpt);
+uint32_t radix_tiles(uint32_t n, int kpt, int rb, bool gen) {
+    const uint32_t tile = (uint32_t)(sort_waves(rb, kpt, gen) * MQ_WAVE * kpt);
     return (n + tile - 1) / tile;
 }
 

@@ -93,11 +93,13 @@ hipError_t launch_radix_hist(const SortSrc& src, const uint32_t* keys, uint32_t 
 uint32_t radix_hist_part_words(int rb, int passes);
 // One stable pass on digit `pass`.  kin == nullptr: first-pass mode from
 // `src` (vin ignored).  hist_pass = this pass's histogram; status holds
-// radix_tiles(n,kpt,rb) * 2^rb words; tile_ctr is zero before the launch.
+// radix_tiles(n,kpt,rb,true) * 2^rb words; tile_ctr is zero before the launch.
 hipError_t launch_radix_pass(int rb, int kpt, const SortSrc& src, const uint32_t* kin, const uint32_t* vin,
                              uint32_t* kout, uint32_t* vout, uint32_t n, int pass, const uint32_t* hist_pass,
                              uint64_t* status, uint32_t* tile_ctr, uint32_t epoch, hipStream_t stream);
-uint32_t radix_tiles(uint32_t n, int kpt, int rb);
+// record tiles of a radix pass over n records (gen: the first pass, reading
+// the input columns; its tiles are never larger than the other passes')
+uint32_t radix_tiles(uint32_t n, int kpt, int rb, bool gen);
 
 // ---- reduce (k_reduce.hip) -------------------------------------------------
 // Segment heads of the sorted records: seg_start[s] = first position of the

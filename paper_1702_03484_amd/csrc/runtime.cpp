@@ -221,7 +221,7 @@ static mapsq_status radix_sort(Ctx* ctx, const SortSrc* src, uint32_t n, int key
     if (n == 0) return MAPSQ_OK;
     const size_t buckets = size_t(1) << rb;
     if (passes * buckets > SMALL_HIST_WORDS) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "radix digit width too small");
-    if (!ctx->ensure_status(size_t(radix_tiles(n, kpt, rb)) * buckets))
+    if (!ctx->ensure_status(size_t(radix_tiles(n, kpt, rb, true)) * buckets))  // the most tiles of any pass
         return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for sort status words");
     HIPCHK(launch_fill_u32(ctx->small + SMALL_CTR, SMALL_SCALARS - SMALL_CTR, 0u, ctx->stream));
     SortSrc none{};
