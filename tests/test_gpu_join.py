@@ -409,6 +409,29 @@ def test_large_join_counts_exactly_before_sorting(sess):
         sess.set_join_options(0, 0)
 
 
+@pytest.mark.parametrize("nl,nr,card,vl,vr,known", [JOIN_CASES[i] for i in (0, 2, 5, 6, 7)])
+def test_exact_count_first_on_small_joins(sess, nl, nr, card, vl, vr, known):
+    """precount=2: the dense per-key count runs before every shuffle, small
+    and skewed ones included; the rows stay those of the oracle."""
+    announce(f"join with the count first nl={nl} nr={nr} card={card}")
+    keys = keyset(nl * 7 + nr, card)
+    lc = random_table(nl, nl, card, vl, key_ids=keys)
+    rc = random_table(nr + 1, nr, card, vr, key_ids=keys)
+    lvars = [0] + list(range(10, 10 + vl))
+    rvars = [0] + list(range(20, 20 + vr))
+    kmax = int(keys.max()) if known else -1
+    sess.set_join_options(semijoin=1, merge=1, precount=2)
+    try:
+        out = sess.join(sess.table(lvars, [dev(c) for c in lc], key_max=kmax),
+                        sess.table(rvars, [dev(c) for c in rc], key_max=kmax), 0)
+        exp = oracle.join(Table(lvars, lc), Table(rvars, rc), 0)
+        assert out.nrows == exp.n == sess.stats().out_rows
+        assert_same_bag(host_table(sess, out), exp)
+        sess.free(out)
+    finally:
+        sess.set_join_options(0, 0)
+
+
 def test_join_too_large_is_refused_without_leak(sess):
     announce("TOO_LARGE: over 2^40 rows and over the arena")
     free0 = None
