@@ -74,8 +74,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void semi_filter_kernel(SemiArgs a, uint6
         }
         __syncthreads();
         uint32_t pos = (uint32_t)s_excl + wex;
-#pragma unroll
-        for (int i = 0; i < SEMI_IPT; i++) {
+        for (int i = 0; i < SEMI_IPT; i++) {  // fully unrolled by the compiler (km stays in registers)
             if ((km[i] >> lane()) & 1ull) {
                 const uint32_t idx = base + (w * SEMI_IPT + i) * MQ_WAVE + lane();
                 const uint32_t at = pos + (uint32_t)__popcll(km[i] & lt);
