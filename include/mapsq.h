@@ -244,6 +244,14 @@ mapsq_status mapsq_serve_step(mapsq_ctx* ctx, int32_t* active, int32_t* waiting)
  * status: the query failed with that status and the ticket is retired. */
 mapsq_status mapsq_poll(mapsq_ctx* ctx, uint64_t ticket, int32_t* done, mapsq_table* out);
 
+/* The next query to end, in the order queries ended (one call per finished
+ * query instead of one per pending ticket).  *done = 0: none has ended that
+ * is not yet retired (*ticket = 0).  *done = 1: *ticket names it and the
+ * call returns what mapsq_poll(ctx, *ticket, ...) would: OK with the result
+ * in *out, or the query's error status.  INVALID_ARG (with *ticket = 0) for
+ * null outputs. */
+mapsq_status mapsq_poll_next(mapsq_ctx* ctx, uint64_t* ticket, int32_t* done, mapsq_table* out);
+
 /* Release an owned table (views are left alone); the struct is zeroed. */
 mapsq_status mapsq_table_free(mapsq_ctx* ctx, mapsq_table* t);
 

@@ -132,6 +132,8 @@ _SIGS = [
       ctypes.POINTER(ctypes.c_uint64)]),
     ("mapsq_serve_step", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     ("mapsq_poll", ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(mapsq_table)]),
+    ("mapsq_poll_next", ctypes.c_int32,
+     [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(mapsq_table)]),
     ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
     ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
     ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
@@ -259,6 +261,20 @@ def mapsq_poll(ctx, ticket: int):
     out = mapsq_table()
     _check(ctx, lib().mapsq_poll(ctx, ticket, ctypes.byref(d), ctypes.byref(out)))
     return bool(d.value), (out if d.value else None)
+
+
+def mapsq_poll_next(ctx):
+    """(ticket, status, table or None) of the next query to end; ticket 0
+    when none has.  A failed query comes back with its error status (no
+    exception); invalid arguments raise MapSQError."""
+    tk = ctypes.c_uint64()
+    d = ctypes.c_int32()
+    out = mapsq_table()
+    st = lib().mapsq_poll_next(ctx, ctypes.byref(tk), ctypes.byref(d), ctypes.byref(out))
+    if not d.value:
+        _check(ctx, st)
+        return 0, 0, None
+    return int(tk.value), int(st), (out if st == 0 else None)
 
 
 def mapsq_table_free(ctx, t: mapsq_table):

@@ -176,6 +176,10 @@ mapsq_status mapsq_poll(mapsq_ctx* c, uint64_t ticket, int32_t* done, mapsq_tabl
     return guarded(c, [&](Ctx* ctx) { return mq::poll(ctx, ticket, done, out); });
 }
 
+mapsq_status mapsq_poll_next(mapsq_ctx* c, uint64_t* ticket, int32_t* done, mapsq_table* out) {
+    return guarded(c, [&](Ctx* ctx) { return mq::poll_next(ctx, ticket, done, out); });
+}
+
 mapsq_status mapsq_table_free(mapsq_ctx* c, mapsq_table* t) {
     return guarded(c, [&](Ctx* ctx) {
         if (!t) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null table");

@@ -86,6 +86,15 @@ static mapsq_status with_zero_key(Ctx* ctx, const mapsq_table& t, mapsq_table* o
 // Cartesian product as a join on a constant key (one segment); the key
 // column is dropped from the result.
 mapsq_status cross_join(Ctx* ctx, const mapsq_table& cur, const mapsq_table& other, mapsq_table* nxt) {
+    // the size is exact before anything runs: refuse what cannot fit
+    const uint64_t total = (uint64_t)std::max<int64_t>(cur.nrows, 0) * (uint64_t)std::max<int64_t>(other.nrows, 0);
+    ctx->last = mapsq_join_stats{};
+    ctx->last.out_rows = (int64_t)std::min<uint64_t>(total, SAT40_HOST);
+    if (total >= SAT40_HOST) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "cross product exceeds 2^40 rows");
+    const double need = (double)align_up(size_t(total) * 4, ARENA_ALIGN) * (1 + cur.ncols + other.ncols);
+    if (need > (double)ctx->arena.free_bytes())
+        return ctx->fail(MAPSQ_ERR_TOO_LARGE,
+                         "cross product (" + std::to_string(total) + " rows) exceeds the arena's free space");
     mapsq_table a{}, b{};
     Block za, zb;
     mapsq_status st = with_zero_key(ctx, cur, &a, &za);

@@ -31,6 +31,11 @@ class Arena {
     char* ptr(size_t off) const { return base_ + off; }
     size_t free_bytes() const;
     size_t largest() const;
+    // size of the allocated block at `off` (0 if none)
+    size_t block_size(size_t off) const {
+        auto it = used_.find(off);
+        return it == used_.end() ? 0 : it->second;
+    }
     char* base() const { return base_; }
     size_t size() const { return size_; }
 
@@ -216,6 +221,7 @@ mapsq_status submit(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const in
                     uint64_t* ticket);
 mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting);
 mapsq_status poll(Ctx* ctx, uint64_t ticket, int32_t* done, mapsq_table* out);
+mapsq_status poll_next(Ctx* ctx, uint64_t* ticket, int32_t* done, mapsq_table* out);
 void destroy_server(Ctx* ctx);
 mapsq_status query_vars(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
                         std::vector<int32_t>* qvars, std::vector<int32_t>* want);

@@ -16,6 +16,7 @@
 #include <deque>
 #include <memory>
 #include <unordered_map>
+#include <unordered_set>
 
 #include "runtime.h"
 
@@ -31,6 +32,7 @@ struct SQuery {
     std::vector<int32_t> qvars, want;
     int state = Q_WAITING;
     mapsq_status err = MAPSQ_OK;
+    std::string why;  // message of the failed step
     bool sized = false;
     std::vector<int64_t> rows;             // pattern sizes (exact, or an upper bound for scans)
     double predicted = 0;                  // predicted intermediate bytes
@@ -44,11 +46,22 @@ struct SQuery {
     uint64_t admitted = 0;  // admission order (the latest is preempted first)
     double reserve = 0;     // budget bytes held while admitted
     int passed_over = 0;    // rounds in which later queries were admitted first
+    int stalls = 0;         // rounds in a row its join step waited for memory
+    bool restarted = false; // started over once, alone, on a less fragmented arena
+    int deferrals = 0;      // times it gave its memory back and went behind the queue
 };
 
 // a waiting query may be passed over by later ones this many rounds, then
 // admission waits for it (no starvation)
 constexpr int MAX_PASSED_OVER = 8;
+// a join step that waited for memory this many rounds in a row stops
+// admission until it runs (no starvation of large queries)
+constexpr int MAX_STALLS = 8;
+// a join step that must wait for memory while other queries wait to be
+// admitted gives its memory back and goes behind them, at most this often:
+// the queries that need most of the arena then run together once the others
+// have drained, rather than each draining the active set on its own
+constexpr int MAX_DEFERRALS = 2;
 // join steps of at least this many records run through the plain join path
 // (merge join, semi-join reduction) rather than the batched kernels
 constexpr int64_t PLAIN_STEP_RECORDS = int64_t(1) << 20;
@@ -65,6 +78,7 @@ struct Server {
     int max_active = 256;
     uint64_t admissions = 0;
     bool hold = false;  // after a preemption: admit nothing until a query ends
+    std::deque<uint64_t> finished;  // tickets in the order their queries ended
 };
 
 void destroy_server(Ctx* ctx) {
@@ -252,12 +266,15 @@ static void fail_query(Ctx* ctx, Server* S, SQuery* q, mapsq_status err) {
     if (q->state == Q_ACTIVE) S->reserved -= q->reserve;
     q->state = Q_FAILED;
     q->err = err;
+    q->why = ctx->err;
     S->hold = false;
+    S->finished.push_back(q->ticket);
 }
 
-// Give back everything a stalled query holds and queue it again at the head:
-// it restarts from its partial matches once a running query has ended.
-static void preempt_query(Ctx* ctx, Server* S, SQuery* q) {
+// Give back everything a stalled query holds and queue it again, at the
+// head (admission then waits for a running query to end) or, deferred, at
+// the tail; it restarts from its partial matches.
+static void preempt_query(Ctx* ctx, Server* S, SQuery* q, bool to_tail = false) {
     for (size_t i = 0; i < q->tabs.size(); i++)
         if (!q->consumed[i]) free_table(ctx, &q->tabs[i]);
     if (q->cur.owned) free_table(ctx, &q->cur);
@@ -266,10 +283,15 @@ static void preempt_query(Ctx* ctx, Server* S, SQuery* q) {
     q->consumed.clear();
     q->steps.clear();
     q->next = 0;
+    q->stalls = 0;
     S->reserved -= q->reserve;
     q->state = Q_WAITING;
-    S->waiting.push_front(q);
-    S->hold = true;
+    if (to_tail) {
+        S->waiting.push_back(q);
+    } else {
+        S->waiting.push_front(q);
+        S->hold = true;
+    }
 }
 
 static void finish_query(Server* S, SQuery* q) {
@@ -278,6 +300,7 @@ static void finish_query(Server* S, SQuery* q) {
     q->state = Q_DONE;
     S->reserved -= q->reserve;
     S->hold = false;
+    S->finished.push_back(q->ticket);
 }
 
 // Map the patterns of a newly admitted query and fix its plan on the exact
@@ -323,7 +346,9 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         for (const SQuery* o : S->active) k += o != q && o->state == Q_ACTIVE;
         return k;
     };
-    for (auto it = S->waiting.begin(); it != S->waiting.end() && !S->hold;) {
+    bool starving = false;
+    for (const SQuery* o : S->active) starving = starving || (o->state == Q_ACTIVE && o->stalls > MAX_STALLS);
+    for (auto it = S->waiting.begin(); it != S->waiting.end() && !S->hold && !starving;) {
         SQuery* q = *it;
         if ((int)S->active.size() >= S->max_active) break;
         if (q->predicted == 0) predict(ctx, q);
@@ -357,38 +382,76 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         free_table(ctx, &q->tabs[pick]);
         q->consumed[pick] = true;
         q->cur = nxt;
+        q->stalls = 0;
         progress++;
         if (++q->next == q->steps.size())
             finish_query(S, q);
         else if (q->cur.nrows >= (int64_t(1) << 31))
-            fail_query(ctx, S, q, MAPSQ_ERR_TOO_LARGE);
+            fail_query(ctx, S, q, ctx->fail(MAPSQ_ERR_TOO_LARGE, "an intermediate of 2^31 rows or more"));
     };
-    // bytes the query could use if every other active query let go of its tables
+    // bytes the query could use if every other query let go of what it
+    // holds: the free space plus every arena block that only other queries'
+    // tables reference (a batch's shared block counts whole)
     auto room_alone = [&](const SQuery* q) {
+        std::unordered_set<uint64_t> own, others;
+        auto tables_of = [](const SQuery* o, auto&& f) {
+            if (o->state == Q_ACTIVE) {
+                f(o->cur);
+                for (size_t i = 0; i < o->tabs.size(); i++)
+                    if (!o->consumed[i]) f(o->tabs[i]);
+            } else if (o->state == Q_DONE) {
+                f(o->result);
+            }
+        };
+        tables_of(q, [&](const mapsq_table& t) {
+            if (t.owned && t.block) own.insert(t.block);
+        });
+        for (auto& kv : S->all)
+            if (kv.second.get() != q)
+                tables_of(kv.second.get(), [&](const mapsq_table& t) {
+                    if (t.owned && t.block && !own.count(t.block)) others.insert(t.block);
+                });
         double b = (double)ctx->arena.free_bytes();
-        for (const SQuery* o : S->active) {
-            if (o == q || o->state != Q_ACTIVE) continue;
-            auto held = [&](const mapsq_table& t) {
-                return t.owned ? 4.0 * (double)t.nrows * t.ncols + 256.0 * t.ncols : 0.0;
-            };
-            b += held(o->cur);
-            for (size_t i = 0; i < o->tabs.size(); i++)
-                if (!o->consumed[i]) b += held(o->tabs[i]);
-        }
+        for (uint64_t blk : others) b += (double)ctx->arena.block_size(size_t(blk - 1));
         return b;
     };
     std::vector<SQuery*> stalled;
     // a failed step: wait for memory while others hold some, unless the
     // exact output could not fit even then
+    // A query alone whose output would fit the free space plus what it holds
+    // (its tables split the free space) starts over once, from a cleaner arena.
     auto failed = [&](SQuery* q, mapsq_status e, int64_t need_rows) {
         const bool memory = e == MAPSQ_ERR_CAPACITY || e == MAPSQ_ERR_TOO_LARGE;
-        if (memory && live_others(q) > 0) {
+        if (memory && need_rows < SAT40_HOST) {
             const PlanStep& ps = q->steps[q->next];
             const double cols = q->cur.ncols + q->tabs[ps.pick].ncols - 1;
             const double need = 4.0 * (double)need_rows * cols;
-            if (need_rows < SAT40_HOST && need <= room_alone(q)) {
-                stalled.push_back(q);
-                return;
+            if (live_others(q) > 0) {
+                if (need <= room_alone(q) && q->deferrals < MAX_DEFERRALS && !S->waiting.empty()) {
+                    q->deferrals++;
+                    preempt_query(ctx, S, q, true);
+                    progress++;
+                    return;
+                }
+                if (need <= room_alone(q)) {
+                    q->stalls++;
+                    stalled.push_back(q);
+                    return;
+                }
+            } else if (!q->restarted) {
+                double own = (double)ctx->arena.free_bytes();
+                std::unordered_set<uint64_t> blocks;
+                if (q->cur.owned && q->cur.block) blocks.insert(q->cur.block);
+                for (size_t i = 0; i < q->tabs.size(); i++)
+                    if (!q->consumed[i] && q->tabs[i].owned && q->tabs[i].block) blocks.insert(q->tabs[i].block);
+                for (uint64_t blk : blocks) own += (double)ctx->arena.block_size(size_t(blk - 1));
+                if (!blocks.empty() && need <= own) {
+                    q->restarted = true;
+                    preempt_query(ctx, S, q);
+                    S->hold = false;  // nothing else runs: admit it again next round
+                    progress++;
+                    return;
+                }
             }
         }
         fail_query(ctx, S, q, memory ? MAPSQ_ERR_TOO_LARGE : e);
@@ -470,9 +533,26 @@ mapsq_status poll(Ctx* ctx, uint64_t ticket, int32_t* done, mapsq_table* out) {
     }
     if (q->state == Q_FAILED) {
         const mapsq_status err = q->err;
+        const std::string msg = "query " + std::to_string(ticket) + " failed: " + q->why;
         *done = 1;
-        S->all.erase(it);
-        return ctx->fail(err, "query " + std::to_string(ticket) + " failed");
+        S->all.erase(it);  // destroys q
+        return ctx->fail(err, msg);
+    }
+    return MAPSQ_OK;
+}
+
+mapsq_status poll_next(Ctx* ctx, uint64_t* ticket, int32_t* done, mapsq_table* out) {
+    if (!ticket || !done || !out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+    *ticket = 0;
+    *done = 0;
+    std::memset(out, 0, sizeof(mapsq_table));
+    Server* S = server(ctx);
+    while (!S->finished.empty()) {
+        const uint64_t tk = S->finished.front();
+        S->finished.pop_front();
+        if (!S->all.count(tk)) continue;  // already retired by mapsq_poll
+        *ticket = tk;
+        return poll(ctx, tk, done, out);
     }
     return MAPSQ_OK;
 }

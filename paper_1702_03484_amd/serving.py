@@ -1,6 +1,6 @@
 """Load generators of the serving API: Poisson arrivals, latency accounting.
 
-``run_continuous`` drives mapsq_submit / mapsq_serve_step / mapsq_poll
+``run_continuous`` drives mapsq_submit / mapsq_serve_step / mapsq_poll_next
 (continuous batching inside the library); ``run_plain`` answers the same
 arrivals one query at a time with mapsq_query.  Both only marshal calls and
 record host clocks; every query runs in the library's HIP kernels.
@@ -59,18 +59,14 @@ def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collec
         rounds += 1
         torch.cuda.current_stream(sess.device).synchronize()
         now = time.perf_counter() - t0
-        for tk in list(pending):
-            j = pending[tk]
-            try:
-                done, t = B.mapsq_poll(sess.ctx, tk)
-            except B.MapSQError as e:
-                status[j] = e.code
-                lat[j] = now - arrivals[j]
-                del pending[tk]
-                continue
-            if done:
-                del pending[tk]
-                lat[j] = now - arrivals[j]
+        while True:  # the queries that ended this round, one call each
+            tk, st, t = B.mapsq_poll_next(sess.ctx)
+            if not tk:
+                break
+            j = pending.pop(tk)
+            status[j] = st
+            lat[j] = now - arrivals[j]
+            if t is not None:
                 if collect is not None:
                     collect[j] = (list(t.vars), sess.to_numpy(t))
                 B.mapsq_table_free(sess.ctx, t)

@@ -94,3 +94,65 @@ def test_plain_and_continuous_agree(sess, served):
     for j in a:
         assert a[j][0] == b[j][0]
         assert all(np.array_equal(x, y) for x, y in zip(a[j][1], b[j][1]))
+
+
+def test_tight_arena_mix_completes_what_completes_alone(sess, served):
+    """In an arena where the largest result fits alone but not beside the
+    others, every query that completes alone completes in the saturated mix
+    with the same rows (it waits for memory instead of failing)."""
+    from paper_1702_03484_amd.engine import MapSQ
+
+    w, qs = served
+    big_alone = _alone(sess, qs)
+    size = {j: 4 * len(v[1][0]) * len(v[1]) for j, v in big_alone.items() if not isinstance(v, int) and v[1]}
+    big = max(size.values())
+    free, _ = B.mapsq_arena_free_bytes(sess.ctx)
+    footprint = (48 << 30) - free
+    arena = footprint + 2 * big + (256 << 20)
+    announce(f"serving: tight arena of {arena >> 20} MiB, largest result {big >> 20} MiB")
+    with MapSQ(arena_bytes=arena) as tight:
+        tight.load(w.s, w.p, w.o)
+        alone = _alone(tight, qs)
+        ok = [j for j in alone if not isinstance(alone[j], int)]
+        assert any(size.get(j, 0) >= big // 2 for j in ok)
+        got = {}
+        summ, lat, status = serving.run_continuous(tight, qs, np.zeros(len(qs)), collect=got)
+        announce(f"serving: tight arena: {len(ok)} complete alone, {summ['completed']} in the mix")
+        for j in ok:
+            assert status[j] == 0, (j, int(status[j]), qs[j])
+            assert got[j][0] == alone[j][0]
+            assert all(np.array_equal(a, b) for a, b in zip(got[j][1], alone[j][1])), j
+        memory = (B.MAPSQ_ERR_CAPACITY, B.MAPSQ_ERR_TOO_LARGE)
+        for j in range(len(qs)):
+            if j not in ok:  # serving reports every memory failure as TOO_LARGE
+                want = B.MAPSQ_ERR_TOO_LARGE if alone[j] in memory else alone[j]
+                assert status[j] == want, (j, int(status[j]), alone[j])
+
+
+def test_poll_next_returns_each_finished_query_once(sess, served):
+    w, qs = served
+    announce("serving: mapsq_poll_next after mapsq_poll")
+    tickets = [B.mapsq_submit(sess.ctx, q) for q in qs[:12]]
+    for _ in range(10_000):
+        active, waiting = B.mapsq_serve_step(sess.ctx)
+        if active == 0 and waiting == 0:
+            break
+    assert active == 0 and waiting == 0
+    try:  # retired here: poll_next skips it
+        done, t = B.mapsq_poll(sess.ctx, tickets[3])
+    except B.MapSQError:  # a query that failed is retired too
+        done, t = True, None
+    assert done
+    if t is not None:
+        B.mapsq_table_free(sess.ctx, t)
+    seen = []
+    while True:
+        tk, st, t = B.mapsq_poll_next(sess.ctx)
+        if not tk:
+            break
+        seen.append(tk)
+        assert (st == 0) == (t is not None)
+        if t is not None:
+            B.mapsq_table_free(sess.ctx, t)
+    assert sorted(seen) == sorted(tickets[:3] + tickets[4:])
+    assert B.mapsq_poll_next(sess.ctx) == (0, 0, None)
