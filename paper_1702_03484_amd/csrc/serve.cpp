@@ -49,6 +49,8 @@ struct SQuery {
     int stalls = 0;         // rounds in a row its join step waited for memory
     bool restarted = false; // started over once, alone, on a less fragmented arena
     int deferrals = 0;      // times it gave its memory back and went behind the queue
+    double wait_bytes = 0;  // output bytes its join step `wait_step` found no room for
+    size_t wait_step = 0;
 };
 
 // a waiting query may be passed over by later ones this many rounds, then
@@ -383,6 +385,7 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         q->consumed[pick] = true;
         q->cur = nxt;
         q->stalls = 0;
+        q->wait_bytes = 0;
         progress++;
         if (++q->next == q->steps.size())
             finish_query(S, q);
@@ -427,6 +430,8 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
             const double cols = q->cur.ncols + q->tabs[ps.pick].ncols - 1;
             const double need = 4.0 * (double)need_rows * cols;
             if (live_others(q) > 0) {
+                q->wait_bytes = need;
+                q->wait_step = q->next;
                 if (need <= room_alone(q) && q->deferrals < MAX_DEFERRALS && !S->waiting.empty()) {
                     q->deferrals++;
                     preempt_query(ctx, S, q, true);
@@ -459,6 +464,14 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     };
     for (SQuery* q : S->active) {
         if (q->state != Q_ACTIVE || q->next >= q->steps.size()) continue;
+        // a step that found no room waits, without running its join again,
+        // until a free block could hold its output
+        if (q->wait_bytes > 0 && q->wait_step == q->next && live_others(q) > 0 &&
+            (double)ctx->arena.largest() < q->wait_bytes) {
+            q->stalls++;
+            stalled.push_back(q);
+            continue;
+        }
         const PlanStep& ps = q->steps[q->next];
         if (ps.cross) {  // rare: run it now through the plain path
             mapsq_table nxt{};
