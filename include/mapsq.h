@@ -218,9 +218,13 @@ mapsq_status mapsq_join_batch(mapsq_ctx* ctx, const mapsq_join_desc* joins, int3
  * together in one batched launch, steps of 2^20 records or more and steps
  * whose inputs are already in key order through the plain join path.  A
  * step that finds no memory waits while other queries hold memory, unless
- * its exact output could not fit even if they let go of everything; when a
- * round makes no progress at all, the most recently admitted waiting query
- * frees what it holds and is queued again at the head, and nothing is
+ * its exact output could not fit even if they let go of everything (free
+ * space plus every block only they reference); while other queries wait to
+ * be admitted it first frees what it holds and goes behind them (at most
+ * twice), and after 8 rounds of waiting admission pauses until it runs.  A
+ * query alone whose own tables split the free space starts over once.  When
+ * a round makes no progress at all, the most recently admitted waiting
+ * query frees what it holds and is queued again at the head, and nothing is
  * admitted until some query ends.  A query fails with TOO_LARGE when a join
  * output cannot fit or an intermediate reaches 2^31 rows.  A query that
  * arrives while others are in flight joins the next round.  Each result is
