@@ -222,6 +222,7 @@ mapsq_status mapsq_join_batch(mapsq_ctx* ctx, const mapsq_join_desc* joins, int3
  * space plus every block only they reference); while other queries wait to
  * be admitted it first frees what it holds and goes behind them (at most
  * twice), and after 8 rounds of waiting admission pauses until it runs.  A
+ * step held up only by results not yet polled tries again next round; a
  * query alone whose own tables split the free space starts over once.  When
  * a round makes no progress at all, the most recently admitted waiting
  * query frees what it holds and is queued again at the head, and nothing is

@@ -395,20 +395,44 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     // bytes the query could use if every other query let go of what it
     // holds: the free space plus every arena block that only other queries'
     // tables reference (a batch's shared block counts whole)
-    auto room_alone = [&](const SQuery* q) {
-        std::unordered_set<uint64_t> own, others;
-        auto tables_of = [](const SQuery* o, auto&& f) {
-            if (o->state == Q_ACTIVE) {
-                f(o->cur);
-                for (size_t i = 0; i < o->tabs.size(); i++)
-                    if (!o->consumed[i]) f(o->tabs[i]);
-            } else if (o->state == Q_DONE) {
-                f(o->result);
-            }
-        };
+    auto tables_of = [](const SQuery* o, auto&& f) {
+        if (o->state == Q_ACTIVE) {
+            f(o->cur);
+            for (size_t i = 0; i < o->tabs.size(); i++)
+                if (!o->consumed[i]) f(o->tabs[i]);
+        } else if (o->state == Q_DONE) {
+            f(o->result);
+        }
+    };
+    auto blocks_of = [&](const SQuery* q) {
+        std::unordered_set<uint64_t> own;
         tables_of(q, [&](const mapsq_table& t) {
             if (t.owned && t.block) own.insert(t.block);
         });
+        return own;
+    };
+    // free space plus the blocks the query holds itself
+    auto own_room = [&](const SQuery* q) {
+        double b = (double)ctx->arena.free_bytes();
+        for (uint64_t blk : blocks_of(q)) b += (double)ctx->arena.block_size(size_t(blk - 1));
+        return b;
+    };
+    // blocks held only by finished results the caller has not polled yet
+    auto unpolled_room = [&](const SQuery* q) {
+        const std::unordered_set<uint64_t> own = blocks_of(q);
+        std::unordered_set<uint64_t> done;
+        for (auto& kv : S->all)
+            if (kv.second->state == Q_DONE)
+                tables_of(kv.second.get(), [&](const mapsq_table& t) {
+                    if (t.owned && t.block && !own.count(t.block)) done.insert(t.block);
+                });
+        double b = 0;
+        for (uint64_t blk : done) b += (double)ctx->arena.block_size(size_t(blk - 1));
+        return b;
+    };
+    auto room_alone = [&](const SQuery* q) {
+        const std::unordered_set<uint64_t> own = blocks_of(q);
+        std::unordered_set<uint64_t> others;
         for (auto& kv : S->all)
             if (kv.second.get() != q)
                 tables_of(kv.second.get(), [&](const mapsq_table& t) {
@@ -416,7 +440,16 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
                 });
         double b = (double)ctx->arena.free_bytes();
         for (uint64_t blk : others) b += (double)ctx->arena.block_size(size_t(blk - 1));
-        return b;
+        // a batch's shared block holding one of q's tables stays while q
+        // holds it; the part that is not q's comes back if q starts over
+        double mine = 0;
+        tables_of(q, [&](const mapsq_table& t) {
+            if (t.owned && t.block && ctx->shared_refs.count(size_t(t.block - 1)))
+                mine += 4.0 * (double)t.nrows * t.ncols;
+        });
+        for (uint64_t blk : own)
+            if (ctx->shared_refs.count(size_t(blk - 1))) b += (double)ctx->arena.block_size(size_t(blk - 1));
+        return b - mine;
     };
     std::vector<SQuery*> stalled;
     // a failed step: wait for memory while others hold some, unless the
@@ -443,14 +476,17 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
                     stalled.push_back(q);
                     return;
                 }
-            } else if (!q->restarted) {
-                double own = (double)ctx->arena.free_bytes();
-                std::unordered_set<uint64_t> blocks;
-                if (q->cur.owned && q->cur.block) blocks.insert(q->cur.block);
-                for (size_t i = 0; i < q->tabs.size(); i++)
-                    if (!q->consumed[i] && q->tabs[i].owned && q->tabs[i].block) blocks.insert(q->tabs[i].block);
-                for (uint64_t blk : blocks) own += (double)ctx->arena.block_size(size_t(blk - 1));
-                if (!blocks.empty() && need <= own) {
+            } else {
+                const double own = own_room(q);
+                // results that ended this round hold memory until the caller
+                // polls them: try again next round
+                const double unpolled = unpolled_room(q);
+                if (need > own && unpolled > 0 && need <= own + unpolled) {
+                    q->stalls++;
+                    progress++;
+                    return;
+                }
+                if (!q->restarted && !blocks_of(q).empty() && need <= own) {
                     q->restarted = true;
                     preempt_query(ctx, S, q);
                     S->hold = false;  // nothing else runs: admit it again next round
@@ -484,7 +520,9 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         }
         const mapsq_table& R = q->tabs[ps.pick];
         const bool sorted = q->cur.sorted_col == col_of(&q->cur, ps.key) + 1 && R.sorted_col == col_of(&R, ps.key) + 1;
-        if (sorted || q->cur.nrows + R.nrows >= PLAIN_STEP_RECORDS) {
+        // a query that started over runs alone through the plain path: its
+        // intermediates then get blocks of their own
+        if (sorted || q->restarted || q->cur.nrows + R.nrows >= PLAIN_STEP_RECORDS) {
             in_plain.push_back(q);
         } else {
             in_batch.push_back(q);
