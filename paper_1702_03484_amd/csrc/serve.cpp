@@ -454,8 +454,12 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     std::vector<SQuery*> stalled;
     // a failed step: wait for memory while others hold some, unless the
     // exact output could not fit even then
-    // A query alone whose output would fit the free space plus what it holds
-    // (its tables split the free space) starts over once, from a cleaner arena.
+    // A step whose output found no room.  With other queries in flight it
+    // waits (or first goes behind the queue) if the output would fit once
+    // they let go of everything.  Alone, it tries again next round when only
+    // results not yet polled stand in the way, and starts over once, from a
+    // cleaner arena, when its own tables split the free space.  Otherwise the
+    // query fails as it would alone.
     auto failed = [&](SQuery* q, mapsq_status e, int64_t need_rows) {
         const bool memory = e == MAPSQ_ERR_CAPACITY || e == MAPSQ_ERR_TOO_LARGE;
         if (memory && need_rows < SAT40_HOST) {
@@ -537,10 +541,12 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         if (st) return st;
         for (size_t k = 0; k < in_batch.size(); k++) {
             SQuery* q = in_batch[k];
-            if (per[k] != MAPSQ_OK)
+            if (per[k] != MAPSQ_OK) {
+                ctx->fail(per[k], "batched join step (" + std::to_string(need[k]) + " output rows) failed");
                 failed(q, per[k], need[k]);
-            else
+            } else {
                 advance(q, outs[k], q->steps[q->next].pick);
+            }
         }
     }
     for (SQuery* q : in_plain) {
