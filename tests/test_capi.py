@@ -42,3 +42,20 @@ def test_null_context_is_rejected_without_gpu_work():
     # NULL arena: INVALID_ARG before any device call
     assert lib.mapsq_create(0, None, 1 << 30, None, ctypes.byref(out)) == binding.MAPSQ_ERR_INVALID_ARG
     assert out.value is None
+
+
+def test_every_context_call_rejects_a_null_context():
+    """Each call that takes a context returns INVALID_ARG for NULL before any
+    device work (all other arguments zero or NULL)."""
+    lib = binding.lib()
+    checked = 0
+    for name, res, args in binding._SIGS:
+        if args[:1] != [binding._P] or name in ("mapsq_destroy", "mapsq_last_error"):
+            continue
+        fn = getattr(lib, name)
+        vals = [None] + [0 if a in (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                    ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double) else None
+                         for a in args[1:]]
+        assert fn(*vals) == binding.MAPSQ_ERR_INVALID_ARG, name
+        checked += 1
+    assert checked >= 20
