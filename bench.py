@@ -282,7 +282,11 @@ def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1
     serving.run_plain(sess, warm_q, np.zeros(len(warm_q)))
     serving.run_continuous(sess, warm_q, np.zeros(len(warm_q)))
     sat_plain, lat_p, st_p = serving.run_plain(sess, qs, np.zeros(len(qs)))
-    sat_cont, _, _ = serving.run_continuous(sess, qs, np.zeros(len(qs)))
+    sat_cont, _, st_c = serving.run_continuous(sess, qs, np.zeros(len(qs)))
+    # the same queries complete, and the same fail with the same status, in
+    # both modes (serving reports every memory failure as TOO_LARGE)
+    mem = np.where(st_p == B.MAPSQ_ERR_CAPACITY, B.MAPSQ_ERR_TOO_LARGE, st_p)
+    sat_cont["same_outcomes_as_plain"] = bool((st_c == mem).all())
     # one query at a time from t = 0: the gaps between completions are service times
     order = np.argsort(lat_p)
     svc = np.diff(np.concatenate([[0.0], lat_p[order]]))
