@@ -8,8 +8,11 @@
 // newly admitted queries map their patterns; then the next join step of
 // every active query runs in one batched launch (mapsq_join_batch's graph).
 // Queries that arrive while others are in flight join at the next round, so
-// their steps share launches with the others'.  The CPU assigns the steps
-// and the GPU joins them (the paper's coprocessing split).
+// their steps share launches with the others'.  A step whose output finds
+// no room waits, goes behind the queue or starts over rather than fail while
+// memory held by other queries could still make room, so every query ends
+// as it would alone (mapsq_query).  The CPU assigns the steps and the GPU
+// joins them (the paper's coprocessing split).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
