@@ -96,7 +96,10 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
             kmax = std::max(kmax, std::max(L->key_max, R->key_max));
         }
     }
-    const int key_bits = known ? bitlen((uint32_t)kmax) : 31;
+    // A join with an unknown key bound may hold any int32 key: its keys are
+    // sorted as k - INT32_MIN (the sign bit flipped), which keeps their
+    // signed order over the full 32 bits; joins with a bound sort k itself.
+    const int key_bits = known ? bitlen((uint32_t)kmax) : 32;
     uint64_t all_rec = 0;
     for (int i = 0; i < n; i++)
         if (plan[i].batched && !plan[i].empty) all_rec += (uint64_t)d[i].left->nrows + (uint64_t)d[i].right->nrows;
@@ -119,6 +122,7 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         BatchJoin& b = J[i];
         b.lkey = L->col[p.lk];
         b.rkey = R->col[p.rk];
+        b.key_base = (L->key_max < 0 || R->key_max < 0) ? INT32_MIN : 0;
         b.nvl = (int)p.lv.size();
         b.nvr = (int)p.rv.size();
         for (int c = 0; c < b.nvl; c++) b.lcol[c] = L->col[p.lv[c]];

@@ -9,85 +9,6 @@
 
 namespace mq {
 
-// ---------------------------------------------------------------- arena ---
-
-void Arena::init(char* base, size_t size) {
-    base_ = base;
-    size_ = size / ARENA_ALIGN * ARENA_ALIGN;
-    free_.clear();
-    used_.clear();
-    if (size_) free_[0] = size_;
-}
-
-size_t Arena::alloc(size_t bytes) {
-    bytes = align_up(std::max<size_t>(bytes, 1), ARENA_ALIGN);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-        if (it->second >= bytes) {
-            size_t off = it->first, sz = it->second;
-            free_.erase(it);
-            if (sz > bytes) free_[off + bytes] = sz - bytes;
-            used_[off] = bytes;
-            return off;
-        }
-    }
-    return SIZE_MAX;
-}
-
-void Arena::free(size_t off) {
-    auto u = used_.find(off);
-    if (u == used_.end()) return;
-    size_t sz = u->second;
-    used_.erase(u);
-    auto nx = free_.lower_bound(off);
-    if (nx != free_.end() && off + sz == nx->first) {
-        sz += nx->second;
-        nx = free_.erase(nx);
-    }
-    if (nx != free_.begin()) {
-        auto pv = std::prev(nx);
-        if (pv->first + pv->second == off) {
-            pv->second += sz;
-            return;
-        }
-    }
-    free_[off] = sz;
-}
-
-void Arena::shrink(size_t off, size_t bytes) {
-    auto u = used_.find(off);
-    if (u == used_.end()) return;
-    bytes = align_up(std::max<size_t>(bytes, 1), ARENA_ALIGN);
-    if (bytes >= u->second) return;
-    size_t tail = off + bytes, tsz = u->second - bytes;
-    u->second = bytes;
-    used_[tail] = tsz;
-    free(tail);
-}
-
-size_t Arena::free_bytes() const {
-    size_t s = 0;
-    for (auto& kv : free_) s += kv.second;
-    return s;
-}
-
-size_t Arena::largest() const {
-    size_t s = 0;
-    for (auto& kv : free_) s = std::max(s, kv.second);
-    return s;
-}
-
-void Block::reset() {
-    if (ctx && off != SIZE_MAX) ctx->arena.free(off);
-    off = SIZE_MAX;
-}
-
-Block alloc_block(Ctx* ctx, size_t bytes) {
-    Block b;
-    b.ctx = ctx;
-    b.off = ctx->arena.alloc(bytes);
-    return b;
-}
-
 uint32_t Ctx::next_epoch() {
     if (++epoch >= (1u << 22)) {
         // every word of the status array is re-tagged as unpublished
@@ -486,34 +407,6 @@ static int find_pred(const Store& S, int32_t p) {
     return int(it - S.preds.begin());
 }
 
-// Allocate an owned table of `rows` rows x `ncols` columns (one block).
-static mapsq_status alloc_table(Ctx* ctx, int64_t rows, int ncols, mapsq_table* t) {
-    const size_t colb = align_up(size_t(std::max<int64_t>(rows, 1)) * 4, ARENA_ALIGN);
-    size_t off = ctx->arena.alloc(colb * std::max(ncols, 1));
-    if (off == SIZE_MAX) return MAPSQ_ERR_CAPACITY;
-    t->owned = 1;
-    t->block = off + 1;
-    t->ncols = ncols;
-    t->nrows = rows;
-    for (int c = 0; c < ncols; c++) t->col[c] = reinterpret_cast<int32_t*>(ctx->arena.ptr(off + c * colb));
-    return MAPSQ_OK;
-}
-
-mapsq_status free_table(Ctx* ctx, mapsq_table* t) {
-    if (t->owned && t->block) {
-        const size_t off = size_t(t->block - 1);
-        auto it = ctx->shared_refs.find(off);
-        if (it != ctx->shared_refs.end() && --it->second > 0) {
-            zero_table(t);
-            return MAPSQ_OK;
-        }
-        if (it != ctx->shared_refs.end()) ctx->shared_refs.erase(it);
-        ctx->arena.free(off);
-    }
-    zero_table(t);
-    return MAPSQ_OK;
-}
-
 mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out) {
     zero_table(out);
     if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
@@ -697,13 +590,27 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
     return MAPSQ_OK;
 }
 
-// ------------------------------------------------------------------- join ---
-
-int col_of(const mapsq_table* t, int32_t v) {
-    for (int c = 0; c < t->ncols; c++)
-        if (t->var[c] == v) return c;
-    return -1;
+// Row ranges of index lookups (one launch, one synchronisation): for each
+// query the [lo, hi) part of its range whose sort columns equal v1 (and v2).
+mapsq_status locate_ranges(Ctx* ctx, const LocateQuery* lq, size_t n, int64_t* out) {
+    if (n == 0) return MAPSQ_OK;
+    Block buf = alloc_block(ctx, n * (sizeof(LocateQuery) + 16));
+    if (!buf.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for range queries");
+    LocateQuery* qd = buf.as<LocateQuery>();
+    int64_t* od = reinterpret_cast<int64_t*>(qd + n);
+    const size_t up = n * sizeof(LocateQuery), down = n * 16;
+    if (!ensure_stage(ctx, std::max(up, down))) return ctx->fail(MAPSQ_ERR_HIP, "pinned staging allocation failed");
+    std::memcpy(ctx->stage, lq, up);
+    hipError_t e = hipMemcpyAsync(qd, ctx->stage, up, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = launch_locate(qd, (int32_t)n, od, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->stage, od, down, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return ctx->fail(MAPSQ_ERR_HIP, std::string("range location: ") + hipGetErrorString(e));
+    std::memcpy(out, ctx->stage, down);
+    return MAPSQ_OK;
 }
+
+// ------------------------------------------------------------------- join ---
 
 mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name) {
     if (!t) return ctx->fail(MAPSQ_ERR_INVALID_ARG, std::string(name) + " is null");
@@ -810,7 +717,11 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         uint64_t kept = 0;
         e = hipSuccess;
         Block cs = alloc_block(ctx, compact_scratch_words((uint64_t)total) * 8);
-        if (!cs.ok()) e = hipErrorOutOfMemory;
+        if (!cs.ok()) {
+            free_table(ctx, &m);
+            free_table(ctx, &f);
+            return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the equality filter's row masks");
+        }
         ph = ctx->prof_begin(4);
         if (e == hipSuccess) e = launch_fill_u32(scalar32(ctx, SC_COUNT), 2, 0u, ctx->stream);
         if (e == hipSuccess) e = launch_compact(c, cs.as<uint64_t>(), ctx->stream);

@@ -193,6 +193,8 @@ inline int bitlen(uint64_t v) {
 mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, int32_t key_var, mapsq_table* out);
 mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out);
 mapsq_status free_table(Ctx* ctx, mapsq_table* t);
+// an owned table of rows x ncols in one arena block (CAPACITY when it does not fit)
+mapsq_status alloc_table(Ctx* ctx, int64_t rows, int ncols, mapsq_table* t);
 mapsq_status load_triples(Ctx* ctx, const int32_t* s, const int32_t* p, const int32_t* o, int64_t n,
                           uint32_t flags);
 mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
@@ -215,6 +217,8 @@ mapsq_table project_table(const mapsq_table& cur, const std::vector<int32_t>& wa
 mapsq_status key_sort_views(Ctx* ctx, const mapsq_pattern* pats, mapsq_table* tabs, int start,
                             const std::vector<PlanStep>& steps);
 bool ensure_stage(Ctx* ctx, size_t bytes);
+// [lo, hi) of each index lookup (2 int64 per query in out); one synchronisation
+mapsq_status locate_ranges(Ctx* ctx, const LocateQuery* q, size_t n, int64_t* out);
 // serving (serve.cpp)
 mapsq_status serve_config(Ctx* ctx, uint64_t budget_bytes, int32_t max_active);
 mapsq_status submit(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,

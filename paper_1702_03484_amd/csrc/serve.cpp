@@ -54,6 +54,11 @@ struct SQuery {
     int deferrals = 0;      // times it gave its memory back and went behind the queue
     double wait_bytes = 0;  // output bytes its join step `wait_step` found no room for
     size_t wait_step = 0;
+    int unpolled_waits = 0;  // rounds its join step waited, alone, for results the caller has not polled
+    uint64_t poll_mark = 0;  // the server's poll count when that count last started over
+    bool await_poll = false; // its admission waits for the caller to poll a result
+    int adm_waits = 0;       // rounds its admission waited for a poll
+    uint64_t adm_mark = 0;   // the server's poll count when that count last started over
 };
 
 // a waiting query may be passed over by later ones this many rounds, then
@@ -70,6 +75,13 @@ constexpr int MAX_DEFERRALS = 2;
 // join steps of at least this many records run through the plain join path
 // (merge join, semi-join reduction) rather than the batched kernels
 constexpr int64_t PLAIN_STEP_RECORDS = int64_t(1) << 20;
+// a query alone whose output needs memory held by finished results the
+// caller has not polled waits this many rounds without a poll, then fails
+constexpr int MAX_UNPOLLED_WAITS = 8;
+// rounds in a row in which no join step completes and no query ends, while
+// queries are in flight or waiting, before the scheduler gives up on them
+// (the policy above always makes progress; this bounds the loop regardless)
+constexpr int MAX_IDLE_ROUNDS = 256;
 
 }  // namespace
 
@@ -84,6 +96,10 @@ struct Server {
     uint64_t admissions = 0;
     bool hold = false;  // after a preemption: admit nothing until a query ends
     std::deque<uint64_t> finished;  // tickets in the order their queries ended
+    uint64_t polls = 0;             // finished queries retired by the caller
+    SQuery* solo = nullptr;         // a query that started over: nothing else is admitted until it ends
+    uint64_t ends = 0;              // queries that ended (done or failed)
+    int idle_rounds = 0;            // rounds in a row without a completed step or an end
 };
 
 void destroy_server(Ctx* ctx) {
@@ -182,19 +198,8 @@ static mapsq_status size_waiting(Ctx* ctx, Server* S) {
         q->sized = true;
     }
     if (lq.empty()) return MAPSQ_OK;
-    Block buf = alloc_block(ctx, lq.size() * (sizeof(LocateQuery) + 16));
-    if (!buf.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for range queries");
-    LocateQuery* qd = buf.as<LocateQuery>();
-    int64_t* od = reinterpret_cast<int64_t*>(qd + lq.size());
-    const size_t up = lq.size() * sizeof(LocateQuery), down = lq.size() * 16;
-    if (!ensure_stage(ctx, std::max(up, down))) return ctx->fail(MAPSQ_ERR_HIP, "pinned staging allocation failed");
-    std::memcpy(ctx->stage, lq.data(), up);
-    hipError_t e = hipMemcpyAsync(qd, ctx->stage, up, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = launch_locate(qd, (int32_t)lq.size(), od, ctx->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ctx->stage, od, down, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) return ctx->fail(MAPSQ_ERR_HIP, std::string("range location: ") + hipGetErrorString(e));
-    const int64_t* r = reinterpret_cast<const int64_t*>(ctx->stage);
+    std::vector<int64_t> r(2 * lq.size());
+    if (mapsq_status st = locate_ranges(ctx, lq.data(), lq.size(), r.data())) return st;
     for (size_t k = 0; k < who.size(); k++) who[k].first->rows[who[k].second] = r[2 * k + 1] - r[2 * k];
     return MAPSQ_OK;
 }
@@ -273,7 +278,9 @@ static void fail_query(Ctx* ctx, Server* S, SQuery* q, mapsq_status err) {
     q->err = err;
     q->why = ctx->err;
     S->hold = false;
+    if (S->solo == q) S->solo = nullptr;
     S->finished.push_back(q->ticket);
+    S->ends++;
 }
 
 // Give back everything a stalled query holds and queue it again, at the
@@ -289,6 +296,8 @@ static void preempt_query(Ctx* ctx, Server* S, SQuery* q, bool to_tail = false) 
     q->steps.clear();
     q->next = 0;
     q->stalls = 0;
+    q->wait_bytes = 0;
+    q->unpolled_waits = 0;
     S->reserved -= q->reserve;
     q->state = Q_WAITING;
     if (to_tail) {
@@ -305,7 +314,9 @@ static void finish_query(Server* S, SQuery* q) {
     q->state = Q_DONE;
     S->reserved -= q->reserve;
     S->hold = false;
+    if (S->solo == q) S->solo = nullptr;
     S->finished.push_back(q->ticket);
+    S->ends++;
 }
 
 // Map the patterns of a newly admitted query and fix its plan on the exact
@@ -350,50 +361,6 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         int k = 0;
         for (const SQuery* o : S->active) k += o != q && o->state == Q_ACTIVE;
         return k;
-    };
-    bool starving = false;
-    for (const SQuery* o : S->active) starving = starving || (o->state == Q_ACTIVE && o->stalls > MAX_STALLS);
-    for (auto it = S->waiting.begin(); it != S->waiting.end() && !S->hold && !starving;) {
-        SQuery* q = *it;
-        if ((int)S->active.size() >= S->max_active) break;
-        if (q->predicted == 0) predict(ctx, q);
-        const double r = q->predicted > S->budget ? 0.0 : q->predicted;
-        if (S->reserved + r > S->budget) {
-            if (++q->passed_over > MAX_PASSED_OVER) break;
-            ++it;
-            continue;
-        }
-        it = S->waiting.erase(it);
-        q->reserve = r;
-        S->reserved += r;
-        S->active.push_back(q);
-        q->state = Q_ACTIVE;
-        q->admitted = ++S->admissions;
-        st = activate(ctx, S, q);
-        if (st == MAPSQ_ERR_CAPACITY && live_others(q) > 0)
-            preempt_query(ctx, S, q);  // its partial matches do not fit yet
-        else if (st)
-            fail_query(ctx, S, q, st == MAPSQ_ERR_CAPACITY ? MAPSQ_ERR_TOO_LARGE : st);
-        if (S->hold) break;
-    }
-    // 2. the next join step of every active query: small ones together in
-    // one batched launch, large or key-sorted ones through the plain path
-    std::vector<SQuery*> in_batch, in_plain;
-    std::vector<mapsq_join_desc> descs;
-    int progress = 0;
-    // a finished step: the intermediate must stay joinable (under 2^31 rows)
-    auto advance = [&](SQuery* q, const mapsq_table& nxt, int pick) {
-        free_table(ctx, &q->cur);
-        free_table(ctx, &q->tabs[pick]);
-        q->consumed[pick] = true;
-        q->cur = nxt;
-        q->stalls = 0;
-        q->wait_bytes = 0;
-        progress++;
-        if (++q->next == q->steps.size())
-            finish_query(S, q);
-        else if (q->cur.nrows >= (int64_t(1) << 31))
-            fail_query(ctx, S, q, ctx->fail(MAPSQ_ERR_TOO_LARGE, "an intermediate of 2^31 rows or more"));
     };
     // bytes the query could use if every other query let go of what it
     // holds: the free space plus every arena block that only other queries'
@@ -454,6 +421,83 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
             if (ctx->shared_refs.count(size_t(blk - 1))) b += (double)ctx->arena.block_size(size_t(blk - 1));
         return b - mine;
     };
+    bool starving = false;
+    for (const SQuery* o : S->active) starving = starving || (o->state == Q_ACTIVE && o->stalls > MAX_STALLS);
+    for (auto it = S->waiting.begin(); it != S->waiting.end() && !S->hold && !starving;) {
+        SQuery* q = *it;
+        if ((int)S->active.size() >= S->max_active) break;
+        if (S->solo && q != S->solo) break;
+        // a query that starts over runs on an arena as clean as mapsq_query
+        // would find it: first the caller polls the finished results (a
+        // bounded number of rounds without a poll)
+        if (S->solo == q && unpolled_room(q) > 0) {
+            if (q->adm_mark != S->polls) {
+                q->adm_mark = S->polls;
+                q->adm_waits = 0;
+            }
+            if (++q->adm_waits <= MAX_UNPOLLED_WAITS) break;
+        }
+        // its partial matches found no room while finished results waited
+        // to be polled: admission waits for a poll (a bounded number of
+        // rounds), then it tries again
+        if (q->await_poll) {
+            if (q->adm_mark != S->polls) {
+                q->await_poll = false;
+                q->adm_waits = 0;
+            } else if (++q->adm_waits <= MAX_UNPOLLED_WAITS) {
+                break;
+            }
+        }
+        if (q->predicted == 0) predict(ctx, q);
+        const double r = q->predicted > S->budget ? 0.0 : q->predicted;
+        if (S->reserved + r > S->budget) {
+            if (++q->passed_over > MAX_PASSED_OVER) break;
+            ++it;
+            continue;
+        }
+        it = S->waiting.erase(it);
+        q->reserve = r;
+        S->reserved += r;
+        S->active.push_back(q);
+        q->state = Q_ACTIVE;
+        q->admitted = ++S->admissions;
+        st = activate(ctx, S, q);
+        if (st == MAPSQ_ERR_CAPACITY && live_others(q) > 0) {
+            preempt_query(ctx, S, q);  // its partial matches do not fit yet
+        } else if (st == MAPSQ_ERR_CAPACITY && !q->await_poll && q->adm_waits == 0 && unpolled_room(q) > 0) {
+            preempt_query(ctx, S, q);  // they may fit once finished results are polled
+            S->hold = false;
+            q->await_poll = true;
+            q->adm_mark = S->polls;
+            break;
+        } else if (st) {
+            fail_query(ctx, S, q, st == MAPSQ_ERR_CAPACITY ? MAPSQ_ERR_TOO_LARGE : st);
+        }
+        if (S->hold) break;
+    }
+    // 2. the next join step of every active query: small ones together in
+    // one batched launch, large or key-sorted ones through the plain path
+    std::vector<SQuery*> in_batch, in_plain;
+    std::vector<mapsq_join_desc> descs;
+    int progress = 0;
+    int steps_done = 0;  // join steps completed this round
+    const uint64_t ends0 = S->ends;
+    // a finished step: the intermediate must stay joinable (under 2^31 rows)
+    auto advance = [&](SQuery* q, const mapsq_table& nxt, int pick) {
+        free_table(ctx, &q->cur);
+        free_table(ctx, &q->tabs[pick]);
+        q->consumed[pick] = true;
+        q->cur = nxt;
+        q->stalls = 0;
+        q->wait_bytes = 0;
+        q->unpolled_waits = 0;
+        progress++;
+        steps_done++;
+        if (++q->next == q->steps.size())
+            finish_query(S, q);
+        else if (q->cur.nrows >= (int64_t(1) << 31))
+            fail_query(ctx, S, q, ctx->fail(MAPSQ_ERR_TOO_LARGE, "an intermediate of 2^31 rows or more"));
+    };
     std::vector<SQuery*> stalled;
     // a failed step: wait for memory while others hold some, unless the
     // exact output could not fit even then
@@ -467,11 +511,19 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
         const bool memory = e == MAPSQ_ERR_CAPACITY || e == MAPSQ_ERR_TOO_LARGE;
         if (memory && need_rows < SAT40_HOST) {
             const PlanStep& ps = q->steps[q->next];
-            const double cols = q->cur.ncols + q->tabs[ps.pick].ncols - 1;
-            const double need = 4.0 * (double)need_rows * cols;
+            const mapsq_table& R = q->tabs[ps.pick];
+            const double cols = q->cur.ncols + R.ncols - 1;
+            // the output, and the join's scratch held while it is written:
+            // 24 B per run of the smaller side for key-sorted inputs, else
+            // 24 B per record
+            const bool sorted = !ps.cross && q->cur.sorted_col == col_of(&q->cur, ps.key) + 1 &&
+                                R.sorted_col == col_of(&R, ps.key) + 1;
+            const double recs = sorted ? (double)std::min(q->cur.nrows, R.nrows) : (double)(q->cur.nrows + R.nrows);
+            const double need = 4.0 * (double)need_rows * cols + 24.0 * recs;
             if (live_others(q) > 0) {
                 q->wait_bytes = need;
                 q->wait_step = q->next;
+                q->unpolled_waits = 0;
                 if (need <= room_alone(q) && q->deferrals < MAX_DEFERRALS && !S->waiting.empty()) {
                     q->deferrals++;
                     preempt_query(ctx, S, q, true);
@@ -485,18 +537,36 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
                 }
             } else {
                 const double own = own_room(q);
-                // results that ended this round hold memory until the caller
-                // polls them: try again next round
+                // finished results hold memory until the caller polls them:
+                // wait for that (without running the join again) for a
+                // bounded number of rounds in which nothing is polled
+                // (those blocks can also split the free space: wait for them
+                // even when the free bytes alone would be enough)
                 const double unpolled = unpolled_room(q);
-                if (need > own && unpolled > 0 && need <= own + unpolled) {
-                    q->stalls++;
-                    progress++;
-                    return;
+                if (unpolled > 0 && need <= own + unpolled) {
+                    // a new wait (another step, or the first) counts from zero
+                    const bool again = q->wait_bytes > 0 && q->wait_step == q->next && q->unpolled_waits > 0;
+                    q->wait_bytes = need;
+                    q->wait_step = q->next;
+                    if (!again || q->poll_mark != S->polls) {
+                        q->unpolled_waits = 0;
+                        q->poll_mark = S->polls;
+                    }
+                    if (++q->unpolled_waits <= MAX_UNPOLLED_WAITS) {
+                        q->stalls++;
+                        progress++;
+                        return;
+                    }
+                    ctx->fail(MAPSQ_ERR_TOO_LARGE, "the step's output needs memory held by finished results "
+                                                   "that were not polled");
                 }
                 if (!q->restarted && !blocks_of(q).empty() && need <= own) {
+                    // it runs again alone, as mapsq_query would: nothing
+                    // else is admitted until it ends
                     q->restarted = true;
                     preempt_query(ctx, S, q);
-                    S->hold = false;  // nothing else runs: admit it again next round
+                    S->hold = false;
+                    S->solo = q;
                     progress++;
                     return;
                 }
@@ -513,6 +583,23 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
             (double)ctx->arena.largest() < q->wait_bytes) {
             q->stalls++;
             stalled.push_back(q);
+            continue;
+        }
+        // alone, waiting for finished results to be polled: the count of
+        // rounds starts over whenever the caller retires a result
+        if (q->wait_bytes > 0 && q->wait_step == q->next && live_others(q) == 0 && q->unpolled_waits > 0 &&
+            (double)ctx->arena.largest() < q->wait_bytes && unpolled_room(q) > 0) {
+            if (q->poll_mark != S->polls) {
+                q->unpolled_waits = 0;
+                q->poll_mark = S->polls;
+            }
+            if (++q->unpolled_waits > MAX_UNPOLLED_WAITS) {
+                ctx->fail(MAPSQ_ERR_TOO_LARGE, "the step's output needs memory held by finished results "
+                                               "that were not polled");
+                fail_query(ctx, S, q, MAPSQ_ERR_TOO_LARGE);
+            }
+            q->stalls++;
+            progress++;
             continue;
         }
         const PlanStep& ps = q->steps[q->next];
@@ -572,6 +659,29 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     S->active.erase(std::remove_if(S->active.begin(), S->active.end(),
                                    [](SQuery* q) { return q->state != Q_ACTIVE; }),
                     S->active.end());
+    // 4. a bound on rounds without a completed join step or an ended query
+    if (steps_done == 0 && S->ends == ends0 && (!S->active.empty() || !S->waiting.empty()))
+        S->idle_rounds++;
+    else
+        S->idle_rounds = 0;
+    if (S->idle_rounds > MAX_IDLE_ROUNDS) {
+        const std::string msg = "serving made no progress in " + std::to_string(MAX_IDLE_ROUNDS) + " rounds";
+        for (SQuery* q : S->active) {
+            ctx->fail(MAPSQ_ERR_STATE, msg);
+            fail_query(ctx, S, q, MAPSQ_ERR_STATE);
+        }
+        for (SQuery* q : S->waiting) {
+            ctx->fail(MAPSQ_ERR_STATE, msg);
+            fail_query(ctx, S, q, MAPSQ_ERR_STATE);
+        }
+        S->active.clear();
+        S->waiting.clear();
+        S->reserved = 0;
+        S->idle_rounds = 0;
+        if (n_active) *n_active = 0;
+        if (n_waiting) *n_waiting = 0;
+        return ctx->fail(MAPSQ_ERR_STATE, msg + "; every query in flight failed with MAPSQ_ERR_STATE");
+    }
     if (n_active) *n_active = (int32_t)S->active.size();
     if (n_waiting) *n_waiting = (int32_t)S->waiting.size();
     return MAPSQ_OK;
@@ -589,12 +699,14 @@ mapsq_status poll(Ctx* ctx, uint64_t ticket, int32_t* done, mapsq_table* out) {
         *out = q->result;
         *done = 1;
         S->all.erase(it);
+        S->polls++;
         return MAPSQ_OK;
     }
     if (q->state == Q_FAILED) {
         const mapsq_status err = q->err;
         const std::string msg = "query " + std::to_string(ticket) + " failed: " + q->why;
         *done = 1;
+        S->polls++;
         S->all.erase(it);  // destroys q
         return ctx->fail(err, msg);
     }

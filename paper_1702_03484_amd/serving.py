@@ -36,9 +36,11 @@ def _summary(lat, status, t_end, arrivals):
     }
 
 
-def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collect=None):
+def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collect=None, max_idle_rounds=5000):
     """Continuous batching: queries are submitted when they arrive; every
-    scheduler round admits, maps and runs one batched join step."""
+    scheduler round admits, maps and runs one batched join step.  Raises
+    RuntimeError after ``max_idle_rounds`` rounds in a row in which no query
+    ended (the library bounds its own rounds without progress as well)."""
     B.mapsq_serve_config(sess.ctx, budget_bytes, max_active)
     n = len(queries)
     lat = np.full(n, np.nan)
@@ -46,6 +48,7 @@ def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collec
     pending = {}
     i = 0
     rounds = 0
+    idle = 0
     t0 = time.perf_counter()
     while i < n or pending:
         now = time.perf_counter() - t0
@@ -59,10 +62,12 @@ def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collec
         rounds += 1
         torch.cuda.current_stream(sess.device).synchronize()
         now = time.perf_counter() - t0
+        idle += 1
         while True:  # the queries that ended this round, one call each
             tk, st, t = B.mapsq_poll_next(sess.ctx)
             if not tk:
                 break
+            idle = 0
             j = pending.pop(tk)
             status[j] = st
             lat[j] = now - arrivals[j]
@@ -70,6 +75,8 @@ def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collec
                 if collect is not None:
                     collect[j] = (list(t.vars), sess.to_numpy(t))
                 B.mapsq_table_free(sess.ctx, t)
+        if idle > max_idle_rounds:
+            raise RuntimeError(f"serving: no query ended in {max_idle_rounds} rounds ({len(pending)} pending)")
     out = _summary(lat, status, time.perf_counter() - t0, arrivals)
     out["rounds"] = rounds
     return out, lat, status

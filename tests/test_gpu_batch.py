@@ -164,3 +164,34 @@ def test_batch_chain(sess):
         assert_same_bag(host_table(sess, o2), exp)
     for t in outs1 + outs2:
         sess.free(t)
+
+
+def test_batch_full_int32_keys_unknown_bound(sess):
+    """Caller tables whose keys span the whole int32 range (negative keys
+    included) and whose key bound is unknown (key_max = -1): each batched
+    join equals the oracle as a bag and mapsq_join row for row (the plain
+    path rebases on the keys' minimum; the batched one sorts all 32 bits)."""
+    announce("batch of joins with keys over [INT32_MIN, INT32_MAX], key_max unknown")
+    r = np.random.default_rng(23)
+    joins, host = [], []
+    for i, (nl, nr, card, vl, vr) in enumerate([(5_000, 7_000, 300, 1, 1), (40_000, 900, 2_000, 2, 0),
+                                                 (1, 1, 1, 0, 1), (12_345, 12_345, 12_000, 1, 2)]):
+        keys = np.unique(r.integers(-(1 << 31), (1 << 31) - 1, size=card * 2, dtype=np.int64))[:card]
+        keys[0] = -(1 << 31)  # the extremes always take part
+        keys[-1] = (1 << 31) - 1
+        keys = keys.astype(np.int32)
+        lc = [keys[r.integers(0, card, nl)]] + [r.integers(-(1 << 31), (1 << 31) - 1, nl, dtype=np.int64).astype(np.int32)
+                                              for _ in range(vl)]
+        rc = [keys[r.integers(0, card, nr)]] + [r.integers(-(1 << 31), (1 << 31) - 1, nr, dtype=np.int64).astype(np.int32)
+                                              for _ in range(vr)]
+        lv = [0] + [10 + k for k in range(vl)]
+        rv = [0] + [20 + k for k in range(vr)]
+        L = sess.table(lv, [dev(c) for c in lc], key_max=-1)
+        R = sess.table(rv, [dev(c) for c in rc], key_max=-1)
+        joins.append((L, R, 0))
+        host.append((Table(lv, lc), Table(rv, rc)))
+    outs = sess.join_batch(joins)
+    assert any(t.nrows > 0 for t in outs)
+    check_against_plain_and_oracle(sess, joins, host, outs)
+    for t in outs:
+        sess.free(t)
