@@ -1,27 +1,38 @@
 """Benchmark of the MapSQ join path on one MI355X.
 
-Workload (default): the plain 2-pattern join ``?x p1 ?y . ?y p2 c`` over
-50M dictionary-encoded int32 triples (32 predicates, Zipf(1.0); subject and
-object IDs Zipf(1.1) over 10M entities), about 194M output rows.  The store
-and its indexes are built once and stay resident in HBM; one step is one
-``mapsq_query`` call: map both patterns, group the records by key (here both
-patterns come from the index sorted on the key, so the join pairs key runs
-directly), count/scan, materialise the result table in HBM, free it.
+Workload (default line): the plain 2-pattern join ``?x p1 ?y . ?y p2 c``
+over 50M dictionary-encoded int32 triples (32 predicates, Zipf(1.0); subject
+and object IDs Zipf(1.1) over 10M entities), about 194M output rows.  The
+store and its indexes are built once and stay resident in HBM; one step is
+one ``mapsq_query`` call: map both patterns, group the records by key (here
+both patterns come from the index sorted on the key, so the join pairs key
+runs directly), count/scan, materialise the result table in HBM, free it.
 ``value`` is joined output rows per second.
+
+Timing protocol: every timed repetition starts cold.  A 2 GiB device buffer
+is written first (eight times the 256 MB last-level cache), the stream is
+synchronised, and only then does the repetition's clock start; the
+repetition ends with a synchronisation.  The headline times ``--steps``
+such repetitions after ``--warmup`` untimed ones; the other legs report the
+median of 5 after 2 warm-ups.
 
 The roofline entry is for the dominant kernel (materialisation): its
 algorithmic bytes per launch divided by its average launch time, timed with
 HIP events recorded by the library on the stream it launches on.
 
-Two more measurements go into the same JSON line: "batched" (512
-independent subqueries, plain one-join-per-call against one batched launch
-per chain step, exact row-for-row agreement checked) and "serving" (a
-resident 500M-triple store, random-walk queries, one query at a time against
-continuous batching, saturated and at Poisson arrival rates, p50/p99).
+Further legs in the same JSON line: the same join forced through the radix
+sort ("cfg2_sort": every record shuffled, the paper's Sort), the
+four-pattern query over 200M triples ("cfg3", whose last join shuffles), a
+map scan with a variable predicate, a 16M + 16M-record shuffle join,
+"batched" (512 independent subqueries, plain one-join-per-call against one
+batched launch per chain step, exact row-for-row agreement checked) and
+"serving" (a resident 500M-triple store, random-walk queries, one query at
+a time against continuous batching, saturated and at Poisson arrival
+rates, p50/p99).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-batched] [--no-serving]
-       python bench.py --cfg4-only | --cfg5-only   (one of the two extra measurements)
+                       [--no-cfg3] [--no-batched] [--no-serving] [--warm]
+       python bench.py --cfg3-only | --cfg4-only | --cfg5-only | --shuffle-only
        python bench.py --copy-calibration   (plain copy of a known size, for PMC scaling)
 """
 from __future__ import annotations
@@ -37,17 +48,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "materialize_cfg2_traffic.json")
+FLUSH_BYTES = 2 << 30  # written before every timed repetition (the last-level cache is 256 MB)
+COLD = True
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def traffic_from_profile():
-    """HBM bytes per materialisation launch from the committed rocprofv3 PMC
-    summary, or None if it is missing or was taken on another kernel source."""
+def traffic_from_profile(path=PROFILE_TRAFFIC):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, or None
+    if it is missing or was taken on other kernel sources."""
     try:
-        d = json.load(open(PROFILE_TRAFFIC))
+        d = json.load(open(path))
     except (OSError, ValueError):
         return None
     from paper_1702_03484_amd.profile_summary import kernel_sha
@@ -55,6 +68,56 @@ def traffic_from_profile():
     if d.get("kernel_source_sha256") != kernel_sha():
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+_flush_buf = None
+
+
+def cold():
+    """Evict the caches (a 2 GiB write), then wait for the device."""
+    global _flush_buf
+    import torch
+
+    if COLD:
+        if _flush_buf is None:
+            _flush_buf = torch.empty(FLUSH_BYTES, dtype=torch.uint8, device="cuda")
+        _flush_buf.fill_(int(time.perf_counter_ns() & 0x7F))
+    torch.cuda.synchronize()
+
+
+def timed_reps(fn, reps=5, warm=2, prof_ctx=None):
+    """``warm`` untimed calls, then ``reps`` cold repetitions of ``fn``
+    (each timed from after the cache flush to a synchronisation).  With
+    ``prof_ctx``, the library's phase profile covers the timed repetitions
+    only and is returned too."""
+    import torch
+
+    from paper_1702_03484_amd import binding as B
+
+    out = None
+    for _ in range(warm):
+        out = fn()
+    torch.cuda.synchronize()
+    if prof_ctx is not None:
+        B.mapsq_profile_enable(prof_ctx, False)
+        B.mapsq_profile_enable(prof_ctx, True)
+    ts = []
+    for _ in range(reps):
+        cold()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    prof = B.mapsq_profile_read(prof_ctx) if prof_ctx is not None else None
+    if prof_ctx is not None:
+        B.mapsq_profile_enable(prof_ctx, False)
+    return ts, out, prof
+
+
+def median(xs):
+    xs = sorted(xs)
+    n = len(xs)
+    return xs[n // 2] if n % 2 else 0.5 * (xs[n // 2 - 1] + xs[n // 2])
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):
@@ -68,18 +131,45 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def cpu_baseline(w):
-    """The oracle, as it stands, on the full workload (one run)."""
-    import oracle
+def cpu_baseline(w, reps=3):
+    """The oracle as it stands, on the whole workload: map of both patterns
+    and the join, median of ``reps`` runs.  numpy runs on one thread; the
+    oracle's C hash join (OpenMP) is timed beside it on all the cores this
+    process may use, for the same map + join + output columns."""
+    import numpy as np
 
-    t0 = time.perf_counter()
-    p1 = oracle.pmt(w.s, w.p, w.o, w.patterns[0], key_var=1)
-    p2 = oracle.pmt(w.s, w.p, w.o, w.patterns[1], key_var=1)
-    rs = oracle.join(p1, p2, 1)
-    el = time.perf_counter() - t0
-    return {"value": rs.n / el, "unit": "rows/s", "cores": 1, "kind": "oracle",
-            "sample": f"whole workload, one run: numpy map of both patterns + sort-merge join, "
-                      f"{rs.n} rows in {el:.2f} s (numpy, single thread)"}, rs.n
+    import oracle
+    from oracle import hashjoin
+
+    cores = len(os.sched_getaffinity(0))
+    ts, n = [], 0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        p1 = oracle.pmt(w.s, w.p, w.o, w.patterns[0], key_var=1)
+        p2 = oracle.pmt(w.s, w.p, w.o, w.patterns[1], key_var=1)
+        rs = oracle.join(p1, p2, 1)
+        ts.append(time.perf_counter() - t0)
+        n = rs.n
+        del rs
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    th, nh = [], 0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        p1 = oracle.pmt(w.s, w.p, w.o, w.patterns[0], key_var=1)
+        p2 = oracle.pmt(w.s, w.p, w.o, w.patterns[1], key_var=1)
+        i, j = hashjoin.hj_pairs(p1.col(1), p2.col(1), nthreads=min(threads, cores))
+        cols = [p1.col(1)[i], p1.col(0)[i]] + [p2.col(v)[j] for v in p2.vars if v != 1]
+        th.append(time.perf_counter() - t0)
+        nh = int(i.size)
+        del i, j, cols
+    el, eh = median(ts), median(th)
+    return {"value": n / el, "unit": "rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole workload, median of {reps} runs: numpy map of both patterns + sort-merge join, "
+                      f"{n} rows in {el:.2f} s on one thread (host has {cores} cores available)",
+            "host_cores": cores,
+            "allcore": {"value": nh / eh, "unit": "rows/s", "cores": min(threads, cores), "kind": "oracle",
+                        "sample": f"whole workload, median of {reps} runs: numpy map + the oracle's C hash join "
+                                  f"(OpenMP, {min(threads, cores)} threads) + output columns, {nh} rows in {eh:.2f} s"}}, n
 
 
 def phase_table(prof):
@@ -121,22 +211,86 @@ def run_shuffle(n=16_000_000, key_bits=24, reps=5):
         L = sess.table([0, 1], [cols[0], vals[0]], key_max=(1 << key_bits) - 1)
         R = sess.table([0, 2], [cols[1], vals[1]], key_max=(1 << key_bits) - 1)
         sess.set_join_options(semijoin=1, merge=1, precount=1)
-        for _ in range(2):
-            sess.free(sess.join(L, R, 0))
-        torch.cuda.synchronize()
-        B.mapsq_profile_enable(sess.ctx, True)
-        t0 = time.perf_counter()
-        for _ in range(reps):
+
+        def one():
             t = sess.join(L, R, 0)
             rows = int(t.nrows)
             sess.free(t)
-        torch.cuda.synchronize()
-        el = (time.perf_counter() - t0) / reps
+            return rows
+
+        ts, rows, prof = timed_reps(one, reps=reps, prof_ctx=sess.ctx)
+        el = median(ts)
         st = sess.stats()
-        phases = phase_table(B.mapsq_profile_read(sess.ctx))
+        phases = phase_table(prof)
     return {"workload": f"join of two {n}-row tables, uniform keys over 2^{key_bits}, one value column each, "
                        "merge join, semi-join and exact pre-count off", "records": 2 * n, "rows": rows, "radix_bits": st.radix_bits,
-            "passes": st.passes, "ms_per_join": round(el * 1e3, 3), "phases": phases}
+            "passes": st.passes, "ms_per_join": round(el * 1e3, 3), "timing": "median of 5 cold repetitions",
+            "phases": phases}
+
+
+def run_cfg3(reps=5):
+    """The four-pattern query over 200M triples (three joins; the last one
+    shuffles), median of ``reps`` cold repetitions of ``mapsq_query``."""
+    import torch
+
+    from paper_1702_03484_amd import binding as B
+    from paper_1702_03484_amd.engine import MapSQ
+    from synth import query_cfg3, store_cfg3
+
+    sel = json.load(open(os.path.join(ROOT, "synth", "cfg3_draw.json")))
+    log("[cfg3] generating the 200M-triple store")
+    t0 = time.perf_counter()
+    w = store_cfg3(seed=sel["seed"])
+    pats = [tuple(p) for p in query_cfg3(w, sel["draw"])]
+    log(f"[cfg3] generated in {time.perf_counter() - t0:.1f} s; query {pats}")
+    with MapSQ(arena_bytes=48 << 30) as sess:
+        info = sess.load(w.s, w.p, w.o)
+        del w
+        torch.cuda.synchronize()
+
+        def one():
+            t = sess.query(pats)
+            rows = int(t.nrows)
+            sess.free(t)
+            return rows
+
+        ts, rows, prof = timed_reps(one, reps=reps, prof_ctx=sess.ctx)
+        st = sess.stats()
+    el = median(ts)
+    log(f"[cfg3] {rows} rows in {el * 1e3:.3f} ms (median)")
+    return {"workload": f"?x p1 ?y . ?x p2 ?z . ?x p3 c . ?w p4 ?y over {info.n_triples} int32 triples "
+                        "(64 predicates Zipf 1.0, s uniform and o Zipf 1.2 over 50M entities)",
+            "patterns": [list(p) for p in pats], "rows": rows, "ms_per_query": round(el * 1e3, 3),
+            "rows_per_s": rows / el, "timing": f"median of {reps} cold repetitions",
+            "last_join": {"path": int(st.path), "records_sorted": int(st.sorted_records), "radix_bits": int(st.radix_bits),
+                          "passes": int(st.passes), "segments": int(st.segments)},
+            "phases": phase_table(prof)}
+
+
+def run_cfg2_sort(sess, w, reps=5):
+    """The headline join with the merge join and the semi-join reduction
+    turned off: every record of both partial-match tables goes through the
+    radix sort (Algorithm 1's Sort), then count, scan and materialisation."""
+    from paper_1702_03484_amd import binding as B
+
+    sess.set_join_options(semijoin=1, merge=1)
+    try:
+        def one():
+            t = sess.query(w.patterns)
+            rows = int(t.nrows)
+            sess.free(t)
+            return rows
+
+        ts, rows, prof = timed_reps(one, reps=reps, prof_ctx=sess.ctx)
+        st = sess.stats()
+    finally:
+        sess.set_join_options()
+    el = median(ts)
+    assert st.path == B.MAPSQ_PATH_SORT
+    return {"workload": "the headline join with every record radix-sorted (merge join and semi-join off)",
+            "rows": rows, "ms_per_query": round(el * 1e3, 3), "rows_per_s": rows / el,
+            "timing": f"median of {reps} cold repetitions", "records_sorted": int(st.sorted_records),
+            "radix_bits": int(st.radix_bits), "passes": int(st.passes), "phases": phase_table(prof)}
 
 
 def run_cfg4(seed=1, n_sub=512, reps=2):
@@ -256,10 +410,18 @@ def run_cfg4(seed=1, n_sub=512, reps=2):
             "exact_vs_plain": exact}
 
 
-def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1.0, 2.0), seed=1):
+def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1.0, 2.0, 4.0), seed=1,
+             row_cap=1 << 26, stream=4000):
     """Serving over the resident store: plain one-query-at-a-time vs
-    continuous batching, Poisson arrivals at fractions of the plain form's
-    saturated rate; p50/p99 latency and completed queries/s."""
+    continuous batching, saturated and with Poisson arrivals at multiples of
+    the plain form's saturated rate; p50/p99 latency and queries/s.
+
+    The query mix is capped like the other workloads: the seeded random-walk
+    stream is drawn, each query is answered once by ``mapsq_query``, and a
+    query whose exact result has more than ``row_cap`` rows (or that cannot
+    fit the arena) is redrawn, i.e. skipped for the next one in the stream;
+    the skipped fraction is reported.  Saturated rates count every query
+    processed (completed or refused) per second of wall time."""
     import numpy as np
     import torch
 
@@ -272,12 +434,30 @@ def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1
     t0 = time.perf_counter()
     w = store_cfg5(n=n_triples, n_entities=max(1000, n_triples // 5))
     log(f"[cfg5] generated in {time.perf_counter() - t0:.1f} s; drawing queries")
-    qs = serving_cfg5(w, warm + n_queries, seed=seed)
+    drawn = serving_cfg5(w, stream, seed=seed)
     sess = MapSQ(arena_bytes=160 << 30)
     info = sess.load(w.s, w.p, w.o)
     del w
     torch.cuda.synchronize()
     log(f"[cfg5] store resident: {info.n_triples} triples, {info.n_predicates} predicates")
+    qs, over, examined, sizes = [], 0, 0, []
+    for q in drawn:
+        examined += 1
+        try:
+            t = B.mapsq_query(sess.ctx, q)
+            n = int(t.nrows)
+            B.mapsq_table_free(sess.ctx, t)
+        except B.MapSQError:
+            n = None
+        if n is None or n > row_cap:
+            over += 1
+            continue
+        qs.append(q)
+        sizes.append(n)
+        if len(qs) == warm + n_queries:
+            break
+    torch.cuda.synchronize()
+    log(f"[cfg5] mix: {len(qs)} queries within {row_cap} rows; {over} of the first {examined} drawn were over")
     warm_q, qs = qs[:warm], qs[warm:]
     serving.run_plain(sess, warm_q, np.zeros(len(warm_q)))
     serving.run_continuous(sess, warm_q, np.zeros(len(warm_q)))
@@ -287,33 +467,29 @@ def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1
     # both modes (serving reports every memory failure as TOO_LARGE)
     mem = np.where(st_p == B.MAPSQ_ERR_CAPACITY, B.MAPSQ_ERR_TOO_LARGE, st_p)
     sat_cont["same_outcomes_as_plain"] = bool((st_c == mem).all())
-    # one query at a time from t = 0: the gaps between completions are service times
-    order = np.argsort(lat_p)
-    svc = np.diff(np.concatenate([[0.0], lat_p[order]]))
-    svc_of = np.empty_like(svc)
-    svc_of[order] = svc
-    ok = st_p == 0
-    log(f"[cfg5] plain service time: completed {svc_of[ok].sum():.3f} s over {ok.sum()} queries, "
-        f"refused {svc_of[~ok].sum():.3f} s over {(~ok).sum()}")
-    for j in np.argsort(-svc_of)[:8]:
-        log(f"[cfg5]   {svc_of[j] * 1e3:8.2f} ms status {int(st_p[j])}: {qs[j]}")
-    log(f"[cfg5] saturated: plain {sat_plain['qps']:.0f} q/s, continuous {sat_cont['qps']:.0f} q/s")
+    log(f"[cfg5] saturated: plain {sat_plain['processed_qps']:.0f} q/s, continuous {sat_cont['processed_qps']:.0f} q/s")
     rows = []
     for f in loads:
-        qps = f * sat_plain["qps"]
+        qps = f * sat_plain["processed_qps"]
         arr = serving.poisson_arrivals(seed, len(qs), qps)
         p, _, _ = serving.run_plain(sess, qs, arr)
         c, _, _ = serving.run_continuous(sess, qs, arr)
         rows.append({"load": f, "offered_qps": qps, "plain": p, "continuous": c})
-        log(f"[cfg5] load {f}: plain p50 {p['p50_ms']:.2f} ms p99 {p['p99_ms']:.2f} ms {p['qps']:.0f} q/s; "
-            f"continuous p50 {c['p50_ms']:.2f} ms p99 {c['p99_ms']:.2f} ms {c['qps']:.0f} q/s")
+        log(f"[cfg5] load {f}: plain p50 {p['p50_ms']:.2f} ms p99 {p['p99_ms']:.2f} ms {p['qps']:.0f} q/s "
+            f"(saturated {p['saturated']}); continuous p50 {c['p50_ms']:.2f} ms p99 {c['p99_ms']:.2f} ms "
+            f"{c['qps']:.0f} q/s (saturated {c['saturated']})")
     sess.close()
     return {"workload": f"{info.n_triples}-triple resident store (128 predicates Zipf 1.0, entities Zipf 1.1 over "
-                        f"{n_triples // 5}), {len(qs)} random-walk queries of 1-5 patterns with 0-2 constants each",
+                        f"{n_triples // 5}), {len(qs)} random-walk queries of 1-5 patterns with 0-2 constants each, "
+                        f"results capped at {row_cap} rows",
+            "mix": {"examined": examined, "over_cap_or_refused": over, "redraw_rate": over / max(1, examined),
+                    "rows_p50": float(np.percentile(sizes, 50)) if sizes else None,
+                    "rows_max": int(max(sizes)) if sizes else None},
             "saturated_plain": sat_plain, "saturated_continuous": sat_cont, "poisson": rows}
 
 
 def main():
+    global COLD
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -321,18 +497,25 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--n", type=int, default=50_000_000, help="triples (default: the full workload)")
+    ap.add_argument("--no-cfg3", action="store_true", help="leave out the 200M-triple four-pattern query")
+    ap.add_argument("--cfg3-only", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="leave out the 512-subquery batched-vs-plain measurement")
     ap.add_argument("--cfg4-only", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="leave out the serving measurement (500M-triple store)")
     ap.add_argument("--cfg5-only", action="store_true")
     ap.add_argument("--shuffle-only", action="store_true", help="only the 16M + 16M-record shuffle join")
+    ap.add_argument("--warm", action="store_true", help="no cache flush before timed repetitions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the join runs on a single "
               "MI355X and there is no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    COLD = not args.warm
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.cfg3_only:
+        print(json.dumps(run_cfg3()), flush=True)
         return
     if args.cfg4_only:
         print(json.dumps(run_cfg4()), flush=True)
@@ -356,6 +539,7 @@ def main():
     w = store_cfg2() if full else store_cfg2(n=args.n, n_entities=max(1000, args.n // 5),
                                                row_cap=4 * args.n)
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s: {w.meta}")
+    left_rows = int((w.p == w.patterns[0][1]).sum())
 
     sess = MapSQ(arena_bytes=32 << 30)
     B.mapsq_profile_enable(sess.ctx, True)
@@ -368,39 +552,17 @@ def main():
     log(f"[bench] store loaded: {info.n_triples} triples, {info.n_predicates} predicates, max id {info.max_id}, "
         f"load {load_s:.2f} s (index build {index_ms:.1f} ms on the GPU)")
 
-    rows = 0
-    for i in range(args.warmup):
+    def step():
         t = sess.query(w.patterns)
         rows = int(t.nrows)
         sess.free(t)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done: {rows} rows per step")
+        return rows
 
-    B.mapsq_profile_enable(sess.ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        t = sess.query(w.patterns)
-        rows = int(t.nrows)
-        sess.free(t)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    prof = B.mapsq_profile_read(sess.ctx)
-    log(f"[bench] timed {args.steps} steps in {el:.4f} s")
-
+    # the headline: --steps cold repetitions after --warmup untimed ones
+    ts, rows, prof = timed_reps(step, reps=args.steps, warm=args.warmup, prof_ctx=sess.ctx)
+    el = sum(ts)
+    log(f"[bench] {rows} rows per step; timed {args.steps} steps in {el:.4f} s (median {median(ts) * 1e3:.3f} ms)")
     phases = phase_table(prof)
-    # Map of a pattern with only a constant object over the whole store: a
-    # scan of the raw columns with ballot compaction (the paper's Map)
-    c = w.patterns[1][2]
-    B.mapsq_profile_enable(sess.ctx, False)
-    B.mapsq_profile_enable(sess.ctx, True)
-    for _ in range(5):
-        t = sess.map((var(0), var(1), c))
-        sess.free(t)
-    torch.cuda.synchronize()
-    mp = phase_table(B.mapsq_profile_read(sess.ctx)).get("map")
-    if mp:
-        mp["pattern"] = "?s ?p c over the 50M-triple store (variable predicate: full scan + compaction)"
     mat = phases["materialize"]
     achieved = mat["gbs"]
     traffic = traffic_from_profile()
@@ -409,16 +571,36 @@ def main():
                 "kernel": "materialize_kernel", "avg_ms": mat["avg_ms"],
                 "bytes_per_launch": mat["bytes_per_launch"]}
 
+    # the same join with every record through the radix sort
+    log("[bench] the same join forced through the radix sort")
+    sort_leg = run_cfg2_sort(sess, w) if full else None
+    # Map of a pattern with only a constant object over the whole store: a
+    # scan of the raw columns with ballot compaction (the paper's Map)
+    c = w.patterns[1][2]
+
+    def scan():
+        t = sess.map((var(0), var(1), c))
+        n = int(t.nrows)
+        sess.free(t)
+        return n
+
+    _, _, mprof = timed_reps(scan, prof_ctx=sess.ctx)
+    mp = phase_table(mprof).get("map")
+    if mp:
+        mp["pattern"] = "?s ?p c over the 50M-triple store (variable predicate: full scan + compaction)"
+        mp["timing"] = "average of 5 cold repetitions"
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on the same workload")
         cpu, cpu_rows = cpu_baseline(w)
         if cpu_rows != rows:
             raise SystemExit(f"oracle row count {cpu_rows} != GPU row count {rows}")
-        log(f"[bench] oracle: {cpu['value']:.3e} rows/s")
+        log(f"[bench] oracle: {cpu['value']:.3e} rows/s (1 thread), {cpu['allcore']['value']:.3e} rows/s "
+            f"({cpu['allcore']['cores']} threads)")
 
     sess.close()
-    del sess
+    del sess, w
     torch.cuda.empty_cache()
 
     def guarded(fn, name):
@@ -430,6 +612,7 @@ def main():
         finally:
             torch.cuda.empty_cache()
 
+    cfg3 = None if (args.no_cfg3 or not full) else guarded(run_cfg3, "cfg3 measurement")
     shuffle = guarded(run_shuffle, "shuffle measurement")
     batched = None if args.no_batched else guarded(run_cfg4, "batched measurement")
     served = None if args.no_serving else guarded(run_cfg5, "serving measurement")
@@ -449,11 +632,14 @@ def main():
         "config": {"workload": "plain 2-pattern join ?x p1 ?y . ?y p2 c over 50M int32 triples "
                                "(32 predicates Zipf 1.0, s/o Zipf 1.1 over 10M entities)" if full else
                                f"plain 2-pattern join, {args.n} triples (reduced)",
-                   "triples": info.n_triples, "rows_per_step": rows, "left_rows": int(sess_stats_left(w)),
-                   "index_build_ms": round(index_ms, 2)},
+                   "triples": info.n_triples, "rows_per_step": rows, "left_rows": left_rows,
+                   "index_build_ms": round(index_ms, 2),
+                   "timing": "each step cold (2 GiB cache flush before it, outside the clock)" if COLD else "warm"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phases,
+        "cfg2_sort": sort_leg,
+        "cfg3": cfg3,
         "map": mp,
         "shuffle": shuffle,
         "batched": batched,
@@ -461,11 +647,6 @@ def main():
     }
     print(json.dumps(out), flush=True)
 
-
-def sess_stats_left(w):
-    import numpy as np
-
-    return int(np.count_nonzero(w.p == w.patterns[0][1]))
 
 
 if __name__ == "__main__":

@@ -407,8 +407,12 @@ static int find_pred(const Store& S, int32_t p) {
     return int(it - S.preds.begin());
 }
 
-mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out) {
+// What a pattern's map needs: the output's metadata (in `out`), the row
+// range of the store to read, and for a scan the equality tests and the
+// source columns.  An empty predicate range leaves rows = 0.
+mapsq_status map_plan(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out, MapPlan* mp) {
     zero_table(out);
+    *mp = MapPlan{};
     if (!ctx->store.loaded) return ctx->fail(MAPSQ_ERR_STATE, "no store loaded");
     const Store& S = ctx->store;
     const int32_t term[3] = {pat->s, pat->p, pat->o};
@@ -445,19 +449,20 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
     const int ncols = (int)vars.size();
     out->ncols = ncols;
     out->key_max = S.max_id;
-    for (int c = 0; c < ncols; c++) out->var[c] = vars[order[c]];
+    for (int c = 0; c < ncols; c++) {
+        out->var[c] = vars[order[c]];
+        mp->src_pos[c] = first_pos[order[c]];
+    }
 
     // the three source columns and the row range to scan
     const int32_t* col[3] = {S.s, S.p, S.o};
     int64_t lo = 0, hi = S.n;
     bool s_const = term[0] >= 0, p_const = term[1] >= 0, o_const = term[2] >= 0;
-    int nterm = 0;
-    int32_t ta[6], tb[6], tc[6];
     int sorted_pos = -1;  // the store position whose values ascend over the rows, if any
     if (p_const) {
         int pi = find_pred(S, term[1]);
         if (pi < 0) {
-            out->nrows = 0;
+            mp->empty = true;
             return MAPSQ_OK;
         }
         lo = S.pred_off[pi];
@@ -508,81 +513,109 @@ mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, ma
         // variable predicate: full scan of the raw columns, constants tested
         for (int pos = 0; pos < 3; pos++)
             if (term[pos] >= 0) {
-                ta[nterm] = pos;
-                tb[nterm] = -1;
-                tc[nterm] = term[pos];
-                nterm++;
+                mp->ta[mp->nterm] = pos;
+                mp->tb[mp->nterm] = -1;
+                mp->tc[mp->nterm] = term[pos];
+                mp->nterm++;
             }
     }
     for (int r = 0; r < nrep; r++) {
-        ta[nterm] = rep_a[r];
-        tb[nterm] = rep_b[r];
-        tc[nterm] = 0;
-        nterm++;
+        mp->ta[mp->nterm] = rep_a[r];
+        mp->tb[mp->nterm] = rep_b[r];
+        mp->tc[mp->nterm] = 0;
+        mp->nterm++;
     }
-    const int64_t rows = hi - lo;
     // rows of an index range (and any order-preserving compaction of them)
     // ascend on the index's next sort column
     if (sorted_pos >= 0 && term[sorted_pos] < 0)
         for (int c = 0; c < ncols; c++)
             if (out->var[c] == -term[sorted_pos] - 1) out->sorted_col = c + 1;
-    if (nterm == 0) {
-        // a view of the store
-        out->owned = 0;
-        out->nrows = rows;
-        for (int c = 0; c < ncols; c++) out->col[c] = const_cast<int32_t*>(col[first_pos[order[c]]]) + lo;
-        return MAPSQ_OK;
-    }
-    // scan + compaction into an owned table (sized for the whole range, then shrunk)
-    mapsq_table t{};
-    if (alloc_table(ctx, rows, ncols, &t)) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the map output");
+    for (int pos = 0; pos < 3; pos++) mp->col[pos] = col[pos];
+    mp->lo = lo;
+    mp->rows = hi - lo;
+    return MAPSQ_OK;
+}
+
+CompactArgs map_scan_args(const MapPlan& mp, int ncols, int32_t* const* out_cols, uint64_t* count) {
     CompactArgs a{};
     a.nin = 3;
-    for (int pos = 0; pos < 3; pos++) a.in[pos] = col[pos] ? col[pos] + lo : nullptr;
-    a.n = (uint64_t)rows;
-    a.nterm = nterm;
-    for (int i = 0; i < nterm; i++) {
-        a.term_a[i] = ta[i];
-        a.term_b[i] = tb[i];
-        a.term_c[i] = tc[i];
+    for (int pos = 0; pos < 3; pos++) a.in[pos] = mp.col[pos] ? mp.col[pos] + mp.lo : nullptr;
+    a.n = (uint64_t)mp.rows;
+    a.nterm = mp.nterm;
+    for (int i = 0; i < mp.nterm; i++) {
+        a.term_a[i] = mp.ta[i];
+        a.term_b[i] = mp.tb[i];
+        a.term_c[i] = mp.tc[i];
     }
     a.nout = ncols;
     for (int c = 0; c < ncols; c++) {
-        a.out_src[c] = first_pos[order[c]];
-        a.out[c] = t.col[c];
+        a.out_src[c] = mp.src_pos[c];
+        a.out[c] = out_cols[c];
     }
-    a.count = scalar64(ctx, SC_COUNT);
-    Block cs = alloc_block(ctx, compact_scratch_words((uint64_t)rows) * 8);
+    a.count = count;
+    return a;
+}
+
+double map_test_bytes(const MapPlan& mp) {
+    // every row reads the columns its equality tests use
+    bool used[3] = {false, false, false};
+    for (int i = 0; i < mp.nterm; i++) {
+        used[mp.ta[i]] = true;
+        if (mp.tb[i] >= 0) used[mp.tb[i]] = true;
+    }
+    return 4.0 * ((int)used[0] + (int)used[1] + (int)used[2]) * (double)mp.rows;
+}
+
+mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out) {
+    MapPlan mp;
+    if (mapsq_status st = map_plan(ctx, pat, key_var, out, &mp)) {
+        zero_table(out);
+        return st;
+    }
+    const int ncols = out->ncols;
+    if (mp.empty) {
+        out->nrows = 0;
+        return MAPSQ_OK;
+    }
+    if (mp.nterm == 0) {
+        // a view of the store
+        out->owned = 0;
+        out->nrows = mp.rows;
+        for (int c = 0; c < ncols; c++) out->col[c] = const_cast<int32_t*>(mp.col[mp.src_pos[c]]) + mp.lo;
+        return MAPSQ_OK;
+    }
+    // scan + compaction into an owned table laid out for the whole range
+    mapsq_table t{};
+    if (alloc_table(ctx, mp.rows, ncols, &t)) {
+        zero_table(out);
+        return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the map output");
+    }
+    CompactArgs a = map_scan_args(mp, ncols, t.col, scalar64(ctx, SC_COUNT));
+    Block cs = alloc_block(ctx, compact_scratch_words((uint64_t)mp.rows) * 8);
     if (!cs.ok()) {
         free_table(ctx, &t);
+        zero_table(out);
         return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the map's row masks");
     }
     int ph = ctx->prof_begin(0);
     hipError_t e = launch_fill_u32(scalar32(ctx, SC_COUNT), 2, 0u, ctx->stream);
     if (e == hipSuccess) e = launch_compact(a, cs.as<uint64_t>(), ctx->stream);
-    {
-        // every row reads the columns its equality tests use; kept rows also
-        // read and write their output columns (added after the count)
-        bool used[3] = {false, false, false};
-        for (int i = 0; i < nterm; i++) {
-            used[ta[i]] = true;
-            if (tb[i] >= 0) used[tb[i]] = true;
-        }
-        const int ncol_test = (int)used[0] + (int)used[1] + (int)used[2];
-        ctx->prof_end(ph, 4.0 * ncol_test * (double)rows);
-    }
+    ctx->prof_end(ph, map_test_bytes(mp));
     if (e != hipSuccess) {
         free_table(ctx, &t);
+        zero_table(out);
         return ctx->fail(MAPSQ_ERR_HIP, std::string("map scan: ") + hipGetErrorString(e));
     }
     uint64_t kept = 0;
     mapsq_status st = readback(ctx, scalar64(ctx, SC_COUNT), 8, &kept);
     if (st) {
         free_table(ctx, &t);
+        zero_table(out);
         return st;
     }
+    // kept rows also read and write their output columns
     if (ph >= 0) ctx->pending[ph].bytes += 8.0 * ncols * (double)kept;
-    // columns were laid out for `rows`; keep the layout, only the row count changes
+    // columns were laid out for the whole range; only the row count changes
     out->owned = 1;
     out->block = t.block;
     out->nrows = (int64_t)kept;

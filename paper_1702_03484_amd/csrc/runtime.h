@@ -192,6 +192,20 @@ inline int bitlen(uint64_t v) {
 // internal entry points (return mapsq_status, set ctx->err)
 mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, int32_t key_var, mapsq_table* out);
 mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out);
+// The plan of one pattern's map: which rows of the store to read and, for a
+// scan, which equality tests to apply (set up by map_plan together with the
+// output table's metadata).
+struct MapPlan {
+    bool empty = false;                        // the predicate does not occur
+    int64_t lo = 0, rows = 0;                  // rows [lo, lo + rows) of the source columns
+    const int32_t* col[3] = {nullptr, nullptr, nullptr};  // source of s, p, o (p is null on an index)
+    int src_pos[MAPSQ_MAX_COLS] = {};          // output column c comes from position src_pos[c]
+    int nterm = 0;                             // 0: the range itself is the answer (a view)
+    int32_t ta[6] = {}, tb[6] = {}, tc[6] = {};  // tests: pos ta == constant tc (tb < 0) or == pos tb
+};
+mapsq_status map_plan(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out, MapPlan* mp);
+CompactArgs map_scan_args(const MapPlan& mp, int ncols, int32_t* const* out_cols, uint64_t* count);
+double map_test_bytes(const MapPlan& mp);
 mapsq_status free_table(Ctx* ctx, mapsq_table* t);
 // an owned table of rows x ncols in one arena block (CAPACITY when it does not fit)
 mapsq_status alloc_table(Ctx* ctx, int64_t rows, int ncols, mapsq_table* t);

@@ -5,11 +5,11 @@
   python -m paper_1702_03484_amd.profile_summary pmc DIR COUNTER [REGEX]
       mean value of COUNTER per dispatch of the kernels matching REGEX, from
       *_counter_collection.csv
-  python -m paper_1702_03484_amd.profile_summary traffic MAT_FETCH MAT_WRITE COPY_FETCH COPY_WRITE COPY_BYTES OUT
-      HBM bytes per materialisation launch: FETCH_SIZE and WRITE_SIZE (KiB
-      per dispatch) each scaled by what the same counter reads for a plain
-      copy of COPY_BYTES, written as JSON together with the SHA-256 of the
-      kernel sources the counters were taken on
+  python -m paper_1702_03484_amd.profile_summary traffic K_FETCH K_WRITE COPY_FETCH COPY_WRITE COPY_BYTES OUT
+      HBM bytes per launch of a kernel: FETCH_SIZE and WRITE_SIZE (KiB per
+      dispatch, from two ``pmc`` summaries) each scaled by what the same
+      counter reads for a plain copy of COPY_BYTES, written as JSON together
+      with the SHA-256 of the device sources the counters were taken on
 """
 from __future__ import annotations
 
@@ -22,12 +22,20 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", "k_reduce.hip"), os.path.join(HERE, "csrc", "tile_ops.h")]
+
+
+def kernel_sources():
+    """Every device source of the library (kernels and the headers they include)."""
+    d = os.path.join(HERE, "csrc")
+    return sorted(os.path.join(d, f) for f in os.listdir(d) if f.endswith((".hip", ".h")))
 
 
 def kernel_sha() -> str:
+    """SHA-256 over every device source: a counter record taken on other
+    kernel code no longer matches."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in kernel_sources():
+        h.update(os.path.basename(p).encode())
         h.update(open(p, "rb").read())
     return h.hexdigest()
 

@@ -22,25 +22,37 @@ def poisson_arrivals(seed: int, n: int, qps: float) -> np.ndarray:
 
 
 def _summary(lat, status, t_end, arrivals):
+    """Completed and processed (completed or refused) queries per second of
+    the span from the first arrival to the end; ``saturated`` when the run
+    ended more than 5% after the last arrival (the queue did not keep up)."""
     ok = status == 0
     done = lat[ok]
+    first = arrivals[0] if len(arrivals) else 0.0
+    span = max(t_end - first, 1e-9)
+    last = arrivals[-1] if len(arrivals) else 0.0
     return {
         "queries": int(len(lat)),
         "completed": int(ok.sum()),
         "rejected": int((status == B.MAPSQ_ERR_TOO_LARGE).sum()),
         "failed": int((~ok & (status != B.MAPSQ_ERR_TOO_LARGE)).sum()),
         "wall_s": float(t_end),
-        "qps": float(ok.sum() / max(t_end - (arrivals[0] if len(arrivals) else 0.0), 1e-9)),
+        "arrival_span_s": float(last - first),
+        "saturated": bool(t_end - first > 1.05 * (last - first)),
+        "qps": float(ok.sum() / span),
+        "processed_qps": float(len(lat) / span),
         "p50_ms": float(np.percentile(done, 50) * 1e3) if done.size else None,
         "p99_ms": float(np.percentile(done, 99) * 1e3) if done.size else None,
     }
 
 
-def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collect=None, max_idle_rounds=5000):
+def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collect=None, max_idle_rounds=5000,
+                   collect_hash=None):
     """Continuous batching: queries are submitted when they arrive; every
     scheduler round admits, maps and runs one batched join step.  Raises
     RuntimeError after ``max_idle_rounds`` rounds in a row in which no query
-    ended (the library bounds its own rounds without progress as well)."""
+    ended (the library bounds its own rounds without progress as well).
+    ``collect[j]`` gets query j's (vars, host columns); ``collect_hash(j,
+    table)`` is called with each result table before it is freed."""
     B.mapsq_serve_config(sess.ctx, budget_bytes, max_active)
     n = len(queries)
     lat = np.full(n, np.nan)
@@ -74,6 +86,8 @@ def run_continuous(sess, queries, arrivals, budget_bytes=0, max_active=0, collec
             if t is not None:
                 if collect is not None:
                     collect[j] = (list(t.vars), sess.to_numpy(t))
+                if collect_hash is not None:
+                    collect_hash(j, t)
                 B.mapsq_table_free(sess.ctx, t)
         if idle > max_idle_rounds:
             raise RuntimeError(f"serving: no query ended in {max_idle_rounds} rounds ({len(pending)} pending)")

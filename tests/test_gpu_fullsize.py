@@ -1,19 +1,40 @@
-"""Full-size parity: the benchmark's 50M-triple join and the 200M-triple
-four-pattern query, checked against the oracle by the row count of every
-key (exact, all keys) and by the exact rows of sampled keys."""
+"""Full-size parity: every result of the five workloads at their full size
+against the oracle, as whole bags.
+
+The oracle's row count and bag hash of each result are stored in
+``tests/golden/fullsize.json`` by ``tests/golden/make_fullsize.py`` (which
+calls only the seeded generators and the oracle).  Here the same inputs are
+generated again, run through the library, and each result table is hashed
+where it lies in device memory (``tests/bag_hash.py``, the oracle's hash
+written with torch and pinned to it).  Equal row counts and equal 128-bit
+hashes of every result: the 50M-triple join (index-merge and forced-shuffle
+paths), the 200M-triple four-pattern query, both joins of every one of the
+512 batched subqueries (batched and one join per call), and the served
+queries of the 500M-triple store (served together and one at a time).
+"""
 import json
 import os
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
-from oracle.core import Table
-from synth import query_cfg3, store_cfg2, store_cfg3
+from paper_1702_03484_amd import binding as B
+from paper_1702_03484_amd import serving
+from paper_1702_03484_amd.engine import MapSQ
+from synth import batch_cfg4, cfg4_vars, query_cfg3, serving_cfg5, store_cfg2, store_cfg3, store_cfg5
+from tests.bag_hash import table_hash
 from tests.conftest import announce
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = json.load(open(os.path.join(HERE, "golden", "fullsize.json")))
+
+
+def expect(entry):
+    r = entry["result"] if "result" in entry else entry
+    return r["vars"], (r["rows"], int(r["h1"]), int(r["h2"]))
 
 
 def runs(sorted_keys):
@@ -26,70 +47,133 @@ def runs(sorted_keys):
 
 
 def test_cfg2_full_size(sess):
+    g = GOLDEN["cfg2"]
     w = store_cfg2()
-    announce(f"cfg2 full size: 50M triples, query {w.patterns}")
+    assert [list(p) for p in w.patterns] == g["patterns"] and w.meta["c"] == g["meta"]["c"]
+    announce(f"cfg2 full size: 50M triples, query {w.patterns}; merge path, semi-join + sort, sort")
     sess.load(w.s, w.p, w.o)
-    t = sess.query(w.patterns)
-    x, y = sess.to_numpy(t)  # projection [?x, ?y]; rows grouped by the join key ?y
-    assert t.vars == [0, 1]
-    P1 = oracle.pmt(w.s, w.p, w.o, w.patterns[0], key_var=1)
-    P2 = oracle.pmt(w.s, w.p, w.o, w.patterns[1], key_var=1)
-    keys, cl, cr = oracle.join_key_counts(P1, P2, 1)
-    assert int(t.nrows) == int(cl @ cr) == w.meta["predicted_rows"]
-    gk, glen = runs(y)
-    assert np.array_equal(gk, keys) and np.array_equal(glen, cl * cr)
-    # exact rows of sampled keys, and the hottest key (a cL x cR block)
-    r = np.random.default_rng(0)
-    starts = np.concatenate([[0], np.cumsum(glen)[:-1]])
-    pick = list(r.choice(keys.size, size=min(25, keys.size), replace=False)) + [int(np.argmax(cl * cr))]
-    for i in pick:
-        k = keys[i]
-        xs = x[starts[i]: starts[i] + glen[i]]
-        lx = np.sort(P1.col(0)[P1.col(1) == k])
-        # the key's rows are the product of its P1 rows and P2 rows, one
-        # block per row of whichever table the planner put on the left
-        a = xs.reshape(cl[i], cr[i])       # P1 on the left: rows constant
-        b = xs.reshape(cr[i], cl[i])       # P2 on the left: rows identical
-        ok_a = np.all(a == a[:, :1]) and np.array_equal(np.sort(a[:, 0]), lx)
-        ok_b = np.all(b == b[:1, :]) and np.array_equal(np.sort(b[0]), lx)
-        assert ok_a or ok_b, f"key {k}"
-    sess.free(t)
+    vs, exp = expect(g)
+    try:
+        # index views paired directly; the larger side filtered by the
+        # smaller's keys, then sorted; every record through the radix sort
+        for merge, semi, path in ((0, 0, B.MAPSQ_PATH_MERGE), (1, 0, B.MAPSQ_PATH_SEMIJOIN), (1, 1, B.MAPSQ_PATH_SORT)):
+            sess.set_join_options(semijoin=semi, merge=merge)
+            t = sess.query(w.patterns)
+            assert sess.stats().path == path
+            got = table_hash(sess, t, vs)
+            y = sess.column(t, list(t.vars).index(1)).cpu().numpy()
+            sess.free(t)
+            assert got == exp, f"path {path}: {got} != {exp}"
+        # the rows of every key (a readable check beside the hash)
+        P1 = oracle.pmt(w.s, w.p, w.o, w.patterns[0], key_var=1)
+        P2 = oracle.pmt(w.s, w.p, w.o, w.patterns[1], key_var=1)
+        keys, cl, cr = oracle.join_key_counts(P1, P2, 1)
+        gk, glen = runs(y)
+        assert np.array_equal(gk, keys) and np.array_equal(glen, cl * cr)
+    finally:
+        sess.set_join_options()
 
 
 def test_cfg3_full_size(sess):
+    g = GOLDEN["cfg3"]
     sel = json.load(open(os.path.join(os.path.dirname(HERE), "synth", "cfg3_draw.json")))
     w = store_cfg3(seed=sel["seed"])
     pats = [tuple(p) for p in query_cfg3(w, sel["draw"])]
-    assert pats == [tuple(p) for p in sel["patterns"]]
+    assert [list(p) for p in pats] == g["patterns"]
     announce(f"cfg3 full size: 200M triples, query {pats}")
     sess.load(w.s, w.p, w.o)
+    del w
     t = sess.query(pats)
-    assert t.vars == [0, 1, 2, 3] and int(t.nrows) == sel["j3_rows"]
-    cols = sess.to_numpy(t)
+    vs, exp = expect(g)
+    got = table_hash(sess, t, vs)
     sess.free(t)
-    # plan-agnostic checks: every value of ?x and of ?y gets exactly as many
-    # rows as the oracle's counting says, and sampled ?x values get exactly
-    # the oracle's rows.  Rows with a given (x, y) from P1 number
-    # cnt_P2(x) * cnt_P3(x) * cnt_P4(y).
-    x, y = cols[0].astype(np.int64), cols[1].astype(np.int64)
-    p1 = oracle.pmt(w.s, w.p, w.o, pats[0])
-    p2 = oracle.pmt(w.s, w.p, w.o, pats[1])
-    p3 = oracle.pmt(w.s, w.p, w.o, pats[2])
-    p4 = oracle.pmt(w.s, w.p, w.o, pats[3], key_var=1)
-    E = w.n_entities
-    c2 = np.bincount(p2.col(0), minlength=E).astype(np.int64)
-    c3 = np.bincount(p3.col(0), minlength=E).astype(np.int64)
-    c4 = np.bincount(p4.col(1), minlength=E).astype(np.int64)
-    wgt = c2[p1.col(0)] * c3[p1.col(0)] * c4[p1.col(1)]
-    assert int(wgt.sum()) == sel["j3_rows"]
-    assert np.array_equal(np.bincount(x, minlength=E), np.bincount(p1.col(0), weights=wgt, minlength=E).astype(np.int64))
-    assert np.array_equal(np.bincount(y, minlength=E), np.bincount(p1.col(1), weights=wgt, minlength=E).astype(np.int64))
-    j2 = oracle.query(w.s, w.p, w.o, pats[:3])
-    xs = np.unique(x)
-    r = np.random.default_rng(1)
-    for k in r.choice(xs, size=min(25, xs.size), replace=False):
-        m = x == k
-        got = Table([0, 1, 2, 3], [c[m] for c in cols])
-        a = Table(j2.vars, [c[j2.col(0) == k] for c in j2.cols])
-        exp = oracle.join(a, p4, 1)
-        assert np.array_equal(oracle.canonical_rows(got, [0, 1, 2, 3]), oracle.canonical_rows(exp, [0, 1, 2, 3]))
+    assert got == exp and exp[0] == sel["j3_rows"]
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    """The 512 subqueries resident in a session of their own."""
+    g = GOLDEN["cfg4"]
+    subs = batch_cfg4(seed=g["args"]["seed"], n_sub=g["args"]["n_sub"])
+    s = MapSQ(arena_bytes=96 << 30)
+    kmax = (1 << 31) - 2
+    tabs = []
+    for sub, gs in zip(subs, g["subqueries"]):
+        v = cfg4_vars(sub)
+        d = {}
+        for name in ("T1", "T2", "T3"):
+            if name in sub:
+                d[name] = s.table(v[name], [torch.from_numpy(c).cuda() for c in sub[name]], key_max=kmax)
+        assert [int(d[k].nrows) for k in ("T1", "T2", "T3") if k in d] == gs["rows"]
+        tabs.append(d)
+    del subs
+    yield s, tabs, g["subqueries"]
+    s.close()
+
+
+def test_cfg4_batched_full_size(cfg4):
+    s, tabs, gold = cfg4
+    announce("cfg4 full size: 512 subqueries, two batched launches, every result hashed against the oracle")
+    first = s.join_batch([(d["T1"], d["T2"], 0) for d in tabs])
+    chain = [i for i, d in enumerate(tabs) if "T3" in d]
+    second = dict(zip(chain, s.join_batch([(first[i], tabs[i]["T3"], 20) for i in chain])))
+    bad = []
+    for i, gs in enumerate(gold):
+        vs, exp = expect(gs["join1"])
+        if table_hash(s, first[i], vs) != exp:
+            bad.append((i, "join1"))
+        if i in second:
+            vs, exp = expect(gs["join2"])
+            if table_hash(s, second[i], vs) != exp:
+                bad.append((i, "join2"))
+    for t in list(first) + list(second.values()):
+        s.free(t)
+    assert not bad, f"{len(bad)} results differ from the oracle, first {bad[:5]}"
+
+
+def test_cfg4_plain_full_size(cfg4):
+    s, tabs, gold = cfg4
+    announce("cfg4 full size: 512 subqueries one join per call, every result hashed against the oracle")
+    bad = []
+    for i, (d, gs) in enumerate(zip(tabs, gold)):
+        r1 = s.join(d["T1"], d["T2"], 0)
+        vs, exp = expect(gs["join1"])
+        if table_hash(s, r1, vs) != exp:
+            bad.append((i, "join1"))
+        if "T3" in d:
+            r2 = s.join(r1, d["T3"], 20)
+            vs, exp = expect(gs["join2"])
+            if table_hash(s, r2, vs) != exp:
+                bad.append((i, "join2"))
+            s.free(r2)
+        s.free(r1)
+    assert not bad, f"{len(bad)} results differ from the oracle, first {bad[:5]}"
+
+
+def test_cfg5_served_full_size():
+    """The served queries of the 500M-triple store whose oracle result stays
+    within the stored row cap: each result, served together with the
+    others (continuous batching) and one at a time (mapsq_query), has the
+    oracle's bag."""
+    g = GOLDEN["cfg5"]
+    a = g["args"]
+    announce(f"cfg5 full size: {a['n']}-triple store, {len(g['parity'])} served queries within {a['row_cap']} rows")
+    w = store_cfg5(seed=a["seed"], n=a["n"])
+    qs = serving_cfg5(w, a["stream"], seed=a["seed"])
+    picked = [e["index"] for e in g["parity"]]
+    queries = [qs[i] for i in picked]
+    assert [[list(p) for p in q] for q in queries] == [e["patterns"] for e in g["parity"]]
+    with MapSQ(arena_bytes=128 << 30) as s:
+        s.load(w.s, w.p, w.o)
+        del w
+        exp = [expect(e) for e in g["parity"]]
+        got = {}
+        serving.run_continuous(s, queries, np.zeros(len(queries)), collect_hash=lambda j, t: got.__setitem__(
+            j, table_hash(s, t, exp[j][0])))
+        bad = [j for j in range(len(queries)) if got.get(j) != exp[j][1]]
+        assert not bad, f"served: queries {[picked[j] for j in bad]} differ from the oracle"
+        for j, q in enumerate(queries):
+            t = s.query(q)
+            h = table_hash(s, t, exp[j][0])
+            s.free(t)
+            assert h == exp[j][1], f"query {picked[j]} alone differs from the oracle"
