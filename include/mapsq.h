@@ -172,6 +172,32 @@ mapsq_status mapsq_map_pattern(mapsq_ctx* ctx, const mapsq_pattern* pattern, int
 mapsq_status mapsq_join(mapsq_ctx* ctx, const mapsq_table* left, const mapsq_table* right, int32_t key_var,
                         mapsq_table* out);
 
+/* Join into caller memory, allocating nothing: for callers that cannot
+ * allocate device memory at call time (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The same join as
+ * mapsq_join -- the same rows in the same order -- except
+ * that the result is written to the caller's columns out_cols[0 ..
+ * left->ncols + right->ncols - 2], each a device array of out_capacity
+ * int32 values owned by the caller, in the column order of mapsq_join, and
+ * that every scratch buffer comes from a fixed device array of the library
+ * (MAPSQ_JOIN_INTO_SCRATCH_BYTES per device, held from the first context on
+ * the device until the process ends) instead of the context's arena.  No
+ * device memory is allocated and the arena is not touched.  On success *out
+ * is a view (owned = 0) of out_cols with the exact row count.
+ * Limits and errors: at most MAPSQ_JOIN_INTO_MAX_RECORDS rows over both
+ * tables (else CAPACITY); the tables share only the key variable (else
+ * UNSUPPORTED); TOO_LARGE when |RS| exceeds out_capacity (the exact count
+ * is then in mapsq_last_join_stats().out_rows); INVALID_ARG for null
+ * output columns when out_capacity > 0.  All calls on one device share the
+ * scratch array: calls that overlap on one device (several host threads,
+ * or contexts on different streams without ordering) race.  Like
+ * mapsq_join, it synchronises once and returns with the materialisation
+ * enqueued on the context's stream. */
+#define MAPSQ_JOIN_INTO_SCRATCH_BYTES (64ull << 20)
+#define MAPSQ_JOIN_INTO_MAX_RECORDS (1ull << 21)
+mapsq_status mapsq_join_into(mapsq_ctx* ctx, const mapsq_table* left, const mapsq_table* right, int32_t key_var,
+                             int32_t* const* out_cols, int64_t out_capacity, mapsq_table* out);
+
 /* Query (Section 2: pattern-by-pattern merging, CPU plans, GPU joins): the
  * bag of solutions of the basic graph pattern pats[0..npats), projected on
  * select_vars[0..nselect) in that order (nselect = 0: every variable, in

@@ -24,6 +24,8 @@ MAPSQ_ERR_STATE = -6
 MAPSQ_PATH_SORT, MAPSQ_PATH_SEMIJOIN, MAPSQ_PATH_MERGE = 0, 1, 2
 MAPSQ_LOAD_DEVICE_PTRS = 1
 MAPSQ_LOAD_DEDUP = 2
+MAPSQ_JOIN_INTO_SCRATCH_BYTES = 64 << 20
+MAPSQ_JOIN_INTO_MAX_RECORDS = 1 << 21
 
 ERROR_NAMES = {
     -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "CAPACITY", -4: "TOO_LARGE", -5: "HIP", -6: "STATE",
@@ -121,6 +123,9 @@ _SIGS = [
      [_P, ctypes.POINTER(mapsq_pattern), ctypes.c_int32, ctypes.POINTER(mapsq_table)]),
     ("mapsq_join", ctypes.c_int32,
      [_P, ctypes.POINTER(mapsq_table), ctypes.POINTER(mapsq_table), ctypes.c_int32, ctypes.POINTER(mapsq_table)]),
+    ("mapsq_join_into", ctypes.c_int32,
+     [_P, ctypes.POINTER(mapsq_table), ctypes.POINTER(mapsq_table), ctypes.c_int32, ctypes.POINTER(_P),
+      ctypes.c_int64, ctypes.POINTER(mapsq_table)]),
     ("mapsq_query", ctypes.c_int32,
      [_P, ctypes.POINTER(mapsq_pattern), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
       ctypes.POINTER(mapsq_table)]),
@@ -211,6 +216,15 @@ def mapsq_map_pattern(ctx, pattern, key_var: int = -1) -> mapsq_table:
 def mapsq_join(ctx, left: mapsq_table, right: mapsq_table, key_var: int) -> mapsq_table:
     out = mapsq_table()
     _check(ctx, lib().mapsq_join(ctx, ctypes.byref(left), ctypes.byref(right), key_var, ctypes.byref(out)))
+    return out
+
+
+def mapsq_join_into(ctx, left: mapsq_table, right: mapsq_table, key_var: int, out_col_ptrs, out_capacity: int) -> mapsq_table:
+    """out_col_ptrs: device addresses of the caller's output columns."""
+    ptrs = (_P * max(1, len(out_col_ptrs)))(*out_col_ptrs)
+    out = mapsq_table()
+    _check(ctx, lib().mapsq_join_into(ctx, ctypes.byref(left), ctypes.byref(right), key_var, ptrs, out_capacity,
+                                      ctypes.byref(out)))
     return out
 
 

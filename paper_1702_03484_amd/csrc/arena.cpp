@@ -94,8 +94,18 @@ int col_of(const mapsq_table* t, int32_t v) {
 
 static void zero_table(mapsq_table* t) { std::memset(t, 0, sizeof(*t)); }
 
-// Allocate an owned table of `rows` rows x `ncols` columns (one block).
+// Allocate an owned table of `rows` rows x `ncols` columns (one block), or
+// hand out the caller's output columns when the context has them.
 mapsq_status alloc_table(Ctx* ctx, int64_t rows, int ncols, mapsq_table* t) {
+    if (ctx->out_cols) {
+        if (rows > ctx->out_cap) return MAPSQ_ERR_CAPACITY;
+        t->owned = 0;
+        t->block = 0;
+        t->ncols = ncols;
+        t->nrows = rows;
+        for (int c = 0; c < ncols; c++) t->col[c] = ctx->out_cols[c];
+        return MAPSQ_OK;
+    }
     const size_t colb = align_up(size_t(std::max<int64_t>(rows, 1)) * 4, ARENA_ALIGN);
     size_t off = ctx->arena.alloc(colb * std::max(ncols, 1));
     if (off == SIZE_MAX) return MAPSQ_ERR_CAPACITY;

@@ -66,7 +66,7 @@ mapsq_status mapsq_create(int device, void* arena, size_t arena_bytes, void* hip
         return MAPSQ_ERR_HIP;
     }
     if (mq::launch_fill_u32(ctx->small, mq::SMALL_WORDS, 0u, ctx->stream) != hipSuccess ||
-        !ctx->ensure_status(1 << 16)) {
+        !ctx->ensure_status(1 << 16) || mq::join_into_setup(device) != MAPSQ_OK) {
         (void)hipHostFree(ctx->pinned);
         delete c;
         return MAPSQ_ERR_HIP;
@@ -144,6 +144,14 @@ mapsq_status mapsq_join(mapsq_ctx* c, const mapsq_table* left, const mapsq_table
     return guarded(c, [&](Ctx* ctx) {
         if (!out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
         return mq::join_tables(ctx, left, right, key_var, out);
+    });
+}
+
+mapsq_status mapsq_join_into(mapsq_ctx* c, const mapsq_table* left, const mapsq_table* right, int32_t key_var,
+                             int32_t* const* out_cols, int64_t out_capacity, mapsq_table* out) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!out) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        return mq::join_into(ctx, left, right, key_var, out_cols, out_capacity, out);
     });
 }
 

@@ -661,6 +661,22 @@ mapsq_status check_table(Ctx* ctx, const mapsq_table* t, const char* name) {
     return MAPSQ_OK;
 }
 
+// Room for a join result of `rows` rows x `nc` columns: the caller's output
+// columns when the call writes there, else the arena's largest free block.
+static mapsq_status result_room(Ctx* ctx, uint64_t rows, int nc) {
+    if (ctx->out_cols) {
+        if (rows > (uint64_t)ctx->out_cap)
+            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result (" + std::to_string(rows) +
+                                                      " rows) exceeds the output capacity (" +
+                                                      std::to_string(ctx->out_cap) + " rows)");
+        return MAPSQ_OK;
+    }
+    if (ctx->arena.largest() < align_up(size_t(rows) * 4, ARENA_ALIGN) * nc)
+        return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result (" + std::to_string(rows) +
+                                                  " rows) exceeds the arena's free space");
+    return MAPSQ_OK;
+}
+
 mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, int32_t key_var, mapsq_table* out) {
     zero_table(out);
     mapsq_status st;
@@ -683,6 +699,8 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     const int nc_mat = 1 + (int)lv.size() + (int)rv.size();
     const int nc_out = nc_mat - (int)extra_r.size();
     if (nc_mat > MAPSQ_MAX_COLS) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 16 columns in the join");
+    if (ctx->out_cols && !extra_r.empty())  // the filter needs a materialised copy of its own
+        return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "a join into caller columns shares only the key variable");
     const uint32_t nL = (uint32_t)L->nrows, nR = (uint32_t)R->nrows;
     const uint32_t N = nL + nR;
 
@@ -707,7 +725,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         hipError_t e;
         int ph;
         if (extra_r.empty()) {
-            out->owned = 1;
+            out->owned = m.owned;
             out->block = m.block;
             out->nrows = (int64_t)total;
             for (int c = 0; c < nc_mat; c++) out->col[c] = m.col[c];
@@ -827,10 +845,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
             return MAPSQ_OK;
         }
         mapsq_table m{};
-        const size_t colb = align_up(size_t(total) * 4, ARENA_ALIGN);
-        if (ctx->arena.largest() < colb * nc_mat)
-            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result (" + std::to_string(total) +
-                                                      " rows) exceeds the arena's free space");
+        if ((st = result_room(ctx, total, nc_mat))) return st;
         if (alloc_table(ctx, (int64_t)total, nc_mat, &m))
             return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds the arena's free space");
         MatArgs a{};
@@ -918,9 +933,10 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
                 out->nrows = 0;
                 return MAPSQ_OK;
             }
-            if ((double)align_up(size_t(total) * 4, ARENA_ALIGN) * nc_mat > (double)ctx->arena.free_bytes())
-                return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result (" + std::to_string(total) +
-                                                          " rows) exceeds the arena's free space");
+            if (ctx->out_cols ? total > (uint64_t)ctx->out_cap
+                              : (double)align_up(size_t(total) * 4, ARENA_ALIGN) * nc_mat >
+                                    (double)ctx->arena.free_bytes())
+                return result_room(ctx, total, nc_mat);
         }
     }
 
@@ -1051,14 +1067,9 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         return MAPSQ_OK;
     }
     mapsq_table m{};
-    {
-        const size_t colb = align_up(size_t(total) * 4, ARENA_ALIGN);
-        if (ctx->arena.largest() < colb * nc_mat)
-            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result (" + std::to_string(total) +
-                                                      " rows) exceeds the arena's free space");
-        if (alloc_table(ctx, (int64_t)total, nc_mat, &m))
-            return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds the arena's free space");
-    }
+    if ((st = result_room(ctx, total, nc_mat))) return st;
+    if (alloc_table(ctx, (int64_t)total, nc_mat, &m))
+        return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds the arena's free space");
     MatArgs a{};
     a.keys = skeys;
     a.vals = svals;

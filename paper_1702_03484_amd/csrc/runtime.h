@@ -139,6 +139,10 @@ struct Ctx {
     void release_graphs();
     // serving scheduler (created on first use)
     Server* server = nullptr;
+    // When set, the next join result is written to these caller-owned
+    // columns (out_cap rows each) instead of an arena table.
+    int32_t* const* out_cols = nullptr;
+    int64_t out_cap = 0;
     // returns an interval handle (-1 when profiling is off)
     int prof_begin(int phase);
     void prof_end(int h, double bytes);
@@ -192,6 +196,11 @@ inline int bitlen(uint64_t v) {
 // internal entry points (return mapsq_status, set ctx->err)
 mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, int32_t key_var, mapsq_table* out);
 mapsq_status map_pattern(Ctx* ctx, const mapsq_pattern* pat, int32_t key_var, mapsq_table* out);
+// mapsq_join_into (noalloc.hip): the scratch array's address on the current
+// device, looked up once per device; the join into caller columns
+mapsq_status join_into_setup(int device);
+mapsq_status join_into(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, int32_t key_var,
+                       int32_t* const* out_cols, int64_t out_capacity, mapsq_table* out);
 // The plan of one pattern's map: which rows of the store to read and, for a
 // scan, which equality tests to apply (set up by map_plan together with the
 // output table's metadata).
