@@ -23,6 +23,7 @@ from .core import (  # noqa: F401
     match_pattern,
     pmt,
     join,
+    join_on,
     join_nested_loop,
     join_key_counts,
     join_cardinality,

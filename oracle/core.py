@@ -195,6 +195,40 @@ def join(L: Table, R: Table, key: int) -> Table:
     return Table([key] + lv + rv, cols)
 
 
+def join_on(L: Table, R: Table, keys) -> Table:
+    """Equi-join of two tables on every variable in ``keys`` at once: the bag
+    of (L row, R row) pairs that agree on all of them, i.e. their natural
+    join when ``keys`` lists every variable both bind.  This is the
+    relational meaning of merging partial matches that share more than one
+    variable (Section 2 merges on one shared variable; the second one must
+    then agree too).  Columns as :func:`join` with key ``keys[0]``; shared
+    variables outside ``keys`` are filtered for equality.
+
+    Each row's tuple of key values is numbered (equal tuples get equal
+    numbers, by ``np.unique`` over the rows of both tables), and the pairs
+    are those of the sort-merge join on that number.
+    """
+    keys = [int(v) for v in keys]
+    assert keys and all(v in L.vars and v in R.vars for v in keys)
+    lv, rv, extra = _out_vars(L, R, keys[0])
+    if L.n == 0 or R.n == 0:
+        i = j = np.zeros(0, np.int64)
+    else:
+        both = np.concatenate([np.stack([L.col(v) for v in keys], axis=1),
+                               np.stack([R.col(v) for v in keys], axis=1)])
+        _, tid = np.unique(both, axis=0, return_inverse=True)
+        tid = tid.reshape(-1)
+        i, j = _pairs_sort_merge(tid[:L.n], tid[L.n:])
+    rest = [v for v in extra if v not in keys]
+    if rest:
+        keep = np.ones(i.shape[0], dtype=bool)
+        for v in rest:
+            keep &= L.col(v)[i] == R.col(v)[j]
+        i, j = i[keep], j[keep]
+    cols = [L.col(keys[0])[i]] + [L.col(v)[i] for v in lv] + [R.col(v)[j] for v in rv]
+    return Table([keys[0]] + lv + rv, cols)
+
+
 def join_nested_loop(L: Table, R: Table, key: int) -> Table:
     """Nested-loop join (named in Section 2 as the plain join): every pair of
     rows is tested.  Pure Python; tiny inputs only."""

@@ -156,6 +156,62 @@ def test_join_extra_shared_variable_is_filtered(data):
     assert rows_set(a) == rows_set(oracle.join_nested_loop(L2, R2, 1))
 
 
+def _tiny_two_key_tables(data):
+    """Tables binding variables 1 and 3 on both sides (plus 0 on the left,
+    2 on the right), values drawn from small ranges so that pairs agree on
+    one shared variable but not the other often."""
+    nl = data.draw(st.integers(0, 30))
+    nr = data.draw(st.integers(0, 30))
+
+    def col(n, hi):
+        return np.array(data.draw(st.lists(st.integers(-2, hi), min_size=n, max_size=n)), np.int32)
+
+    L = Table([1, 0, 3], [col(nl, 4), col(nl, 50), col(nl, 3)])
+    R = Table([3, 2, 1], [col(nr, 3), col(nr, 50), col(nr, 4)])
+    return L, R
+
+
+@settings(max_examples=200, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(st.data())
+def test_join_on_two_keys_equals_nested_loops(data):
+    """The two-variable join is the bag of row pairs that agree on both
+    variables, enumerated here by plain nested loops."""
+    L, R = _tiny_two_key_tables(data)
+    got = oracle.join_on(L, R, [1, 3])
+    assert got.vars == [1, 0, 3, 2]
+    exp = []
+    for a in range(L.n):
+        for b in range(R.n):
+            if L.col(1)[a] == R.col(1)[b] and L.col(3)[a] == R.col(3)[b]:
+                exp.append((int(L.col(1)[a]), int(L.col(0)[a]), int(L.col(3)[a]), int(R.col(2)[b])))
+    assert rows_set(got) == sorted(exp)
+    # joining on the first variable and filtering the second gives the same bag
+    assert rows_set(oracle.join(L, R, 1)) == sorted(exp)
+    # key order only changes which variable leads the columns
+    swapped = oracle.join_on(L, R, [3, 1])
+    assert sorted(swapped.vars) == sorted(got.vars)
+    assert rows_set(swapped, got.vars) == sorted(exp)
+
+
+def test_join_on_equals_sqlite():
+    r = np.random.default_rng(8)
+    n1, n2 = 4000, 3000
+    L = Table([0, 5, 1], [r.integers(0, 40, n1), r.integers(0, 30, n1), r.integers(0, 1000, n1)])
+    R = Table([5, 2, 0], [r.integers(0, 30, n2), r.integers(0, 1000, n2), r.integers(0, 40, n2)])
+    con = sqlite3.connect(":memory:")
+    con.execute("create table L(x int, y int, a int)")
+    con.execute("create table R(y int, b int, x int)")
+    con.executemany("insert into L values(?,?,?)", L.rows().tolist())
+    con.executemany("insert into R values(?,?,?)", R.rows().tolist())
+    exp = sorted(con.execute("select L.x, L.y, L.a, R.b from L join R on L.x = R.x and L.y = R.y").fetchall())
+    got = oracle.join_on(L, R, [0, 5])
+    assert got.vars == [0, 5, 1, 2]
+    assert rows_set(got) == exp
+    # an empty side: no rows, every column
+    E = Table([5, 2, 0], [np.zeros(0, np.int32)] * 3)
+    assert oracle.join_on(L, E, [0, 5]).n == 0 and oracle.join_on(L, E, [0, 5]).vars == [0, 5, 1, 2]
+
+
 def test_cardinality_closed_form():
     # |RS| = sum_k cL(k) * cR(k), computed here from two bincounts
     L = Table([0, 1], random_table(1, 20000, 500, 1, key_ids=np.arange(700)))

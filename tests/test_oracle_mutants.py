@@ -74,7 +74,21 @@ def pin_query_bruteforce():
         assert _rows(a) == _rows(b)
 
 
-PINS = [pin_table1, pin_nested_loops, pin_closed_form, pin_map_bruteforce, pin_query_bruteforce]
+def pin_two_key_nested_loops():
+    r = np.random.default_rng(5)
+    for n1, n2 in ((40, 30), (25, 60)):
+        L = Table([1, 0, 3], [r.integers(0, 4, n1), r.integers(0, 9, n1), r.integers(0, 3, n1)])
+        R = Table([3, 2, 1], [r.integers(0, 3, n2), r.integers(0, 9, n2), r.integers(0, 4, n2)])
+        exp = sorted((int(L.col(1)[a]), int(L.col(0)[a]), int(L.col(3)[a]), int(R.col(2)[b]))
+                     for a in range(n1) for b in range(n2)
+                     if L.col(1)[a] == R.col(1)[b] and L.col(3)[a] == R.col(3)[b])
+        got = oracle.join_on(L, R, [1, 3])
+        assert got.vars == [1, 0, 3, 2]
+        assert sorted(map(tuple, got.rows().tolist())) == exp
+
+
+PINS = [pin_table1, pin_nested_loops, pin_closed_form, pin_map_bruteforce, pin_query_bruteforce,
+        pin_two_key_nested_loops]
 
 
 def _caught():
@@ -152,6 +166,24 @@ def mut_right_from_left(L, R, key):
     return Table([key] + lv + rv, cols)
 
 
+def mut_join_on_first_key_only(L, R, keys):
+    # the pairs agree on the first key only (the others never compared)
+    lv, rv, extra = core._out_vars(L, R, keys[0])
+    i, j = _orig_pairs(L.col(keys[0]), R.col(keys[0]))
+    cols = [L.col(keys[0])[i]] + [L.col(v)[i] for v in lv] + [R.col(v)[j] for v in rv]
+    return Table([keys[0]] + lv + rv, cols)
+
+
+def mut_join_on_separate_numbering(L, R, keys):
+    # each table numbers its own key tuples: equal numbers no longer mean equal tuples
+    lv, rv, extra = core._out_vars(L, R, keys[0])
+    _, tl = np.unique(np.stack([L.col(v) for v in keys], 1), axis=0, return_inverse=True)
+    _, tr = np.unique(np.stack([R.col(v) for v in keys], 1), axis=0, return_inverse=True)
+    i, j = _orig_pairs(tl.reshape(-1), tr.reshape(-1))
+    cols = [L.col(keys[0])[i]] + [L.col(v)[i] for v in lv] + [R.col(v)[j] for v in rv]
+    return Table([keys[0]] + lv + rv, cols)
+
+
 MUTANTS = [
     ("_pairs_sort_merge", mut_drop_last_group),
     ("_pairs_sort_merge", mut_transposed_index),
@@ -160,13 +192,15 @@ MUTANTS = [
     ("match_pattern", mut_wrong_position),
     ("join", mut_no_extra_filter),
     ("join", mut_right_from_left),
+    ("join_on", mut_join_on_first_key_only),
+    ("join_on", mut_join_on_separate_numbering),
 ]
 
 
 @pytest.mark.parametrize("name,fn", MUTANTS, ids=[m[1].__name__ for m in MUTANTS])
 def test_planted_mistake_is_caught(monkeypatch, name, fn):
     monkeypatch.setattr(core, name, fn)
-    if name in ("match_pattern", "join"):
+    if name in ("match_pattern", "join", "join_on"):
         monkeypatch.setattr(oracle, name, fn)
     caught = _caught()
     assert caught, f"no pin caught the planted mistake {fn.__name__}"
