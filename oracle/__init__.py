@@ -24,6 +24,7 @@ from .core import (  # noqa: F401
     pmt,
     join,
     join_on,
+    join_on_cardinality,
     join_nested_loop,
     join_key_counts,
     join_cardinality,

@@ -22,9 +22,11 @@ design notes of the repository): bag semantics with no implicit
 de-duplication; only variables become columns (constants such as
 "Hospital" in Table 1 are not materialised); output columns are
 ``[key, left values in left order, right values in right order]`` as in
-Table 1(c); further shared variables become an equality filter after the
-key join; a pattern that shares nothing with the bound variables joins by
-cross product; row order is not part of the result (compare as multisets).
+Table 1(c); when two tables share more than one variable, every shared
+variable must agree (``join_on`` joins on all of them; ``join`` joins on one
+and filters the others, the same bag); a pattern that shares nothing with
+the bound variables joins by cross product; row order is not part of the
+result (compare as multisets).
 
 Pins (tests marked ``not gpu``): Table 1 of the paper as a golden fixture;
 nested loops on tiny inputs; brute-force enumeration of query witnesses;
@@ -229,6 +231,22 @@ def join_on(L: Table, R: Table, keys) -> Table:
     return Table([keys[0]] + lv + rv, cols)
 
 
+def join_on_cardinality(L: Table, R: Table, keys) -> int:
+    """|join_on(L, R, keys)| before any further equality filter: the sum over
+    key tuples of (rows of L with the tuple) x (rows of R with it)."""
+    keys = [int(v) for v in keys]
+    if L.n == 0 or R.n == 0:
+        return 0
+    both = np.concatenate([np.stack([L.col(v) for v in keys], axis=1),
+                           np.stack([R.col(v) for v in keys], axis=1)])
+    _, tid = np.unique(both, axis=0, return_inverse=True)
+    tid = tid.reshape(-1)
+    m = int(tid.max()) + 1
+    cl = np.bincount(tid[:L.n], minlength=m).astype(np.int64)
+    cr = np.bincount(tid[L.n:], minlength=m).astype(np.int64)
+    return int(cl @ cr)
+
+
 def join_nested_loop(L: Table, R: Table, key: int) -> Table:
     """Nested-loop join (named in Section 2 as the plain join): every pair of
     rows is tested.  Pure Python; tiny inputs only."""
@@ -284,9 +302,10 @@ def query(s, p, o, patterns, select=None, max_rows=None) -> Table:
 
     Fixed oracle order: start from pattern 0, then repeatedly take the
     lowest-index remaining pattern that shares a variable with the bound
-    ones and join on the first shared variable in the query's
-    first-appearance order (the rest are filtered by equality); with none
-    connected, take the lowest-index one by cross product.  Columns end in
+    ones and join on every shared variable at once (:func:`join_on`, the
+    same bag as joining on the first shared one and filtering the others
+    for equality, without the larger intermediate); with none connected,
+    take the lowest-index one by cross product.  Columns end in
     first-appearance order, then ``select`` projects.  With ``max_rows``,
     an intermediate that would exceed it raises OverflowError before it is
     built (a guard on the oracle's memory; results are unchanged).
@@ -313,9 +332,9 @@ def query(s, p, o, patterns, select=None, max_rows=None) -> Table:
         else:
             nxt = tabs[pick]
             shared = [v for v in order if v in cur.vars and v in nxt.vars]
-            if max_rows is not None and join_cardinality(cur, nxt, shared[0]) > max_rows:
+            if max_rows is not None and join_on_cardinality(cur, nxt, shared) > max_rows:
                 raise OverflowError("intermediate over max_rows")
-            cur = join(cur, nxt, shared[0])
+            cur = join_on(cur, nxt, shared)
         left.remove(pick)
     vs = [v for v in order if v in cur.vars]
     cur = Table(vs, [cur.col(v) for v in vs], n=cur.n)

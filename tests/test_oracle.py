@@ -207,6 +207,7 @@ def test_join_on_equals_sqlite():
     got = oracle.join_on(L, R, [0, 5])
     assert got.vars == [0, 5, 1, 2]
     assert rows_set(got) == exp
+    assert oracle.join_on_cardinality(L, R, [0, 5]) == len(exp)
     # an empty side: no rows, every column
     E = Table([5, 2, 0], [np.zeros(0, np.int32)] * 3)
     assert oracle.join_on(L, E, [0, 5]).n == 0 and oracle.join_on(L, E, [0, 5]).vars == [0, 5, 1, 2]
