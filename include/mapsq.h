@@ -117,6 +117,7 @@ typedef struct {
 #define MAPSQ_PATH_SORT 0     /* LSD radix sort of both sides' records */
 #define MAPSQ_PATH_SEMIJOIN 1 /* the same after the semi-join reduction of the larger side */
 #define MAPSQ_PATH_MERGE 2    /* both sides already sorted on the key: runs paired directly */
+#define MAPSQ_PATH_COMPOSITE 3 /* radix sort on a composite key of two shared variables */
 
 /* Create a context on `device`.  `arena` is device memory of `arena_bytes`
  * bytes owned by the caller and kept alive until mapsq_destroy; it must be
@@ -162,8 +163,15 @@ mapsq_status mapsq_predicate_stats(mapsq_ctx* ctx, int32_t predicate, int64_t* t
 mapsq_status mapsq_map_pattern(mapsq_ctx* ctx, const mapsq_pattern* pattern, int32_t key_var, mapsq_table* out);
 
 /* Join (Algorithm 1): RS = left JOIN right on variable `key_var`, which both
- * tables must bind.  Other variables bound by both sides are filtered for
- * equality after the key join.  Tables may be views, owned results or
+ * tables must bind.  When both tables bind a further variable, the join is
+ * on the composite key (key_var, k2), k2 being the first such variable in
+ * the left table's column order: the records are sorted on both variables
+ * (as one packed word when their two ranges fit 32 bits, else on k2 and
+ * then stably on key_var) and only pairs that agree on both meet, so the
+ * result is the natural join and right's copy of k2 is never materialised
+ * (stats path MAPSQ_PATH_COMPOSITE; mapsq_set_join_options can ask for the
+ * single-variable join plus an equality filter instead).  Any third shared
+ * variable is filtered for equality after the join.  Tables may be views, owned results or
  * caller-owned columns (owned = 0, key_max = bound or -1).  Each side may
  * hold at most 2^31 - 1 rows.  TOO_LARGE when |RS| exceeds the arena's free
  * space or 2^40 rows (nothing is allocated then).  Enqueues the sort and the
@@ -294,8 +302,9 @@ mapsq_status mapsq_last_join_stats(mapsq_ctx* ctx, mapsq_join_stats* out);
  * gives the same rows in the same order. */
 mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_per_thread);
 
-/* How mapsq_join / mapsq_query group records by key; every choice gives
- * the same rows in the same order (or the same error).
+/* How mapsq_join / mapsq_query group records by key; every choice of
+ * semijoin, merge and precount gives the same rows in the same order (or the
+ * same error); composite gives the same rows (the same bag).
  * semijoin: a record whose key the other side lacks meets no partner in
  *   Reduce (Algorithm 1), so it can be left out of the shuffle.  0 =
  *   automatic (the larger side has at least 2^16 records and 4 times the
@@ -308,8 +317,13 @@ mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_p
  *   whose result cannot fit in the arena, ends without sorting.  0 =
  *   automatic (shuffles of at least 2^24 records), 1 = never, 2 = every
  *   shuffle.  Without it the same outcome comes after the sort.
+ * composite: 0 = a second variable both tables bind is part of the join key
+ *   (see mapsq_join), 1 = join on key_var alone and filter the second
+ *   variable for equality afterwards (the larger intermediate the paper's
+ *   one-variable merge implies).
  * INVALID_ARG for other values. */
-mapsq_status mapsq_set_join_options(mapsq_ctx* ctx, int32_t semijoin, int32_t merge, int32_t precount);
+mapsq_status mapsq_set_join_options(mapsq_ctx* ctx, int32_t semijoin, int32_t merge, int32_t precount,
+                                    int32_t composite);
 
 /* Per-phase device time and algorithmic bytes, accumulated while profiling
  * is on.  Phases: 0 map (range location and scan/compaction), 1 sort

@@ -21,7 +21,7 @@ MAPSQ_ERR_CAPACITY = -3
 MAPSQ_ERR_TOO_LARGE = -4
 MAPSQ_ERR_HIP = -5
 MAPSQ_ERR_STATE = -6
-MAPSQ_PATH_SORT, MAPSQ_PATH_SEMIJOIN, MAPSQ_PATH_MERGE = 0, 1, 2
+MAPSQ_PATH_SORT, MAPSQ_PATH_SEMIJOIN, MAPSQ_PATH_MERGE, MAPSQ_PATH_COMPOSITE = 0, 1, 2, 3
 MAPSQ_LOAD_DEVICE_PTRS = 1
 MAPSQ_LOAD_DEDUP = 2
 MAPSQ_JOIN_INTO_SCRATCH_BYTES = 64 << 20
@@ -142,7 +142,7 @@ _SIGS = [
     ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
     ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
     ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
-    ("mapsq_set_join_options", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    ("mapsq_set_join_options", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_profile_enable", ctypes.c_int32, [_P, ctypes.c_int32]),
     ("mapsq_profile_read", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_profile)]),
     ("mapsq_tune_record", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -301,12 +301,12 @@ def mapsq_last_join_stats(ctx) -> mapsq_join_stats:
     return out
 
 
-def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0, precount: int = 0):
+def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0, precount: int = 0, composite: int = 0):
     """semijoin: 0 automatic, 1 never, 2 always; merge: 0 when both sides are
     sorted on the key, 1 never; precount (exact |RS| before sorting): 0 for
-    shuffles of 2^24+ records, 1 never, 2 always.  Every choice gives the same
-    rows in the same order."""
-    _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge, precount))
+    shuffles of 2^24+ records, 1 never, 2 always; composite: 0 a second
+    shared variable is part of the join key, 1 it is filtered afterwards."""
+    _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge, precount, composite))
 
 
 def mapsq_set_tuning(ctx, radix_bits: int = 0, keys_per_thread: int = 0):

@@ -203,14 +203,17 @@ mapsq_status mapsq_last_join_stats(mapsq_ctx* c, mapsq_join_stats* out) {
     });
 }
 
-mapsq_status mapsq_set_join_options(mapsq_ctx* c, int32_t semijoin, int32_t merge, int32_t precount) {
+mapsq_status mapsq_set_join_options(mapsq_ctx* c, int32_t semijoin, int32_t merge, int32_t precount,
+                                    int32_t composite) {
     return guarded(c, [&](Ctx* ctx) {
         if (semijoin < 0 || semijoin > 2) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "semijoin must be 0, 1 or 2");
         if (merge < 0 || merge > 1) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "merge must be 0 or 1");
         if (precount < 0 || precount > 2) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "precount must be 0, 1 or 2");
+        if (composite < 0 || composite > 1) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "composite must be 0 or 1");
         ctx->semijoin = semijoin;
         ctx->merge_mode = merge;
         ctx->precount = precount;
+        ctx->composite = composite;
         return (mapsq_status)MAPSQ_OK;
     });
 }

@@ -71,8 +71,11 @@ __device__ __forceinline__ bool rec_is_head(const RecView& r, uint32_t idx, uint
     return idx < n && (idx == 0 || (r.kprev >> fs) != (r.k >> fs));
 }
 
-// sum pass: heads of every tile of the block's run
-__global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __restrict__ keys, uint32_t n,
+// sum pass: heads of every tile of the block's run (BRK: a record flagged in
+// brk also heads a segment: the further words of a composite key change)
+template <bool BRK>
+__global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __restrict__ keys,
+                                                             const uint8_t* __restrict__ brk, uint32_t n,
                                                              uint32_t fs, uint64_t* __restrict__ run_tot,
                                                              uint32_t* __restrict__ tloc, RunGrid g) {
     __shared__ uint32_t s_wtot[MQ_WAVES];
@@ -84,10 +87,12 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __r
     for (uint32_t tile = t0; tile < t1; tile++) {
         const uint32_t base = tile * HEADS_TILE;
         uint32_t k[HEADS_IPT];
+        bool f[HEADS_IPT];
 #pragma unroll
         for (int i = 0; i < HEADS_IPT; i++) {
             const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
             k[i] = idx < n ? keys[idx] : 0u;
+            f[i] = BRK && idx < n && brk[idx] != 0;
         }
         uint32_t run = 0;
 #pragma unroll
@@ -95,7 +100,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __r
             const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
             uint32_t kp = __shfl_up(k[i], 1, MQ_WAVE);
             if (lane() == 0 && idx > 0 && idx < n) kp = keys[idx - 1];
-            run += (uint32_t)__popcll(__ballot(idx < n && (idx == 0 || (kp >> fs) != (k[i] >> fs))));
+            const bool head = (kp >> fs) != (k[i] >> fs) || f[i];
+            run += (uint32_t)__popcll(__ballot(idx < n && (idx == 0 || head)));
         }
         if (lane() == 0) s_wtot[w] = run;
         __syncthreads();
@@ -112,7 +118,9 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_sum_kernel(const uint32_t* __r
 }
 
 // write pass: one tile per block
+template <bool BRK>
 __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* __restrict__ keys,
+                                                               const uint8_t* __restrict__ brk,
                                                                const uint32_t* __restrict__ vals, uint32_t n,
                                                                uint32_t n_left, uint32_t fs,
                                                                const uint64_t* __restrict__ run_excl,
@@ -125,13 +133,20 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
     const uint32_t tile = blockIdx.x;
     const uint32_t base = tile * HEADS_TILE;
     RecView r[HEADS_IPT];
+    bool f[HEADS_IPT], fnext[HEADS_IPT];  // this record / the next one flagged in brk
 #pragma unroll
-    for (int i = 0; i < HEADS_IPT; i++) r[i] = rec_view(keys, vals, n, base + (w * HEADS_IPT + i) * MQ_WAVE + lane());
+    for (int i = 0; i < HEADS_IPT; i++) {
+        const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
+        r[i] = rec_view(keys, vals, n, idx);
+        f[i] = BRK && idx < n && brk[idx] != 0;
+        fnext[i] = BRK && idx + 1 < n && brk[idx + 1] != 0;
+    }
     uint64_t hm[HEADS_IPT];
     uint32_t run = 0;
 #pragma unroll
     for (int i = 0; i < HEADS_IPT; i++) {
-        hm[i] = __ballot(rec_is_head(r[i], base + (w * HEADS_IPT + i) * MQ_WAVE + lane(), n, fs));
+        const uint32_t idx = base + (w * HEADS_IPT + i) * MQ_WAVE + lane();
+        hm[i] = __ballot(rec_is_head(r[i], idx, n, fs) || f[i]);
         run += (uint32_t)__popcll(hm[i]);
     }
     if (lane() == 0) s_wtot[w] = run;
@@ -148,7 +163,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
         if (idx < n) {
             const bool is_r = fs ? (r[i].k & 1u) != 0 : r[i].v >= n_left;
             const bool prev_r = fs ? (r[i].kprev & 1u) != 0 : r[i].vprev >= n_left;
-            const bool last = idx + 1 == n || (r[i].knext >> fs) != (r[i].k >> fs);
+            const bool last = idx + 1 == n || (r[i].knext >> fs) != (r[i].k >> fs) || fnext[i];
             const bool first_r = is_r && (h || !prev_r);
             if (h) seg_start[bef] = idx;
             if (first_r || (last && !is_r)) {
@@ -189,17 +204,24 @@ size_t seg_scratch_bytes(uint32_t n) {
 
 hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
                             int side_bit, uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, void* scratch,
-                            hipStream_t stream) {
+                            hipStream_t stream, const uint8_t* brk) {
     const uint32_t fs = side_bit ? 1u : 0u;
     if (n == 0) return hipSuccess;
     const RunGrid g = heads_grid(n);
     const SegScratch ss = seg_scratch(scratch, n);
-    heads_sum_kernel<<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, n, fs, ss.h_run, ss.h_tloc, g);
+    if (brk)
+        heads_sum_kernel<true><<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, brk, n, fs, ss.h_run, ss.h_tloc, g);
+    else
+        heads_sum_kernel<false><<<g.blocks, MQ_BLOCK, 0, stream>>>(keys, nullptr, n, fs, ss.h_run, ss.h_tloc, g);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_scan_runs(ss.h_run, g.blocks, nullptr, nseg, nullptr, nullptr, stream);
     if (e != hipSuccess) return e;
-    heads_write_kernel<<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, fs ? nullptr : vals, n, n_left, fs, ss.h_run,
-                                                         ss.h_tloc, g, seg_start, seg_split);
+    if (brk)
+        heads_write_kernel<true><<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, brk, fs ? nullptr : vals, n, n_left, fs,
+                                                                   ss.h_run, ss.h_tloc, g, seg_start, seg_split);
+    else
+        heads_write_kernel<false><<<g.ntiles, MQ_BLOCK, 0, stream>>>(keys, nullptr, fs ? nullptr : vals, n, n_left,
+                                                                    fs, ss.h_run, ss.h_tloc, g, seg_start, seg_split);
     return hipGetLastError();
 }
 

@@ -88,6 +88,77 @@ hipError_t launch_gather(const int32_t* src, const uint32_t* idx, int32_t* out, 
     return hipGetLastError();
 }
 
+// Composite key of up to MAX_KEY_WORDS columns packed into one word:
+// OR over j of (col_j - base_j) << shift_j (the caller makes sure the
+// relative ranges fit side by side in 32 bits; every shift is below 32).
+__global__ void pack_keys_kernel(PackArgs a, uint64_t n, uint32_t* __restrict__ out) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t k = 0;
+        for (int j = 0; j < a.ncols; j++) k |= ((uint32_t)a.col[j][i] - (uint32_t)a.base[j]) << a.shift[j];
+        out[i] = k;
+    }
+}
+hipError_t launch_pack_keys(const PackArgs& a, uint64_t n, uint32_t* out, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    if (a.ncols < 1 || a.ncols > MAX_KEY_WORDS) return hipErrorInvalidValue;
+    for (int j = 0; j < a.ncols; j++)
+        if (a.shift[j] < 0 || a.shift[j] > 31) return hipErrorInvalidValue;
+    pack_keys_kernel<<<grid_for(n, 256 * 4, 8192), 256, 0, stream>>>(a, n, out);
+    return hipGetLastError();
+}
+
+// Breaks between consecutive sorted records in the further words of a
+// composite key: brk[i] = 1 when record ids[i] differs from record
+// ids[i - 1] in any of the words (LEFT cells from lcol, RIGHT cells from
+// rcol), else 0; brk[0] = 0.  Each wave shares its lanes' cells through
+// shuffles; lane 0 loads its predecessor's.
+__global__ __launch_bounds__(256) void key_breaks_kernel(BreakArgs a, const uint32_t* __restrict__ ids, uint32_t n,
+                                                         uint8_t* __restrict__ brk) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    // every lane of a wave iterates together (the shuffles need all 64)
+    const uint32_t n_up = (n + MQ_WAVE - 1) / MQ_WAVE * MQ_WAVE;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_up; i += stride) {
+        const bool in = i < n;
+        const uint32_t r = in ? ids[i] : 0u;
+        bool diff = false;
+        for (int j = 0; j < a.nw; j++) {
+            const int32_t v = in ? (r < a.n_left ? a.lcol[j][r] : a.rcol[j][r - a.n_left]) : 0;
+            int32_t pv = __shfl_up(v, 1, MQ_WAVE);
+            if (lane() == 0 && in && i > 0) {
+                const uint32_t q = ids[i - 1];
+                pv = q < a.n_left ? a.lcol[j][q] : a.rcol[j][q - a.n_left];
+            }
+            diff |= v != pv;
+        }
+        if (in) brk[i] = (i > 0 && diff) ? 1 : 0;
+    }
+}
+hipError_t launch_key_breaks(const BreakArgs& a, const uint32_t* ids, uint32_t n, uint8_t* brk, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    if (a.nw < 1 || a.nw > MAX_KEY_WORDS) return hipErrorInvalidValue;
+    key_breaks_kernel<<<grid_for(n, 256 * 4, 8192), 256, 0, stream>>>(a, ids, n, brk);
+    return hipGetLastError();
+}
+
+// One column of both sides in record order: out[i] = the cell of record
+// ids[i] (a LEFT row when ids[i] < n_left, else RIGHT row ids[i] - n_left),
+// relative to base.
+__global__ void side_gather_kernel(const int32_t* __restrict__ lcol, const int32_t* __restrict__ rcol,
+                                   uint32_t n_left, const uint32_t* __restrict__ ids, uint32_t n, int32_t base,
+                                   uint32_t* __restrict__ out) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t r = ids[i];
+        const int32_t v = r < n_left ? lcol[r] : rcol[r - n_left];
+        out[i] = (uint32_t)v - (uint32_t)base;
+    }
+}
+hipError_t launch_side_gather(const int32_t* lcol, const int32_t* rcol, uint32_t n_left, const uint32_t* ids,
+                              uint32_t n, int32_t base, uint32_t* out, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    side_gather_kernel<<<grid_for(n, 256 * 4, 8192), 256, 0, stream>>>(lcol, rcol, n_left, ids, n, base, out);
+    return hipGetLastError();
+}
+
 // Min and max of a[0..na) and b[0..nb): 8 independent loads in flight per
 // thread, a block-level reduction, then one atomic pair per block (atomics
 // on one address serialise, so there are few blocks).

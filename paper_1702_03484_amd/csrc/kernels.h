@@ -109,9 +109,12 @@ uint32_t radix_tiles(uint32_t n, int kpt, int rb, bool gen);
 // launches below (run totals and per-tile offsets; no clearing needed).
 // side_bit: the side is the key's low bit (a carried shuffle) instead of
 // payload >= n_left; segments then group keys >> 1.
+// brk (may be null): one flag per sorted record, 1 where the further words
+// of a composite key change (launch_key_breaks); segments then also start
+// at every flagged record.
 hipError_t launch_seg_heads(const uint32_t* keys, const uint32_t* vals, uint32_t n, uint32_t n_left,
                             int side_bit, uint32_t* seg_start, uint32_t* seg_split, uint32_t* nseg, void* scratch,
-                            hipStream_t stream);
+                            hipStream_t stream, const uint8_t* brk = nullptr);
 // count[s] = (split - start) * (end - split); seg_off = exclusive scan of the
 // counts (saturating at 2^40-1); *total = the full sum.  max_seg bounds the
 // device count *nseg (sizes the grids).
@@ -279,6 +282,31 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t stre
 // out[i] = src[idx[i]] - base
 hipError_t launch_gather(const int32_t* src, const uint32_t* idx, int32_t* out, uint64_t n, int32_t base,
                          hipStream_t stream);
+// Composite keys of up to MAX_KEY_WORDS variables.  Packed: out[i] = OR
+// over j of (col[j][i] - base[j]) << shift[j] as u32 (the caller makes sure
+// the relative ranges fit side by side; shifts in [0, 31]).
+constexpr int MAX_KEY_WORDS = 3;
+struct PackArgs {
+    const int32_t* col[MAX_KEY_WORDS];
+    int32_t base[MAX_KEY_WORDS];
+    int32_t shift[MAX_KEY_WORDS];
+    int32_t ncols;
+};
+hipError_t launch_pack_keys(const PackArgs& a, uint64_t n, uint32_t* out, hipStream_t stream);
+// Not packed: brk[i] = 1 when sorted record ids[i] differs from ids[i - 1]
+// in any of the nw further key words (record r < n_left reads lcol[j][r],
+// else rcol[j][r - n_left]); brk[0] = 0.
+struct BreakArgs {
+    const int32_t* lcol[MAX_KEY_WORDS];
+    const int32_t* rcol[MAX_KEY_WORDS];
+    uint32_t n_left;
+    int32_t nw;
+};
+hipError_t launch_key_breaks(const BreakArgs& a, const uint32_t* ids, uint32_t n, uint8_t* brk, hipStream_t stream);
+// out[i] = cell of record ids[i] minus base, the record being LEFT row
+// ids[i] of lcol (ids[i] < n_left) or RIGHT row ids[i] - n_left of rcol.
+hipError_t launch_side_gather(const int32_t* lcol, const int32_t* rcol, uint32_t n_left, const uint32_t* ids,
+                              uint32_t n, int32_t base, uint32_t* out, hipStream_t stream);
 // minmax[0] = min, minmax[1] = max over the int32 values of two segments
 // (minmax pre-set to INT32_MAX / INT32_MIN by the caller).
 hipError_t launch_minmax(const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int32_t* minmax,

@@ -94,7 +94,7 @@ static inline uint32_t* scalar32(Ctx* ctx, int word) { return ctx->small + SMALL
 static inline uint32_t* counter(Ctx* ctx, int i) { return ctx->small + SMALL_CTR + i; }
 
 // scalar slots (u32 word index inside the scalar area)
-enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12, SC_PRECOUNT = 14, SC_MAXPAIRS = 16 };
+enum { SC_NSEG = 0, SC_TOTAL = 2, SC_COUNT = 4, SC_MINMAX = 6, SC_BAD = 8, SC_NPRED = 9, SC_MINMAX2 = 10, SC_SEMI = 12, SC_PRECOUNT = 14, SC_MAXPAIRS = 16, SC_MINMAX3 = 18 };
 // counter slots
 enum { CT_PASS0 = 0, CT_COUNT = 9, CT_SEMI = 11 };
 
@@ -696,6 +696,34 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         }
         rv.push_back(c);  // materialised (filtered copies dropped afterwards)
     }
+    // Further variables both tables bind join as part of a composite key
+    // (key_var, then the others in the left table's column order) instead
+    // of being filtered after a join on key_var alone: only pairs that agree
+    // on every shared variable meet.  The right table's copies are then
+    // neither materialised nor filtered.
+    int kl[MAX_KEY_WORDS] = {lk, -1, -1}, kr[MAX_KEY_WORDS] = {rk, -1, -1};
+    int nkeys = 1;
+    if (ctx->composite == 0 && !extra_r.empty()) {
+        for (int c = 0; c < L->ncols && nkeys < MAX_KEY_WORDS; c++) {
+            if (c == lk) continue;
+            const int cr = col_of(R, L->var[c]);
+            if (cr >= 0) {
+                kl[nkeys] = c;
+                kr[nkeys] = cr;
+                nkeys++;
+            }
+        }
+        for (int j = 1; j < nkeys; j++) {
+            for (size_t i = 0; i < extra_r.size(); i++)
+                if (extra_r[i] == kr[j]) {
+                    extra_r.erase(extra_r.begin() + i);
+                    extra_l.erase(extra_l.begin() + i);
+                    break;
+                }
+            rv.erase(std::find(rv.begin(), rv.end(), kr[j]));
+        }
+    }
+    const bool composite = nkeys > 1;
     const int nc_mat = 1 + (int)lv.size() + (int)rv.size();
     const int nc_out = nc_mat - (int)extra_r.size();
     if (nc_mat > MAPSQ_MAX_COLS) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 16 columns in the join");
@@ -805,7 +833,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // this key): Reduce straight from the two sides' key runs, no shuffle.
     const int32_t* lkey = L->col[lk];
     const int32_t* rkey = R->col[rk];
-    if (ctx->merge_mode == 0 && L->sorted_col == lk + 1 && R->sorted_col == rk + 1) {
+    if (!composite && ctx->merge_mode == 0 && L->sorted_col == lk + 1 && R->sorted_col == rk + 1) {
         const bool small_left = nL <= nR;
         const uint32_t nsm = small_left ? nL : nR, nbg = small_left ? nR : nL;
         const size_t sb4 = align_up(size_t(nsm) * 4, ARENA_ALIGN);
@@ -879,9 +907,29 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         return finish(m, total);
     }
 
-    // key range: known bound, else a min/max pass
+    // key range: known bound, else a min/max pass (a composite key: every
+    // variable's range from one read-back)
     int32_t kmin = 0, kmax;
-    if (L->key_max >= 0 && R->key_max >= 0) {
+    int32_t wmin[MAX_KEY_WORDS] = {0, 0, 0}, wmax[MAX_KEY_WORDS] = {0, 0, 0};
+    if (composite) {
+        static_assert(MAX_KEY_WORDS == 3, "one scalar pair per key word");
+        const int slot[MAX_KEY_WORDS] = {SC_MINMAX, SC_MINMAX2, SC_MINMAX3};
+        int32_t init[2] = {INT32_MAX, INT32_MIN};
+        std::memcpy(ctx->pinned, init, 8);
+        for (int j = 0; j < nkeys; j++) {
+            int32_t* mm = reinterpret_cast<int32_t*>(scalar32(ctx, slot[j]));
+            HIPCHK(hipMemcpyAsync(mm, ctx->pinned, 8, hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(launch_minmax(L->col[kl[j]], nL, R->col[kr[j]], nR, mm, ctx->stream));
+        }
+        int32_t r[SC_MINMAX3 + 2 - SC_MINMAX];  // scalar words SC_MINMAX .. SC_MINMAX3 + 1
+        if ((st = readback(ctx, scalar32(ctx, SC_MINMAX), sizeof(r), r))) return st;
+        for (int j = 0; j < nkeys; j++) {
+            wmin[j] = r[slot[j] - SC_MINMAX];
+            wmax[j] = r[slot[j] - SC_MINMAX + 1];
+        }
+        kmin = wmin[0];
+        kmax = wmax[0];
+    } else if (L->key_max >= 0 && R->key_max >= 0) {
         kmax = std::max(L->key_max, R->key_max);
     } else {
         int32_t init[2] = {INT32_MAX, INT32_MIN};
@@ -894,7 +942,17 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         kmin = r[0];
         kmax = r[1];
     }
-    const int key_bits = bitlen((uint64_t)((int64_t)kmax - (int64_t)kmin));
+    // bits of each key variable's relative range; a composite key whose
+    // ranges fit side by side in one 32-bit word is sorted packed (key_var
+    // highest), otherwise word by word from the last variable to key_var
+    int wbits[MAX_KEY_WORDS] = {bitlen((uint64_t)((int64_t)kmax - (int64_t)kmin)), 0, 0};
+    int key_bits = wbits[0];
+    for (int j = 1; j < nkeys; j++) {
+        wbits[j] = bitlen((uint64_t)((int64_t)wmax[j] - (int64_t)wmin[j]));
+        key_bits += wbits[j];
+    }
+    const int low_bits = key_bits - wbits[0];  // the shift of key_var in a packed word
+    const bool packed = composite && key_bits <= 32 && low_bits <= 31;
     int rb, kpt;
     pick_tuning(ctx, key_bits, rb, kpt, (uint64_t)nL + nR);
 
@@ -903,7 +961,8 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // records): a join with no key in common, or whose output cannot fit in
     // the arena's free space at all, then ends without sorting anything.
     // On a join that fits it costs about as much as the count phase.
-    const bool precount = ctx->precount == 2 || (ctx->precount == 0 && (uint64_t)N >= PRECOUNT_MIN_RECORDS);
+    const bool precount =
+        !composite && (ctx->precount == 2 || (ctx->precount == 0 && (uint64_t)N >= PRECOUNT_MIN_RECORDS));
     if (precount) {
         const uint64_t range = (uint64_t)((int64_t)kmax - (int64_t)kmin) + 1;
         Block cnt;
@@ -961,7 +1020,9 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         const uint64_t range = (uint64_t)((int64_t)kmax - (int64_t)kmin) + 1;
         const uint64_t words = (range + 31) / 32;
         bool semi = false;
-        if (ctx->semijoin == 0)
+        if (composite)
+            semi = false;
+        else if (ctx->semijoin == 0)
             semi = nb >= SEMI_MIN_RECORDS && (uint64_t)nsm * SEMI_RATIO <= nb && words <= (uint64_t)nb;
         else if (ctx->semijoin == 2)
             semi = words * 4 <= (uint64_t(1) << 30);
@@ -1009,7 +1070,8 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // value column the records carry that value instead of their position
     // (the side moves into the key's low bit), so Reduce reads the values
     // in sorted order instead of gathering them through the positions.
-    const bool carry = js.path != MAPSQ_PATH_SEMIJOIN && lv.size() <= 1 && rv.size() <= 1 && key_bits <= 31;
+    const bool carry =
+        !composite && js.path != MAPSQ_PATH_SEMIJOIN && lv.size() <= 1 && rv.size() <= 1 && key_bits <= 31;
     const int sort_bits = carry ? key_bits + 1 : key_bits;
     if (carry) pick_tuning(ctx, sort_bits, rb, kpt, (uint64_t)Ns);
     SortSrc src{lkey, nL, rkey, nR, kmin, nullptr, nullptr, carry ? 1 : 0};
@@ -1018,15 +1080,83 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         src.v1 = rv.empty() ? rkey : R->col[rv[0]];
     }
     int res, passes;
+    const uint8_t* brk = nullptr;  // break flags of a composite key sorted word by word
+    Block cbuf;                    // packed composite keys, or those flags
+    if (composite) {
+        js.path = MAPSQ_PATH_COMPOSITE;
+        cbuf = alloc_block(ctx, packed ? nb4 : align_up(size_t(N), ARENA_ALIGN));
+        if (!cbuf.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for composite keys");
+    }
     ph = ctx->prof_begin(1);
-    if ((st = radix_sort(ctx, js.path == MAPSQ_PATH_SEMIJOIN ? nullptr : &src, Ns, sort_bits, rb, kpt, b, &res,
-                         &passes)))
-        return st;
-    // histogram reads 4N; the first pass reads 4N keys (8N records after a
-    // semi-join, plus the carried value cells), later passes 8N; every pass
-    // writes 8N
-    ctx->prof_end(ph, 16.0 * Ns * passes + (js.path == MAPSQ_PATH_SEMIJOIN ? 4.0 * Ns : 0.0) +
-                          (carry ? 4.0 * (lv.size() * (double)nL + rv.size() * (double)nR) : 0.0));
+    double sort_bytes;
+    if (packed) {
+        // one key word per record: the variables' relative values side by
+        // side, key_var in the highest bits
+        uint32_t* pk = cbuf.as<uint32_t>();
+        PackArgs pl{}, pr{};
+        pl.ncols = pr.ncols = nkeys;
+        for (int j = 0, sh = low_bits; j < nkeys; j++) {
+            pl.col[j] = L->col[kl[j]];
+            pr.col[j] = R->col[kr[j]];
+            pl.base[j] = pr.base[j] = wmin[j];
+            pl.shift[j] = pr.shift[j] = wbits[j] ? sh : 0;  // a zero-width word adds nothing
+            if (j + 1 < nkeys) sh -= wbits[j + 1];
+        }
+        HIPCHK(launch_pack_keys(pl, nL, pk, ctx->stream));
+        HIPCHK(launch_pack_keys(pr, nR, pk + nL, ctx->stream));
+        SortSrc ps{reinterpret_cast<const int32_t*>(pk), nL, reinterpret_cast<const int32_t*>(pk) + nL, nR, 0,
+                   nullptr, nullptr, 0};
+        if ((st = radix_sort(ctx, &ps, Ns, key_bits, rb, kpt, b, &res, &passes))) return st;
+        // packing reads every key column and writes the packed word
+        sort_bytes = 4.0 * (nkeys + 1) * Ns + 16.0 * Ns * passes;
+    } else if (composite) {
+        // LSD over the words: a stable sort on the last variable, then on
+        // each earlier one of the records in the order so far (its cells
+        // gathered through the record ids), ending with key_var; records end
+        // grouped by the whole key, LEFT ahead of RIGHT inside each group
+        int rbj, kptj, rj, pj;
+        passes = 0;
+        const int last = nkeys - 1;
+        pick_tuning(ctx, wbits[last], rbj, kptj, (uint64_t)Ns);
+        SortSrc sl{L->col[kl[last]], nL, R->col[kr[last]], nR, wmin[last], nullptr, nullptr, 0};
+        if ((st = radix_sort(ctx, &sl, Ns, wbits[last], rbj, kptj, b, &rj, &pj))) return st;
+        passes += pj;
+        for (int j = last - 1; j >= 0; j--) {
+            HIPCHK(launch_side_gather(L->col[kl[j]], R->col[kr[j]], nL, b.v[rj], Ns, wmin[j], b.k[1 - rj],
+                                      ctx->stream));
+            SortBufs bj{{b.k[1 - rj], b.k[rj]}, {b.v[rj], b.v[1 - rj]}};
+            pick_tuning(ctx, wbits[j], rbj, kptj, (uint64_t)Ns);
+            if ((st = radix_sort(ctx, nullptr, Ns, wbits[j], rbj, kptj, bj, &rj, &pj))) return st;
+            b = bj;
+            passes += pj;
+        }
+        res = rj;
+        rb = rbj;
+        BreakArgs ba{};
+        ba.n_left = nL;
+        ba.nw = nkeys - 1;
+        for (int j = 1; j < nkeys; j++) {
+            ba.lcol[j - 1] = L->col[kl[j]];
+            ba.rcol[j - 1] = R->col[kr[j]];
+        }
+        uint8_t* fl = cbuf.as<uint8_t>();
+        HIPCHK(launch_key_breaks(ba, b.v[res], Ns, fl, ctx->stream));
+        brk = fl;
+        // every sort, the gather of each earlier variable between them
+        // (read 4N ids, 4N cells, write 4N), and the break flags (read 4N
+        // ids and 4N cells per further variable, write N)
+        sort_bytes = 16.0 * Ns * passes + 12.0 * (nkeys - 1) * Ns + (4.0 + 4.0 * (nkeys - 1) + 1.0) * Ns;
+    } else {
+        if ((st = radix_sort(ctx, js.path == MAPSQ_PATH_SEMIJOIN ? nullptr : &src, Ns, sort_bits, rb, kpt, b, &res,
+                             &passes)))
+            return st;
+        // histogram reads 4N; the first pass reads 4N keys (8N records after a
+        // semi-join, plus the carried value cells), later passes 8N; every pass
+        // writes 8N
+        sort_bytes = 16.0 * Ns * passes + (js.path == MAPSQ_PATH_SEMIJOIN ? 4.0 * Ns : 0.0) +
+                     (carry ? 4.0 * (lv.size() * (double)nL + rv.size() * (double)nR) : 0.0);
+    }
+    ctx->prof_end(ph, sort_bytes);
     const uint32_t* skeys = b.k[res];
     const uint32_t* svals = b.v[res];
     uint32_t* seg_start = b.k[1 - res];
@@ -1036,7 +1166,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     if (!ss.ok()) return ctx->fail(MAPSQ_ERR_CAPACITY, "arena: no room for the segment scans");
     ph = ctx->prof_begin(2);
     HIPCHK(launch_seg_heads(skeys, svals, Ns, nL, carry ? 1 : 0, seg_start, seg_split, scalar32(ctx, SC_NSEG),
-                            ss.as<void>(), ctx->stream));
+                            ss.as<void>(), ctx->stream, brk));
     HIPCHK(launch_seg_count(Ns, seg_start, scalar32(ctx, SC_NSEG), Ns, seg_split, seg_off, scalar64(ctx, SC_TOTAL),
                             scalar64(ctx, SC_MAXPAIRS), ss.as<void>(), ctx->stream));
     uint32_t sc[SC_MAXPAIRS + 2];  // scalar words 0 .. SC_MAXPAIRS + 1
@@ -1050,7 +1180,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     const uint32_t nseg = sc[0];
     // heads: read 4N keys and 4N payloads, write 4S starts and 4S splits;
     // count: read 8S starts and 4S splits, write 8S offsets
-    if (ph >= 0) ctx->pending[ph].bytes = 8.0 * Ns + 28.0 * nseg;
+    if (ph >= 0) ctx->pending[ph].bytes = (brk ? 9.0 : 8.0) * Ns + 28.0 * nseg;
     uint64_t total;
     std::memcpy(&total, &sc[2], 8);
     js.segments = nseg;
@@ -1080,7 +1210,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     a.n = Ns;
     a.n_left = nL;
     a.key_base = kmin;
-    a.key_shift = carry ? 1 : 0;
+    a.key_shift = carry ? 1 : (packed ? low_bits : 0);
     a.nl = (int)lv.size();
     a.nr = (int)rv.size();
     for (int i = 0; i < a.nl; i++) a.lcol[i] = L->col[lv[i]];

@@ -113,6 +113,7 @@ struct Ctx {
     int32_t semijoin = 0;    // 0 automatic, 1 never, 2 always
     int32_t merge_mode = 0;  // 0 merge join of key-sorted tables, 1 never
     int32_t precount = 0;    // exact |RS| before shuffles: 0 of 2^24+ records, 1 never, 2 always
+    int32_t composite = 0;   // 0 a second shared variable joins as part of the key, 1 it is filtered
     // autotuned choices: (key bits << 8 | log2 records) -> (rb << 8 | kpt)
     std::map<uint32_t, uint32_t> tuned;
     mapsq_join_stats last{};

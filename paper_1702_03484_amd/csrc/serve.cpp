@@ -515,11 +515,15 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
             const double cols = q->cur.ncols + R.ncols - 1;
             // the output, and the join's scratch held while it is written:
             // 24 B per run of the smaller side for key-sorted inputs, else
-            // 24 B per record
-            const bool sorted = !ps.cross && q->cur.sorted_col == col_of(&q->cur, ps.key) + 1 &&
+            // 24 B per record (28 B when a second shared variable makes the
+            // key composite)
+            int shared = 0;
+            for (int c = 0; c < R.ncols; c++) shared += col_of(&q->cur, R.var[c]) >= 0 ? 1 : 0;
+            const bool comp = !ps.cross && shared >= 2 && ctx->composite == 0;
+            const bool sorted = !ps.cross && !comp && q->cur.sorted_col == col_of(&q->cur, ps.key) + 1 &&
                                 R.sorted_col == col_of(&R, ps.key) + 1;
             const double recs = sorted ? (double)std::min(q->cur.nrows, R.nrows) : (double)(q->cur.nrows + R.nrows);
-            const double need = 4.0 * (double)need_rows * cols + 24.0 * recs;
+            const double need = 4.0 * (double)need_rows * cols + (comp ? 28.0 : 24.0) * recs;
             if (live_others(q) > 0) {
                 q->wait_bytes = need;
                 q->wait_step = q->next;

@@ -85,10 +85,13 @@ class MapSQ:
 
     # ---- tables <-> tensors -------------------------------------------------
 
-    def set_join_options(self, semijoin: int = 0, merge: int = 0, precount: int = 0):
+    def set_join_options(self, semijoin: int = 0, merge: int = 0, precount: int = 0, composite: int = 0):
         """semijoin 0 automatic / 1 never / 2 always; merge 0 automatic / 1 never;
-        precount 0 shuffles of 2^24+ records / 1 never / 2 always."""
-        B.mapsq_set_join_options(self.ctx, semijoin, merge, precount)
+        precount 0 shuffles of 2^24+ records / 1 never / 2 always; composite 0
+        a second shared variable joins as part of the key / 1 filtered after."""
+        B.mapsq_set_join_options(self.ctx, semijoin, merge, precount, composite)
+
+
     def table(self, vars, tensors, key_max: int = -1, sorted_col: int = 0) -> B.mapsq_table:
         """Wrap caller-owned int32 device tensors (kept alive by this session);
         sorted_col = 1 + a column the caller guarantees to be ascending."""
