@@ -256,15 +256,27 @@ def run_cfg3(reps=5):
 
         ts, rows, prof = timed_reps(one, reps=reps, prof_ctx=sess.ctx)
         st = sess.stats()
+        plan_sizes = sess.last_plan()
+        # the same query planned on exact join sizes counted on the GPU
+        sess.set_planner(True)
+        try:
+            tx, rows_x, _ = timed_reps(one, reps=reps)
+            plan_exact = sess.last_plan()
+        finally:
+            sess.set_planner(False)
+        assert rows_x == rows
     el = median(ts)
-    log(f"[cfg3] {rows} rows in {el * 1e3:.3f} ms (median)")
+    log(f"[cfg3] {rows} rows in {el * 1e3:.3f} ms (median); exact-size plan {median(tx) * 1e3:.3f} ms")
     return {"workload": f"?x p1 ?y . ?x p2 ?z . ?x p3 c . ?w p4 ?y over {info.n_triples} int32 triples "
                         "(64 predicates Zipf 1.0, s uniform and o Zipf 1.2 over 50M entities)",
             "patterns": [list(p) for p in pats], "rows": rows, "ms_per_query": round(el * 1e3, 3),
             "rows_per_s": rows / el, "timing": f"median of {reps} cold repetitions",
             "last_join": {"path": int(st.path), "records_sorted": int(st.sorted_records), "radix_bits": int(st.radix_bits),
                           "passes": int(st.passes), "segments": int(st.segments)},
-            "phases": phase_table(prof)}
+            "phases": phase_table(prof),
+            "plans": {"step": "(pattern, key variable, rows, join sizes counted)",
+                      "pattern_sizes": plan_sizes, "exact_join_sizes": plan_exact,
+                      "ms_exact_join_sizes": round(median(tx) * 1e3, 3)}}
 
 
 def run_cfg2_sort(sess, w, reps=5):
@@ -468,6 +480,32 @@ def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1
     mem = np.where(st_p == B.MAPSQ_ERR_CAPACITY, B.MAPSQ_ERR_TOO_LARGE, st_p)
     sat_cont["same_outcomes_as_plain"] = bool((st_c == mem).all())
     log(f"[cfg5] saturated: plain {sat_plain['processed_qps']:.0f} q/s, continuous {sat_cont['processed_qps']:.0f} q/s")
+    # the plain form with each query planned on exact join sizes counted on
+    # the GPU (serving plans on pattern sizes): plans that differ, and rate
+    plans = []
+    for q in qs:
+        t = B.mapsq_query(sess.ctx, q)
+        B.mapsq_table_free(sess.ctx, t)
+        plans.append(B.mapsq_last_plan(sess.ctx))
+    sess.set_planner(True)
+    try:
+        sat_exact, _, st_x = serving.run_plain(sess, qs, np.zeros(len(qs)))
+        differ, smaller = 0, 0
+        for q, ps in zip(qs, plans):
+            t = B.mapsq_query(sess.ctx, q)
+            B.mapsq_table_free(sess.ctx, t)
+            px = B.mapsq_last_plan(sess.ctx)
+            if [s_[:2] for s_ in px] != [s_[:2] for s_ in ps]:
+                differ += 1
+                if max([s_[2] for s_ in px[1:-1]] or [0]) < max([s_[2] for s_ in ps[1:-1]] or [0]):
+                    smaller += 1
+    finally:
+        sess.set_planner(False)
+    sat_exact["same_outcomes_as_plain"] = bool((st_x == st_p).all())
+    planner = {"plain_exact_join_sizes": sat_exact, "plans_differ": differ,
+               "smaller_largest_intermediate": smaller, "queries": len(qs)}
+    log(f"[cfg5] exact-size plans: {differ} of {len(qs)} differ ({smaller} with a smaller largest intermediate); "
+        f"plain {sat_exact['processed_qps']:.0f} q/s")
     rows = []
     for f in loads:
         qps = f * sat_plain["processed_qps"]
@@ -485,7 +523,7 @@ def run_cfg5(n_triples=500_000_000, n_queries=600, warm=100, loads=(0.25, 0.5, 1
             "mix": {"examined": examined, "over_cap_or_refused": over, "redraw_rate": over / max(1, examined),
                     "rows_p50": float(np.percentile(sizes, 50)) if sizes else None,
                     "rows_max": int(max(sizes)) if sizes else None},
-            "saturated_plain": sat_plain, "saturated_continuous": sat_cont, "poisson": rows}
+            "saturated_plain": sat_plain, "saturated_continuous": sat_cont, "planner": planner, "poisson": rows}
 
 
 def main():

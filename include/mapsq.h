@@ -217,6 +217,43 @@ mapsq_status mapsq_join_into(mapsq_ctx* ctx, const mapsq_table* left, const maps
 mapsq_status mapsq_query(mapsq_ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* select_vars,
                          int32_t nselect, mapsq_table* out);
 
+/* Join order of mapsq_query (the host's share of the CPU/GPU split: the
+ * CPU assigns the subqueries, the GPU joins them; abstract and Section 2).
+ * MAPSQ_PLAN_SIZES (the default): greedy on the exact partial-match sizes
+ * -- start from the smallest table, then take the smallest table that
+ * shares a variable with the bound ones.  MAPSQ_PLAN_EXACT: greedy on exact
+ * join sizes counted on the GPU -- the first join is the pair of connected
+ * tables with the smallest exact |RS|, and every later step joins the
+ * connected table whose exact |RS| with the running result is smallest;
+ * each candidate is counted by the join's own path up to the exact count
+ * (a merge of key runs for index views in key order, dense per-key counts
+ * where the key range allows, else sort and count), without writing rows.
+ * Ties go to the lowest pattern index.  A table that shares nothing joins
+ * by cross product last.  Both give the same bag.  The serving loop plans
+ * with MAPSQ_PLAN_SIZES (it sizes queries before running them).
+ * INVALID_ARG for another mode. */
+#define MAPSQ_PLAN_SIZES 0
+#define MAPSQ_PLAN_EXACT 1
+mapsq_status mapsq_set_planner(mapsq_ctx* ctx, int32_t mode);
+
+/* One step of the plan mapsq_query ran: step 0 is the start pattern (its
+ * partial-match rows, key_var -1); step k >= 1 joins pattern `pattern` on
+ * key_var (-1 for a cross product) and gives `rows` rows; `candidates` is
+ * the number of join sizes counted on the GPU to choose it (0 when the plan
+ * came from pattern sizes). */
+typedef struct {
+    int32_t pattern;
+    int32_t key_var;
+    int64_t rows;
+    int32_t candidates;
+    int32_t reserved;
+} mapsq_plan_step;
+
+/* The plan of the context's last successful mapsq_query: its steps are
+ * copied to out[0 .. min(n, cap)) and *n is set to the step count (the
+ * number of patterns).  STATE when no query has completed. */
+mapsq_status mapsq_last_plan(mapsq_ctx* ctx, mapsq_plan_step* out, int32_t cap, int32_t* n);
+
 /* One join of a batch: left JOIN right on key_var (see mapsq_join). */
 typedef struct {
     const mapsq_table* left;

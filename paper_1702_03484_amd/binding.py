@@ -91,6 +91,19 @@ class mapsq_profile(ctypes.Structure):
     ]
 
 
+class mapsq_plan_step(ctypes.Structure):
+    _fields_ = [
+        ("pattern", ctypes.c_int32),
+        ("key_var", ctypes.c_int32),
+        ("rows", ctypes.c_int64),
+        ("candidates", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+MAPSQ_PLAN_SIZES, MAPSQ_PLAN_EXACT = 0, 1
+
+
 class mapsq_join_desc(ctypes.Structure):
     _fields_ = [
         ("left", ctypes.POINTER(mapsq_table)),
@@ -141,6 +154,9 @@ _SIGS = [
      [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(mapsq_table)]),
     ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
     ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
+    ("mapsq_set_planner", ctypes.c_int32, [_P, ctypes.c_int32]),
+    ("mapsq_last_plan", ctypes.c_int32,
+     [_P, ctypes.POINTER(mapsq_plan_step), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     ("mapsq_set_tuning", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_set_join_options", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_profile_enable", ctypes.c_int32, [_P, ctypes.c_int32]),
@@ -307,6 +323,19 @@ def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0, precount: int
     shuffles of 2^24+ records, 1 never, 2 always; composite: 0 a second
     shared variable is part of the join key, 1 it is filtered afterwards."""
     _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge, precount, composite))
+
+
+def mapsq_set_planner(ctx, mode: int):
+    _check(ctx, lib().mapsq_set_planner(ctx, mode))
+
+
+def mapsq_last_plan(ctx) -> list:
+    """The last query's plan: [(pattern, key_var, rows, candidates counted), ...]."""
+    n = ctypes.c_int32(0)
+    _check(ctx, lib().mapsq_last_plan(ctx, None, 0, ctypes.byref(n)))
+    steps = (mapsq_plan_step * max(1, n.value))()
+    _check(ctx, lib().mapsq_last_plan(ctx, steps, n.value, ctypes.byref(n)))
+    return [(s.pattern, s.key_var, int(s.rows), s.candidates) for s in steps[:n.value]]
 
 
 def mapsq_set_tuning(ctx, radix_bits: int = 0, keys_per_thread: int = 0):

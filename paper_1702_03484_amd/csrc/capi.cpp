@@ -218,6 +218,26 @@ mapsq_status mapsq_set_join_options(mapsq_ctx* c, int32_t semijoin, int32_t merg
     });
 }
 
+mapsq_status mapsq_set_planner(mapsq_ctx* c, int32_t mode) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (mode != MAPSQ_PLAN_SIZES && mode != MAPSQ_PLAN_EXACT)
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "planner mode must be MAPSQ_PLAN_SIZES or MAPSQ_PLAN_EXACT");
+        ctx->planner = mode;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
+mapsq_status mapsq_last_plan(mapsq_ctx* c, mapsq_plan_step* out, int32_t cap, int32_t* n) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!n || cap < 0 || (cap > 0 && !out)) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "bad output arguments");
+        *n = 0;
+        if (ctx->last_plan.empty()) return ctx->fail(MAPSQ_ERR_STATE, "no query has completed");
+        *n = (int32_t)ctx->last_plan.size();
+        for (int32_t i = 0; i < std::min(cap, *n); i++) out[i] = ctx->last_plan[i];
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
 mapsq_status mapsq_set_tuning(mapsq_ctx* c, int32_t radix_bits, int32_t keys_per_thread) {
     return guarded(c, [&](Ctx* ctx) {
         if (radix_bits != 0 && (radix_bits < 4 || radix_bits > 11))

@@ -2,7 +2,9 @@
 // coprocessing (abstract; Section 2: partial matching per pattern, then
 // pattern-by-pattern merging of the partial results on a shared variable).
 // The host maps every pattern (exact partial-match sizes come back from the
-// index ranges), orders the joins greedily and hands each one to the GPU.
+// index ranges), orders the joins greedily -- on those pattern sizes, or on
+// exact join sizes that the GPU counts for every candidate step -- and hands
+// each join to the GPU.
 #include <algorithm>
 #include <cstring>
 
@@ -167,30 +169,57 @@ mapsq_status query_vars(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, cons
     return MAPSQ_OK;
 }
 
-// Views re-made from the other index where that puts their rows in the
-// order of the key they are joined on (the first step's key for the start
-// table), so that the join pairs key runs without a shuffle.  Owned tables
-// and views already in key order are left alone.
+// Table i re-made from the other index where that puts its rows in the
+// order of `key` (so that a join on it pairs key runs without a shuffle).
+// Owned tables and views already in key order are left alone.
+static mapsq_status view_on_key(Ctx* ctx, const mapsq_pattern* pats, mapsq_table* tabs, int i, int32_t key) {
+    const int kc = col_of(&tabs[i], key);
+    if (tabs[i].owned || kc < 0 || tabs[i].sorted_col == kc + 1) return MAPSQ_OK;
+    mapsq_table t{};
+    if (mapsq_status st = map_pattern(ctx, &pats[i], key, &t)) return st;
+    if (t.owned)
+        free_table(ctx, &t);
+    else if (t.sorted_col == 1)
+        tabs[i] = t;
+    return MAPSQ_OK;
+}
+
+// Views re-made for a whole plan: each picked table on its step's key, the
+// start table on the first step's key.
 mapsq_status key_sort_views(Ctx* ctx, const mapsq_pattern* pats, mapsq_table* tabs, int start,
                             const std::vector<PlanStep>& steps) {
-    auto one = [&](int i, int32_t key) -> mapsq_status {
-        const int kc = col_of(&tabs[i], key);
-        if (tabs[i].owned || kc < 0 || tabs[i].sorted_col == kc + 1) return MAPSQ_OK;
-        mapsq_table t{};
-        if (mapsq_status st = map_pattern(ctx, &pats[i], key, &t)) return st;
-        if (t.owned)
-            free_table(ctx, &t);
-        else if (t.sorted_col == 1)
-            tabs[i] = t;
-        return MAPSQ_OK;
-    };
     for (size_t k = 0; k < steps.size(); k++) {
         if (steps[k].cross) continue;
-        if (mapsq_status st = one(steps[k].pick, steps[k].key)) return st;
+        if (mapsq_status st = view_on_key(ctx, pats, tabs, steps[k].pick, steps[k].key)) return st;
         if (k == 0)
-            if (mapsq_status st = one(start, steps[k].key)) return st;
+            if (mapsq_status st = view_on_key(ctx, pats, tabs, start, steps[k].key)) return st;
     }
     return MAPSQ_OK;
+}
+
+// Exact |a JOIN b| on key (and every further shared variable, as the join
+// itself groups them): the join's own path up to its count, no rows
+// written.  A count that cannot run (no scratch, over 2^40 rows) reads as
+// the largest size, so the candidate goes last; the join itself then
+// reports what stops it.
+static int64_t count_join(Ctx* ctx, const mapsq_table& a, const mapsq_table& b, int32_t key) {
+    mapsq_table t{};
+    ctx->count_only = true;
+    const mapsq_status st = join_tables(ctx, &a, &b, key, &t);
+    ctx->count_only = false;
+    if (st) {
+        ctx->err.clear();
+        return INT64_MAX;
+    }
+    return t.nrows;
+}
+
+// The variable a join of tables with variables `a` and `b` uses as its key:
+// the first shared one in the query's first-appearance order (-1: none).
+static int32_t first_shared(const std::vector<int32_t>& qvars, const mapsq_table& a, const mapsq_table& b) {
+    for (int32_t v : qvars)
+        if (binds(a, v) && binds(b, v)) return v;
+    return -1;
 }
 
 mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,
@@ -215,35 +244,111 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
             return st;
         }
     }
-    std::vector<std::vector<int32_t>> tv(npats);
-    std::vector<int64_t> tr(npats);
-    for (int i = 0; i < npats; i++) {
-        tv[i].assign(tabs[i].var, tabs[i].var + tabs[i].ncols);
-        tr[i] = tabs[i].nrows;
-    }
-    int start;
-    std::vector<PlanStep> steps;
-    greedy_plan(tv, tr, qvars, &start, &steps);
-    if (mapsq_status s2 = key_sort_views(ctx, pats, tabs.data(), start, steps)) {
-        cleanup();
-        return s2;
-    }
-    mapsq_table cur = tabs[start];
-    used[start] = true;
-    for (const PlanStep& ps : steps) {
+    std::vector<mapsq_plan_step> plan;
+    mapsq_table cur{};
+    // one join step: cur JOIN tabs[pick] (a cross product when key < 0)
+    auto step = [&](int pick, int32_t key, int32_t candidates) -> mapsq_status {
         mapsq_table nxt{};
-        mapsq_status st = ps.cross ? cross_join(ctx, cur, tabs[ps.pick], &nxt)
-                                   : join_tables(ctx, &cur, &tabs[ps.pick], ps.key, &nxt);
+        mapsq_status st = key < 0 ? cross_join(ctx, cur, tabs[pick], &nxt)
+                                  : join_tables(ctx, &cur, &tabs[pick], key, &nxt);
         if (st) {
             free_table(ctx, &cur);
             cleanup();
             return st;
         }
         free_table(ctx, &cur);
-        free_table(ctx, &tabs[ps.pick]);
-        used[ps.pick] = true;
+        free_table(ctx, &tabs[pick]);
+        used[pick] = true;
         cur = nxt;
+        plan.push_back(mapsq_plan_step{pick, key, cur.nrows, candidates, 0});
+        return MAPSQ_OK;
+    };
+
+    if (ctx->planner == MAPSQ_PLAN_EXACT && npats > 2) {
+        // first join: the connected pair with the smallest exact |RS|, the
+        // smaller table (ties: lower index) on the left
+        int64_t best = INT64_MAX;
+        int bl = -1, br = -1, counted = 0;
+        int32_t bkey = -1;
+        for (int i = 0; i < npats; i++)
+            for (int j = i + 1; j < npats; j++) {
+                const int32_t key = first_shared(qvars, tabs[i], tabs[j]);
+                if (key < 0) continue;
+                const bool i_left = tabs[i].nrows <= tabs[j].nrows;
+                const int l = i_left ? i : j, r = i_left ? j : i;
+                if (mapsq_status st = view_on_key(ctx, pats, tabs.data(), l, key)) return cleanup(), st;
+                if (mapsq_status st = view_on_key(ctx, pats, tabs.data(), r, key)) return cleanup(), st;
+                const int64_t n = count_join(ctx, tabs[l], tabs[r], key);
+                counted++;
+                if (bl < 0 || n < best) {
+                    best = n;
+                    bl = l;
+                    br = r;
+                    bkey = key;
+                }
+            }
+        if (bl < 0) {  // no two patterns share a variable: cross products from the smallest
+            bl = 0;
+            for (int i = 1; i < npats; i++)
+                if (tabs[i].nrows < tabs[bl].nrows) bl = i;
+        }
+        if (mapsq_status st = view_on_key(ctx, pats, tabs.data(), bl, bkey)) return cleanup(), st;
+        if (br >= 0)
+            if (mapsq_status st = view_on_key(ctx, pats, tabs.data(), br, bkey)) return cleanup(), st;
+        cur = tabs[bl];
+        used[bl] = true;
+        plan.push_back(mapsq_plan_step{bl, -1, cur.nrows, 0, 0});
+        if (br >= 0)
+            if (mapsq_status st = step(br, bkey, counted)) return st;
+        // then the connected table whose exact |RS| with the result is smallest
+        while ((int)plan.size() < npats) {
+            int pick = -1;
+            int32_t pkey = -1;
+            int64_t pbest = INT64_MAX;
+            counted = 0;
+            for (int j = 0; j < npats; j++) {
+                if (used[j]) continue;
+                const int32_t key = first_shared(qvars, cur, tabs[j]);
+                if (key < 0) continue;
+                if (mapsq_status st = view_on_key(ctx, pats, tabs.data(), j, key)) {
+                    free_table(ctx, &cur);
+                    cleanup();
+                    return st;
+                }
+                const int64_t n = count_join(ctx, cur, tabs[j], key);
+                counted++;
+                if (pick < 0 || n < pbest) {
+                    pbest = n;
+                    pick = j;
+                    pkey = key;
+                }
+            }
+            if (pick < 0)  // nothing connected: the smallest remaining table by cross product
+                for (int j = 0; j < npats; j++)
+                    if (!used[j] && (pick < 0 || tabs[j].nrows < tabs[pick].nrows)) pick = j;
+            if (mapsq_status st = step(pick, pkey, counted)) return st;
+        }
+    } else {
+        std::vector<std::vector<int32_t>> tv(npats);
+        std::vector<int64_t> tr(npats);
+        for (int i = 0; i < npats; i++) {
+            tv[i].assign(tabs[i].var, tabs[i].var + tabs[i].ncols);
+            tr[i] = tabs[i].nrows;
+        }
+        int start;
+        std::vector<PlanStep> steps;
+        greedy_plan(tv, tr, qvars, &start, &steps);
+        if (mapsq_status s2 = key_sort_views(ctx, pats, tabs.data(), start, steps)) {
+            cleanup();
+            return s2;
+        }
+        cur = tabs[start];
+        used[start] = true;
+        plan.push_back(mapsq_plan_step{start, -1, cur.nrows, 0, 0});
+        for (const PlanStep& ps : steps)
+            if (mapsq_status st = step(ps.pick, ps.cross ? -1 : ps.key, 0)) return st;
     }
+    ctx->last_plan = plan;
     // projection (bag): pick the selected columns in the requested order
     mapsq_table res = project_table(cur, want);
     *out = res;

@@ -867,9 +867,9 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         ctx->last = js;
         if (total >= SAT40_HOST) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds 2^40 rows");
         set_meta(out);
-        if (total == 0) {
+        if (total == 0 || ctx->count_only) {
             out->owned = 1;
-            out->nrows = 0;
+            out->nrows = (int64_t)total;
             return MAPSQ_OK;
         }
         mapsq_table m{};
@@ -961,8 +961,10 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // records): a join with no key in common, or whose output cannot fit in
     // the arena's free space at all, then ends without sorting anything.
     // On a join that fits it costs about as much as the count phase.
-    const bool precount =
-        !composite && (ctx->precount == 2 || (ctx->precount == 0 && (uint64_t)N >= PRECOUNT_MIN_RECORDS));
+    // (a count-only call takes it whenever the key range allows: it is the
+    // whole answer there)
+    const bool precount = !composite && (ctx->precount == 2 || ctx->count_only ||
+                                         (ctx->precount == 0 && (uint64_t)N >= PRECOUNT_MIN_RECORDS));
     if (precount) {
         const uint64_t range = (uint64_t)((int64_t)kmax - (int64_t)kmin) + 1;
         Block cnt;
@@ -986,10 +988,10 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
             js.out_rows = (int64_t)std::min<uint64_t>(total, SAT40_HOST);
             ctx->last = js;
             if (total >= SAT40_HOST) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds 2^40 rows");
-            if (total == 0) {
+            if (total == 0 || ctx->count_only) {
                 set_meta(out);
                 out->owned = 1;
-                out->nrows = 0;
+                out->nrows = (int64_t)total;
                 return MAPSQ_OK;
             }
             if (ctx->out_cols ? total > (uint64_t)ctx->out_cap
@@ -1191,9 +1193,9 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     ctx->last = js;
     if (total >= SAT40_HOST) return ctx->fail(MAPSQ_ERR_TOO_LARGE, "join result exceeds 2^40 rows");
     set_meta(out);
-    if (total == 0) {
+    if (total == 0 || ctx->count_only) {
         out->owned = 1;
-        out->nrows = 0;
+        out->nrows = (int64_t)total;
         return MAPSQ_OK;
     }
     mapsq_table m{};

@@ -114,6 +114,11 @@ struct Ctx {
     int32_t merge_mode = 0;  // 0 merge join of key-sorted tables, 1 never
     int32_t precount = 0;    // exact |RS| before shuffles: 0 of 2^24+ records, 1 never, 2 always
     int32_t composite = 0;   // 0 a second shared variable joins as part of the key, 1 it is filtered
+    int32_t planner = 0;     // mapsq_query join order: 0 pattern sizes, 1 exact join sizes
+    // join_tables stops once the exact |RS| is known (nrows set, no columns)
+    bool count_only = false;
+    // the plan mapsq_query ran last: start pattern, then each join step
+    std::vector<mapsq_plan_step> last_plan;
     // autotuned choices: (key bits << 8 | log2 records) -> (rb << 8 | kpt)
     std::map<uint32_t, uint32_t> tuned;
     mapsq_join_stats last{};

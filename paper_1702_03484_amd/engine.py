@@ -80,6 +80,14 @@ class MapSQ:
     def stats(self) -> B.mapsq_join_stats:
         return B.mapsq_last_join_stats(self.ctx)
 
+    def set_planner(self, exact: bool):
+        """mapsq_query join order from exact join sizes counted on the GPU
+        (True) or from pattern sizes (False, the default)."""
+        B.mapsq_set_planner(self.ctx, B.MAPSQ_PLAN_EXACT if exact else B.MAPSQ_PLAN_SIZES)
+
+    def last_plan(self) -> list:
+        return B.mapsq_last_plan(self.ctx)
+
     def set_tuning(self, radix_bits: int = 0, keys_per_thread: int = 0):
         B.mapsq_set_tuning(self.ctx, radix_bits, keys_per_thread)
 
