@@ -13,6 +13,8 @@ Contents
               order-independent multiset hash.
 ``hashjoin``  a plain C hash join (``hashjoin.c``, OpenMP) used as a second,
               independently written witness and for host timing.
+``dictionary`` term <-> identifier encoding by its plain definition (a Python
+              dict; identifiers dense, in order of first appearance).
 
 Every function cites the passage of the paper it follows (Feng, Zhang and
 Feng, "MapSQ: A MapReduce-based Framework for SPARQL Queries on GPU",
