@@ -32,7 +32,7 @@ rates, p50/p99).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-cfg3] [--no-batched] [--no-serving] [--warm]
-       python bench.py --cfg3-only | --cfg4-only | --cfg5-only | --shuffle-only
+       python bench.py --cfg3-only | --cfg4-only | --cfg5-only | --shuffle-only | --dict-only
        python bench.py --copy-calibration   (plain copy of a known size, for PMC scaling)
 """
 from __future__ import annotations
@@ -277,6 +277,63 @@ def run_cfg3(reps=5):
             "plans": {"step": "(pattern, key variable, rows, join sizes counted)",
                       "pattern_sizes": plan_sizes, "exact_join_sizes": plan_exact,
                       "ms_exact_join_sizes": round(median(tx) * 1e3, 3)}}
+
+
+def run_dict(n_terms=10_000_000, n_vocab=2_000_000, reps=5):
+    """Dictionary encoding of an RDF-shaped term stream resident in HBM
+    (Zipf(1.1) frequencies over a 2M-term vocabulary of IRIs and literals):
+    one encode of the whole batch into a fresh dictionary per repetition,
+    and the decode of every identifier back to text; median of ``reps``
+    cold repetitions.  Beside it, the oracle's dictionary (a Python dict)
+    on the first 1M terms."""
+    import numpy as np
+    import torch
+
+    from oracle import dictionary as D
+    from paper_1702_03484_amd.engine import MapSQ
+    from synth import rdf_terms
+
+    log(f"[dict] drawing {n_terms} terms over {n_vocab}")
+    data, off, _ = rdf_terms(1, n_terms, n_vocab)
+    text = int(off[-1])
+    with MapSQ(arena_bytes=16 << 30) as sess:
+        dd = torch.from_numpy(data).cuda()
+        do = torch.from_numpy(off).cuda()
+        state = {}
+
+        def enc():
+            sess.dict_create(n_terms, 2 * text)
+            ids, new = sess.dict_encode(dd, do)
+            state["ids"], state["new"] = ids, new
+            return new
+
+        te, _, _ = timed_reps(enc, reps=reps)
+        ids = state["ids"]
+
+        def dec():
+            b, o = sess.dict_decode(ids)
+            state["dec"] = (b, o)
+            return int(o[-1])
+
+        td, back, _ = timed_reps(dec, reps=reps)
+        assert back == text and torch.equal(state["dec"][0], dd) and torch.equal(state["dec"][1], do)
+        distinct = state["new"]
+    sample = 1_000_000
+    terms = D.split_terms(data[:int(off[sample])].tobytes(), off[:sample + 1])
+    t0 = time.perf_counter()
+    D.encode(terms)
+    cpu_s = time.perf_counter() - t0
+    e, d = median(te), median(td)
+    log(f"[dict] encode {n_terms / e / 1e6:.0f} M terms/s ({text / e / 1e9:.1f} GB/s of text), "
+        f"decode {n_terms / d / 1e6:.0f} M terms/s; oracle {sample / cpu_s / 1e6:.2f} M terms/s")
+    return {"workload": f"{n_terms} RDF-shaped terms (IRIs and literals), Zipf 1.1 over {n_vocab}, "
+                        f"{text} bytes of text, device buffers",
+            "distinct": distinct, "encode_ms": round(e * 1e3, 3), "encode_terms_per_s": n_terms / e,
+            "encode_text_gbs": round(text / e / 1e9, 1), "decode_ms": round(d * 1e3, 3),
+            "decode_terms_per_s": n_terms / d, "decode_text_gbs": round(text / d / 1e9, 1),
+            "timing": f"median of {reps} cold repetitions; encode into a fresh dictionary each time, "
+                      "decode includes its size read-back",
+            "cpu_oracle": {"terms_per_s": sample / cpu_s, "sample": f"first {sample} terms, Python dict, 1 thread"}}
 
 
 def run_cfg2_sort(sess, w, reps=5):
@@ -542,6 +599,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="leave out the serving measurement (500M-triple store)")
     ap.add_argument("--cfg5-only", action="store_true")
     ap.add_argument("--shuffle-only", action="store_true", help="only the 16M + 16M-record shuffle join")
+    ap.add_argument("--dict-only", action="store_true", help="only the term dictionary encode/decode")
+    ap.add_argument("--no-dict", action="store_true", help="leave out the term dictionary measurement")
     ap.add_argument("--warm", action="store_true", help="no cache flush before timed repetitions")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -563,6 +622,9 @@ def main():
         return
     if args.shuffle_only:
         print(json.dumps(run_shuffle()), flush=True)
+        return
+    if args.dict_only:
+        print(json.dumps(run_dict()), flush=True)
         return
 
     import torch
@@ -652,6 +714,7 @@ def main():
 
     cfg3 = None if (args.no_cfg3 or not full) else guarded(run_cfg3, "cfg3 measurement")
     shuffle = guarded(run_shuffle, "shuffle measurement")
+    dictionary = None if args.no_dict else guarded(run_dict, "dictionary measurement")
     batched = None if args.no_batched else guarded(run_cfg4, "batched measurement")
     served = None if args.no_serving else guarded(run_cfg5, "serving measurement")
     out = {
@@ -680,6 +743,7 @@ def main():
         "cfg3": cfg3,
         "map": mp,
         "shuffle": shuffle,
+        "dictionary": dictionary,
         "batched": batched,
         "serving": served,
     }

@@ -328,6 +328,47 @@ mapsq_status mapsq_poll(mapsq_ctx* ctx, uint64_t ticket, int32_t* done, mapsq_ta
  * null outputs. */
 mapsq_status mapsq_poll_next(mapsq_ctx* ctx, uint64_t* ticket, int32_t* done, mapsq_table* out);
 
+/* ---- term dictionary --------------------------------------------------
+ * Table 1 writes the example with string terms; the join works on their
+ * identifiers.  A context holds one dictionary on the device that maps byte
+ * strings to dense identifiers 0, 1, 2, ... in order of first appearance
+ * and back: a batch of terms is hashed (FNV-1a, 64-bit) and inserted into an
+ * open-addressing table with a 64-bit CAS per claimed slot, the first
+ * occurrences of terms it did not hold are numbered in batch order after the
+ * terms it held, and their bytes are appended to its byte store.  Encoding a
+ * batch and then another gives the identifiers of encoding both at once.
+ * Terms are arbitrary byte strings (no terminator; the empty string is a
+ * term).  A batch is bytes plus n + 1 int64 offsets starting at 0 and never
+ * decreasing: term i is bytes[offsets[i] .. offsets[i + 1]). */
+#define MAPSQ_DICT_DEVICE_PTRS 1u /* every buffer of the call is device memory (else host) */
+#define MAPSQ_DICT_LOOKUP 2u      /* encode without adding: an unknown term gives -1 */
+
+/* (Re)create the context's dictionary, empty, with room for max_terms terms
+ * (1 .. 2^30) and max_bytes bytes of term text (0 .. 2^40) in the arena:
+ * 16 bytes per term of hash table and 8 of offsets, plus the text.  Drops
+ * any dictionary the context had.  CAPACITY when the arena has no room. */
+mapsq_status mapsq_dict_create(mapsq_ctx* ctx, int64_t max_terms, int64_t max_bytes);
+
+/* Identifiers of a batch of n terms (n <= min(2^26, max_terms)), written to
+ * ids[0 .. n) (int32).  Terms the dictionary lacks are added (unless
+ * MAPSQ_DICT_LOOKUP) and *n_new (may be NULL) gets their number.
+ * INVALID_ARG for bad offsets (checked before any byte is read); CAPACITY
+ * when the new terms would exceed max_terms or max_bytes (the dictionary is
+ * then left exactly as it was); STATE without a dictionary.  Synchronises. */
+mapsq_status mapsq_dict_encode(mapsq_ctx* ctx, const uint8_t* bytes, const int64_t* offsets, int64_t n,
+                               uint32_t flags, int32_t* ids, int64_t* n_new);
+
+/* Terms of n identifiers (n <= 2^26): their bytes back to back in
+ * bytes[0 .. need) and n + 1 offsets in offsets[] (starting at 0).  *need
+ * (may be NULL) gets the byte count; TOO_LARGE when it exceeds cap_bytes
+ * (nothing is written then); INVALID_ARG for an identifier outside
+ * [0, terms).  Synchronises. */
+mapsq_status mapsq_dict_decode(mapsq_ctx* ctx, const int32_t* ids, int64_t n, uint32_t flags, int64_t* offsets,
+                               uint8_t* bytes, int64_t cap_bytes, int64_t* need);
+
+/* Terms and bytes of text the dictionary holds (STATE without one). */
+mapsq_status mapsq_dict_info(mapsq_ctx* ctx, int64_t* terms, int64_t* bytes);
+
 /* Release an owned table (views are left alone); the struct is zeroed. */
 mapsq_status mapsq_table_free(mapsq_ctx* ctx, mapsq_table* t);
 

@@ -154,6 +154,12 @@ _SIGS = [
      [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(mapsq_table)]),
     ("mapsq_table_free", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_table)]),
     ("mapsq_last_join_stats", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_join_stats)]),
+    ("mapsq_dict_create", ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int64]),
+    ("mapsq_dict_encode", ctypes.c_int32,
+     [_P, _P, _P, ctypes.c_int64, ctypes.c_uint32, _P, ctypes.POINTER(ctypes.c_int64)]),
+    ("mapsq_dict_decode", ctypes.c_int32,
+     [_P, _P, ctypes.c_int64, ctypes.c_uint32, _P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    ("mapsq_dict_info", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     ("mapsq_set_planner", ctypes.c_int32, [_P, ctypes.c_int32]),
     ("mapsq_last_plan", ctypes.c_int32,
      [_P, ctypes.POINTER(mapsq_plan_step), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -323,6 +329,43 @@ def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0, precount: int
     shuffles of 2^24+ records, 1 never, 2 always; composite: 0 a second
     shared variable is part of the join key, 1 it is filtered afterwards."""
     _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge, precount, composite))
+
+
+MAPSQ_DICT_DEVICE_PTRS = 1
+MAPSQ_DICT_LOOKUP = 2
+
+
+def mapsq_dict_create(ctx, max_terms: int, max_bytes: int):
+    _check(ctx, lib().mapsq_dict_create(ctx, max_terms, max_bytes))
+
+
+def mapsq_dict_encode(ctx, bytes_ptr: int, offsets_ptr: int, n: int, flags: int, ids_ptr: int) -> int:
+    """Pointers are host or device addresses (flags); returns the number of new terms."""
+    nn = ctypes.c_int64(0)
+    _check(ctx, lib().mapsq_dict_encode(ctx, bytes_ptr, offsets_ptr, n, flags, ids_ptr, ctypes.byref(nn)))
+    return nn.value
+
+
+def mapsq_dict_decode(ctx, ids_ptr: int, n: int, flags: int, offsets_ptr: int, bytes_ptr: int, cap_bytes: int) -> int:
+    """Returns the byte count written (raises TOO_LARGE with the need in the message)."""
+    need = ctypes.c_int64(0)
+    _check(ctx, lib().mapsq_dict_decode(ctx, ids_ptr, n, flags, offsets_ptr, bytes_ptr, cap_bytes, ctypes.byref(need)))
+    return need.value
+
+
+def mapsq_dict_need(ctx, ids_ptr: int, n: int, flags: int, offsets_ptr: int) -> int:
+    """Bytes a decode of these identifiers needs (a decode with no room)."""
+    need = ctypes.c_int64(0)
+    st = lib().mapsq_dict_decode(ctx, ids_ptr, n, flags, offsets_ptr, None, 0, ctypes.byref(need))
+    if st not in (MAPSQ_OK, MAPSQ_ERR_TOO_LARGE):
+        _check(ctx, st)
+    return need.value
+
+
+def mapsq_dict_info(ctx):
+    t, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(ctx, lib().mapsq_dict_info(ctx, ctypes.byref(t), ctypes.byref(b)))
+    return t.value, b.value
 
 
 def mapsq_set_planner(ctx, mode: int):

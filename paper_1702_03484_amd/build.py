@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmapsq.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["k_sort.hip", "k_reduce.hip", "k_map.hip", "k_util.hip", "k_batch.hip", "k_semi.hip", "k_merge.hip", "noalloc.hip", "runtime.cpp", "arena.cpp", "planner.cpp",
+SOURCES = ["k_sort.hip", "k_reduce.hip", "k_map.hip", "k_util.hip", "k_batch.hip", "k_semi.hip", "k_merge.hip", "noalloc.hip", "k_dict.hip", "dict.cpp", "runtime.cpp", "arena.cpp", "planner.cpp",
            "batch.cpp", "serve.cpp", "capi.cpp"]
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

@@ -218,6 +218,32 @@ mapsq_status mapsq_set_join_options(mapsq_ctx* c, int32_t semijoin, int32_t merg
     });
 }
 
+mapsq_status mapsq_dict_create(mapsq_ctx* c, int64_t max_terms, int64_t max_bytes) {
+    return guarded(c, [&](Ctx* ctx) { return mq::dict_create(ctx, max_terms, max_bytes); });
+}
+
+mapsq_status mapsq_dict_encode(mapsq_ctx* c, const uint8_t* bytes, const int64_t* offsets, int64_t n, uint32_t flags,
+                               int32_t* ids, int64_t* n_new) {
+    return guarded(c, [&](Ctx* ctx) { return mq::dict_encode(ctx, bytes, offsets, n, flags, ids, n_new); });
+}
+
+mapsq_status mapsq_dict_decode(mapsq_ctx* c, const int32_t* ids, int64_t n, uint32_t flags, int64_t* offsets,
+                               uint8_t* bytes, int64_t cap_bytes, int64_t* need) {
+    return guarded(c, [&](Ctx* ctx) { return mq::dict_decode(ctx, ids, n, flags, offsets, bytes, cap_bytes, need); });
+}
+
+mapsq_status mapsq_dict_info(mapsq_ctx* c, int64_t* terms, int64_t* bytes) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (!terms || !bytes) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");
+        *terms = 0;
+        *bytes = 0;
+        if (!ctx->dict.made) return ctx->fail(MAPSQ_ERR_STATE, "no dictionary (mapsq_dict_create)");
+        *terms = ctx->dict.nterms;
+        *bytes = ctx->dict.nbytes;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
 mapsq_status mapsq_set_planner(mapsq_ctx* c, int32_t mode) {
     return guarded(c, [&](Ctx* ctx) {
         if (mode != MAPSQ_PLAN_SIZES && mode != MAPSQ_PLAN_EXACT)

@@ -270,6 +270,55 @@ hipError_t launch_batch(const BatchHdr* hdr_dev, int rb, int kpt, int passes, hi
 // Rows per materialisation chunk of the batched kernels.
 uint32_t batch_chunk_rows();
 
+// ---- dictionary encoding of terms (k_dict.hip) ------------------------------
+// The dictionary on the device: a hash table of 64-bit slots (mask + 1 of
+// them, a power of two; ~0 = empty), and the terms in identifier order as
+// bytes with nterms + 1 offsets.
+struct DictDev {
+    uint64_t* table;
+    uint64_t mask;
+    int64_t* off;
+    uint8_t* bytes;
+    uint32_t nterms;
+};
+// A batch of n terms: bytes[off[i] .. off[i + 1]) is term i.
+struct TermsDev {
+    const uint8_t* bytes;
+    const int64_t* off;
+    uint32_t n;
+};
+// Per-batch device scratch: u32 arrays of n (rep, first, flag, rank), u64
+// arrays of n (blen, boff), scalars and the scan partials
+// (scan_part_bytes(n)).  first must hold ~0 before the launch and err 0.
+struct DictScratch {
+    uint32_t *rep, *first, *flag, *rank;
+    uint64_t *blen, *boff;
+    uint32_t* new_terms;
+    uint64_t* new_bytes;
+    void* part;
+    uint32_t* err;
+};
+constexpr uint32_t DICT_SCAN_MAX = 1u << 26;  // terms per batch
+size_t scan_part_bytes(uint32_t n);
+// err |= 1 unless off[0] == 0 and off is non-decreasing over n + 1 entries
+hipError_t launch_dict_check_offsets(const int64_t* off, uint32_t n, uint32_t* err, hipStream_t s);
+// hash and insert (insert = 0: look up only), then number the new terms:
+// *new_terms, *new_bytes, rank and boff of their first occurrences
+hipError_t launch_dict_encode_front(const DictDev& d, const TermsDev& t, int insert, DictScratch w, hipStream_t s);
+// ids[i]: the identifier of term i (new terms: base + rank; absent: -1)
+hipError_t launch_dict_ids(const TermsDev& t, DictScratch w, uint32_t base, int32_t* ids, hipStream_t s);
+// commit = 1: append the new terms (identifiers from base, bytes from
+// bbase) and re-point their slots; commit = 0: empty the slots the batch
+// claimed, restoring the table
+hipError_t launch_dict_commit(const DictDev& d, const TermsDev& t, DictScratch w, uint32_t base, int64_t bbase,
+                              int commit, hipStream_t s);
+// decoding: len[i] of each identifier (err |= 1 for one outside the
+// dictionary), pos = their exclusive scan, *total = the sum
+hipError_t launch_dict_decode(const DictDev& d, const int32_t* ids, uint32_t n, uint64_t* len, uint64_t* pos,
+                              uint64_t* total, void* part, uint32_t* err, hipStream_t s);
+hipError_t launch_dict_gather(const DictDev& d, const int32_t* ids, uint32_t n, const uint64_t* pos, uint8_t* out,
+                              hipStream_t s);
+
 // ---- utilities (k_util.hip) -----------------------------------------------
 // Between the two passes of a two-pass scan: the run totals tot[0..nruns)
 // (nruns <= 1024) become their exclusive prefix sums, in place, capped at

@@ -93,6 +93,19 @@ struct Store {
     uint64_t bytes = 0;
 };
 
+// The term dictionary of a context (mapsq_dict_*): arena blocks holding the
+// hash table, the offsets and the bytes of the terms in identifier order.
+struct Dict {
+    bool made = false;
+    int64_t cap_terms = 0, cap_bytes = 0;
+    size_t table_off = SIZE_MAX, off_off = SIZE_MAX, bytes_off = SIZE_MAX;
+    uint64_t* table = nullptr;
+    uint64_t slots = 0;  // a power of two above 2 * cap_terms
+    int64_t* off = nullptr;
+    uint8_t* bytes = nullptr;
+    int64_t nterms = 0, nbytes = 0;
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -145,6 +158,7 @@ struct Ctx {
     void release_graphs();
     // serving scheduler (created on first use)
     Server* server = nullptr;
+    Dict dict;
     // When set, the next join result is written to these caller-owned
     // columns (out_cap rows each) instead of an arena table.
     int32_t* const* out_cols = nullptr;
@@ -248,6 +262,13 @@ mapsq_status key_sort_views(Ctx* ctx, const mapsq_pattern* pats, mapsq_table* ta
 bool ensure_stage(Ctx* ctx, size_t bytes);
 // [lo, hi) of each index lookup (2 int64 per query in out); one synchronisation
 mapsq_status locate_ranges(Ctx* ctx, const LocateQuery* q, size_t n, int64_t* out);
+// term dictionary (dict.cpp)
+mapsq_status dict_create(Ctx* ctx, int64_t max_terms, int64_t max_bytes);
+mapsq_status dict_encode(Ctx* ctx, const uint8_t* bytes, const int64_t* offsets, int64_t n, uint32_t flags,
+                         int32_t* ids, int64_t* n_new);
+mapsq_status dict_decode(Ctx* ctx, const int32_t* ids, int64_t n, uint32_t flags, int64_t* offsets, uint8_t* bytes,
+                         int64_t cap_bytes, int64_t* need_bytes);
+void dict_release(Ctx* ctx);
 // serving (serve.cpp)
 mapsq_status serve_config(Ctx* ctx, uint64_t budget_bytes, int32_t max_active);
 mapsq_status submit(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int32_t* sel, int32_t nsel,

@@ -80,6 +80,55 @@ class MapSQ:
     def stats(self) -> B.mapsq_join_stats:
         return B.mapsq_last_join_stats(self.ctx)
 
+    # ---- term dictionary -----------------------------------------------------
+    def dict_create(self, max_terms: int, max_bytes: int):
+        B.mapsq_dict_create(self.ctx, max_terms, max_bytes)
+
+    def dict_encode(self, data, offsets, lookup: bool = False):
+        """Identifiers of the terms data[offsets[i]:offsets[i+1]]: numpy
+        buffers (host path, returns numpy) or device tensors (uint8 data,
+        int64 offsets; returns an int32 tensor).  Returns (ids, new terms)."""
+        flags = B.MAPSQ_DICT_LOOKUP if lookup else 0
+        if isinstance(offsets, torch.Tensor):
+            assert offsets.is_cuda and offsets.dtype == torch.int64 and data.dtype == torch.uint8
+            n = offsets.numel() - 1
+            ids = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
+            new = B.mapsq_dict_encode(self.ctx, data.data_ptr(), offsets.data_ptr(), n,
+                                      flags | B.MAPSQ_DICT_DEVICE_PTRS, ids.data_ptr())
+            return ids[:n], new
+        if isinstance(data, (bytes, bytearray)):
+            data = np.frombuffer(data, dtype=np.uint8)
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        n = offsets.size - 1
+        ids = np.empty(max(n, 1), dtype=np.int32)
+        new = B.mapsq_dict_encode(self.ctx, data.ctypes.data if data.size else None, offsets.ctypes.data, n, flags,
+                                  ids.ctypes.data)
+        return ids[:n], new
+
+    def dict_decode(self, ids):
+        """(bytes, int64 offsets) of the terms of `ids` (numpy int32 on the
+        host, or an int32 device tensor: then device tensors come back)."""
+        if isinstance(ids, torch.Tensor):
+            ids = ids.contiguous()
+            n = ids.numel()
+            off = torch.empty(n + 1, dtype=torch.int64, device=ids.device)
+            need = B.mapsq_dict_need(self.ctx, ids.data_ptr(), n, B.MAPSQ_DICT_DEVICE_PTRS, off.data_ptr())
+            out = torch.empty(max(need, 1), dtype=torch.uint8, device=ids.device)
+            B.mapsq_dict_decode(self.ctx, ids.data_ptr(), n, B.MAPSQ_DICT_DEVICE_PTRS, off.data_ptr(), out.data_ptr(),
+                                need)
+            return out[:need], off
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        n = ids.size
+        off = np.empty(n + 1, dtype=np.int64)
+        need = B.mapsq_dict_need(self.ctx, ids.ctypes.data, n, 0, off.ctypes.data)
+        out = np.empty(max(need, 1), dtype=np.uint8)
+        B.mapsq_dict_decode(self.ctx, ids.ctypes.data, n, 0, off.ctypes.data, out.ctypes.data, need)
+        return out[:need].tobytes(), off
+
+    def dict_info(self):
+        return B.mapsq_dict_info(self.ctx)
+
     def set_planner(self, exact: bool):
         """mapsq_query join order from exact join sizes counted on the GPU
         (True) or from pattern sizes (False, the default)."""

@@ -2,8 +2,8 @@
 benchmark.
 
 This package only draws data: dictionary-encoded int32 triple stores, the
-triple patterns of the queries run over them, and random partial-match
-tables.  It contains none of the join's arithmetic (no map, no sort, no
+triple patterns of the queries run over them, random partial-match tables,
+and streams of RDF-shaped string terms.  It contains none of the join's arithmetic (no map, no sort, no
 per-key counting of the join itself), so that neither side of a parity test
 can inherit a mistake from it.
 """
@@ -22,4 +22,5 @@ from .gen import (  # noqa: F401
     serving_cfg5,
     store_cfg5,
     var,
+    rdf_terms,
 )

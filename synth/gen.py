@@ -431,3 +431,37 @@ def serving_cfg5(w: Workload, n_queries: int, seed: int = 1, sample: int = 20_00
             pats.append(tuple(pat))
         out.append(pats)
     return out
+
+
+def rdf_terms(seed: int, n_terms: int, n_vocab: int, q: float = 1.1, max_literal: int = 80) -> tuple:
+    """A stream of ``n_terms`` RDF-shaped byte-string terms drawn from a
+    vocabulary of ``n_vocab`` distinct terms with Zipf(q) frequencies: IRIs
+    ``<http://example.org/{kind}/{k}>`` (kinds by class of rank) and, for one
+    rank in five, quoted literals of 0..max_literal random lowercase bytes.
+    Returns (uint8 bytes, int64 offsets of n_terms + 1, the vocabulary as a
+    list of bytes in rank order)."""
+    r = _rng(7000 + seed, 0)
+    kinds = [b"person", b"org", b"pub", b"course", b"dept"]
+    vocab = []
+    lens = r.integers(0, max_literal + 1, n_vocab)
+    for k in range(n_vocab):
+        if k % 5 == 4:
+            lit = r.integers(97, 123, int(lens[k]), dtype=np.int64).astype(np.uint8).tobytes()
+            vocab.append(b'"' + lit + b'"')
+        else:
+            vocab.append(b"<http://example.org/" + kinds[k % 5] + b"/" + str(k).encode() + b">")
+    ranks = zipf_bounded(r, n_terms, n_vocab, q) - 1
+    # a random bijection of ranks to vocabulary entries (hot terms of every kind)
+    perm = r.permutation(n_vocab)
+    picks = perm[ranks]
+    vlen = np.array([len(v) for v in vocab], dtype=np.int64)
+    voff = np.zeros(n_vocab + 1, dtype=np.int64)
+    voff[1:] = np.cumsum(vlen)
+    vbytes = np.frombuffer(b"".join(vocab), dtype=np.uint8)
+    off = np.zeros(n_terms + 1, dtype=np.int64)
+    off[1:] = np.cumsum(vlen[picks])
+    # gather every picked term's bytes: position j of the output takes byte
+    # (j - off[i]) of term i
+    owner = np.repeat(np.arange(n_terms, dtype=np.int64), vlen[picks])
+    src = voff[picks][owner] + (np.arange(off[-1], dtype=np.int64) - off[:-1][owner])
+    return vbytes[src].copy(), off, vocab
