@@ -107,11 +107,15 @@ __global__ void dict_insert_kernel(DictDev d, TermsDev t, int insert, uint32_t* 
 }
 
 // first[j] = lowest batch index whose term claimed slot-owner j (first[]
-// pre-set to ~0)
+// pre-set to ~0).  A plain read skips the atomic once a lower index is in:
+// a frequent term would otherwise send every occurrence's atomic to one
+// address, and those serialise.
 __global__ void dict_first_kernel(const uint32_t* __restrict__ rep, uint32_t n, uint32_t* __restrict__ first) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t r = rep[i];
-        if (r != DICT_NONE && (r & DICT_NEW)) atomicMin(first + (r & ~DICT_NEW), i);
+        if (r == DICT_NONE || !(r & DICT_NEW)) continue;
+        uint32_t* f = first + (r & ~DICT_NEW);
+        if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > i) atomicMin(f, i);
     }
 }
 

@@ -833,7 +833,14 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // this key): Reduce straight from the two sides' key runs, no shuffle.
     const int32_t* lkey = L->col[lk];
     const int32_t* rkey = R->col[rk];
-    if (!composite && ctx->merge_mode == 0 && L->sorted_col == lk + 1 && R->sorted_col == rk + 1) {
+    // A count-only call on two large sorted tables counts from dense per-key
+    // counts instead (two streaming passes over the keys), when the key range
+    // allows: the merge pass searches the larger table once per key run of
+    // the smaller one, which costs far more there.
+    const bool dense_count = ctx->count_only && std::min(nL, nR) >= COUNT_DENSE_MIN &&
+                             L->key_max >= 0 && R->key_max >= 0 &&
+                             (uint64_t)std::max(L->key_max, R->key_max) < PRECOUNT_MAX_RANGE;
+    if (!composite && !dense_count && ctx->merge_mode == 0 && L->sorted_col == lk + 1 && R->sorted_col == rk + 1) {
         const bool small_left = nL <= nR;
         const uint32_t nsm = small_left ? nL : nR, nbg = small_left ? nR : nL;
         const size_t sb4 = align_up(size_t(nsm) * 4, ARENA_ALIGN);

@@ -188,6 +188,9 @@ constexpr uint64_t SEMI_RATIO = 4;
 // the key range needs at most PRECOUNT_MAX_RANGE counters
 constexpr uint64_t PRECOUNT_MIN_RECORDS = uint64_t(1) << 24;
 constexpr uint64_t PRECOUNT_MAX_RANGE = uint64_t(1) << 28;
+// a count-only join of two key-sorted tables whose smaller side has at
+// least this many rows counts densely instead of merging
+constexpr uint32_t COUNT_DENSE_MIN = 1u << 16;
 // materialisation with one 256-row sub-chunk per wave when the output has
 // fewer rows than this per segment on average (per-row segment searches)
 constexpr uint64_t SPARSE_ROWS_PER_SEG = 64;
