@@ -1,7 +1,8 @@
 // Map of Algorithm 1 on gfx950: scan a range of the store (or any SoA
 // table), keep the rows that pass the pattern's equality tests, and emit
-// the variable columns in input order.  Two passes with no ordering between
-// blocks (no tile counter, no look-back).  In the test pass block b owns a
+// the variable columns in input order.  Up to 2^31 rows, one launch
+// (compact_fused_kernel below); beyond that, two passes with no ordering
+// between blocks (no tile counter, no look-back).  In the test pass block b owns a
 // contiguous run of tiles; it reads only the columns the tests use and
 // stores one __ballot word per 64 rows, the kept rows of its run before
 // each tile, and its run's total.  One block turns the run totals into
@@ -26,14 +27,20 @@ struct CompactGrid {
     uint64_t ntiles, chunk, blocks;
 };
 
-__host__ __device__ inline CompactGrid compact_grid(uint64_t n) {
+__host__ __device__ inline CompactGrid grid_of_runs(uint64_t n, uint64_t max_blocks) {
     CompactGrid g;
     g.ntiles = (n + CMP_TILE - 1) / CMP_TILE;
-    const uint64_t want = g.ntiles < CMP_MAX_BLOCKS ? g.ntiles : CMP_MAX_BLOCKS;
+    const uint64_t want = g.ntiles < max_blocks ? g.ntiles : max_blocks;
     g.chunk = want ? (g.ntiles + want - 1) / want : 0;
     g.blocks = g.chunk ? (g.ntiles + g.chunk - 1) / g.chunk : 0;
     return g;
 }
+
+__host__ __device__ inline CompactGrid compact_grid(uint64_t n) { return grid_of_runs(n, CMP_MAX_BLOCKS); }
+
+// the single-launch kernel: 8 blocks per CU keep twice the loads in flight
+constexpr uint64_t CMP_FUSED_BLOCKS = 2048;
+__host__ __device__ inline CompactGrid compact_grid_fused(uint64_t n) { return grid_of_runs(n, CMP_FUSED_BLOCKS); }
 
 // the kept count of the calling wave's 64-row slot i sits in lane i of `mine`
 __device__ __forceinline__ uint64_t pick_slot(const uint64_t (&km)[CMP_IPT]) {
@@ -164,20 +171,183 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_write_kernel(CompactArgs a, 
     }
 }
 
+// One launch for scans whose runs have at most CMP_FUSED_CHUNK tiles: block
+// b (in the order blocks start, from a tile counter) tests the tiles of run
+// b as the test pass does, keeping each tile's in-run offset and each wave's
+// offset inside the tile in LDS; wave 0 publishes the run's kept count and
+// looks back over the earlier runs for their total; then every wave writes
+// the rows its own mask words mark (the words it stored itself, so no block
+// barrier is needed between tiles).  A selective scan thus reads its tested
+// columns once and touches only the tiles with kept rows a second time,
+// from the same block, without a second launch over every tile.
+constexpr uint32_t CMP_FUSED_CHUNK = 512;
+// A run keeping at most this many rows lists them (record index by run
+// position) in LDS during its test phase and writes them with the whole
+// block after the look-back; larger runs walk their tiles' masks again.
+constexpr uint32_t CMP_LIST = 2048;
+
+// The first test's operands of one tile's row slots for the calling thread,
+// from clamped indices and unconditionally (a load under a per-lane
+// condition would wait for the one before it).
+__device__ __forceinline__ void load_first_test(const int32_t* A, const int32_t* B, int32_t c0, uint64_t n,
+                                                uint64_t base, uint32_t w, int32_t (&va)[CMP_IPT],
+                                                int32_t (&vb)[CMP_IPT]) {
+#pragma unroll
+    for (int i = 0; i < CMP_IPT; i++) {
+        const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
+        const uint64_t at = idx < n ? idx : n - 1;
+        va[i] = A ? A[at] : 0;
+        vb[i] = B ? B[at] : c0;
+    }
+}
+
+__global__ __launch_bounds__(MQ_BLOCK) void compact_fused_kernel(CompactArgs a, uint64_t* __restrict__ status,
+                                                                 uint32_t* __restrict__ run_ctr,
+                                                                 uint64_t* __restrict__ mask, CompactGrid g) {
+    __shared__ uint32_t s_wtot[2][MQ_WAVES];
+    __shared__ uint32_t s_tloc[CMP_FUSED_CHUNK];
+    __shared__ uint32_t s_wofs[CMP_FUSED_CHUNK][MQ_WAVES];
+    __shared__ uint32_t s_list[CMP_LIST];
+    __shared__ uint32_t s_slot;
+    __shared__ uint64_t s_pos;
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint64_t lt = lanemask_lt();
+    const uint32_t run_id = next_tile(run_ctr, &s_slot);
+    const uint64_t t0 = (uint64_t)run_id * g.chunk;
+    const uint64_t t1 = t0 + g.chunk < g.ntiles ? t0 + g.chunk : g.ntiles;
+    const int32_t* A0 = a.nterm > 0 ? a.in[a.term_a[0]] : nullptr;
+    const int32_t* B0 = a.nterm > 0 && a.term_b[0] >= 0 ? a.in[a.term_b[0]] : nullptr;
+    const int32_t c0 = a.nterm > 0 ? a.term_c[0] : 0;
+    uint32_t run_tot = 0;  // kept rows of the run's tiles so far (same in every thread)
+    for (uint64_t tile = t0; tile < t1; tile++) {
+        const uint64_t base = tile * CMP_TILE;
+        int32_t va[CMP_IPT], vb[CMP_IPT];
+        load_first_test(A0, B0, c0, a.n, base, w, va, vb);
+        bool ok[CMP_IPT];
+#pragma unroll
+        for (int i = 0; i < CMP_IPT; i++) {
+            const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
+            ok[i] = idx < a.n && (!A0 || va[i] == vb[i]);
+        }
+        for (int t = 1; t < a.nterm; t++) {
+            const int32_t* A = a.in[a.term_a[t]];
+            const int32_t* B = a.term_b[t] >= 0 ? a.in[a.term_b[t]] : nullptr;
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++) {
+                const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
+                if (ok[i]) ok[i] = A[idx] == (B ? B[idx] : a.term_c[t]);
+            }
+        }
+        uint64_t km[CMP_IPT];
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < CMP_IPT; i++) {
+            km[i] = __ballot(ok[i]);
+            run += (uint32_t)__popcll(km[i]);
+        }
+        const uint64_t mine = pick_slot(km);
+        if (lane() < (uint32_t)CMP_IPT) mask[tile * CMP_TILE_WORDS + w * CMP_IPT + lane()] = mine;
+        // one barrier per tile: the wave totals alternate between two slots,
+        // and no wave can be two barriers ahead of a reader
+        const int sl = (int)(tile & 1);
+        if (lane() == 0) s_wtot[sl][w] = run;
+        __syncthreads();
+        uint32_t ttot = 0, wex = 0;
+#pragma unroll
+        for (int i = 0; i < MQ_WAVES; i++) {
+            if ((uint32_t)i < w) wex += s_wtot[sl][i];
+            ttot += s_wtot[sl][i];
+        }
+        if (lane() == 0) s_wofs[tile - t0][w] = wex;
+        if (threadIdx.x == 0) s_tloc[tile - t0] = run_tot;
+        // the kept rows' record indices by their position in the run
+        if (run_tot + ttot <= CMP_LIST && run != 0) {
+            uint32_t at = run_tot + wex;
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++) {
+                if ((km[i] >> lane()) & 1ull)
+                    s_list[at + (uint32_t)__popcll(km[i] & lt)] =
+                        (uint32_t)(base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane()));
+                at += (uint32_t)__popcll(km[i]);
+            }
+        }
+        run_tot += ttot;
+    }
+    __syncthreads();  // s_wofs, s_tloc and s_list complete
+    if (w == 0) {
+        const uint64_t ex = tile_prefix_wave0(status, run_id, 1u, run_tot);
+        if (lane() == 0) {
+            s_pos = ex;
+            if (run_id == g.blocks - 1) *a.count = ex + run_tot;
+        }
+    }
+    __syncthreads();
+    if (run_tot == 0) return;
+    const uint64_t pos_run = s_pos;
+    if (run_tot <= CMP_LIST) {
+        // every kept row of the run at once: consecutive threads, consecutive outputs
+        for (uint32_t j = threadIdx.x; j < run_tot; j += MQ_BLOCK) {
+            const uint32_t idx = s_list[j];
+            for (int c = 0; c < a.nout; c++) a.out[c][pos_run + j] = a.in[a.out_src[c]][idx];
+        }
+        return;
+    }
+    for (uint64_t tile = t0; tile < t1; tile++) {
+        const uint64_t mine = lane() < (uint32_t)CMP_IPT ? mask[tile * CMP_TILE_WORDS + w * CMP_IPT + lane()] : 0ull;
+        if (__ballot(mine != 0ull) == 0ull) continue;  // none of this wave's rows kept here
+        const uint64_t base = tile * CMP_TILE;
+        const uint64_t pos = pos_run + s_tloc[tile - t0] + s_wofs[tile - t0][w];
+        uint64_t km[CMP_IPT];
+        uint32_t rel[CMP_IPT];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int i = 0; i < CMP_IPT; i++) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, i);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine >> 32), i);
+            km[i] = (uint64_t)hi << 32 | lo;
+            rel[i] = acc + (uint32_t)__popcll(km[i] & lt);
+            acc += (uint32_t)__popcll(km[i]);
+        }
+        for (int c = 0; c < a.nout; c++) {
+            const int32_t* __restrict__ src = a.in[a.out_src[c]];
+            int32_t* __restrict__ dst = a.out[c];
+            int32_t v[CMP_IPT];
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++) {
+                const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
+                v[i] = (km[i] >> lane()) & 1ull ? src[idx] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++)
+                if ((km[i] >> lane()) & 1ull) dst[pos + rel[i]] = v[i];
+        }
+    }
+}
+
 size_t compact_scratch_words(uint64_t n) {
     const CompactGrid g = compact_grid(n);
-    return (size_t)(g.blocks + (g.ntiles + 1) / 2 + g.ntiles * CMP_TILE_WORDS);
+    // run totals (u64 per run), in-run tile offsets (u32 per tile), the mask
+    // words of whole tiles, then the fused kernel's run counter (one word)
+    // and its look-back status words (one per run)
+    return (size_t)(g.blocks + (g.ntiles + 1) / 2 + g.ntiles * CMP_TILE_WORDS + 1 + CMP_FUSED_BLOCKS);
 }
 
 hipError_t launch_compact(const CompactArgs& a, uint64_t* scratch, hipStream_t stream) {
     if (a.n == 0) return hipSuccess;
     const CompactGrid g = compact_grid(a.n);
     if (g.ntiles * MQ_BLOCK > 0xffffffffull) return hipErrorInvalidValue;  // grid size in work-items is 32-bit
-    // scratch: run totals (u64 per test block), in-run tile offsets (u32 per
-    // tile), then the mask words of whole tiles
     uint64_t* counts = scratch;
     uint32_t* tloc = reinterpret_cast<uint32_t*>(scratch + g.blocks);
     uint64_t* mask = scratch + g.blocks + (g.ntiles + 1) / 2;
+    const CompactGrid gf = compact_grid_fused(a.n);
+    if (gf.chunk <= CMP_FUSED_CHUNK) {
+        uint64_t* ctr = mask + g.ntiles * CMP_TILE_WORDS;  // word 0: run counter; then status words
+        hipError_t e = launch_fill_u64(ctr, 1 + gf.blocks, 0ull, stream);
+        if (e != hipSuccess) return e;
+        compact_fused_kernel<<<(uint32_t)gf.blocks, MQ_BLOCK, 0, stream>>>(a, ctr + 1, reinterpret_cast<uint32_t*>(ctr),
+                                                                          mask, gf);
+        return hipGetLastError();
+    }
     compact_test_kernel<<<(uint32_t)g.blocks, MQ_BLOCK, 0, stream>>>(a, counts, tloc, mask, g);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_scan_runs(counts, (uint32_t)g.blocks, a.count, nullptr, nullptr, nullptr, stream);

@@ -32,12 +32,14 @@ class MapSQ:
             autotune.install(self, autotune.DEFAULT_TABLE if tuning == _DEFAULT_TUNING else tuning)
 
     def close(self):
-        """Destroy the context and drop the arena and kept tensors."""
+        """Destroy the context and drop the arena and kept tensors (returned
+        to the device, not kept in torch's cache: arenas are large)."""
         if self.ctx is not None:
             B.mapsq_destroy(self.ctx)
             self.ctx = None
         self.arena = None
         self._keep.clear()
+        torch.cuda.empty_cache()
 
     def __enter__(self):
         return self

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def s():
-    with MapSQ(arena_bytes=16 << 30) as m:
+    with MapSQ(arena_bytes=4 << 30) as m:
         yield m
 
 
