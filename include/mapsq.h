@@ -437,6 +437,17 @@ mapsq_status mapsq_profile_read(mapsq_ctx* ctx, mapsq_profile* out);
 mapsq_status mapsq_tune_record(mapsq_ctx* ctx, int32_t key_bits, int32_t log2_records, int32_t radix_bits,
                                int32_t keys_per_thread);
 
+/* Grid cap of the materialisation launches (their waves stride over the
+ * output's work items): 64 .. 65536 blocks, or 0 for automatic (the
+ * autotuned entry for the output's size class, else 8192).  Every choice
+ * gives the same rows in the same order. */
+mapsq_status mapsq_set_mat_tuning(mapsq_ctx* ctx, int32_t max_blocks);
+
+/* Autotuner table of the materialisation grid cap: for outputs of about
+ * 2^(log2_rows-1) .. 2^log2_rows rows use max_blocks (64 .. 65536);
+ * max_blocks = 0 removes the entry. */
+mapsq_status mapsq_tune_record_mat(mapsq_ctx* ctx, int32_t log2_rows, int32_t max_blocks);
+
 /* Bytes of the arena still free, and the largest free block. */
 mapsq_status mapsq_arena_free_bytes(mapsq_ctx* ctx, uint64_t* free_bytes, uint64_t* largest_block);
 

@@ -168,6 +168,8 @@ _SIGS = [
     ("mapsq_profile_enable", ctypes.c_int32, [_P, ctypes.c_int32]),
     ("mapsq_profile_read", ctypes.c_int32, [_P, ctypes.POINTER(mapsq_profile)]),
     ("mapsq_tune_record", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    ("mapsq_set_mat_tuning", ctypes.c_int32, [_P, ctypes.c_int32]),
+    ("mapsq_tune_record_mat", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_arena_free_bytes", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
@@ -397,6 +399,14 @@ def mapsq_profile_read(ctx) -> mapsq_profile:
 
 def mapsq_tune_record(ctx, key_bits: int, log2_records: int, radix_bits: int, keys_per_thread: int):
     _check(ctx, lib().mapsq_tune_record(ctx, key_bits, log2_records, radix_bits, keys_per_thread))
+
+
+def mapsq_set_mat_tuning(ctx, max_blocks: int = 0):
+    _check(ctx, lib().mapsq_set_mat_tuning(ctx, max_blocks))
+
+
+def mapsq_tune_record_mat(ctx, log2_rows: int, max_blocks: int):
+    _check(ctx, lib().mapsq_tune_record_mat(ctx, log2_rows, max_blocks))
 
 
 def mapsq_arena_free_bytes(ctx):

@@ -314,6 +314,29 @@ mapsq_status mapsq_tune_record(mapsq_ctx* c, int32_t key_bits, int32_t log2_reco
     });
 }
 
+mapsq_status mapsq_set_mat_tuning(mapsq_ctx* c, int32_t max_blocks) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (max_blocks != 0 && (max_blocks < 64 || max_blocks > 65536))
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "max_blocks must be 0 or in [64, 65536]");
+        ctx->tune_mat_blocks = max_blocks;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
+mapsq_status mapsq_tune_record_mat(mapsq_ctx* c, int32_t log2_rows, int32_t max_blocks) {
+    return guarded(c, [&](Ctx* ctx) {
+        if (log2_rows < 0 || log2_rows > 41) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "log2_rows in [0, 41]");
+        if (max_blocks == 0) {
+            ctx->mat_tuned.erase((uint32_t)log2_rows);
+            return (mapsq_status)MAPSQ_OK;
+        }
+        if (max_blocks < 64 || max_blocks > 65536)
+            return ctx->fail(MAPSQ_ERR_INVALID_ARG, "max_blocks must be 0 or in [64, 65536]");
+        ctx->mat_tuned[(uint32_t)log2_rows] = (uint32_t)max_blocks;
+        return (mapsq_status)MAPSQ_OK;
+    });
+}
+
 mapsq_status mapsq_arena_free_bytes(mapsq_ctx* c, uint64_t* free_bytes, uint64_t* largest_block) {
     return guarded(c, [&](Ctx* ctx) {
         if (!free_bytes || !largest_block) return ctx->fail(MAPSQ_ERR_INVALID_ARG, "null output");

@@ -465,16 +465,17 @@ hipError_t launch_materialize(const MatArgs& a, hipStream_t stream) {
     if (a.seg_major && (a.row_begin != 0 || a.seg_cl != nullptr)) return hipErrorInvalidValue;
     const int nc = 1 + a.nl + a.nr;
     const uint64_t rows = a.row_end - a.row_begin;
+    const uint64_t cap = a.max_blocks ? a.max_blocks : MAT_MAX_BLOCKS;
     // narrow joins get the value-column split fixed at compile time
 #define MQ_LAUNCH(C, L)                                                                             \
     if (a.seg_major) {                                                                              \
         const uint64_t groups = (a.seg_count + MQ_WAVE - 1) / MQ_WAVE;                              \
-        uint32_t blocks = (uint32_t)std::min<uint64_t>((groups + MQ_WAVES - 1) / MQ_WAVES, 256ull * 32); \
+        uint32_t blocks = (uint32_t)std::min<uint64_t>((groups + MQ_WAVES - 1) / MQ_WAVES, cap);       \
         mat_seg_kernel<C, L><<<std::max(blocks, 1u), MQ_BLOCK, 0, stream>>>(a);                     \
     } else {                                                                                        \
         const uint64_t crows = a.sparse ? 4 * MQ_WAVE : MatShape<C>::WROWS;                         \
         uint64_t chunks = (rows + crows - 1) / crows;                                               \
-        uint32_t blocks = (uint32_t)std::min<uint64_t>((chunks + MQ_WAVES - 1) / MQ_WAVES, 256ull * 32); \
+        uint32_t blocks = (uint32_t)std::min<uint64_t>((chunks + MQ_WAVES - 1) / MQ_WAVES, cap);       \
         materialize_kernel<C, L><<<blocks, MQ_BLOCK, 0, stream>>>(a);                               \
     }
     if (nc <= 4) {

@@ -168,7 +168,9 @@ struct MatArgs {
     // needs row_begin == 0, row_end == |RS| and seg_cl == null
     int32_t seg_major;
     uint32_t seg_count;  // host copy of *nseg (sizes the segment-major grid)
+    uint32_t max_blocks; // grid cap of the launch (0: MAT_MAX_BLOCKS); waves stride over the work
 };
+constexpr uint32_t MAT_MAX_BLOCKS = 256 * 32;
 // Segment-major materialisation pays for sparse outputs: fewer than
 // MAT_SEG_ROWS_PER_SEG output rows per key on average and no key product
 // above MAT_SEG_MAX_PAIRS, so a wave writes at most 4,096 rows.  With a few

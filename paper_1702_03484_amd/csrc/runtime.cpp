@@ -112,6 +112,12 @@ struct SortBufs {
     uint32_t* v[2];
 };
 
+uint32_t Ctx::mat_blocks(uint64_t rows) const {
+    if (tune_mat_blocks) return (uint32_t)tune_mat_blocks;
+    auto it = mat_tuned.find((uint32_t)bitlen(rows));
+    return it == mat_tuned.end() ? 0u : it->second;
+}
+
 void pick_tuning(Ctx* ctx, int key_bits, int& rb, int& kpt, uint64_t nrec) {
     rb = ctx->tune_rb;
     kpt = ctx->tune_kpt;
@@ -900,6 +906,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
         a.row_begin = 0;
         a.row_end = total;
         a.sparse = total < SPARSE_ROWS_PER_SEG * (uint64_t)nseg ? 1 : 0;
+        a.max_blocks = ctx->mat_blocks(total);
         ph = ctx->prof_begin(3);
         hipError_t e = launch_materialize(a, ctx->stream);
         // writes 4 B per output cell and reads the segment table (the value
@@ -1230,6 +1237,7 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     a.sparse = total < SPARSE_ROWS_PER_SEG * (uint64_t)nseg ? 1 : 0;
     a.seg_major = mat_seg_use(total, nseg, max_pairs) ? 1 : 0;
     a.seg_count = nseg;
+    a.max_blocks = ctx->mat_blocks(total);
     // values in sorted record order when output rows outnumber records
     // (each record's values are then read many times)
     const int nv = std::max(a.nl, a.nr);

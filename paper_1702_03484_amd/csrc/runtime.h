@@ -134,6 +134,11 @@ struct Ctx {
     std::vector<mapsq_plan_step> last_plan;
     // autotuned choices: (key bits << 8 | log2 records) -> (rb << 8 | kpt)
     std::map<uint32_t, uint32_t> tuned;
+    // materialisation grid cap: explicit (0: automatic), and autotuned by
+    // log2 of the output rows
+    int32_t tune_mat_blocks = 0;
+    std::map<uint32_t, uint32_t> mat_tuned;
+    uint32_t mat_blocks(uint64_t rows) const;
     mapsq_join_stats last{};
     // profiling: pairs of events around phases, harvested after a sync
     bool prof = false;
