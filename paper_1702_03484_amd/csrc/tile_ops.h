@@ -485,6 +485,37 @@ __device__ __forceinline__ void mat_rows_slow(const MatJoin& a, const uint64_t* 
     }
 }
 
+// Rows [j, j + nk) of one lane, the segments of its sub-chunk staged in
+// LDS: m_off[t] is segment (s + t)'s output offset and m_u holds its LEFT
+// start, RIGHT start, LEFT count, RIGHT count and output key (MAT_LDS_META
+// words apart), so a row needs one search in LDS and then only its value
+// loads.
+constexpr uint32_t MAT_LDS_META = 128;  // segments staged with their runs (28 B each)
+
+template <int NC, int NLC>
+__device__ __forceinline__ void mat_rows_meta(const MatJoin& a, const uint64_t* m_off, const uint32_t* m_u, uint32_t m,
+                                              uint64_t j, int nk, int32_t (&v)[NC][4]) {
+    const int nl = NLC >= 0 ? NLC : a.nl, nr = NLC >= 0 ? NC - 1 - NLC : a.nr;
+    const int nc = 1 + nl + nr;
+    uint32_t t[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) t[k] = k < nk ? seg_of(m_off, 0, m - 1, j + k) : 0u;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if (k < nk) {
+            SegPos p;
+            p.st = m_u[t[k]];
+            p.sp = m_u[MAT_LDS_META + t[k]];
+            p.cl = m_u[2 * MAT_LDS_META + t[k]];
+            p.cr = m_u[3 * MAT_LDS_META + t[k]];
+            p.left_inner = left_inner_of(p.cl, p.cr, nl, nr);
+            seg_locate(p, j + k - m_off[t[k]]);
+            v[0][k] = (int32_t)m_u[4 * MAT_LDS_META + t[k]];
+            row_values<NC>(a, nl, nc, seg_lpos(p), seg_rpos(p), v, k);
+        }
+    }
+}
+
 // The segment of row j (the last s with seg_off[s] <= j), given a guess:
 // the segment of an earlier row of the same wave, or 0.  When j still lies
 // in the guess's segment or the next one, three independent loads settle
@@ -646,9 +677,32 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
             // search), then each lane's own segment and rows
             const uint64_t jlast = (jend < jq + 4 * MQ_WAVE ? jend : jq + 4 * MQ_WAVE) - 1;
             const uint32_t s_last = wave_seg_of(a.seg_off, s, a.ns - 1, jlast, true);
+            const uint32_t m = s_last - s + 1;
+            nk = jl < jend ? (int)min((uint64_t)4, jend - jl) : 0;
+            if (lds && m <= MAT_LDS_META) {
+                // few segments (mid-density keys): each one's offset, runs and
+                // key staged once, coalesced, in the wave's LDS rows
+                uint64_t* m_off = lds;
+                uint32_t* m_u = reinterpret_cast<uint32_t*>(lds + MAT_LDS_META);
+                __builtin_amdgcn_wave_barrier();  // earlier reads of these rows are done
+                for (uint32_t t = lane(); t < m; t += MQ_WAVE) {
+                    SegPos p;
+                    seg_open<NC>(a, s + t, nl, nr, p);
+                    m_off[t] = a.seg_off[s + t];
+                    m_u[t] = p.st;
+                    m_u[MAT_LDS_META + t] = p.sp;
+                    m_u[2 * MAT_LDS_META + t] = p.cl;
+                    m_u[3 * MAT_LDS_META + t] = p.cr;
+                    m_u[4 * MAT_LDS_META + t] = (a.keys[p.st] >> a.key_shift) + (uint32_t)a.key_base;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (nk > 0) mat_rows_meta<NC, NLC>(a, m_off, m_u, m, jl, nk, v);
+                goto store;
+            }
             // many segments (a sparse stretch of the output): their offsets in
             // LDS, so that each lane's searches stay on chip
-            const uint32_t m = s_last - s + 1;
             const uint64_t* off = a.seg_off;
             uint32_t off0 = 0;
             if (lds && m > 2 && m <= MAT_LDS_SEGS) {
@@ -660,11 +714,11 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
                 off = lds;
                 off0 = s;
             }
-            nk = jl < jend ? (int)min((uint64_t)4, jend - jl) : 0;
             if (nk > 0)
                 mat_rows_slow<NC, NLC>(a, off, off0, seg_of(off, s - off0, s_last - off0, jl) + off0, s_last, jl,
                                        nk, v);
         }
+    store:
         if (nk == 4) {
 #pragma unroll
             for (int col = 0; col < NC; col++)
