@@ -2,9 +2,11 @@
 
   python -m paper_1702_03484_amd.profile_summary stats DIR
       per-kernel calls / average / total duration from *_kernel_stats.csv
-  python -m paper_1702_03484_amd.profile_summary pmc DIR COUNTER [REGEX]
+  python -m paper_1702_03484_amd.profile_summary pmc DIR COUNTER [REGEX [FIRST]]
       mean value of COUNTER per dispatch of the kernels matching REGEX, from
-      *_counter_collection.csv
+      *_counter_collection.csv (with FIRST: over the first FIRST matching
+      dispatches in dispatch order only, e.g. one leg of a run whose later
+      legs launch the same kernel)
   python -m paper_1702_03484_amd.profile_summary traffic K_FETCH K_WRITE COPY_FETCH COPY_WRITE COPY_BYTES OUT
       HBM bytes per launch of a kernel: FETCH_SIZE and WRITE_SIZE (KiB per
       dispatch, from two ``pmc`` summaries) each scaled by what the same
@@ -56,13 +58,15 @@ def stats(d):
     return out
 
 
-def pmc(d, counter, regex=".*"):
+def pmc(d, counter, regex=".*", first=None):
     rows = list(csv.DictReader(open(_one(d, "*counter_collection.csv"))))
     rx = re.compile(regex)
+    sel = [r for r in rows if r.get("Counter_Name") == counter and rx.search(r.get("Kernel_Name", ""))]
+    sel.sort(key=lambda r: int(r.get("Dispatch_Id", 0)))
+    if first is not None:
+        sel = sel[:first]
     per = {}
-    for r in rows:
-        if r.get("Counter_Name") != counter or not rx.search(r.get("Kernel_Name", "")):
-            continue
+    for r in sel:
         per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return {k: {"dispatches": len(v), "mean": sum(v) / len(v)} for k, v in per.items()}
 
@@ -73,7 +77,8 @@ def main(argv):
         for r in stats(argv[1]):
             print(f"{r['kernel'][:100]:100s} {r['calls']:6d} {r['avg_us']:12.1f} us {r['total_ms']:10.3f} ms {r['pct']:6.2f}%")
     elif cmd == "pmc":
-        print(json.dumps(pmc(argv[1], argv[2], argv[3] if len(argv) > 3 else ".*"), indent=1))
+        print(json.dumps(pmc(argv[1], argv[2], argv[3] if len(argv) > 3 else ".*",
+                             int(argv[4]) if len(argv) > 4 else None), indent=1))
     elif cmd == "traffic":
         mf, mw, cf, cw = (json.load(open(p)) for p in argv[1:5])
         copy_bytes = float(argv[5])
