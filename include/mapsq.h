@@ -102,7 +102,9 @@ typedef struct {
     uint64_t device_bytes; /* arena bytes held by the store and its indexes */
 } mapsq_store_facts;
 
-/* What the last join of a context did (filled by mapsq_join and mapsq_query). */
+/* What the last join of a context did (filled by mapsq_join and mapsq_query;
+ * after a mapsq_join_batch that ran joins in the batched kernels, the sums
+ * over those joins, path MAPSQ_PATH_SEMIJOIN when any of them was filtered). */
 typedef struct {
     int64_t left_rows, right_rows;
     int64_t segments;      /* distinct keys among the |L|+|R| sorted records */
@@ -267,7 +269,12 @@ typedef struct {
  * device-side placement of every result in one output region and the
  * materialisation), then the stream is synchronised once and outs[i] is
  * filled.  Each join's result equals what mapsq_join returns for it, row for
- * row.  Joins the batched kernels do not cover (more than 8 output columns
+ * row.  Semi-join reduction (mapsq_set_join_options' semijoin: automatic
+ * when a join's larger side has at least twice the smaller side's rows):
+ * a blocked Bloom filter of the smaller side's keys (16 bits per row) drops
+ * the larger side's records whose key it cannot hold before the sort; it
+ * has no false negatives, so the rows and their order do not change.
+ * Joins the batched kernels do not cover (more than 8 output columns
  * or a further shared variable) and results that do not fit the output
  * region run through the plain path afterwards.  The result tables of one
  * batch share an arena block that is released when the last of them is
@@ -387,7 +394,9 @@ mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_p
  *   Reduce (Algorithm 1), so it can be left out of the shuffle.  0 =
  *   automatic (the larger side has at least 2^16 records and 4 times the
  *   smaller side's, and the key bitmap is no larger than the larger side's
- *   key column), 1 = never, 2 = whenever the bitmap fits in 1 GiB.
+ *   key column), 1 = never, 2 = whenever the bitmap fits in 1 GiB.  In
+ *   mapsq_join_batch (a Bloom filter per join): 0 = when the larger side
+ *   has at least twice the smaller side's rows, 1 = never, 2 = every join.
  * merge: 0 = pair the key runs directly when both tables are sorted on the
  *   key (sorted_col), 1 = always shuffle.
  * precount: before a shuffle, count |RS| exactly from dense per-key counts
@@ -450,6 +459,14 @@ mapsq_status mapsq_tune_record_mat(mapsq_ctx* ctx, int32_t log2_rows, int32_t ma
 
 /* Bytes of the arena still free, and the largest free block. */
 mapsq_status mapsq_arena_free_bytes(mapsq_ctx* ctx, uint64_t* free_bytes, uint64_t* largest_block);
+
+/* Fault injection for tests of the error paths: after `after` more arena
+ * allocations of this context succeed, the next one fails as if the arena
+ * were full (once; after < 0 disables).  The environment variable
+ * MAPSQ_FAULT=alloc:N sets the same at mapsq_create.  Every call must then
+ * end with its documented status (CAPACITY or TOO_LARGE for memory), free
+ * everything it allocated, and leave the context usable. */
+mapsq_status mapsq_debug_fail_alloc(mapsq_ctx* ctx, int64_t after);
 
 #ifdef __cplusplus
 }

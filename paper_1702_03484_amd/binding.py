@@ -171,6 +171,7 @@ _SIGS = [
     ("mapsq_set_mat_tuning", ctypes.c_int32, [_P, ctypes.c_int32]),
     ("mapsq_tune_record_mat", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
     ("mapsq_arena_free_bytes", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+    ("mapsq_debug_fail_alloc", ctypes.c_int32, [_P, ctypes.c_int64]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
 
@@ -414,6 +415,10 @@ def mapsq_arena_free_bytes(ctx):
     b = ctypes.c_uint64()
     _check(ctx, lib().mapsq_arena_free_bytes(ctx, ctypes.byref(a), ctypes.byref(b)))
     return int(a.value), int(b.value)
+
+
+def mapsq_debug_fail_alloc(ctx, after: int):
+    _check(ctx, lib().mapsq_debug_fail_alloc(ctx, after))
 
 
 def make_table(vars, col_ptrs, nrows: int, key_max: int = -1, sorted_col: int = 0) -> mapsq_table:

@@ -18,6 +18,7 @@ void Arena::init(char* base, size_t size) {
 }
 
 size_t Arena::alloc(size_t bytes) {
+    if (fail_after >= 0 && fail_after-- == 0) return SIZE_MAX;
     bytes = align_up(std::max<size_t>(bytes, 1), ARENA_ALIGN);
     for (auto it = free_.begin(); it != free_.end(); ++it) {
         if (it->second >= bytes) {

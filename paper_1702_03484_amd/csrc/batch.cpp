@@ -139,9 +139,30 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         tile_join.insert(tile_join.end(), b.ntiles, (uint32_t)i);
     }
     const uint64_t nrec = tiles * TILE;
+    // Semi-join filters: automatic for joins whose larger side has at least
+    // twice the smaller side's rows (the probed side is the larger one),
+    // every join with semijoin = 2, none with semijoin = 1.  16 bits per
+    // build-side row, at least 64 words.
+    std::vector<uint64_t> filt_at(n, 0);
+    uint64_t filt_words = 0;
+    for (int i = 0; i < n; i++) {
+        BatchJoin& b = J[i];
+        if (!plan[i].batched || invalid[i] || plan[i].empty || ctx->semijoin == 1) continue;
+        const uint32_t small = std::min(b.nl, b.nr), big = std::max(b.nl, b.nr);
+        if (ctx->semijoin == 0 && (uint64_t)big < 2ull * small) continue;
+        uint64_t words = 64;
+        while (words < (uint64_t(small) + 3) / 4) words <<= 1;
+        b.fmask = (uint32_t)(words - 1);
+        b.probe_right = b.nr > b.nl ? 1u : 0u;
+        filt_at[i] = filt_words + 1;  // the pointer is set once the scratch exists
+        filt_words += words;
+    }
 
     std::vector<mapsq_table> res(n);
     std::vector<bool> done(invalid);
+    mapsq_join_stats bst{};  // sums over the joins the batched kernels ran
+    bst.path = MAPSQ_PATH_SORT;
+    bool batched_any = false;
     auto fail_all = [&](mapsq_status code, const std::string& msg) {
         for (int i = 0; i < n; i++) {
             free_table(ctx, &res[i]);
@@ -169,7 +190,8 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         const size_t hist_bytes = align_up(size_t(n) * passes * buckets * 4, ARENA_ALIGN);
         const size_t tj_bytes = align_up(tiles * 4, ARENA_ALIGN);
         const size_t jd_bytes = align_up(sizeof(BatchJoin) * n, ARENA_ALIGN);
-        Block scratch = alloc_block(ctx, nb4 * 6 + hist_bytes + tj_bytes + jd_bytes);
+        const size_t filt_bytes = align_up(filt_words * 8, ARENA_ALIGN);
+        Block scratch = alloc_block(ctx, nb4 * 6 + hist_bytes + tj_bytes + jd_bytes + filt_bytes);
         bool room = scratch.ok() && ctx->ensure_status(size_t(tiles) * buckets);
         if (room && ctx->bhdr_off == SIZE_MAX) {
             ctx->bhdr_off = ctx->arena.alloc(sizeof(BatchHdr));
@@ -220,6 +242,10 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         for (uint32_t c = 0; c < nsval; c++)
             H.sval[c] = reinterpret_cast<int32_t*>(ctx->arena.ptr(svb.off) + c * nb4);
         H.out_cap_words = region.ok() ? cap_bytes / 4 : 0;
+        H.filt = reinterpret_cast<uint64_t*>(sb + nb4 * 6 + hist_bytes + tj_bytes + jd_bytes);
+        H.filt_words = filt_words;
+        for (int i = 0; i < n; i++)
+            if (filt_at[i]) J[i].filt = H.filt + (filt_at[i] - 1);
         // upload header, descriptors and the tile map through pinned staging
         const size_t up = sizeof(BatchHdr) + sizeof(BatchJoin) * n + tiles * 4;
         if (!ensure_stage(ctx, up)) return ctx->fail(MAPSQ_ERR_HIP, "pinned staging allocation failed");
@@ -274,8 +300,14 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
             for (int i = 0; i < n; i++) {
                 const BatchJoin& b = J[i];
                 if (!plan[i].batched || plan[i].empty) continue;
-                const double N = double(b.nl) + b.nr;
-                bytes += 16.0 * N * passes + 8.0 * N + 28.0 * b.nseg;
+                // every record's key read twice (histograms, first pass; the
+                // filter's side once more when there is one), the kept
+                // records (N) written by the first pass and moved by the
+                // others, then heads and counts over them
+                const double all = double(b.nl) + b.nr;
+                const double N = b.nrec;
+                const double build = b.filt ? (b.probe_right ? b.nl : b.nr) : 0.0;
+                bytes += 8.0 * all + 4.0 * build + 8.0 * N + 16.0 * N * (passes - 1) + 8.0 * N + 28.0 * b.nseg;
                 if (b.status == 0) {
                     const double cells = b.nvl * double(b.nl) + b.nvr * double(b.nr);
                     const uint32_t nv = (uint32_t)std::max(b.nvl, b.nvr);
@@ -285,8 +317,18 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
                 }
                 ctx->acc.rows_out += (int64_t)b.total;
                 ctx->acc.joins += 1;
+                bst.left_rows += b.nl;
+                bst.right_rows += b.nr;
+                bst.segments += b.nseg;
+                bst.out_rows += (int64_t)b.total;
+                bst.sorted_records += b.nrec;
+                if (b.filt) bst.path = MAPSQ_PATH_SEMIJOIN;
+                batched_any = true;
             }
             ctx->prof_end(ph, bytes);
+            bst.radix_bits = rb;
+            bst.passes = passes;
+            bst.key_bits = key_bits;
         }
         for (int i = 0; i < n; i++)
             if (plan[i].batched && !plan[i].empty && J[i].status == 2) {
@@ -347,6 +389,7 @@ plain_rest:
         done[i] = true;
     }
     for (int i = 0; i < n; i++) outs[i] = res[i];
+    if (batched_any) ctx->last = bst;
     return MAPSQ_OK;
 }
 

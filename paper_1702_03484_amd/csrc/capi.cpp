@@ -2,6 +2,7 @@
 // arguments, selects the context's device for the duration of the call and
 // keeps C++ exceptions from crossing the ABI.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -71,8 +72,23 @@ mapsq_status mapsq_create(int device, void* arena, size_t arena_bytes, void* hip
         delete c;
         return MAPSQ_ERR_HIP;
     }
+    // MAPSQ_FAULT=alloc:N: the context's (N+1)-th arena allocation fails
+    if (const char* f = std::getenv("MAPSQ_FAULT")) {
+        if (std::strncmp(f, "alloc:", 6) == 0) {
+            char* end = nullptr;
+            const long long n = std::strtoll(f + 6, &end, 10);
+            if (end != f + 6 && *end == '\0' && n >= 0) ctx->arena.fail_after = n;
+        }
+    }
     *out = c;
     return MAPSQ_OK;
+}
+
+mapsq_status mapsq_debug_fail_alloc(mapsq_ctx* c, int64_t after) {
+    return guarded(c, [&](Ctx* ctx) {
+        ctx->arena.fail_after = after < 0 ? -1 : after;
+        return (mapsq_status)MAPSQ_OK;
+    });
 }
 
 mapsq_status mapsq_destroy(mapsq_ctx* c) {

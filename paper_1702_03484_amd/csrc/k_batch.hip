@@ -28,37 +28,101 @@ __device__ __forceinline__ uint32_t bsrc_key(const BatchJoin& J, uint32_t idx) {
     return (uint32_t)k - (uint32_t)J.key_base;
 }
 
+// Semi-join reduction (a record whose key the other side lacks meets no
+// partner in Reduce): a blocked Bloom filter per join holds the relative
+// keys of one side; a key selects one 64-bit word of it and three bits in
+// that word (a multiplicative hash finished by a xor-shift-multiply round),
+// so a probe is one load.  It has no false negatives: a dropped record
+// never had a partner, and the kept records keep their relative order, so
+// every key that has partners on both sides yields the same runs, and the
+// same rows in the same order, as without the filter.
+__device__ __forceinline__ uint64_t bloom_hash(uint32_t k) {
+    uint64_t x = (uint64_t)k * 0x9E3779B97F4A7C15ull;
+    x ^= x >> 29;
+    x *= 0xBF58476D1CE4E5B9ull;
+    return x ^ (x >> 32);
+}
+__device__ __forceinline__ uint64_t bloom_bits(uint64_t x) {
+    return (1ull << (x & 63)) | (1ull << ((x >> 6) & 63)) | (1ull << ((x >> 12) & 63));
+}
+__device__ __forceinline__ uint32_t bloom_word(uint64_t x, uint32_t fmask) { return (uint32_t)(x >> 32) & fmask; }
+
+// Whether record idx (relative key k) of join J goes through the sort: the
+// side the filter was built from always does, the probed side only when the
+// filter may hold its key.
+__device__ __forceinline__ bool bkeep(const BatchJoin& J, uint32_t idx, uint32_t k) {
+    if (!J.filt || (idx >= J.nl) != (J.probe_right != 0)) return true;
+    const uint64_t x = bloom_hash(k);
+    const uint64_t m = bloom_bits(x);
+    return (J.filt[bloom_word(x, J.fmask)] & m) == m;
+}
+
 template <int RB>
 __global__ void bclear_kernel(const BatchHdr* __restrict__ h) {
     const uint64_t words = (uint64_t)h->njoins * h->passes * Radix<RB>::BUCKETS;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
-        h->hist[i] = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += stride) h->hist[i] = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < h->filt_words; i += stride) h->filt[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x < h->passes + 4) h->ctr[threadIdx.x] = 0;
 }
 
-// Per-join digit histograms of all passes.  Block b takes a contiguous range
-// of record tiles and flushes its LDS counts whenever the join changes.
+// Filters of the joins that have one: every record of the build side sets
+// its key's bits (a word already holding them is left alone).
+template <int KPT>
+__global__ __launch_bounds__(MQ_BLOCK) void bfilt_kernel(const BatchHdr* __restrict__ h) {
+    constexpr uint32_t TILE = MQ_BLOCK * KPT;
+    for (uint32_t t = blockIdx.x; t < h->total_tiles; t += gridDim.x) {
+        const BatchJoin& J = h->joins[h->tile_join[t]];
+        if (!J.filt) continue;
+        const uint32_t base = (t - J.tile_off) * TILE;
+        // LEFT records [0, nl) build when RIGHT is probed, else RIGHT [nl, nl + nr)
+        const uint32_t b0 = J.probe_right ? 0u : J.nl;
+        const uint32_t b1 = J.probe_right ? J.nl : J.nl + J.nr;
+        const uint32_t i0 = max(base, b0), i1 = min(base + TILE, b1);
+        for (uint32_t i = i0 + threadIdx.x; i < i1; i += MQ_BLOCK) {
+            const uint64_t x = bloom_hash(bsrc_key(J, i));
+            const uint64_t m = bloom_bits(x);
+            unsigned long long* wp = reinterpret_cast<unsigned long long*>(J.filt + bloom_word(x, J.fmask));
+            if ((__hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & m) != m)
+                atomicOr(wp, (unsigned long long)m);
+        }
+    }
+}
+
+// Per-join digit histograms of all passes, over the records the semi-join
+// filter keeps, and the number of kept records of each join.  Block b takes
+// a contiguous range of record tiles and flushes its LDS counts whenever the
+// join changes.
 template <int RB, int KPT>
 __global__ __launch_bounds__(MQ_BLOCK) void bhist_kernel(const BatchHdr* __restrict__ h) {
     using R = Radix<RB>;
     constexpr uint32_t TILE = MQ_BLOCK * KPT;
     __shared__ uint32_t sh[R::MAXP * R::BUCKETS];
+    __shared__ uint32_t s_kept;
     const uint32_t T = h->total_tiles, passes = h->passes;
     const uint32_t t0 = (uint32_t)((uint64_t)blockIdx.x * T / gridDim.x);
     const uint32_t t1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * T / gridDim.x);
     for (int i = threadIdx.x; i < R::MAXP * R::BUCKETS; i += MQ_BLOCK) sh[i] = 0;
+    if (threadIdx.x == 0) s_kept = 0;
     __syncthreads();
+    auto flush = [&](int64_t jf) {
+        for (uint32_t i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
+            const uint32_t c = sh[i];
+            if (c) atomicAdd(&h->hist[(uint64_t)jf * passes * R::BUCKETS + i], c);
+            sh[i] = 0;
+        }
+        if (threadIdx.x == 0) {
+            if (s_kept) atomicAdd(&h->joins[jf].nrec, s_kept);
+            s_kept = 0;
+        }
+    };
     int64_t cur = -1;
     for (uint32_t t = t0; t < t1; t++) {
         const uint32_t j = h->tile_join[t];
         if ((int64_t)j != cur) {
             if (cur >= 0) {
                 __syncthreads();
-                for (uint32_t i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
-                    const uint32_t c = sh[i];
-                    if (c) atomicAdd(&h->hist[(uint64_t)cur * passes * R::BUCKETS + i], c);
-                    sh[i] = 0;
-                }
+                flush(cur);
                 __syncthreads();
             }
             cur = j;
@@ -71,19 +135,19 @@ __global__ __launch_bounds__(MQ_BLOCK) void bhist_kernel(const BatchHdr* __restr
         for (int i = 0; i < KPT; i++) {
             k[i] = bsrc_key(J, min(base + i * MQ_BLOCK + threadIdx.x, n - 1));
         }
+        uint32_t kept = 0;
 #pragma unroll
         for (int i = 0; i < KPT; i++) {
             const uint32_t idx = base + i * MQ_BLOCK + threadIdx.x;
-            if (idx < n)
+            if (idx < n && bkeep(J, idx, k[i])) {
+                kept++;
                 for (uint32_t p = 0; p < passes; p++) atomicAdd(&sh[p * R::BUCKETS + ((k[i] >> (p * RB)) & R::MASK)], 1u);
+            }
         }
+        if (kept) atomicAdd(&s_kept, kept);
     }
     __syncthreads();
-    if (cur >= 0)
-        for (uint32_t i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
-            const uint32_t c = sh[i];
-            if (c) atomicAdd(&h->hist[(uint64_t)cur * passes * R::BUCKETS + i], c);
-        }
+    if (cur >= 0) flush(cur);
 }
 
 template <int RB, int KPT, bool GEN>
@@ -101,10 +165,15 @@ __global__ __launch_bounds__(MQ_BLOCK) void bpass_kernel(const BatchHdr* __restr
         if (t >= T) break;
         const uint32_t j = h->tile_join[t];
         const BatchJoin& J = h->joins[j];
-        const uint32_t n = J.nl + J.nr;
+        // the first pass reads every record from the tables and scatters the
+        // kept ones; later passes see the kept records only (the join's
+        // tiles past them have nothing to do and no later tile waits on them)
+        const uint32_t n = GEN ? J.nl + J.nr : J.nrec;
         const uint32_t base = (t - J.tile_off) * TILE;
+        if (base >= n) continue;
         const uint32_t valid_n = min(TILE, n - base);
         uint32_t key[KPT], val[KPT];
+        uint32_t keep = 0;
         const uint32_t* kin = GEN ? nullptr : h->keys[src] + J.rec_off;
         const uint32_t* vin = GEN ? nullptr : h->vals[src] + J.rec_off;
 #pragma unroll
@@ -116,14 +185,19 @@ __global__ __launch_bounds__(MQ_BLOCK) void bpass_kernel(const BatchHdr* __restr
                 const uint32_t k = bsrc_key(J, min(idx, n - 1));
                 key[i] = ok ? k : 0u;
                 val[i] = idx;
+                if (ok && bkeep(J, idx, k)) keep |= 1u << i;
             } else {
                 key[i] = ok ? kin[idx] : 0u;
                 val[i] = ok ? vin[idx] : 0u;
             }
         }
-        sort_tile<RB, KPT>(sm, key, val, valid_n, pass * RB,
-                           h->hist + ((uint64_t)j * passes + pass) * R::BUCKETS, h->status, t, J.tile_off, epoch,
-                           h->keys[dst] + J.rec_off, h->vals[dst] + J.rec_off);
+        const uint32_t* ghist = h->hist + ((uint64_t)j * passes + pass) * R::BUCKETS;
+        if (GEN)
+            sort_tile<RB, KPT, MQ_WAVES, true>(sm, key, val, valid_n, pass * RB, ghist, h->status, t, J.tile_off,
+                                               epoch, h->keys[dst] + J.rec_off, h->vals[dst] + J.rec_off, keep);
+        else
+            sort_tile<RB, KPT>(sm, key, val, valid_n, pass * RB, ghist, h->status, t, J.tile_off, epoch,
+                               h->keys[dst] + J.rec_off, h->vals[dst] + J.rec_off);
     }
 }
 
@@ -141,9 +215,11 @@ __global__ __launch_bounds__(MQ_BLOCK) void bheads_kernel(BatchHdr* __restrict__
         const uint32_t j = h->tile_join[t];
         BatchJoin& J = h->joins[j];
         const uint32_t lt = t - J.tile_off;
-        heads_tile<KPT>(sm, h->keys[fin] + J.rec_off, h->vals[fin] + J.rec_off, J.nl + J.nr, J.nl, lt * TILE, t,
-                        J.tile_off, lt + 1 == J.ntiles, h->keys[1 - fin] + J.rec_off, h->vals[1 - fin] + J.rec_off,
-                        &J.nseg, h->status, epoch);
+        const uint32_t n = J.nrec;
+        if (lt * TILE >= n) continue;  // beyond the kept records (block-uniform)
+        heads_tile<KPT>(sm, h->keys[fin] + J.rec_off, h->vals[fin] + J.rec_off, n, J.nl, lt * TILE, t, J.tile_off,
+                        (lt + 1) * TILE >= n, h->keys[1 - fin] + J.rec_off, h->vals[1 - fin] + J.rec_off, &J.nseg,
+                        h->status, epoch);
     }
 }
 
@@ -164,7 +240,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void bcount_kernel(BatchHdr* __restrict__
         const uint32_t ns = J.nseg;
         if (lt * TILE >= ns) continue;  // beyond the join's segments (block-uniform)
         const uint32_t last = (ns + TILE - 1) / TILE - 1;
-        count_tile<KPT>(sm, J.nl + J.nr, ns, lt * TILE, t, J.tile_off, lt == last, h->keys[1 - fin] + J.rec_off,
+        count_tile<KPT>(sm, J.nrec, ns, lt * TILE, t, J.tile_off, lt == last, h->keys[1 - fin] + J.rec_off,
                         h->vals[1 - fin] + J.rec_off, h->seg_off + J.rec_off, &J.total, h->status, epoch,
                         &J.max_pairs);
     }
@@ -243,7 +319,7 @@ __device__ __forceinline__ uint32_t wave_join_of(const BatchJoin* __restrict__ j
 // place of the record-id gathers.
 __device__ __forceinline__ bool bjoin_uses_sval(const BatchHdr* h, const BatchJoin& J) {
     const uint32_t nv = (uint32_t)max(J.nvl, J.nvr);
-    return J.status == 0 && nv > 0 && nv <= h->nsval && J.total >= (uint64_t)J.nl + J.nr;
+    return J.status == 0 && nv > 0 && nv <= h->nsval && J.total >= (uint64_t)J.nrec;
 }
 
 template <int KPT>
@@ -253,8 +329,9 @@ __global__ __launch_bounds__(MQ_BLOCK) void bgather_kernel(const BatchHdr* __res
     for (uint32_t t = blockIdx.x; t < h->total_tiles; t += gridDim.x) {
         const BatchJoin& J = h->joins[h->tile_join[t]];
         if (!bjoin_uses_sval(h, J)) continue;
-        const uint32_t n = J.nl + J.nr;
+        const uint32_t n = J.nrec;
         const uint32_t i0 = (t - J.tile_off) * TILE;
+        if (i0 >= n) continue;
         const uint32_t i1 = min(i0 + TILE, n);
         const uint32_t* vals = h->vals[fin] + J.rec_off;
         for (uint32_t i = i0 + threadIdx.x; i < i1; i += MQ_BLOCK) {
@@ -289,7 +366,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
         mj.seg_split = h->vals[1 - fin] + J.rec_off;
         mj.seg_off = h->seg_off + J.rec_off;
         mj.ns = J.nseg;
-        mj.n = J.nl + J.nr;
+        mj.n = J.nrec;
         mj.n_left = J.nl;
         mj.key_base = J.key_base;
         mj.key_shift = 0;
@@ -321,7 +398,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restri
 template <int RB, int KPT>
 static hipError_t launch_batch_t(const BatchHdr* hdr, int passes, hipStream_t stream) {
     BatchHdr* h = const_cast<BatchHdr*>(hdr);
-    bclear_kernel<RB><<<64, MQ_BLOCK, 0, stream>>>(hdr);
+    bclear_kernel<RB><<<256, MQ_BLOCK, 0, stream>>>(hdr);
+    bfilt_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
     bhist_kernel<RB, KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
     for (int p = 0; p < passes; p++) {
         if (p == 0) bpass_kernel<RB, KPT, true><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr, p);

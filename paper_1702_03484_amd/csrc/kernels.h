@@ -242,6 +242,14 @@ struct BatchJoin {
     uint64_t chunk_off;         // first materialisation work item
     uint64_t max_pairs;         // largest key product (zero before the launch)
     uint32_t seg_major;         // work items are groups of 64 keys, not row chunks
+    // Semi-join reduction: a blocked Bloom filter (fmask + 1 words, a power
+    // of two) of the keys of one side; records of the other side (RIGHT when
+    // probe_right, else LEFT) whose key it does not hold are dropped before
+    // the sort.  filt = nullptr: every record is kept.
+    uint64_t* filt;
+    uint32_t fmask;
+    uint32_t probe_right;
+    uint32_t nrec;              // records kept (written on the device; zero before the launch)
 };
 
 struct BatchHdr {
@@ -265,6 +273,8 @@ struct BatchHdr {
     // by joins with at least as many output rows as records; nsval = 0: none
     int32_t* sval[BATCH_MAXNC - 1];
     uint32_t nsval;
+    uint64_t* filt;             // every join's filter words (cleared by the launch)
+    uint64_t filt_words;
 };
 
 // The whole batch in kernel launches (a graph capture records them).

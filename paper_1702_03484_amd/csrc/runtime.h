@@ -38,6 +38,9 @@ class Arena {
     }
     char* base() const { return base_; }
     size_t size() const { return size_; }
+    // Fault injection: when >= 0, each allocation counts it down and the one
+    // that finds it at 0 fails as if the arena were full (then it is -1).
+    int64_t fail_after = -1;
 
    private:
     char* base_ = nullptr;

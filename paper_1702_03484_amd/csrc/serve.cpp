@@ -158,6 +158,7 @@ static mapsq_status size_waiting(Ctx* ctx, Server* S) {
     const Store& St = ctx->store;
     std::vector<LocateQuery> lq;
     std::vector<std::pair<SQuery*, int>> who;
+    std::vector<SQuery*> sized;
     for (SQuery* q : S->waiting) {
         if (q->sized) continue;
         q->rows.assign(q->pats.size(), 0);
@@ -195,12 +196,15 @@ static mapsq_status size_waiting(Ctx* ctx, Server* S) {
             lq.push_back(x);
             who.emplace_back(q, (int)i);
         }
-        q->sized = true;
+        sized.push_back(q);
     }
-    if (lq.empty()) return MAPSQ_OK;
-    std::vector<int64_t> r(2 * lq.size());
-    if (mapsq_status st = locate_ranges(ctx, lq.data(), lq.size(), r.data())) return st;
-    for (size_t k = 0; k < who.size(); k++) who[k].first->rows[who[k].second] = r[2 * k + 1] - r[2 * k];
+    if (!lq.empty()) {
+        std::vector<int64_t> r(2 * lq.size());
+        // on failure no query counts as sized: the next round sizes them again
+        if (mapsq_status st = locate_ranges(ctx, lq.data(), lq.size(), r.data())) return st;
+        for (size_t k = 0; k < who.size(); k++) who[k].first->rows[who[k].second] = r[2 * k + 1] - r[2 * k];
+    }
+    for (SQuery* q : sized) q->sized = true;
     return MAPSQ_OK;
 }
 
@@ -356,7 +360,13 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     // rounds stops that).  A prediction above the whole budget reserves
     // nothing: the exact size of each of its joins decides (step 2).
     mapsq_status st = size_waiting(ctx, S);
-    if (st) return st;
+    // no room even for the index range lookups: this round admits nothing
+    // (the waiting queries are sized again in the next one)
+    const bool unsized = st == MAPSQ_ERR_CAPACITY;
+    if (unsized)
+        st = MAPSQ_OK;
+    else if (st)
+        return st;
     auto live_others = [&](const SQuery* q) {
         int k = 0;
         for (const SQuery* o : S->active) k += o != q && o->state == Q_ACTIVE;
@@ -423,7 +433,7 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     };
     bool starving = false;
     for (const SQuery* o : S->active) starving = starving || (o->state == Q_ACTIVE && o->stalls > MAX_STALLS);
-    for (auto it = S->waiting.begin(); it != S->waiting.end() && !S->hold && !starving;) {
+    for (auto it = S->waiting.begin(); it != S->waiting.end() && !S->hold && !starving && !unsized;) {
         SQuery* q = *it;
         if ((int)S->active.size() >= S->max_active) break;
         if (S->solo && q != S->solo) break;

@@ -63,14 +63,18 @@ __device__ __forceinline__ void scan_buckets(const uint32_t* in, uint32_t* out, 
 // (wave*KPT + i)*64 + lane; positions >= valid_n are padding).  Ranks the
 // digits, publishes the tile's digit counts, looks back over the join's
 // earlier tiles, and scatters the tile to kout/vout (join-relative).
-// `ghist` is the join's digit histogram of this pass.  Every thread of the
+// `ghist` is the join's digit histogram of this pass.  MASKED: element i of
+// a thread takes part only when bit i of `keep` is set; the kept elements
+// are ranked and scattered as if the others were absent (the histogram and
+// every tile's totals count kept elements only).  Every thread of the
 // block calls it.
-template <int RB, int KPT, int NW = MQ_WAVES>
+template <int RB, int KPT, int NW = MQ_WAVES, bool MASKED = false>
 __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint32_t (&key)[KPT],
                                           const uint32_t (&val)[KPT], uint32_t valid_n, int shift,
                                           const uint32_t* __restrict__ ghist, uint64_t* __restrict__ status,
                                           uint32_t tile, uint32_t first_tile, uint32_t epoch,
-                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                          uint32_t keep = ~0u) {
     using R = Radix<RB>;
     constexpr int NT = NW * MQ_WAVE;                       // threads of the block
     constexpr int BPT = (R::BUCKETS + NT - 1) / NT;        // buckets per thread
@@ -89,10 +93,11 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
     static_assert(NT * KPT <= 65536 && KPT % 2 == 0, "16-bit ranks");
     uint32_t rank2[KPT / 2];
     const uint64_t lt = lanemask_lt();
+    uint32_t wkept = 0;  // MASKED: this wave's kept elements
 #pragma unroll
     for (int i = 0; i < KPT; i++) {
         const uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
-        const bool ok = off < valid_n;
+        const bool ok = off < valid_n && (!MASKED || ((keep >> i) & 1u));
         const uint32_t dg = (key[i] >> shift) & R::MASK;
         // lanes whose digit differs in some bit: per bit, the ballot of
         // that bit xor this lane's bit spread over 64 bits (0 or all ones)
@@ -105,7 +110,9 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
             diff_lo |= (uint32_t)m ^ spread;
             diff_hi |= (uint32_t)(m >> 32) ^ spread;
         }
-        const uint64_t peers = __ballot(ok) & ~((uint64_t)diff_hi << 32 | diff_lo);
+        const uint64_t okm = __ballot(ok);
+        if (MASKED) wkept += (uint32_t)__popcll(okm);
+        const uint64_t peers = okm & ~((uint64_t)diff_hi << 32 | diff_lo);
         const uint32_t below = __popcll(peers & lt);
         const uint32_t old = ok ? sm.wcnt[w][dg] : 0u;
         if (ok && below == 0) sm.wcnt[w][dg] = old + (uint32_t)__popcll(peers);
@@ -114,7 +121,14 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
         else
             rank2[i / 2] |= (old + below) << 16;
     }
+    if (MASKED && ln == 0) sm.tmp[w] = wkept;
     __syncthreads();
+    uint32_t nkept = valid_n;  // records the tile scatters
+    if (MASKED) {
+        nkept = 0;
+#pragma unroll
+        for (int i = 0; i < NW; i++) nkept += sm.tmp[i];
+    }
 
     // per digit: exclusive prefix over waves, tile total, local digit starts
     uint32_t tot[BPT];
@@ -158,7 +172,7 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
 #pragma unroll
     for (int i = 0; i < KPT; i++) {
         const uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
-        if (off < valid_n) {
+        if (off < valid_n && (!MASKED || ((keep >> i) & 1u))) {
             const uint32_t dg = (key[i] >> shift) & R::MASK;
             const uint32_t pos = sm.local[dg] + sm.wcnt[w][dg] + ((rank2[i / 2] >> (16 * (i % 2))) & 0xffffu);
             sm.keys[pos] = key[i];
@@ -166,7 +180,7 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
         }
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < valid_n; j += NT) {
+    for (uint32_t j = threadIdx.x; j < nkept; j += NT) {
         const uint32_t k = sm.keys[j];
         const uint32_t dg = (k >> shift) & R::MASK;
         const uint32_t g = sm.goff[dg] + (j - sm.local[dg]);

@@ -195,3 +195,56 @@ def test_batch_full_int32_keys_unknown_bound(sess):
     check_against_plain_and_oracle(sess, joins, host, outs)
     for t in outs:
         sess.free(t)
+
+
+def test_batch_semijoin_filter(sess):
+    """The batched semi-join reduction (a Bloom filter of the smaller side's
+    keys drops the larger side's records without a partner before the sort)
+    gives the same rows in the same order with the filter off, automatic and
+    forced, equal to the oracle and to mapsq_join: mostly unmatched larger
+    sides on either side, a larger side with no partner at all, sides that
+    the automatic rule leaves unfiltered, record counts at tile edges."""
+    announce("batch: semi-join filter off, automatic and forced")
+    specs = [  # (nl, nr, key universe, vl, vr, disjoint)
+        (200_000, 2_000, 1_000_000, 1, 2, False),
+        (3_000, 150_001, 500_000, 2, 0, False),
+        (4096 * 8 + 1, 4096 - 1, 100_000, 1, 1, False),
+        (50_000, 30_000, 1_000, 3, 1, False),
+        (80_000, 1_000, 50_000, 0, 2, True),
+        (4096 * 4, 4096 * 2, 20_000, 1, 0, False),
+        (1, 70_000, 10, 1, 1, False),
+    ]
+    joins, host = [], []
+    for i, (nl, nr, U, vl, vr, disjoint) in enumerate(specs):
+        keys = np.arange(U, dtype=np.int64) * 7 + 3
+        rkeys = keys + 1 if disjoint else keys
+        lc = random_table(700 + 2 * i, nl, U, vl, key_ids=keys)
+        rc = random_table(701 + 2 * i, nr, U, vr, key_ids=rkeys)
+        lv = [0] + [10 + k for k in range(vl)]
+        rv = [0] + [20 + k for k in range(vr)]
+        km = int(max(keys.max(), rkeys.max())) if i % 2 else -1
+        joins.append((sess.table(lv, [dev(c) for c in lc], key_max=km),
+                      sess.table(rv, [dev(c) for c in rc], key_max=km), 0))
+        host.append((Table(lv, lc), Table(rv, rc)))
+    outs, stats = {}, {}
+    for mode in (1, 0, 2):
+        sess.set_join_options(semijoin=mode)
+        try:
+            outs[mode] = sess.join_batch(joins)
+            stats[mode] = sess.stats()
+        finally:
+            sess.set_join_options()
+    allrec = sum(nl + nr for nl, nr, *_ in specs)
+    assert stats[1].sorted_records == allrec and stats[1].path == B.MAPSQ_PATH_SORT
+    assert stats[0].path == B.MAPSQ_PATH_SEMIJOIN and stats[0].sorted_records < allrec // 2
+    assert stats[2].sorted_records <= stats[0].sorted_records
+    for mode in (0, 2):
+        assert stats[mode].out_rows == stats[1].out_rows
+        for i, (a, b) in enumerate(zip(outs[1], outs[mode])):
+            assert a.nrows == b.nrows and a.vars == b.vars, (mode, i)
+            for c in range(a.ncols):
+                assert torch.equal(sess.column(a, c), sess.column(b, c)), (mode, i, c)
+    check_against_plain_and_oracle(sess, joins, host, outs[0])
+    for ts in outs.values():
+        for t in ts:
+            sess.free(t)

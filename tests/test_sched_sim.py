@@ -20,6 +20,10 @@ schedules.  What must hold in every scenario:
 * with a caller that never polls while queries run, the loop still ends:
   a step that waits for unpolled results fails with TOO_LARGE after a
   bounded number of rounds.
+
+A second build of the same host sources under AddressSanitizer (leak
+detection on) and UndefinedBehaviorSanitizer runs a subset of the scenarios;
+any report fails the test.
 """
 import itertools
 import json
@@ -47,9 +51,27 @@ def sim(tmp_path_factory):
     return exe
 
 
+@pytest.fixture(scope="module")
+def sim_sanitized(tmp_path_factory):
+    """The same host code built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (any report aborts the run)."""
+    cxx = shutil.which("g++")
+    if cxx is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("needs g++ and the HIP headers")
+    exe = str(tmp_path_factory.mktemp("sched_sim_san") / "sim")
+    flags = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+    r = subprocess.run([cxx, "-std=c++17", "-O1", *flags, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                        "-I" + CSRC, *SOURCES, "-o", exe], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-300:])
+    return exe
+
+
 def run(exe, seed, nq, arena_mb, budget_permille, arrive_every, poll_every, max_active):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
     out = subprocess.run([exe, str(seed), str(nq), str(arena_mb), str(budget_permille), str(arrive_every),
-                          str(poll_every), str(max_active)], capture_output=True, text=True, timeout=120, check=True)
+                          str(poll_every), str(max_active)], capture_output=True, text=True, timeout=300, env=env)
+    assert out.returncode == 0, out.stderr[-4000:]
     return json.loads(out.stdout)
 
 
@@ -93,3 +115,13 @@ def test_loop_ends_without_polls(sim, seed):
     with TOO_LARGE where it needed that memory)."""
     for arena, budget, arrive, maxa in itertools.product([256, 1024, 4096], [300, 3000], [0, 1], [0, 4]):
         check(run(sim, seed, 40, arena, budget, arrive, 0, maxa), polls=False)
+
+
+@pytest.mark.parametrize("seed", [3, 104])
+def test_scheduler_under_sanitizers(sim_sanitized, seed):
+    """The scheduler, planner and arena under AddressSanitizer (with leak
+    detection) and UndefinedBehaviorSanitizer: polling and non-polling
+    callers, tight and roomy arenas, every scenario clean and its outcomes
+    as in the plain build's checks."""
+    for arena, budget, arrive, poll, maxa in itertools.product([256, 4096], [300, 3000], [0, 1], [0, 1], [0, 4]):
+        check(run(sim_sanitized, seed, 60, arena, budget, arrive, poll, maxa), polls=poll > 0)
