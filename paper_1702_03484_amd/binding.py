@@ -11,7 +11,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmapsq.so")
+# MAPSQ_LIB=debug selects the bounds-checked build (libmapsq_debug.so)
+LIB_PATH = os.path.join(HERE, "libmapsq_debug.so" if os.environ.get("MAPSQ_LIB") == "debug" else "libmapsq.so")
 MAX_COLS = 16
 
 MAPSQ_OK = 0

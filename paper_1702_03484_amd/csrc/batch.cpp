@@ -130,6 +130,7 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         if (p.empty) continue;
         b.nl = (uint32_t)L->nrows;
         b.nr = (uint32_t)R->nrows;
+        b.nrec = b.nl + b.nr;  // a filtered join's kept count is set on the device
         if ((uint64_t)b.nl + b.nr >= (1ull << 32)) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "a join with 2^32 records");
         b.ntiles = (uint32_t)((uint64_t(b.nl) + b.nr + TILE - 1) / TILE);
         b.tile_off = (uint32_t)tiles;
@@ -154,6 +155,7 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         while (words < (uint64_t(small) + 3) / 4) words <<= 1;
         b.fmask = (uint32_t)(words - 1);
         b.probe_right = b.nr > b.nl ? 1u : 0u;
+        b.nrec = 0;
         filt_at[i] = filt_words + 1;  // the pointer is set once the scratch exists
         filt_words += words;
     }
@@ -223,12 +225,13 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         H.njoins = (uint32_t)n;
         H.total_tiles = (uint32_t)tiles;
         H.passes = (uint32_t)passes;
-        if (ctx->epoch + passes + 2 >= (1u << 22)) {
+        // epochs: one per radix pass, heads, counts, the semi-join compaction
+        if (ctx->epoch + passes + 3 >= (1u << 22)) {
             (void)launch_fill_u64(ctx->status, ctx->status_words, 0ull, ctx->stream);
             ctx->epoch = 0;
         }
         H.epoch0 = ctx->epoch + 1;
-        ctx->epoch += passes + 2;
+        ctx->epoch += passes + 3;
         for (int k = 0; k < 2; k++) {
             H.keys[k] = reinterpret_cast<uint32_t*>(sb + nb4 * k);
             H.vals[k] = reinterpret_cast<uint32_t*>(sb + nb4 * (2 + k));
@@ -300,14 +303,19 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
             for (int i = 0; i < n; i++) {
                 const BatchJoin& b = J[i];
                 if (!plan[i].batched || plan[i].empty) continue;
-                // every record's key read twice (histograms, first pass; the
-                // filter's side once more when there is one), the kept
-                // records (N) written by the first pass and moved by the
-                // others, then heads and counts over them
+                // unfiltered: histogram and first pass read every key, the
+                // first pass writes N records and later passes move them;
+                // filtered: the filter's side read once to build it, every
+                // key read once by the compaction, which writes the N kept
+                // records; the histogram reads their keys, and every pass
+                // moves them; then heads and counts over the N records
                 const double all = double(b.nl) + b.nr;
                 const double N = b.nrec;
-                const double build = b.filt ? (b.probe_right ? b.nl : b.nr) : 0.0;
-                bytes += 8.0 * all + 4.0 * build + 8.0 * N + 16.0 * N * (passes - 1) + 8.0 * N + 28.0 * b.nseg;
+                if (b.filt)
+                    bytes += 4.0 * (b.probe_right ? b.nl : b.nr) + 4.0 * all + 8.0 * N + 4.0 * N + 16.0 * N * passes;
+                else
+                    bytes += 8.0 * all + 8.0 * N + 16.0 * N * (passes - 1);
+                bytes += 8.0 * N + 28.0 * b.nseg;
                 if (b.status == 0) {
                     const double cells = b.nvl * double(b.nl) + b.nvr * double(b.nr);
                     const uint32_t nv = (uint32_t)std::max(b.nvl, b.nvr);

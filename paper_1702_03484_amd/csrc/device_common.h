@@ -10,6 +10,25 @@
 
 namespace mq {
 
+// Bounds-checked build (-DMQ_DEBUG; `python -m paper_1702_03484_amd.build
+// --debug` writes libmapsq_debug.so, loaded when MAPSQ_LIB=debug): every
+// data-dependent store index of the sort, segment, materialisation and
+// compaction kernels is checked against the extent of what it writes; an
+// index outside it is printed with its file and line and the store is
+// skipped, so a wrong index shows up as a message instead of a memory fault.
+// In the normal build the check is the constant true and costs nothing.
+#ifdef MQ_DEBUG
+__device__ __noinline__ inline bool dbg_in_bounds(uint64_t i, uint64_t n, const char* file, int line) {
+    if (i < n) return true;
+    printf("mapsq bounds check: %s:%d index %llu outside [0, %llu)\n", file, line, (unsigned long long)i,
+           (unsigned long long)n);
+    return false;
+}
+#define MQ_IN_BOUNDS(i, n) ::mq::dbg_in_bounds((uint64_t)(i), (uint64_t)(n), __FILE__, __LINE__)
+#else
+#define MQ_IN_BOUNDS(i, n) true
+#endif
+
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 

@@ -89,65 +89,130 @@ __global__ __launch_bounds__(MQ_BLOCK) void bfilt_kernel(const BatchHdr* __restr
     }
 }
 
-// Per-join digit histograms of all passes, over the records the semi-join
-// filter keeps, and the number of kept records of each join.  Block b takes
-// a contiguous range of record tiles and flushes its LDS counts whenever the
-// join changes.
+// Semi-join compaction of the filtered joins: tile by tile in order (a tile
+// counter), the records the filter keeps go, in input order, to the front
+// of the join's region of the spare sort buffers as (relative key, record
+// index), where the histogram and the first radix pass read them as a later
+// pass reads its input.  A decoupled look-back over the join's tiles gives
+// each tile its offset; the join's last tile writes the kept count.  (Packed
+// densely first, the kept records fill the first pass's tiles: scattered
+// straight from sparse tiles, each tile would put only a few records in
+// each digit bucket and the pass's writes would break into partial lines.)
+template <int KPT>
+__global__ __launch_bounds__(MQ_BLOCK) void bcompact_kernel(const BatchHdr* __restrict__ h) {
+    constexpr uint32_t TILE = MQ_BLOCK * KPT;
+    __shared__ uint32_t s_wtot[MQ_WAVES];
+    __shared__ uint64_t s_excl;
+    __shared__ uint32_t s_tile;
+    const uint32_t T = h->total_tiles, passes = h->passes;
+    const uint32_t epoch = h->epoch0 + passes + 2;
+    const uint32_t w = threadIdx.x / MQ_WAVE;
+    const uint64_t lt = lanemask_lt();
+    for (;;) {
+        const uint32_t t = next_tile(&h->ctr[passes + 2], &s_tile);
+        if (t >= T) break;
+        BatchJoin& J = h->joins[h->tile_join[t]];
+        if (!J.filt) continue;  // block-uniform
+        const uint32_t n = J.nl + J.nr;
+        const uint32_t base = (t - J.tile_off) * TILE;
+        uint32_t k[KPT];
+#pragma unroll
+        for (int i = 0; i < KPT; i++) k[i] = bsrc_key(J, min(base + (w * KPT + i) * MQ_WAVE + lane(), n - 1));
+        uint64_t km[KPT];
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < KPT; i++) {
+            const uint32_t idx = base + (w * KPT + i) * MQ_WAVE + lane();
+            km[i] = __ballot(idx < n && bkeep(J, idx, k[i]));
+            run += (uint32_t)__popcll(km[i]);
+        }
+        if (lane() == 0) s_wtot[w] = run;
+        __syncthreads();
+        uint32_t wex = 0, ttot = 0;
+#pragma unroll
+        for (int i = 0; i < MQ_WAVES; i++) {
+            if ((uint32_t)i < w) wex += s_wtot[i];
+            ttot += s_wtot[i];
+        }
+        if (w == 0) {
+            const uint64_t ex = tile_prefix_wave(h->status, t, J.tile_off, epoch, ttot);
+            if (lane() == 0) {
+                s_excl = ex;
+                if (t - J.tile_off + 1 == J.ntiles) J.nrec = (uint32_t)(ex + ttot);
+            }
+        }
+        __syncthreads();
+        uint32_t pos = (uint32_t)s_excl + wex;
+        uint32_t* ko = h->keys[1] + J.rec_off;
+        uint32_t* vo = h->vals[1] + J.rec_off;
+#pragma unroll
+        for (int i = 0; i < KPT; i++) {
+            if ((km[i] >> lane()) & 1ull) {
+                const uint32_t at = pos + (uint32_t)__popcll(km[i] & lt);
+                if (MQ_IN_BOUNDS(at, n)) {
+                    ko[at] = k[i];
+                    vo[at] = base + (w * KPT + i) * MQ_WAVE + lane();
+                }
+            }
+            pos += (uint32_t)__popcll(km[i]);
+        }
+    }
+}
+
+// Per-join digit histograms of all passes over the records the sort takes:
+// every record of an unfiltered join (read from the tables), the compacted
+// kept records of a filtered one.  Block b takes a contiguous range of
+// record tiles and flushes its LDS counts whenever the join changes.
 template <int RB, int KPT>
 __global__ __launch_bounds__(MQ_BLOCK) void bhist_kernel(const BatchHdr* __restrict__ h) {
     using R = Radix<RB>;
     constexpr uint32_t TILE = MQ_BLOCK * KPT;
     __shared__ uint32_t sh[R::MAXP * R::BUCKETS];
-    __shared__ uint32_t s_kept;
     const uint32_t T = h->total_tiles, passes = h->passes;
     const uint32_t t0 = (uint32_t)((uint64_t)blockIdx.x * T / gridDim.x);
     const uint32_t t1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * T / gridDim.x);
     for (int i = threadIdx.x; i < R::MAXP * R::BUCKETS; i += MQ_BLOCK) sh[i] = 0;
-    if (threadIdx.x == 0) s_kept = 0;
     __syncthreads();
-    auto flush = [&](int64_t jf) {
-        for (uint32_t i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
-            const uint32_t c = sh[i];
-            if (c) atomicAdd(&h->hist[(uint64_t)jf * passes * R::BUCKETS + i], c);
-            sh[i] = 0;
-        }
-        if (threadIdx.x == 0) {
-            if (s_kept) atomicAdd(&h->joins[jf].nrec, s_kept);
-            s_kept = 0;
-        }
-    };
     int64_t cur = -1;
     for (uint32_t t = t0; t < t1; t++) {
         const uint32_t j = h->tile_join[t];
         if ((int64_t)j != cur) {
             if (cur >= 0) {
                 __syncthreads();
-                flush(cur);
+                for (uint32_t i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
+                    const uint32_t c = sh[i];
+                    if (c) atomicAdd(&h->hist[(uint64_t)cur * passes * R::BUCKETS + i], c);
+                    sh[i] = 0;
+                }
                 __syncthreads();
             }
             cur = j;
         }
         const BatchJoin& J = h->joins[j];
-        const uint32_t n = J.nl + J.nr;
+        const bool packed = J.filt != nullptr;
+        const uint32_t n = J.nrec;
         const uint32_t base = (t - J.tile_off) * TILE;
+        if (base >= n) continue;  // past the kept records (block-uniform)
+        const uint32_t* kc = h->keys[1] + J.rec_off;
         uint32_t k[KPT];
 #pragma unroll
         for (int i = 0; i < KPT; i++) {
-            k[i] = bsrc_key(J, min(base + i * MQ_BLOCK + threadIdx.x, n - 1));
+            const uint32_t idx = min(base + i * MQ_BLOCK + threadIdx.x, n - 1);
+            k[i] = packed ? kc[idx] : bsrc_key(J, idx);
         }
-        uint32_t kept = 0;
 #pragma unroll
         for (int i = 0; i < KPT; i++) {
             const uint32_t idx = base + i * MQ_BLOCK + threadIdx.x;
-            if (idx < n && bkeep(J, idx, k[i])) {
-                kept++;
+            if (idx < n)
                 for (uint32_t p = 0; p < passes; p++) atomicAdd(&sh[p * R::BUCKETS + ((k[i] >> (p * RB)) & R::MASK)], 1u);
-            }
         }
-        if (kept) atomicAdd(&s_kept, kept);
     }
     __syncthreads();
-    if (cur >= 0) flush(cur);
+    if (cur >= 0)
+        for (uint32_t i = threadIdx.x; i < passes * R::BUCKETS; i += MQ_BLOCK) {
+            const uint32_t c = sh[i];
+            if (c) atomicAdd(&h->hist[(uint64_t)cur * passes * R::BUCKETS + i], c);
+        }
 }
 
 template <int RB, int KPT, bool GEN>
@@ -165,39 +230,35 @@ __global__ __launch_bounds__(MQ_BLOCK) void bpass_kernel(const BatchHdr* __restr
         if (t >= T) break;
         const uint32_t j = h->tile_join[t];
         const BatchJoin& J = h->joins[j];
-        // the first pass reads every record from the tables and scatters the
-        // kept ones; later passes see the kept records only (the join's
-        // tiles past them have nothing to do and no later tile waits on them)
-        const uint32_t n = GEN ? J.nl + J.nr : J.nrec;
+        // the first pass of an unfiltered join reads its records from the
+        // tables; every other pass (and the first one of a filtered join)
+        // reads the sorted records of the previous one (the compacted kept
+        // records), and the join's tiles past them have nothing to do (no
+        // later tile of the join waits on them)
+        const bool gen = GEN && !J.filt;
+        const uint32_t n = J.nrec;
         const uint32_t base = (t - J.tile_off) * TILE;
         if (base >= n) continue;
         const uint32_t valid_n = min(TILE, n - base);
         uint32_t key[KPT], val[KPT];
-        uint32_t keep = 0;
-        const uint32_t* kin = GEN ? nullptr : h->keys[src] + J.rec_off;
-        const uint32_t* vin = GEN ? nullptr : h->vals[src] + J.rec_off;
+        const uint32_t* kin = h->keys[src] + J.rec_off;
+        const uint32_t* vin = h->vals[src] + J.rec_off;
 #pragma unroll
         for (int i = 0; i < KPT; i++) {
             const uint32_t off = (w * KPT + i) * MQ_WAVE + lane();
             const uint32_t idx = base + off;
             const bool ok = off < valid_n;
-            if (GEN) {
+            if (gen) {
                 const uint32_t k = bsrc_key(J, min(idx, n - 1));
                 key[i] = ok ? k : 0u;
                 val[i] = idx;
-                if (ok && bkeep(J, idx, k)) keep |= 1u << i;
             } else {
                 key[i] = ok ? kin[idx] : 0u;
                 val[i] = ok ? vin[idx] : 0u;
             }
         }
-        const uint32_t* ghist = h->hist + ((uint64_t)j * passes + pass) * R::BUCKETS;
-        if (GEN)
-            sort_tile<RB, KPT, MQ_WAVES, true>(sm, key, val, valid_n, pass * RB, ghist, h->status, t, J.tile_off,
-                                               epoch, h->keys[dst] + J.rec_off, h->vals[dst] + J.rec_off, keep);
-        else
-            sort_tile<RB, KPT>(sm, key, val, valid_n, pass * RB, ghist, h->status, t, J.tile_off, epoch,
-                               h->keys[dst] + J.rec_off, h->vals[dst] + J.rec_off);
+        sort_tile<RB, KPT>(sm, key, val, valid_n, pass * RB, h->hist + ((uint64_t)j * passes + pass) * R::BUCKETS,
+                           h->status, t, J.tile_off, epoch, h->keys[dst] + J.rec_off, h->vals[dst] + J.rec_off, n);
     }
 }
 
@@ -336,6 +397,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void bgather_kernel(const BatchHdr* __res
         const uint32_t* vals = h->vals[fin] + J.rec_off;
         for (uint32_t i = i0 + threadIdx.x; i < i1; i += MQ_BLOCK) {
             const uint32_t r = vals[i];
+            if (!MQ_IN_BOUNDS(r, J.nl + J.nr)) continue;
             if (r < J.nl) {
                 for (int c = 0; c < J.nvl; c++) h->sval[c][J.rec_off + i] = J.lcol[c][r];
             } else {
@@ -400,6 +462,7 @@ static hipError_t launch_batch_t(const BatchHdr* hdr, int passes, hipStream_t st
     BatchHdr* h = const_cast<BatchHdr*>(hdr);
     bclear_kernel<RB><<<256, MQ_BLOCK, 0, stream>>>(hdr);
     bfilt_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
+    bcompact_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
     bhist_kernel<RB, KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
     for (int p = 0; p < passes; p++) {
         if (p == 0) bpass_kernel<RB, KPT, true><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr, p);

@@ -38,8 +38,10 @@ __host__ __device__ inline CompactGrid grid_of_runs(uint64_t n, uint64_t max_blo
 
 __host__ __device__ inline CompactGrid compact_grid(uint64_t n) { return grid_of_runs(n, CMP_MAX_BLOCKS); }
 
-// the single-launch kernel: 8 blocks per CU keep twice the loads in flight
-constexpr uint64_t CMP_FUSED_BLOCKS = 2048;
+// the single-launch kernel: one resident round of blocks (4-5 per CU); each
+// block then runs about a dozen tiles back to back (more blocks, each with
+// fewer tiles, measured slower: they wait for a second round)
+constexpr uint64_t CMP_FUSED_BLOCKS = 1024;
 __host__ __device__ inline CompactGrid compact_grid_fused(uint64_t n) { return grid_of_runs(n, CMP_FUSED_BLOCKS); }
 
 // the kept count of the calling wave's 64-row slot i sits in lane i of `mine`
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_write_kernel(CompactArgs a, 
             }
 #pragma unroll
             for (int i = 0; i < CMP_IPT; i++)
-                if ((km[i] >> lane()) & 1ull) dst[pos + rel[i]] = v[i];
+                if ((km[i] >> lane()) & 1ull && MQ_IN_BOUNDS(pos + rel[i], a.n)) dst[pos + rel[i]] = v[i];
         }
     }
 }
@@ -192,15 +194,22 @@ constexpr uint32_t CMP_LIST = 2048;
 __device__ __forceinline__ void load_first_test(const int32_t* A, const int32_t* B, int32_t c0, uint64_t n,
                                                 uint64_t base, uint32_t w, int32_t (&va)[CMP_IPT],
                                                 int32_t (&vb)[CMP_IPT]) {
+    // tile-relative 32-bit offsets from a wave-uniform base (base < n)
+    const int32_t* Ab = A ? A + base : nullptr;
+    const int32_t* Bb = B ? B + base : nullptr;
+    const uint64_t left = n - 1 - base;
+    const uint32_t lim = left < CMP_TILE ? (uint32_t)left : (uint32_t)(CMP_TILE - 1);
 #pragma unroll
     for (int i = 0; i < CMP_IPT; i++) {
-        const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
-        const uint64_t at = idx < n ? idx : n - 1;
-        va[i] = A ? A[at] : 0;
-        vb[i] = B ? B[at] : c0;
+        const uint32_t off = min((w * CMP_IPT + i) * MQ_WAVE + lane(), lim);
+        va[i] = Ab ? Ab[off] : 0;
+        vb[i] = Bb ? Bb[off] : c0;
     }
 }
 
+// MULTI: the pattern has further equality tests after the first; PAIR: the
+// first test compares two columns (else a column with a constant, or none)
+template <bool MULTI, bool PAIR>
 __global__ __launch_bounds__(MQ_BLOCK) void compact_fused_kernel(CompactArgs a, uint64_t* __restrict__ status,
                                                                  uint32_t* __restrict__ run_ctr,
                                                                  uint64_t* __restrict__ mask, CompactGrid g) {
@@ -216,35 +225,57 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_fused_kernel(CompactArgs a, 
     const uint64_t t0 = (uint64_t)run_id * g.chunk;
     const uint64_t t1 = t0 + g.chunk < g.ntiles ? t0 + g.chunk : g.ntiles;
     const int32_t* A0 = a.nterm > 0 ? a.in[a.term_a[0]] : nullptr;
-    const int32_t* B0 = a.nterm > 0 && a.term_b[0] >= 0 ? a.in[a.term_b[0]] : nullptr;
+    const int32_t* B0 = PAIR ? a.in[a.term_b[0]] : nullptr;
     const int32_t c0 = a.nterm > 0 ? a.term_c[0] : 0;
     uint32_t run_tot = 0;  // kept rows of the run's tiles so far (same in every thread)
     for (uint64_t tile = t0; tile < t1; tile++) {
         const uint64_t base = tile * CMP_TILE;
-        int32_t va[CMP_IPT], vb[CMP_IPT];
-        load_first_test(A0, B0, c0, a.n, base, w, va, vb);
-        bool ok[CMP_IPT];
+        // the kept rows of each 64-row slot as one ballot word (kept in
+        // scalar registers: no per-row flags stay live)
+        uint64_t km[CMP_IPT];
+        if (base + CMP_TILE <= a.n) {
+            // a whole tile: the wave's row slots are one base address plus
+            // constant offsets, and a constant right side needs no loads
+            const uint64_t wbase = base + (uint64_t)(w * CMP_IPT * MQ_WAVE) + lane();
+            if (PAIR) {
+                int32_t va[CMP_IPT], vb[CMP_IPT];
 #pragma unroll
-        for (int i = 0; i < CMP_IPT; i++) {
-            const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
-            ok[i] = idx < a.n && (!A0 || va[i] == vb[i]);
-        }
-        for (int t = 1; t < a.nterm; t++) {
-            const int32_t* A = a.in[a.term_a[t]];
-            const int32_t* B = a.term_b[t] >= 0 ? a.in[a.term_b[t]] : nullptr;
+                for (int i = 0; i < CMP_IPT; i++) {
+                    va[i] = A0[wbase + i * MQ_WAVE];
+                    vb[i] = B0[wbase + i * MQ_WAVE];
+                }
+#pragma unroll
+                for (int i = 0; i < CMP_IPT; i++) km[i] = __ballot(va[i] == vb[i]);
+            } else if (A0) {
+                int32_t va[CMP_IPT];
+#pragma unroll
+                for (int i = 0; i < CMP_IPT; i++) va[i] = A0[wbase + i * MQ_WAVE];
+#pragma unroll
+                for (int i = 0; i < CMP_IPT; i++) km[i] = __ballot(va[i] == c0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < CMP_IPT; i++) km[i] = ~0ull;
+            }
+        } else {
+            int32_t va[CMP_IPT], vb[CMP_IPT];
+            load_first_test(A0, B0, c0, a.n, base, w, va, vb);
 #pragma unroll
             for (int i = 0; i < CMP_IPT; i++) {
                 const uint64_t idx = base + (uint64_t)((w * CMP_IPT + i) * MQ_WAVE + lane());
-                if (ok[i]) ok[i] = A[idx] == (B ? B[idx] : a.term_c[t]);
+                km[i] = __ballot(idx < a.n && (!A0 || va[i] == vb[i]));
             }
         }
-        uint64_t km[CMP_IPT];
+        // further tests read their columns for every row slot, like the first
+        for (int t = 1; MULTI && t < a.nterm; t++) {
+            int32_t va[CMP_IPT], vb[CMP_IPT];
+            load_first_test(a.in[a.term_a[t]], a.term_b[t] >= 0 ? a.in[a.term_b[t]] : nullptr, a.term_c[t], a.n,
+                            base, w, va, vb);
+#pragma unroll
+            for (int i = 0; i < CMP_IPT; i++) km[i] &= __ballot(va[i] == vb[i]);
+        }
         uint32_t run = 0;
 #pragma unroll
-        for (int i = 0; i < CMP_IPT; i++) {
-            km[i] = __ballot(ok[i]);
-            run += (uint32_t)__popcll(km[i]);
-        }
+        for (int i = 0; i < CMP_IPT; i++) run += (uint32_t)__popcll(km[i]);
         const uint64_t mine = pick_slot(km);
         if (lane() < (uint32_t)CMP_IPT) mask[tile * CMP_TILE_WORDS + w * CMP_IPT + lane()] = mine;
         // one barrier per tile: the wave totals alternate between two slots,
@@ -288,6 +319,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_fused_kernel(CompactArgs a, 
         // every kept row of the run at once: consecutive threads, consecutive outputs
         for (uint32_t j = threadIdx.x; j < run_tot; j += MQ_BLOCK) {
             const uint32_t idx = s_list[j];
+            if (!MQ_IN_BOUNDS(pos_run + j, a.n)) continue;
             for (int c = 0; c < a.nout; c++) a.out[c][pos_run + j] = a.in[a.out_src[c]][idx];
         }
         return;
@@ -319,7 +351,7 @@ __global__ __launch_bounds__(MQ_BLOCK) void compact_fused_kernel(CompactArgs a, 
             }
 #pragma unroll
             for (int i = 0; i < CMP_IPT; i++)
-                if ((km[i] >> lane()) & 1ull) dst[pos + rel[i]] = v[i];
+                if ((km[i] >> lane()) & 1ull && MQ_IN_BOUNDS(pos + rel[i], a.n)) dst[pos + rel[i]] = v[i];
         }
     }
 }
@@ -344,8 +376,10 @@ hipError_t launch_compact(const CompactArgs& a, uint64_t* scratch, hipStream_t s
         uint64_t* ctr = mask + g.ntiles * CMP_TILE_WORDS;  // word 0: run counter; then status words
         hipError_t e = launch_fill_u64(ctr, 1 + gf.blocks, 0ull, stream);
         if (e != hipSuccess) return e;
-        compact_fused_kernel<<<(uint32_t)gf.blocks, MQ_BLOCK, 0, stream>>>(a, ctr + 1, reinterpret_cast<uint32_t*>(ctr),
-                                                                          mask, gf);
+        const bool multi = a.nterm > 1, pair = a.nterm > 0 && a.term_b[0] >= 0;
+        auto* k = multi ? (pair ? compact_fused_kernel<true, true> : compact_fused_kernel<true, false>)
+                        : (pair ? compact_fused_kernel<false, true> : compact_fused_kernel<false, false>);
+        k<<<(uint32_t)gf.blocks, MQ_BLOCK, 0, stream>>>(a, ctr + 1, reinterpret_cast<uint32_t*>(ctr), mask, gf);
         return hipGetLastError();
     }
     compact_test_kernel<<<(uint32_t)g.blocks, MQ_BLOCK, 0, stream>>>(a, counts, tloc, mask, g);

@@ -165,10 +165,10 @@ __global__ __launch_bounds__(MQ_BLOCK) void heads_write_kernel(const uint32_t* _
             const bool prev_r = fs ? (r[i].kprev & 1u) != 0 : r[i].vprev >= n_left;
             const bool last = idx + 1 == n || (r[i].knext >> fs) != (r[i].k >> fs) || fnext[i];
             const bool first_r = is_r && (h || !prev_r);
-            if (h) seg_start[bef] = idx;
+            if (h && MQ_IN_BOUNDS(bef, n)) seg_start[bef] = idx;
             if (first_r || (last && !is_r)) {
                 const uint32_t sid = h ? bef : bef - 1u;  // record 0 is always a head
-                seg_split[sid] = first_r ? idx : idx + 1;
+                if (MQ_IN_BOUNDS(sid, n)) seg_split[sid] = first_r ? idx : idx + 1;
             }
         }
         pos += (uint32_t)__popcll(hm[i]);

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(NW * MQ_WAVE) void radix_pass_kernel(SortSrc src, c
             val[i] = ok ? vt[off] : 0u;
         }
     }
-    sort_tile<RB, KPT, NW>(sm, key, val, valid_n, shift, ghist, status, tile, 0, epoch, kout, vout);
+    sort_tile<RB, KPT, NW>(sm, key, val, valid_n, shift, ghist, status, tile, 0, epoch, kout, vout, n);
 }
 
 #define MQ_RB_LIST(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)

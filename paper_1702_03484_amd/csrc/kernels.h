@@ -249,7 +249,7 @@ struct BatchJoin {
     uint64_t* filt;
     uint32_t fmask;
     uint32_t probe_right;
-    uint32_t nrec;              // records kept (written on the device; zero before the launch)
+    uint32_t nrec;              // records sorted: nl + nr, or (filtered) the kept count, written on the device
 };
 
 struct BatchHdr {

@@ -63,18 +63,16 @@ __device__ __forceinline__ void scan_buckets(const uint32_t* in, uint32_t* out, 
 // (wave*KPT + i)*64 + lane; positions >= valid_n are padding).  Ranks the
 // digits, publishes the tile's digit counts, looks back over the join's
 // earlier tiles, and scatters the tile to kout/vout (join-relative).
-// `ghist` is the join's digit histogram of this pass.  MASKED: element i of
-// a thread takes part only when bit i of `keep` is set; the kept elements
-// are ranked and scattered as if the others were absent (the histogram and
-// every tile's totals count kept elements only).  Every thread of the
-// block calls it.
-template <int RB, int KPT, int NW = MQ_WAVES, bool MASKED = false>
+// `ghist` is the join's digit histogram of this pass; n_out the records of
+// the output (checked in the bounds-checked build only).  Every thread of
+// the block calls it.
+template <int RB, int KPT, int NW = MQ_WAVES>
 __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint32_t (&key)[KPT],
                                           const uint32_t (&val)[KPT], uint32_t valid_n, int shift,
                                           const uint32_t* __restrict__ ghist, uint64_t* __restrict__ status,
                                           uint32_t tile, uint32_t first_tile, uint32_t epoch,
                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                          uint32_t keep = ~0u) {
+                                          uint32_t n_out) {
     using R = Radix<RB>;
     constexpr int NT = NW * MQ_WAVE;                       // threads of the block
     constexpr int BPT = (R::BUCKETS + NT - 1) / NT;        // buckets per thread
@@ -93,11 +91,10 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
     static_assert(NT * KPT <= 65536 && KPT % 2 == 0, "16-bit ranks");
     uint32_t rank2[KPT / 2];
     const uint64_t lt = lanemask_lt();
-    uint32_t wkept = 0;  // MASKED: this wave's kept elements
 #pragma unroll
     for (int i = 0; i < KPT; i++) {
         const uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
-        const bool ok = off < valid_n && (!MASKED || ((keep >> i) & 1u));
+        const bool ok = off < valid_n;
         const uint32_t dg = (key[i] >> shift) & R::MASK;
         // lanes whose digit differs in some bit: per bit, the ballot of
         // that bit xor this lane's bit spread over 64 bits (0 or all ones)
@@ -110,9 +107,7 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
             diff_lo |= (uint32_t)m ^ spread;
             diff_hi |= (uint32_t)(m >> 32) ^ spread;
         }
-        const uint64_t okm = __ballot(ok);
-        if (MASKED) wkept += (uint32_t)__popcll(okm);
-        const uint64_t peers = okm & ~((uint64_t)diff_hi << 32 | diff_lo);
+        const uint64_t peers = __ballot(ok) & ~((uint64_t)diff_hi << 32 | diff_lo);
         const uint32_t below = __popcll(peers & lt);
         const uint32_t old = ok ? sm.wcnt[w][dg] : 0u;
         if (ok && below == 0) sm.wcnt[w][dg] = old + (uint32_t)__popcll(peers);
@@ -121,14 +116,7 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
         else
             rank2[i / 2] |= (old + below) << 16;
     }
-    if (MASKED && ln == 0) sm.tmp[w] = wkept;
     __syncthreads();
-    uint32_t nkept = valid_n;  // records the tile scatters
-    if (MASKED) {
-        nkept = 0;
-#pragma unroll
-        for (int i = 0; i < NW; i++) nkept += sm.tmp[i];
-    }
 
     // per digit: exclusive prefix over waves, tile total, local digit starts
     uint32_t tot[BPT];
@@ -172,7 +160,7 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
 #pragma unroll
     for (int i = 0; i < KPT; i++) {
         const uint32_t off = (w * KPT + i) * MQ_WAVE + ln;
-        if (off < valid_n && (!MASKED || ((keep >> i) & 1u))) {
+        if (off < valid_n) {
             const uint32_t dg = (key[i] >> shift) & R::MASK;
             const uint32_t pos = sm.local[dg] + sm.wcnt[w][dg] + ((rank2[i / 2] >> (16 * (i % 2))) & 0xffffu);
             sm.keys[pos] = key[i];
@@ -180,12 +168,14 @@ __device__ __forceinline__ void sort_tile(SortSmem<RB, KPT, NW>& sm, const uint3
         }
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < nkept; j += NT) {
+    for (uint32_t j = threadIdx.x; j < valid_n; j += NT) {
         const uint32_t k = sm.keys[j];
         const uint32_t dg = (k >> shift) & R::MASK;
         const uint32_t g = sm.goff[dg] + (j - sm.local[dg]);
-        kout[g] = k;
-        vout[g] = sm.vals[j];
+        if (MQ_IN_BOUNDS(g, n_out)) {
+            kout[g] = k;
+            vout[g] = sm.vals[j];
+        }
     }
 }
 
@@ -253,10 +243,10 @@ __device__ __forceinline__ void heads_tile(HeadsSmem& sm, const uint32_t* __rest
         const uint32_t idx = base + (w * IPT + i) * MQ_WAVE + lane();
         const bool h = (hm[i] >> lane()) & 1ull;
         const uint32_t before = pos + (uint32_t)__popcll(hm[i] & lt);  // heads before this record
-        if (h) seg_start[before] = idx;
+        if (h && MQ_IN_BOUNDS(before, n)) seg_start[before] = idx;
         if ((wbits >> i) & 1u) {
             const uint32_t sid = h ? before : before - 1u;  // record 0 is always a head
-            seg_split[sid] = ((sbits >> i) & 1u) ? idx : idx + 1;
+            if (MQ_IN_BOUNDS(sid, n)) seg_split[sid] = ((sbits >> i) & 1u) ? idx : idx + 1;
         }
         pos += (uint32_t)__popcll(hm[i]);
     }
@@ -627,6 +617,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
             for (int q = 0; q < Q; q++) {
                 if (q >= qn) break;
                 const uint64_t jl = j0 + (uint64_t)q * (4 * MQ_WAVE) + 4ull * lane();
+                if (!MQ_IN_BOUNDS(jl + 3, jend)) continue;
 #pragma unroll
                 for (int col = 0; col < NC; col++)
                     if (col < nc)
@@ -733,6 +724,7 @@ __device__ __forceinline__ void mat_wave_chunk(const MatJoin& a, uint64_t j0, ui
                                        nk, v);
         }
     store:
+        if (nk > 0 && !MQ_IN_BOUNDS(jl + nk - 1, jend)) nk = 0;
         if (nk == 4) {
 #pragma unroll
             for (int col = 0; col < NC; col++)
@@ -811,6 +803,7 @@ __device__ __forceinline__ void mat_seg_group(const MatJoin& mj, uint32_t grp, u
         const uint32_t outer = rr / ci, inner = rr - outer * ci;
         const uint32_t lpos = kst + (left_in ? inner : outer);
         const uint32_t rpos = ksp + (left_in ? outer : inner);
+        if (!MQ_IN_BOUNDS(j, row_end)) continue;
         mj.out[0][j] = s_key[lo];
         if (mj.sorted_vals) {
 #pragma unroll
