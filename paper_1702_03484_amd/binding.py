@@ -11,8 +11,11 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# MAPSQ_LIB=debug selects the bounds-checked build (libmapsq_debug.so)
-LIB_PATH = os.path.join(HERE, "libmapsq_debug.so" if os.environ.get("MAPSQ_LIB") == "debug" else "libmapsq.so")
+# MAPSQ_LIB=debug selects the bounds-checked build (libmapsq_debug.so); any
+# other value is the path of another build of the library
+_ENV_LIB = os.environ.get("MAPSQ_LIB", "")
+LIB_PATH = (os.path.join(HERE, "libmapsq_debug.so") if _ENV_LIB == "debug"
+            else _ENV_LIB or os.path.join(HERE, "libmapsq.so"))
 MAX_COLS = 16
 
 MAPSQ_OK = 0

@@ -17,12 +17,21 @@ namespace mq {
 constexpr int SEMI_IPT = 16;
 
 // keys outside [base, base + range) (a caller's key bound that does not
-// hold) set nothing
+// hold) set nothing.  Of a run of equal keys in consecutive lanes (a side
+// sorted on the key) only the first lane sets the bit, and a bit found set
+// already is not set again, so repeated keys do not queue on one word.
 __global__ __launch_bounds__(MQ_BLOCK) void bitmap_set_kernel(const int32_t* __restrict__ keys, uint32_t n,
                                                               int32_t base, uint64_t range, uint32_t* __restrict__ bm) {
-    for (uint32_t i = blockIdx.x * MQ_BLOCK + threadIdx.x; i < n; i += gridDim.x * MQ_BLOCK) {
-        const uint32_t k = (uint32_t)keys[i] - (uint32_t)base;
-        if (k < range) atomicOr(&bm[k >> 5], 1u << (k & 31u));
+    for (uint32_t i0 = blockIdx.x * MQ_BLOCK; i0 < n; i0 += gridDim.x * MQ_BLOCK) {
+        const uint32_t i = i0 + threadIdx.x;
+        const uint32_t k = i < n ? (uint32_t)keys[i] - (uint32_t)base : ~0u;
+        const uint32_t kp = __shfl_up(k, 1, MQ_WAVE);
+        const bool first = lane() == 0 || kp != k;
+        if (i < n && first && k < range) {
+            const uint32_t bit = 1u << (k & 31u);
+            if (!(__hip_atomic_load(&bm[k >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
+                atomicOr(&bm[k >> 5], bit);
+        }
     }
 }
 
