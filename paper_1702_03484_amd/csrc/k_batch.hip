@@ -12,7 +12,13 @@
 
 namespace mq {
 
+// Persistent grids are sized to one resident round of blocks on the 256 CUs
+// (a block beyond it only starts when another ends): 4 blocks per CU for
+// the kernels of up to 128 VGPRs, 5 for those of up to 96, 8 for the
+// histogram's 48 (measured on the 512-join batch: 6% off the launch).
 constexpr uint32_t BATCH_BLOCKS = 1024;
+constexpr uint32_t BATCH_BLOCKS_5 = 1280;
+constexpr uint32_t BATCH_BLOCKS_8 = 2048;
 constexpr uint32_t BMAT_BLOCKS = 2048;
 constexpr int BMAT_RPT = 8;
 constexpr uint32_t BMAT_WROWS = MQ_WAVE * BMAT_RPT;
@@ -215,8 +221,9 @@ __global__ __launch_bounds__(MQ_BLOCK) void bhist_kernel(const BatchHdr* __restr
         }
 }
 
+// at most 168 VGPRs (3 waves per SIMD instead of 2)
 template <int RB, int KPT, bool GEN>
-__global__ __launch_bounds__(MQ_BLOCK) void bpass_kernel(const BatchHdr* __restrict__ h, int pass) {
+__global__ __launch_bounds__(MQ_BLOCK, 3) void bpass_kernel(const BatchHdr* __restrict__ h, int pass) {
     using R = Radix<RB>;
     constexpr uint32_t TILE = MQ_BLOCK * KPT;
     __shared__ SortSmem<RB, KPT> sm;
@@ -411,7 +418,8 @@ __global__ __launch_bounds__(MQ_BLOCK) void bgather_kernel(const BatchHdr* __res
 // waves, each chunk's join found by a 64-ary search over the joins.
 static_assert(MAT_SEG_LDS_WORDS <= (int)MAT_LDS_SEGS, "a wave's LDS rows hold a key group");
 
-__global__ __launch_bounds__(MQ_BLOCK) void bmat_kernel(const BatchHdr* __restrict__ h) {
+// at most 128 VGPRs (4 waves per SIMD): a few spill, the gathers overlap more
+__global__ __launch_bounds__(MQ_BLOCK, 4) void bmat_kernel(const BatchHdr* __restrict__ h) {
     __shared__ uint64_t s_segs[MQ_WAVES][MAT_LDS_SEGS];
     const uint64_t nchunks = h->total_chunks;
     const uint32_t passes = h->passes;
@@ -462,13 +470,13 @@ static hipError_t launch_batch_t(const BatchHdr* hdr, int passes, hipStream_t st
     BatchHdr* h = const_cast<BatchHdr*>(hdr);
     bclear_kernel<RB><<<256, MQ_BLOCK, 0, stream>>>(hdr);
     bfilt_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
-    bcompact_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
-    bhist_kernel<RB, KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
+    bcompact_kernel<KPT><<<BATCH_BLOCKS_5, MQ_BLOCK, 0, stream>>>(hdr);
+    bhist_kernel<RB, KPT><<<BATCH_BLOCKS_8, MQ_BLOCK, 0, stream>>>(hdr);
     for (int p = 0; p < passes; p++) {
         if (p == 0) bpass_kernel<RB, KPT, true><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr, p);
         else bpass_kernel<RB, KPT, false><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr, p);
     }
-    bheads_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(h);
+    bheads_kernel<KPT><<<BATCH_BLOCKS_5, MQ_BLOCK, 0, stream>>>(h);
     bcount_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(h);
     bplace_kernel<<<1, MQ_BLOCK, 0, stream>>>(h);
     bgather_kernel<KPT><<<BATCH_BLOCKS, MQ_BLOCK, 0, stream>>>(hdr);
