@@ -139,8 +139,9 @@ __host__ __device__ constexpr int sort_waves(int rb, int kpt, bool gen) {
     return rb <= 8 && kpt == 16 && !gen ? 8 : 4;
 }
 
+// the first pass is held to 128 VGPRs (4 waves per SIMD instead of 3, no spills)
 template <int RB, int KPT, bool GEN, int NW = sort_waves(RB, KPT, GEN)>
-__global__ __launch_bounds__(NW * MQ_WAVE) void radix_pass_kernel(SortSrc src, const uint32_t* __restrict__ kin,
+__global__ __launch_bounds__(NW * MQ_WAVE, GEN ? 4 : 1) void radix_pass_kernel(SortSrc src, const uint32_t* __restrict__ kin,
                                                                   const uint32_t* __restrict__ vin,
                                                                   uint32_t* __restrict__ kout,
                                                                   uint32_t* __restrict__ vout, uint32_t n, int shift,
