@@ -16,7 +16,7 @@ __global__ void fill_kernel(T* __restrict__ p, uint64_t n, T v) {
         p[i] = v;
 }
 
-constexpr uint32_t SCAN_RUNS_MAX = 4 * 256;
+constexpr uint32_t SCAN_RUNS_MAX = 8 * 256;
 
 __global__ __launch_bounds__(256) void scan_runs_kernel(uint64_t* __restrict__ tot, uint32_t nruns,
                                                         uint64_t* __restrict__ total64,
@@ -25,10 +25,10 @@ __global__ __launch_bounds__(256) void scan_runs_kernel(uint64_t* __restrict__ t
                                                         uint64_t* __restrict__ max_out) {
     __shared__ uint64_t tmp[MQ_WAVES];
     __shared__ uint64_t s_mx[MQ_WAVES];
-    uint64_t v[4], sum = 0, mx = 0;
+    uint64_t v[8], sum = 0, mx = 0;
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const uint32_t i = threadIdx.x * 4 + k;
+    for (int k = 0; k < 8; k++) {
+        const uint32_t i = threadIdx.x * 8 + k;
         v[k] = i < nruns ? tot[i] : 0ull;
         sum += v[k];
         if (run_max && i < nruns) mx = run_max[i] > mx ? run_max[i] : mx;
@@ -36,8 +36,8 @@ __global__ __launch_bounds__(256) void scan_runs_kernel(uint64_t* __restrict__ t
     uint64_t all;
     uint64_t ex = block_excl_scan<uint64_t>(sum, tmp, &all);  // each total < 2^41: no overflow
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const uint32_t i = threadIdx.x * 4 + k;
+    for (int k = 0; k < 8; k++) {
+        const uint32_t i = threadIdx.x * 8 + k;
         if (i < nruns) tot[i] = ex > SAT40 ? SAT40 : ex;
         ex += v[k];
     }
