@@ -66,6 +66,73 @@ void greedy_plan(const std::vector<std::vector<int32_t>>& vars, const std::vecto
 
 mapsq_status cross_join(Ctx* ctx, const mapsq_table& a, const mapsq_table& b, mapsq_table* out);
 
+// Each pattern's variables (first occurrence order) with their distinct
+// counts: a subject or object variable of a constant predicate takes the
+// predicate's distinct subjects or objects (at most the pattern's rows),
+// anything else the rows.  A join keeps |L| |R| / max(distinct keys) rows,
+// a cross product |L| |R|; after a step every distinct count is capped by
+// its rows (System-R style).
+std::vector<double> estimate_steps(const Ctx* ctx, const mapsq_pattern* pats, const std::vector<int64_t>& rows,
+                                   int start, const std::vector<PlanStep>& steps, double* scan_bytes,
+                                   std::vector<size_t>* out_cols) {
+    const Store& St = ctx->store;
+    const size_t m = rows.size();
+    std::vector<std::vector<int32_t>> vars(m);
+    std::vector<std::vector<double>> dist(m);
+    double scans = 0;
+    for (size_t i = 0; i < m; i++) {
+        const mapsq_pattern& p = pats[i];
+        const int32_t t[3] = {p.s, p.p, p.o};
+        double ds = (double)rows[i], dob = (double)rows[i];
+        if (p.p >= 0 && St.pred_ds.size() == St.preds.size()) {
+            auto it = std::lower_bound(St.preds.begin(), St.preds.end(), p.p);
+            if (it != St.preds.end() && *it == p.p) {
+                const size_t pi = size_t(it - St.preds.begin());
+                ds = std::min(ds, (double)St.pred_ds[pi]);
+                dob = std::min(dob, (double)St.pred_do[pi]);
+            }
+        }
+        for (int k = 0; k < 3; k++)
+            if (t[k] < 0) {
+                const int32_t v = -t[k] - 1;
+                if (std::find(vars[i].begin(), vars[i].end(), v) != vars[i].end()) continue;
+                vars[i].push_back(v);
+                dist[i].push_back(k == 0 ? ds : (k == 2 ? dob : (double)rows[i]));
+            }
+        const bool scan = p.p < 0 || (p.s < 0 && (p.s == p.p || p.s == p.o)) || (p.p < 0 && p.p == p.o);
+        if (scan) scans += 4.0 * vars[i].size() * (double)rows[i];
+    }
+    if (scan_bytes) *scan_bytes = scans;
+    std::vector<double> est_rows;
+    double cur_rows = (double)rows[start];
+    std::vector<int32_t> cv = vars[start];
+    std::vector<double> cd = dist[start];
+    for (const PlanStep& ps : steps) {
+        const double r2 = (double)rows[ps.pick];
+        double est;
+        if (ps.cross) {
+            est = cur_rows * r2;
+        } else {
+            double d1 = 1, d2 = 1;
+            for (size_t k = 0; k < cv.size(); k++)
+                if (cv[k] == ps.key) d1 = cd[k];
+            for (size_t k = 0; k < vars[ps.pick].size(); k++)
+                if (vars[ps.pick][k] == ps.key) d2 = dist[ps.pick][k];
+            est = cur_rows * r2 / std::max(1.0, std::max(d1, d2));
+        }
+        for (size_t k = 0; k < vars[ps.pick].size(); k++)
+            if (std::find(cv.begin(), cv.end(), vars[ps.pick][k]) == cv.end()) {
+                cv.push_back(vars[ps.pick][k]);
+                cd.push_back(dist[ps.pick][k]);
+            }
+        for (double& d : cd) d = std::min(d, est);
+        est_rows.push_back(est);
+        if (out_cols) out_cols->push_back(cv.size());
+        cur_rows = est;
+    }
+    return est_rows;
+}
+
 // Table with one extra all-zero column bound to CROSS_VAR (owned scratch).
 static mapsq_status with_zero_key(Ctx* ctx, const mapsq_table& t, mapsq_table* out, Block* zeros) {
     if (t.ncols >= MAPSQ_MAX_COLS) return ctx->fail(MAPSQ_ERR_UNSUPPORTED, "more than 16 columns");
@@ -246,11 +313,14 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
     }
     std::vector<mapsq_plan_step> plan;
     mapsq_table cur{};
-    // one join step: cur JOIN tabs[pick] (a cross product when key < 0)
-    auto step = [&](int pick, int32_t key, int32_t candidates) -> mapsq_status {
+    // one join step: cur JOIN tabs[pick] (a cross product when key < 0);
+    // est_rows is the step's expected output (negative: none)
+    auto step = [&](int pick, int32_t key, int32_t candidates, double est_rows) -> mapsq_status {
         mapsq_table nxt{};
+        ctx->join_est_rows = key < 0 ? -1.0 : est_rows;
         mapsq_status st = key < 0 ? cross_join(ctx, cur, tabs[pick], &nxt)
                                   : join_tables(ctx, &cur, &tabs[pick], key, &nxt);
+        ctx->join_est_rows = -1.0;
         if (st) {
             free_table(ctx, &cur);
             cleanup();
@@ -298,8 +368,8 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
         cur = tabs[bl];
         used[bl] = true;
         plan.push_back(mapsq_plan_step{bl, -1, cur.nrows, 0, 0});
-        if (br >= 0)
-            if (mapsq_status st = step(br, bkey, counted)) return st;
+        if (br >= 0)  // its size was counted exactly
+            if (mapsq_status st = step(br, bkey, counted, (double)best)) return st;
         // then the connected table whose exact |RS| with the result is smallest
         while ((int)plan.size() < npats) {
             int pick = -1;
@@ -326,7 +396,7 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
             if (pick < 0)  // nothing connected: the smallest remaining table by cross product
                 for (int j = 0; j < npats; j++)
                     if (!used[j] && (pick < 0 || tabs[j].nrows < tabs[pick].nrows)) pick = j;
-            if (mapsq_status st = step(pick, pkey, counted)) return st;
+            if (mapsq_status st = step(pick, pkey, counted, (double)pbest)) return st;
         }
     } else {
         std::vector<std::vector<int32_t>> tv(npats);
@@ -342,11 +412,14 @@ mapsq_status query(Ctx* ctx, const mapsq_pattern* pats, int32_t npats, const int
             cleanup();
             return s2;
         }
+        const std::vector<double> est = estimate_steps(ctx, pats, tr, start, steps);
         cur = tabs[start];
         used[start] = true;
         plan.push_back(mapsq_plan_step{start, -1, cur.nrows, 0, 0});
-        for (const PlanStep& ps : steps)
-            if (mapsq_status st = step(ps.pick, ps.cross ? -1 : ps.key, 0)) return st;
+        for (size_t k = 0; k < steps.size(); k++) {
+            const PlanStep& ps = steps[k];
+            if (mapsq_status st = step(ps.pick, ps.cross ? -1 : ps.key, 0, est[k])) return st;
+        }
     }
     ctx->last_plan = plan;
     // projection (bag): pick the selected columns in the requested order

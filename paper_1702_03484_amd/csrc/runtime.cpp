@@ -685,6 +685,8 @@ static mapsq_status result_room(Ctx* ctx, uint64_t rows, int nc) {
 
 mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, int32_t key_var, mapsq_table* out) {
     zero_table(out);
+    const double est_rows = ctx->join_est_rows;  // this call's estimate only
+    ctx->join_est_rows = -1.0;
     mapsq_status st;
     if ((st = check_table(ctx, L, "left")) || (st = check_table(ctx, R, "right"))) return st;
     const int lk = col_of(L, key_var), rk = col_of(R, key_var);
@@ -977,8 +979,11 @@ mapsq_status join_tables(Ctx* ctx, const mapsq_table* L, const mapsq_table* R, i
     // On a join that fits it costs about as much as the count phase.
     // (a count-only call takes it whenever the key range allows: it is the
     // whole answer there)
+    // (automatic mode skips it when the caller's estimate of the output is
+    // far below the free space: the pre-count then mostly costs time)
+    const bool est_small = est_rows >= 0.0 && est_rows * 4.0 * nc_mat * 8.0 < (double)ctx->arena.free_bytes();
     const bool precount = !composite && (ctx->precount == 2 || ctx->count_only ||
-                                         (ctx->precount == 0 && (uint64_t)N >= PRECOUNT_MIN_RECORDS));
+                                         (ctx->precount == 0 && (uint64_t)N >= PRECOUNT_MIN_RECORDS && !est_small));
     if (precount) {
         const uint64_t range = (uint64_t)((int64_t)kmax - (int64_t)kmin) + 1;
         Block cnt;

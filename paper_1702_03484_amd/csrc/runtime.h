@@ -129,6 +129,11 @@ struct Ctx {
     int32_t semijoin = 0;    // 0 automatic, 1 never, 2 always
     int32_t merge_mode = 0;  // 0 merge join of key-sorted tables, 1 never
     int32_t precount = 0;    // exact |RS| before shuffles: 0 of 2^24+ records, 1 never, 2 always
+    // The caller's estimate of the next join's output rows (the planner's and
+    // the server's plans set it; < 0: none), read and cleared by join_tables:
+    // in automatic mode the exact pre-count is skipped when the output at
+    // that size would take at most 1/8 of the arena's free space.
+    double join_est_rows = -1.0;
     int32_t composite = 0;   // 0 a second shared variable joins as part of the key, 1 it is filtered
     int32_t planner = 0;     // mapsq_query join order: 0 pattern sizes, 1 exact join sizes
     // join_tables stops once the exact |RS| is known (nrows set, no columns)
@@ -270,6 +275,12 @@ mapsq_status cross_join(Ctx* ctx, const mapsq_table& a, const mapsq_table& b, ma
 mapsq_table project_table(const mapsq_table& cur, const std::vector<int32_t>& want);
 mapsq_status key_sort_views(Ctx* ctx, const mapsq_pattern* pats, mapsq_table* tabs, int start,
                             const std::vector<PlanStep>& steps);
+// System-R estimates of a plan's step outputs (rows), from the patterns'
+// partial-match sizes and the store's per-predicate distinct subjects and
+// objects; *scan_bytes (if given) gets the bytes the plan's scans write.
+std::vector<double> estimate_steps(const Ctx* ctx, const mapsq_pattern* pats, const std::vector<int64_t>& rows,
+                                   int start, const std::vector<PlanStep>& steps, double* scan_bytes = nullptr,
+                                   std::vector<size_t>* out_cols = nullptr);
 bool ensure_stage(Ctx* ctx, size_t bytes);
 // [lo, hi) of each index lookup (2 int64 per query in out); one synchronisation
 mapsq_status locate_ranges(Ctx* ctx, const LocateQuery* q, size_t n, int64_t* out);

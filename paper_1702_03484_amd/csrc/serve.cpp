@@ -43,6 +43,7 @@ struct SQuery {
     std::vector<bool> consumed;
     int start = 0;
     std::vector<PlanStep> steps;
+    std::vector<double> est;               // estimated output rows of each step
     size_t next = 0;
     mapsq_table cur{};
     mapsq_table result{};
@@ -213,61 +214,23 @@ static mapsq_status size_waiting(Ctx* ctx, Server* S) {
 // keys) from the per-predicate statistics (System-R style), plus the scan
 // outputs and the join scratch (24 B per record).
 static void predict(Ctx* ctx, SQuery* q) {
-    const Store& St = ctx->store;
     const size_t m = q->pats.size();
     std::vector<std::vector<int32_t>> vars(m);
-    std::vector<std::vector<double>> dist(m);
-    double bytes = 0;
     for (size_t i = 0; i < m; i++) {
         const mapsq_pattern& p = q->pats[i];
-        const int32_t t[3] = {p.s, p.p, p.o};
-        double ds = (double)q->rows[i], dob = (double)q->rows[i];
-        if (p.p >= 0 && St.pred_ds.size() == St.preds.size()) {
-            auto it = std::lower_bound(St.preds.begin(), St.preds.end(), p.p);
-            if (it != St.preds.end() && *it == p.p) {
-                const size_t pi = size_t(it - St.preds.begin());
-                ds = std::min(ds, (double)St.pred_ds[pi]);
-                dob = std::min(dob, (double)St.pred_do[pi]);
-            }
-        }
-        for (int k = 0; k < 3; k++)
-            if (t[k] < 0) {
-                const int32_t v = -t[k] - 1;
-                if (std::find(vars[i].begin(), vars[i].end(), v) != vars[i].end()) continue;
-                vars[i].push_back(v);
-                dist[i].push_back(k == 0 ? ds : (k == 2 ? dob : (double)q->rows[i]));
-            }
-        const bool scan = p.p < 0 || (p.s < 0 && (p.s == p.p || p.s == p.o)) || (p.p < 0 && p.p == p.o);
-        if (scan) bytes += 4.0 * vars[i].size() * (double)q->rows[i];
+        for (int32_t t : {p.s, p.p, p.o})
+            if (t < 0 && std::find(vars[i].begin(), vars[i].end(), -t - 1) == vars[i].end()) vars[i].push_back(-t - 1);
     }
     int start;
     std::vector<PlanStep> steps;
     greedy_plan(vars, q->rows, q->qvars, &start, &steps);
+    double bytes = 0;
+    std::vector<size_t> cols;
+    const std::vector<double> est = estimate_steps(ctx, q->pats.data(), q->rows, start, steps, &bytes, &cols);
     double rows = (double)q->rows[start];
-    std::vector<int32_t> cv = vars[start];
-    std::vector<double> cd = dist[start];
-    for (const PlanStep& ps : steps) {
-        const double r2 = (double)q->rows[ps.pick];
-        double est;
-        if (ps.cross) {
-            est = rows * r2;
-        } else {
-            double d1 = 1, d2 = 1;
-            for (size_t k = 0; k < cv.size(); k++)
-                if (cv[k] == ps.key) d1 = cd[k];
-            for (size_t k = 0; k < vars[ps.pick].size(); k++)
-                if (vars[ps.pick][k] == ps.key) d2 = dist[ps.pick][k];
-            est = rows * r2 / std::max(1.0, std::max(d1, d2));
-        }
-        bytes += 24.0 * (rows + r2);
-        for (size_t k = 0; k < vars[ps.pick].size(); k++)
-            if (std::find(cv.begin(), cv.end(), vars[ps.pick][k]) == cv.end()) {
-                cv.push_back(vars[ps.pick][k]);
-                cd.push_back(dist[ps.pick][k]);
-            }
-        for (double& d : cd) d = std::min(d, est);
-        bytes += 4.0 * cv.size() * est;
-        rows = est;
+    for (size_t k = 0; k < steps.size(); k++) {
+        bytes += 24.0 * (rows + (double)q->rows[steps[k].pick]) + 4.0 * (double)cols[k] * est[k];
+        rows = est[k];
     }
     q->predicted = bytes;
 }
@@ -341,6 +304,7 @@ static mapsq_status activate(Ctx* ctx, Server* S, SQuery* q) {
         rows[i] = q->tabs[i].nrows;
     }
     greedy_plan(vars, rows, q->qvars, &q->start, &q->steps);
+    q->est = estimate_steps(ctx, q->pats.data(), rows, q->start, q->steps);
     if (mapsq_status st = key_sort_views(ctx, q->pats.data(), q->tabs.data(), q->start, q->steps)) return st;
     q->cur = q->tabs[q->start];
     q->consumed[q->start] = true;
@@ -656,7 +620,9 @@ mapsq_status serve_step(Ctx* ctx, int32_t* n_active, int32_t* n_waiting) {
     for (SQuery* q : in_plain) {
         const PlanStep& ps = q->steps[q->next];
         mapsq_table nxt{};
+        ctx->join_est_rows = q->est[q->next];
         st = join_tables(ctx, &q->cur, &q->tabs[ps.pick], ps.key, &nxt);
+        ctx->join_est_rows = -1.0;
         if (st)
             failed(q, st, ctx->last.out_rows);
         else
