@@ -95,11 +95,14 @@ __device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
 
 // Exclusive prefix of tile `tile` over tiles [first_tile, tile) for one
 // status column; `stride` is the distance between consecutive tiles' words.
-// Reads up to 8 predecessors per round so their load latencies overlap;
-// spins until predecessors publish.  Sums saturate at 2^40 - 1.
+// Reads up to 4 predecessors per round so their load latencies overlap;
+// spins until predecessors publish.  Sums saturate at 2^40 - 1.  (Windows of
+// 8 and 16 were slower on a 16M + 16M-record sort, 0.81 and 1.13 against
+// 0.79 ms: every poll is a device-scope load, and wider polls add traffic
+// the spinning waves compete for.)
 __device__ __forceinline__ uint64_t lookback(const uint64_t* status, uint32_t tile, uint32_t first_tile,
                                              uint32_t stride, uint32_t epoch) {
-    constexpr int WIN = 8;
+    constexpr int WIN = 4;
     uint64_t excl = 0;
     int64_t t = (int64_t)tile - 1;
     while (t >= (int64_t)first_tile) {
@@ -128,11 +131,13 @@ __device__ __forceinline__ uint64_t lookback(const uint64_t* status, uint32_t ti
 // Wave-parallel look-back over one status column (stride 1): each probe
 // reads the LB_PER_LANE * 64 predecessors below `top` at once (lane L the
 // LB_PER_LANE nearest after those of lanes < L) and stops at the nearest
-// inclusive prefix.  When many tiles finish together, a tile walks back over
-// aggregates until it meets an inclusive prefix, so a wide window keeps that
-// walk short.  Every lane of the calling wave must call it; all lanes return
-// the exclusive prefix of `tile` (saturating at 2^40 - 1).
-constexpr int LB_PER_LANE = 4;
+// inclusive prefix.  One word per lane was the fastest window on the
+// 512-join batched launch (67.9 ms, against 69.4 with 2 words per lane,
+// 71.0 with 4 and 72.8 with 8): a wider probe shortens the walk over
+// aggregates but every word is a device-scope load.  Every lane of the
+// calling wave must call it; all lanes return the exclusive prefix of `tile`
+// (saturating at 2^40 - 1).
+constexpr int LB_PER_LANE = 1;
 
 __device__ __forceinline__ uint64_t wave_lookback(const uint64_t* status, uint32_t tile, uint32_t first_tile,
                                                   uint32_t epoch) {

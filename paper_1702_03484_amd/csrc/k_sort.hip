@@ -1,5 +1,5 @@
-// Shuffle of Algorithm 1 ("sort intermediates"): stable LSD radix sort of
-// (u32 key, u32 payload) pairs for gfx950.
+// The Shuffle step of Algorithm 1 (both sides' records grouped by key):
+// stable LSD radix sort of (u32 key, u32 payload) pairs for gfx950.
 //
 // One histogram launch counts the digits of every pass at once; each pass is
 // then one launch that ranks a tile in LDS and scatters it to its final
