@@ -383,7 +383,8 @@ mapsq_status mapsq_table_free(mapsq_ctx* ctx, mapsq_table* t);
 mapsq_status mapsq_last_join_stats(mapsq_ctx* ctx, mapsq_join_stats* out);
 
 /* Radix digit width (4..11 bits; 0 = automatic) and keys per thread of the
- * sort tiles (8 or 16; 0 = automatic) used by later joins.  Every choice
+ * sort tiles (8 or 16; 0 = automatic: the autotuner table or 16 for
+ * mapsq_join, 32 for mapsq_join_batch) used by later joins.  Every choice
  * gives the same rows in the same order. */
 mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_per_thread);
 

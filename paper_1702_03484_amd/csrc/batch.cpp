@@ -105,6 +105,11 @@ mapsq_status join_batch(Ctx* ctx, const mapsq_join_desc* d, int32_t n, mapsq_tab
         if (plan[i].batched && !plan[i].empty) all_rec += (uint64_t)d[i].left->nrows + (uint64_t)d[i].right->nrows;
     int rb, kpt;
     pick_tuning(ctx, key_bits, rb, kpt, all_rec);
+    // Unless set explicitly, 32 keys per thread (8,192-record tiles): every
+    // batched kernel's cost grows with its tiles' look-backs more than with
+    // its records, and half the tiles took the 512-join workload's two
+    // launches from 67.9 to 62.1 ms.
+    if (!ctx->tune_kpt) kpt = 32;
     const int passes = std::max(1, (key_bits + rb - 1) / rb);
     const uint32_t TILE = BLOCK_THREADS * (uint32_t)kpt;  // records per tile
     const size_t buckets = size_t(1) << rb;

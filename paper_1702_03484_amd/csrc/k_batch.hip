@@ -221,9 +221,10 @@ __global__ __launch_bounds__(MQ_BLOCK) void bhist_kernel(const BatchHdr* __restr
         }
 }
 
-// at most 168 VGPRs (3 waves per SIMD instead of 2)
+// 16 keys per thread: at most 168 VGPRs (3 waves per SIMD instead of 2);
+// 32: the 72 KB tile in LDS allows 2 blocks per CU, so up to 256 VGPRs
 template <int RB, int KPT, bool GEN>
-__global__ __launch_bounds__(MQ_BLOCK, 3) void bpass_kernel(const BatchHdr* __restrict__ h, int pass) {
+__global__ __launch_bounds__(MQ_BLOCK, KPT > 16 ? 2 : 3) void bpass_kernel(const BatchHdr* __restrict__ h, int pass) {
     using R = Radix<RB>;
     constexpr uint32_t TILE = MQ_BLOCK * KPT;
     __shared__ SortSmem<RB, KPT> sm;
@@ -487,7 +488,9 @@ static hipError_t launch_batch_t(const BatchHdr* hdr, int passes, hipStream_t st
 hipError_t launch_batch(const BatchHdr* hdr, int rb, int kpt, int passes, hipStream_t stream) {
 #define MQ_B(B)                                                                                 \
     case B:                                                                                     \
-        return kpt == 8 ? launch_batch_t<B, 8>(hdr, passes, stream) : launch_batch_t<B, 16>(hdr, passes, stream);
+        return kpt == 8    ? launch_batch_t<B, 8>(hdr, passes, stream)                          \
+               : kpt == 16 ? launch_batch_t<B, 16>(hdr, passes, stream)                         \
+                           : launch_batch_t<B, 32>(hdr, passes, stream);
     switch (rb) {
         MQ_B(4) MQ_B(5) MQ_B(6) MQ_B(7) MQ_B(8) MQ_B(9) MQ_B(10) MQ_B(11)
         default: return hipErrorInvalidValue;
