@@ -394,14 +394,20 @@ __device__ __forceinline__ bool bjoin_uses_sval(const BatchHdr* h, const BatchJo
 template <int KPT>
 __global__ __launch_bounds__(MQ_BLOCK) void bgather_kernel(const BatchHdr* __restrict__ h) {
     constexpr uint32_t TILE = MQ_BLOCK * KPT;
+    // work units of at most 4,096 records whatever the tile size (with
+    // 8,192-record units the launch took 6.40 instead of 5.67 ms)
+    constexpr uint32_t UNIT = TILE < 4096u ? TILE : 4096u;
+    constexpr uint32_t UPT = TILE / UNIT;
     const int fin = (h->passes - 1) & 1;
-    for (uint32_t t = blockIdx.x; t < h->total_tiles; t += gridDim.x) {
+    const uint32_t nu = h->total_tiles * UPT;
+    for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
+        const uint32_t t = u / UPT;
         const BatchJoin& J = h->joins[h->tile_join[t]];
         if (!bjoin_uses_sval(h, J)) continue;
         const uint32_t n = J.nrec;
-        const uint32_t i0 = (t - J.tile_off) * TILE;
+        const uint32_t i0 = (t - J.tile_off) * TILE + (u % UPT) * UNIT;
         if (i0 >= n) continue;
-        const uint32_t i1 = min(i0 + TILE, n);
+        const uint32_t i1 = min(i0 + UNIT, n);
         const uint32_t* vals = h->vals[fin] + J.rec_off;
         for (uint32_t i = i0 + threadIdx.x; i < i1; i += MQ_BLOCK) {
             const uint32_t r = vals[i];
