@@ -248,3 +248,37 @@ def test_batch_semijoin_filter(sess):
     for ts in outs.values():
         for t in ts:
             sess.free(t)
+
+
+def test_batch_keys_per_thread_agree(sess):
+    """The batched launch at 8, 16 and 32 keys per thread (tiles of 2,048,
+    4,096 and 8,192 records; 32 is the default) gives the same rows in the
+    same order, equal to the oracle and to mapsq_join; the joins' record
+    counts fall below, on and just past tile edges of every size, and the
+    filtered (semi-join) and unfiltered paths both run."""
+    announce("batch: 8, 16 and 32 keys per thread agree")
+    joins, host = make_batch(sess, 5, 24, max_rows=120_000)
+    for i, (nl, nr) in enumerate([(8192, 8191), (8193, 2048), (4096, 12_289), (2047, 40_000)]):
+        keys = np.arange(3_000, dtype=np.int64) * 5 + 1
+        lc = random_table(900 + 2 * i, nl, 3_000, 1, key_ids=keys)
+        rc = random_table(901 + 2 * i, nr, 3_000, 2, key_ids=keys)
+        lv, rv = [0, 10], [0, 20, 21]
+        joins.append((sess.table(lv, [dev(c) for c in lc], key_max=-1),
+                      sess.table(rv, [dev(c) for c in rc], key_max=-1), 0))
+        host.append((Table(lv, lc), Table(rv, rc)))
+    outs = {}
+    try:
+        for kpt in (8, 16, 0):
+            sess.set_tuning(0, kpt)
+            outs[kpt] = sess.join_batch(joins)
+    finally:
+        sess.set_tuning(0, 0)
+    for kpt in (8, 16):
+        for i, (a, b) in enumerate(zip(outs[0], outs[kpt])):
+            assert a.nrows == b.nrows and a.vars == b.vars, (kpt, i)
+            for c in range(a.ncols):
+                assert torch.equal(sess.column(a, c), sess.column(b, c)), (kpt, i, c)
+    check_against_plain_and_oracle(sess, joins, host, outs[0])
+    for ts in outs.values():
+        for t in ts:
+            sess.free(t)
