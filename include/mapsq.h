@@ -403,7 +403,10 @@ mapsq_status mapsq_set_tuning(mapsq_ctx* ctx, int32_t radix_bits, int32_t keys_p
  * precount: before a shuffle, count |RS| exactly from dense per-key counts
  *   (two passes over the keys), so that a join with no key in common, or
  *   whose result cannot fit in the arena, ends without sorting.  0 =
- *   automatic (shuffles of at least 2^24 records), 1 = never, 2 = every
+ *   automatic: shuffles of at least 2^24 records, except the join steps of
+ *   mapsq_query and of the server whose planned output (the System-R
+ *   estimate of the pattern-size plan, or the exact planner's count) would
+ *   take at most 1/8 of the arena's free space; 1 = never, 2 = every
  *   shuffle.  Without it the same outcome comes after the sort.
  * composite: 0 = a second variable both tables bind is part of the join key
  *   (see mapsq_join), 1 = join on key_var alone and filter the second

@@ -333,7 +333,8 @@ def mapsq_last_join_stats(ctx) -> mapsq_join_stats:
 def mapsq_set_join_options(ctx, semijoin: int = 0, merge: int = 0, precount: int = 0, composite: int = 0):
     """semijoin: 0 automatic, 1 never, 2 always; merge: 0 when both sides are
     sorted on the key, 1 never; precount (exact |RS| before sorting): 0 for
-    shuffles of 2^24+ records, 1 never, 2 always; composite: 0 a second
+    shuffles of 2^24+ records unless a planned step's expected output is
+    small, 1 never, 2 always; composite: 0 a second
     shared variable is part of the join key, 1 it is filtered afterwards."""
     _check(ctx, lib().mapsq_set_join_options(ctx, semijoin, merge, precount, composite))
 

@@ -146,7 +146,8 @@ class MapSQ:
 
     def set_join_options(self, semijoin: int = 0, merge: int = 0, precount: int = 0, composite: int = 0):
         """semijoin 0 automatic / 1 never / 2 always; merge 0 automatic / 1 never;
-        precount 0 shuffles of 2^24+ records / 1 never / 2 always; composite 0
+        precount 0 shuffles of 2^24+ records (not planned steps with a small
+        expected output) / 1 never / 2 always; composite 0
         a second shared variable joins as part of the key / 1 filtered after."""
         B.mapsq_set_join_options(self.ctx, semijoin, merge, precount, composite)
 
