@@ -130,13 +130,14 @@ __global__ __launch_bounds__(HRED_WAVES * MQ_WAVE) void hist_reduce_kernel(const
 
 uint32_t radix_hist_part_words(int rb, int passes) { return HIST_BLOCKS * (uint32_t)passes << rb; }
 
-// Waves per block of a radix pass: 8 (8,192-record tiles, half the tile-id
-// atomics and look-backs of 4-wave blocks; two blocks still fit a CU's LDS)
-// for digits of up to 8 bits at 16 keys per thread, else 4.  The first pass
-// (reading the input columns) needs more registers: at 3 waves per SIMD only
-// one 8-wave block would fit a CU, so it keeps 4-wave blocks.
+// Waves per block of a radix pass for digits of up to 8 bits at 16 keys per
+// thread: 16 for a carried pass (16,384-record tiles in 140 KB of LDS, one
+// block and 4 waves per SIMD on a CU) and 8 for the first pass (8,192-record
+// tiles, two blocks per CU at its 128-VGPR bound), else 4.  Fewer, larger
+// tiles mean fewer tile-id atomics and look-backs: on a 16M + 16M-record
+// sort 4- and 8-wave blocks took 0.79 ms, 8 and 8 0.76 ms, 8 and 16 0.75 ms.
 __host__ __device__ constexpr int sort_waves(int rb, int kpt, bool gen) {
-    return rb <= 8 && kpt == 16 && !gen ? 8 : 4;
+    return rb <= 8 && kpt == 16 ? (gen ? 8 : 16) : 4;
 }
 
 // the first pass is held to 128 VGPRs (4 waves per SIMD instead of 3, no spills)
